@@ -1,0 +1,51 @@
+"""Rays of a 2-D scan, FP64 (test infrastructure; see oracle/__init__.py).
+
+The paper states no scan geometry (its data come from a baggage scanner whose geometry
+is not given), so the conventions below are this project's reading:
+  * view v at angle a = angle0 + v * angle_span / n_views;
+  * bin b at detector coordinate u = (b - (n_bins - 1) / 2) * bin_pitch;
+  * parallel beam: the line x cos a + y sin a = u, direction (-sin a, cos a);
+  * fan beam with a flat detector: source at sod * (cos a, sin a), detector centre at
+    -(sdd - sod) * (cos a, sin a), detector axis (-sin a, cos a); the ray joins the
+    source to the bin centre.
+Ray index y = v * n_bins + b. Every geometry attribute is read by name from `g`.
+"""
+import numpy as np
+
+
+def view_angles(g):
+    return g.angle0 + np.arange(g.n_views, dtype=np.float64) * (g.angle_span / g.n_views)
+
+
+def bin_offsets(g):
+    return (np.arange(g.n_bins, dtype=np.float64) - (g.n_bins - 1) / 2.0) * g.bin_pitch
+
+
+def rays(g, views=None):
+    """(origin [M,2], unit direction [M,2]) for the selected views (default: all)."""
+    ang = view_angles(g)
+    if views is not None:
+        ang = ang[np.asarray(views)]
+    u = bin_offsets(g)
+    nv, nb = ang.size, u.size
+    cos_a = np.repeat(np.cos(ang), nb)
+    sin_a = np.repeat(np.sin(ang), nb)
+    uu = np.tile(u, nv)
+    if g.kind == 0:      # parallel
+        origin = np.stack([uu * cos_a, uu * sin_a], axis=1)
+        direction = np.stack([-sin_a, cos_a], axis=1)
+    elif g.kind == 1:    # fan, flat detector
+        src = g.sod * np.stack([cos_a, sin_a], axis=1)
+        det = (-(g.sdd - g.sod)) * np.stack([cos_a, sin_a], axis=1) \
+            + uu[:, None] * np.stack([-sin_a, cos_a], axis=1)
+        v = det - src
+        direction = v / np.linalg.norm(v, axis=1, keepdims=True)
+        origin = src
+    else:
+        raise ValueError("geometry kind must be 0 (parallel) or 1 (fan)")
+    return origin, direction
+
+
+def pixel_edges(g):
+    """x (equally y) coordinates of the n+1 pixel boundaries, image centred at 0."""
+    return (np.arange(g.n + 1, dtype=np.float64) - g.n / 2.0) * g.pixel

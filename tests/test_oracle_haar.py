@@ -1,0 +1,101 @@
+"""Pins of the CPU reference's Haar synthesis Omega (eq. 1.2): orthonormality, agreement
+with an independent textbook cascade, leaf constancy on trees, and the hand example."""
+import numpy as np
+import pytest
+
+from oracle import haar, siddon, geometry, wam
+from paper_1508_04458_amd import synth
+from golden_io import load
+
+
+@pytest.mark.parametrize("n,L", [(2, 1), (8, 1), (8, 3), (16, 2), (32, 4)])
+def test_orthonormal_and_matches_cascade(n, L):
+    O = haar.synthesis_matrix(n, L)
+    np.testing.assert_allclose((O.T @ O).toarray(), np.eye(n * n), atol=1e-14)
+    rng = np.random.default_rng(n + L)
+    beta = rng.normal(size=(n, n))
+    mu = (O @ beta.ravel()).reshape(n, n)
+    np.testing.assert_allclose(mu, haar.cascade_synthesis(beta, L), atol=1e-13)
+    np.testing.assert_allclose(haar.cascade_analysis(mu, L), beta, atol=1e-13)
+    assert abs(np.linalg.norm(mu) - np.linalg.norm(beta)) < 1e-12
+
+
+def test_golden_2x2_columns():
+    O = haar.synthesis_matrix(2, 1).toarray()
+    np.testing.assert_allclose(O[:, 0], [0.5, 0.5, 0.5, 0.5])
+    np.testing.assert_allclose(O[:, 1], [0.5, -0.5, 0.5, -0.5])
+    np.testing.assert_allclose(O[:, 2], [0.5, 0.5, -0.5, -0.5])
+    np.testing.assert_allclose(O[:, 3], [0.5, -0.5, -0.5, 0.5])
+
+
+def test_cascade_hand_example():
+    # a = 4, b = 2, c = 6, d = 0  ->  LL = 6, D1 = (4-2+6-0)/2 = 4, D2 = (4+2-6-0)/2 = 0, D3 = (4-2-6+0)/2 = -2
+    out = haar.cascade_analysis(np.array([[4.0, 2.0], [6.0, 0.0]]), 1)
+    np.testing.assert_allclose(out, [[6.0, 4.0], [0.0, -2.0]])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_leaf_constant_on_random_tree(seed):
+    n, L = 32, 3
+    mask = synth.random_tree_mask(n, L, seed)
+    assert haar.valid_mask(mask, L)
+    O = haar.synthesis_matrix(n, L)
+    beta = np.random.default_rng(seed).normal(size=(n, n)) * mask
+    mu = (O @ beta.ravel()).reshape(n, n)
+    lev = haar.leaf_level_map(mask, L)
+    for r in range(n):
+        for c in range(n):
+            s = 1 << lev[r, c]
+            r0, c0 = (r // s) * s, (c // s) * s
+            assert abs(mu[r, c] - mu[r0, c0]) < 1e-13
+
+
+def test_valid_mask_rejects_orphans():
+    n, L = 16, 2
+    m = haar.approx_mask(n, L)
+    assert haar.valid_mask(m, L)
+    bad = m.copy()
+    f = np.zeros((8, 8), bool)
+    f[3, 3] = True           # a level-1 node split while its parent is not
+    haar.set_split(bad, 1, f)
+    assert not haar.valid_mask(bad, L)
+
+
+@pytest.mark.parametrize("name,L", [("parallel64", 2), ("fan96", 3)])
+def test_phi_columns_equal_quadrant_chords(name, L):
+    """phi(y|z) from H Omega (sparse product) equals 2^-l sum_q s_k(q) chord(y, quadrant q)
+    computed by brute-force box clipping (and 2^-L chord(y, block) for approximations)."""
+    g = synth.CONFIGS[name]["geom"]()
+    H = siddon.system_matrix(g)
+    O = haar.synthesis_matrix(g.n, L)
+    Phi, act = wam.phi_matrix(H, O, haar.full_mask(g.n), g.pixel)
+    Phi = Phi.tocsc()
+    o, e = geometry.rays(g)
+    edges = geometry.pixel_edges(g)
+    rng = np.random.default_rng(5)
+    n = g.n
+    for _ in range(12):
+        lev = int(rng.integers(1, L + 1))
+        m = n >> lev
+        i, j = rng.integers(0, m, 2)
+        s = 1 << lev
+        h = s >> 1
+        q = {}
+        for qy in (0, 1):
+            for qx in (0, 1):
+                x0 = edges[j * s + qx * h]
+                x1 = edges[j * s + (qx + 1) * h]
+                y0 = edges[i * s + qy * h]
+                y1 = edges[i * s + (qy + 1) * h]
+                q[qy, qx] = siddon.box_chord(o, e, x0, x1, y0, y1)
+        d1 = (q[0, 0] - q[0, 1] + q[1, 0] - q[1, 1]) * 2.0 ** -lev
+        d2 = (q[0, 0] + q[0, 1] - q[1, 0] - q[1, 1]) * 2.0 ** -lev
+        d3 = (q[0, 0] - q[0, 1] - q[1, 0] + q[1, 1]) * 2.0 ** -lev
+        for zr, zc, ref in ((i, m + j, d1), (m + i, j, d2), (m + i, m + j, d3)):
+            col = np.asarray(Phi[:, zr * n + zc].todense()).ravel()
+            ref = np.where(np.abs(ref) <= 1e-12 * g.pixel, 0.0, ref)
+            assert np.abs(col - ref).max() < 1e-12
+        if lev == L:
+            llc = np.asarray(Phi[:, i * n + j].todense()).ravel()
+            ref = sum(q.values()) * 2.0 ** -L
+            assert np.abs(llc - ref).max() < 1e-12
