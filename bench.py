@@ -1,0 +1,216 @@
+"""Benchmark: tree-adaptive wavelet AM on one MI355X (fan512 workload).
+
+A step is one complete reconstruction of Algorithm 1 with the tree rule: 100 iterations
+from beta = 0 on the approximation-only 3-level tree, expanding at iterations 21, 43 and 85
+(the paper's 64/128/256-of-300 schedule scaled to 100 iterations). Inputs (counts, I0)
+are resident in HBM before timing starts. Prints ONE JSON line.
+
+Extra fields:
+  gray_voxel_per_s  sum_j 2 W_j / time, W_j = (ray, active coefficient) pairs with phi != 0
+  full_am           image-domain AM (levels = 0) on the same GPU: it/s, and the time it
+                    needs to reach the tree run's final I-divergence (equal-objective)
+  roofline          the update kernel (sign-split backprojection + eq. 1.9 zero), timed with
+                    HIP events on the library's stream over the timed steps
+  cpu_baseline      the FP64 CPU oracle on a bounded sample of the same workload
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "AM iter/s + GRay-voxel/s (fwd+back), tree vs full AM, same GPU, equal I-div"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="fan512")
+    ap.add_argument("--geometry", default="f64", choices=["f32", "f64"])
+    ap.add_argument("--full-iters", type=int, default=300, help="cap for the equal-I-div full-AM run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full-am", action="store_true")
+    ap.add_argument("--cpu-views", type=int, default=36)
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("wamct_kernels.hip", "wamct_geom.h", "wamct_internal.h"):
+        with open(os.path.join(ROOT, "paper_1508_04458_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_hash, config):
+    """HBM bytes per launch of the update kernel from committed rocprofv3 PMC summaries,
+    only if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_update_{config}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_hash") != kernel_hash:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(P, n_views_sample):
+    """The FP64 oracle (never tuned) on a view subset of the same scan: Algorithm 1 with
+    the same schedule; time of the solve (trees, Phi builds and iterations; not H or b)
+    scaled by n_views / n_views_sample, as AM iterations per second."""
+    import numpy as np
+    from oracle import siddon, wam
+    from paper_1508_04458_amd import synth
+    g = P.geom
+    step = max(1, g.n_views // n_views_sample)
+    views = np.arange(0, g.n_views, step)[:n_views_sample]
+    rows = (views[:, None] * g.n_bins + np.arange(g.n_bins)[None, :]).ravel()
+    H = siddon.system_matrix(g, views=views)
+    t0 = time.perf_counter()
+    r = wam.wam_solve(H, g.n, P.levels, P.d[rows], P.i0, P.n_iters, g.pixel, schedule=P.schedule)
+    dt = time.perf_counter() - t0
+    scale = g.n_views / len(views)
+    per_iter = dt * scale / P.n_iters
+    return {"value": 1.0 / per_iter, "unit": "AM iter/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 NumPy/SciPy oracle, Algorithm 1 with the tree rule, {P.n_iters} iterations "
+                       f"(expansions {P.schedule}) on {len(views)} of {g.n_views} views; solve time "
+                       f"{dt:.1f} s scaled by {scale:.0f}; setup (H, b) excluded; single thread"),
+            "final_idiv_sample": float(r["idiv"][-1])}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the view-sharded "
+              "multi-GPU design is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+    if args.no_cpu_baseline is False:
+        # the CPU baseline is a single-threaded oracle
+        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            os.environ[k] = "1"
+    import numpy as np
+    import torch
+    from paper_1508_04458_amd import api, synth
+
+    P = synth.make_problem(args.config)
+    g = P.geom
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    d = torch.as_tensor(P.d, dtype=torch.float32, device=dev)
+    ctx = api.Context(g, P.levels, "f32", device=dev, geometry=args.geometry)
+    ctx.set_data(d, P.i0)
+    J, sched = P.n_iters, list(P.schedule)
+    idiv = torch.empty(J + 1, dtype=torch.float64, device=dev)
+
+    # ---- tree statistics per segment (untimed): W_j and |Z_s| of each tree
+    ctx.reset()
+    marks = [0] + sched + [J]
+    seg = []
+    for k, (a, b) in enumerate(zip(marks[:-1], marks[1:])):
+        if k > 0:
+            ctx.expand(0.1)
+        st = ctx.tree_stats()
+        seg.append(dict(start=a, iters=b - a, w=st["w"], n_active=st["n_active"], z0=st["z0"]))
+        ctx.iterate(b - a)
+    pairs = sum(2 * s["w"] * s["iters"] for s in seg)
+    w_update_avg = sum(s["w"] * s["iters"] for s in seg) / J
+    active_avg = sum(s["n_active"] * s["iters"] for s in seg) / J
+
+    def step():
+        ctx.reset()
+        ctx.solve(J, sched, 0.1, idiv)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tim = ctx.get_timing()
+    ctx.timing(False)
+    tr = idiv.cpu().numpy()
+    ms_step = dt * 1e3 / args.steps
+    it_s = J * args.steps / dt
+
+    # ---- roofline of the dominant kernel (update: sign-split backprojection + eq. 1.9)
+    up = tim["update"]
+    upd_ms = up["ms"] / max(1, up["launches"])
+    M = g.n_rays
+    # stored-Phi equivalent: 8 B per (ray, coefficient) pair (FP32 value + int32 index),
+    # plus q-hat (4 B per ray) and b, beta read + beta written (12 B per active coefficient)
+    alg_bytes = 8.0 * w_update_avg + 4.0 * M + 12.0 * active_avg
+    achieved = alg_bytes / (upd_ms * 1e-3) / 1e9
+    khash = kernel_source_hash()
+    traffic = measured_traffic(khash, args.config)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_gather<float,double,kUpdate>", "avg_launch_ms": round(upd_ms, 5),
+            "launches": up["launches"], "alg_bytes_per_launch": int(alg_bytes), "kernel_hash": khash}
+    timing_ms = {k: round(v["ms"] / args.steps, 4) for k, v in tim.items()}
+
+    out = {"metric": METRIC, "value": round(it_s, 2), "unit": "AM iter/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if args.geometry == "f32" else "f32 data, f64 ray geometry",
+           "data": "synthetic",
+           "config": {"workload": f"{args.config}: 2-D fan beam {g.n}x{g.n}, {g.n_views} views x {g.n_bins} bins, "
+                                  f"{P.levels}-level tree-adaptive wavelet AM, {J} iterations, expansions at {sched}",
+                      "levels": P.levels, "iterations": J, "schedule": sched, "rays": M, "pixels": g.n * g.n},
+           "gray_voxel_per_s": round(pairs * args.steps / dt / 1e9, 3),
+           "pixel_equiv_gray_voxel_per_s": None,
+           "final_idiv": float(tr[-1]),
+           "trees": seg,
+           "time_ms_per_step_by_kernel": timing_ms,
+           "roofline": roof}
+
+    # ---- full-image AM (levels = 0) on the same GPU: equal-I-div comparison
+    if not args.no_full_am:
+        full = api.Context(g, 0, "f32", device=dev, geometry=args.geometry)
+        full.set_data(d, P.i0)
+        cap = args.full_iters
+        fidiv = torch.empty(cap + 1, dtype=torch.float64, device=dev)
+        full.reset()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        full.solve(cap, [], 0.1, fidiv)
+        torch.cuda.synchronize()
+        t_full = time.perf_counter() - t1
+        ft = fidiv.cpu().numpy()
+        w_pix = full.tree_stats()["w"]
+        target = tr[-1]
+        hit = np.nonzero(ft <= target)[0]
+        k_star = int(hit[0]) if hit.size else None
+        full_it_s = cap / t_full
+        eq = {"tree_final_idiv": float(target), "full_iters_to_reach": k_star,
+              "full_idiv_at_cap": float(ft[-1]), "cap": cap}
+        if k_star is not None:
+            t_eq = k_star / full_it_s
+            eq.update(full_time_ms=round(t_eq * 1e3, 3), tree_time_ms=round(ms_step, 3),
+                      tree_speedup=round(t_eq * 1e3 / ms_step, 3))
+        out["full_am"] = {"iter_per_s": round(full_it_s, 2), "w_per_pass": int(w_pix),
+                          "gray_voxel_per_s": round(2 * w_pix * full_it_s / 1e9, 3)}
+        out["pixel_equiv_gray_voxel_per_s"] = round(2 * w_pix * it_s / 1e9, 3)
+        out["equal_idiv"] = eq
+        full.close()
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(P, args.cpu_views)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/*
+ * wamct: wavelet-tree alternating minimization (AM) for transmission CT on AMD MI355X.
+ *
+ * C ABI of the hot path of the method of Degirmenci, O'Sullivan and Politte,
+ * "Multiresolution Approach to Acceleration of Iterative Image Reconstruction for X-Ray
+ * Imaging for Security Applications" (arXiv 1508.04458). Every step runs in HIP kernels
+ * for gfx950; the host code only validates, allocates at creation, and launches.
+ *
+ * Conventions (mm, mm^-1):
+ *   image    n x n pixels of size `pixel`, centred on the origin, row-major [r][c];
+ *            pixel (r, c) covers x in [(c - n/2) pixel, (c + 1 - n/2) pixel), y likewise with r.
+ *   sinogram [view][bin], bin fastest; ray y = view * n_bins + bin through the bin centre.
+ *            View v has angle a = angle0 + v * angle_span / n_views, bin b sits at
+ *            u = (b - (n_bins - 1) / 2) * bin_pitch on the detector axis (-sin a, cos a).
+ *            Parallel beam: the line x cos a + y sin a = u. Fan beam (flat detector): from
+ *            the source sod (cos a, sin a) to the point -(sdd - sod)(cos a, sin a) + u (-sin a, cos a).
+ *   wavelets orthonormal 2-D Haar with `levels` levels in Mallat layout (an n x n array):
+ *            at level l (1..L), with m = n >> l, node (l, i, j) covers pixel rows
+ *            [i 2^l, (i+1) 2^l) and columns [j 2^l, (j+1) 2^l); its details sit at
+ *            [i][m+j] (D1), [m+i][j] (D2), [m+i][m+j] (D3); the approximation of root (i, j)
+ *            sits at [i][j], i, j < n >> L. Basis: approximation 2^-L on the root block;
+ *            detail k = 2^-l s_k on the node block with quadrant signs over (top-left,
+ *            top-right, bottom-left, bottom-right) s1 = (+,-,+,-), s2 = (+,+,-,-),
+ *            s3 = (+,-,-,+), "top" = smaller row index.
+ *   tree     the active set Z_s (footnote to eq. 1.61) is a uint8 n x n mask in Mallat
+ *            layout: approximations always active; a node's three details are active
+ *            together ("split"), and only if its parent is split or it is a root.
+ *            levels = 0 is image-domain AM (Omega = I, every pixel active).
+ *
+ * Arrays: every bulk array argument is a DEVICE pointer owned by the caller, of the
+ * context's element type (float for WAMCT_F32, double for WAMCT_F64) unless stated
+ * otherwise; struct arguments are host memory, copied during the call. All work is
+ * ordered on the stream given at creation; calls return after enqueueing unless they
+ * return a host value, which synchronizes that stream.
+ *
+ * Errors: every call returns a wamct_status and never aborts; wamct_last_error(ctx)
+ * gives the message of the last failing call on that context (NULL ctx: the last
+ * failure of wamct_create/wamct_validate in this thread).
+ */
+#ifndef WAMCT_H
+#define WAMCT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WAMCT_OK = 0,
+  WAMCT_E_INVALID = 1,     /* bad argument, geometry or data */
+  WAMCT_E_UNSUPPORTED = 2, /* valid request this build does not implement */
+  WAMCT_E_OOM = 3,         /* device allocation failed */
+  WAMCT_E_HIP = 4,         /* HIP runtime error (message carries hipGetErrorString) */
+  WAMCT_E_NUMERIC = 5,     /* non-finite values where finite ones are required */
+  WAMCT_E_STATE = 6        /* call out of order (e.g. iterate before set_data) */
+} wamct_status;
+
+enum { WAMCT_PARALLEL = 0, WAMCT_FAN = 1 };
+enum { WAMCT_F32 = 0, WAMCT_F64 = 1 };
+
+/* Scan geometry (the paper gives none; see the conventions above). */
+typedef struct {
+  int32_t kind;        /* WAMCT_PARALLEL or WAMCT_FAN */
+  int32_t n;           /* image is n x n; 2 <= n <= 8192 */
+  double pixel;        /* pixel size [mm], > 0 */
+  int32_t n_views;     /* >= 1 */
+  double angle0;       /* [rad] */
+  double angle_span;   /* [rad]; view v at angle0 + v * angle_span / n_views */
+  int32_t n_bins;      /* >= 1 */
+  double bin_pitch;    /* [mm] at the detector, > 0 */
+  double sod;          /* fan: source to isocentre [mm], > image circumradius */
+  double sdd;          /* fan: source to detector [mm], > sod */
+} wamct_geometry;
+
+typedef struct {
+  int32_t levels;      /* Haar levels L, 0 <= L <= 8, n divisible by 2^L (Results: L = 3) */
+  int32_t dtype;       /* WAMCT_F32 or WAMCT_F64: element type of every bulk array */
+  int32_t geometry;    /* WAMCT_F32 or WAMCT_F64 (>= dtype): precision of the ray geometry,
+                          chord lengths and per-ray/per-coefficient sums. WAMCT_F64 keeps
+                          chords exact to ~1e-13 mm; WAMCT_F32 chords carry an absolute error
+                          of about 1e-7 times the image half-diagonal. */
+} wamct_options;
+
+enum {                 /* kernel classes reported by wamct_get_timing */
+  WAMCT_K_SYNTH = 0,   /* mu = Omega beta over the active tree                      */
+  WAMCT_K_FORWARD = 1, /* ray-driven projection over tree leaves, q = I0 exp(-p), I-div */
+  WAMCT_K_UPDATE = 2,  /* node-driven sign-split backprojection + eq. 1.9 zero        */
+  WAMCT_K_TREE = 3,    /* Z0, tree expansion, work-list compaction                  */
+  WAMCT_K_OTHER = 4,   /* reductions, transforms, operator calls                    */
+  WAMCT_NK = 5
+};
+
+/* Check geometry and options on the host only (no GPU use). Returns WAMCT_E_INVALID
+ * with a message in msg (NUL-terminated, at most msg_len bytes; msg may be NULL). */
+wamct_status wamct_validate(const wamct_geometry* geom, const wamct_options* opt,
+                            char* msg, int32_t msg_len);
+
+typedef struct wamct_ctx wamct_ctx;   /* opaque; owns every device work buffer */
+
+/* Create a context on the current HIP device: validates, allocates every device buffer
+ * the iteration needs (iterating allocates nothing), builds the ray table and the
+ * approximation-only tree (Results: the initial tree) with beta = 0 (beta^(0) is an input
+ * of Algorithm 1 whose value the paper does not give). `stream` is a hipStream_t
+ * (NULL = default stream). On success *out owns the context (free with wamct_destroy). */
+wamct_status wamct_create(const wamct_geometry* geom, const wamct_options* opt,
+                          void* stream, wamct_ctx** out);
+wamct_status wamct_destroy(wamct_ctx* ctx);
+const char* wamct_last_error(const wamct_ctx* ctx);
+const char* wamct_version(void);
+wamct_status wamct_set_stream(wamct_ctx* ctx, void* stream);
+
+/* Measured data of the Beer's-law model q(y) = I0(y) exp(-sum_x h(y|x) mu(x))
+ * (Introduction). d: counts, [n_views * n_bins], finite and >= 0. i0: per-ray incident
+ * counts of the same shape, or NULL to use the scalar i0_scalar (> 0). Both are COPIED
+ * into the context. Also precomputes b(z) = sum_y d(y) phi(y|z) for every coefficient
+ * (eq. 1.6; Algorithm 1 "Precompute") as Omega^T (H^T d). Synchronizes (validation). */
+wamct_status wamct_set_data(wamct_ctx* ctx, const void* d, const void* i0, double i0_scalar);
+
+/* beta = 0 and the approximation-only tree. */
+wamct_status wamct_reset(wamct_ctx* ctx);
+/* Set beta (Mallat, n*n) and the tree mask (uint8 device array, n*n). The mask must be a
+ * valid tree (checked; E_INVALID otherwise); beta is zeroed outside it (inactive
+ * coefficients are zero). Synchronizes. */
+wamct_status wamct_set_state(wamct_ctx* ctx, const void* beta, const uint8_t* mask);
+/* Copy beta and the mask out (either may be NULL); *iter_host (nullable) receives the
+ * number of iterations applied since the last reset/set_state. */
+wamct_status wamct_get_state(wamct_ctx* ctx, void* beta, uint8_t* mask, int32_t* iter_host);
+
+/* n_iters iterations of Algorithm 1 on the current tree: q-hat = I0 exp(-Phi beta),
+ * b-hat+/- (eq. 1.10), Z0 (eq. 1.61, recomputed only when the tree changed) and the
+ * closed-form zero of eq. 1.9 for every active coefficient. idiv (nullable, device
+ * double[n_iters]) receives I(d || q-hat^(j)) before each update (footnote to the
+ * Introduction). Coefficients whose surrogate has no finite minimizer are held and
+ * counted (wamct_tree_stats). E_STATE before wamct_set_data. */
+wamct_status wamct_iterate(wamct_ctx* ctx, int32_t n_iters, double* idiv);
+
+/* Tree rule of the Results section: synthesize mu, threshold = frac * max(mu) (FP64);
+ * every leaf at level >= 1 with a pixel above the threshold (strict) gets its three
+ * details activated at zero; one level per call; nothing if max(mu) <= 0.
+ * *n_split_host (nullable) receives the number of split nodes. Synchronizes. */
+wamct_status wamct_expand(wamct_ctx* ctx, double frac, int32_t* n_split_host);
+
+/* Algorithm 1 with the tree schedule: for j in [0, n_iters): expand (frac) first if j is
+ * listed in expand_at (host int32[n_expand], ascending), then iterate once. idiv
+ * (nullable, device double[n_iters + 1]) gets I(d || q-hat^(j)) for every j and after the
+ * last update. Synchronizes once per expansion. */
+wamct_status wamct_solve(wamct_ctx* ctx, int32_t n_iters, const int32_t* expand_at,
+                         int32_t n_expand, double frac, double* idiv);
+
+/* mu = Omega beta for the current state (eq. 1.2), mu: [n*n]. */
+wamct_status wamct_synthesize(wamct_ctx* ctx, void* mu);
+/* p = H mu for an arbitrary image mu [n*n] (pixel-level ray tracing), p: [n_rays]. */
+wamct_status wamct_project(wamct_ctx* ctx, const void* mu, void* p);
+/* img = H^T y, y: [n_rays], img: [n*n]. */
+wamct_status wamct_backproject(wamct_ctx* ctx, const void* y, void* img);
+/* Sign-split coefficient backprojections over the current tree (eq. 1.10):
+ * bp(z) = sum_{phi(y|z) > 0} y phi(y|z) and bm(z) = sum_{phi(y|z) < 0} y phi(y|z) for
+ * active z, 0 elsewhere; bp, bm: [n*n] Mallat. */
+wamct_status wamct_backproject_split(wamct_ctx* ctx, const void* y, void* bp, void* bm);
+/* q-hat = I0 exp(-Phi beta) of the current state into q [n_rays] (nullable), and
+ * I(d || q-hat) into *idiv (device double, nullable). E_STATE before set_data. */
+wamct_status wamct_forward(wamct_ctx* ctx, void* q, double* idiv);
+/* I(d || q) for q [n_rays] into *out (device double). */
+wamct_status wamct_idiv(wamct_ctx* ctx, const void* q, double* out);
+/* The precomputed b (eq. 1.6) for every coefficient, [n*n] Mallat. */
+wamct_status wamct_get_b(wamct_ctx* ctx, void* b);
+/* Host copies of the current tree's Z0 (eq. 1.61), W = number of (ray, active
+ * coefficient) pairs with phi != 0, the number of active coefficients, and the number of
+ * coefficient updates held since the last reset (any pointer may be NULL). Synchronizes. */
+wamct_status wamct_tree_stats(wamct_ctx* ctx, double* z0, int64_t* w, int64_t* n_active,
+                              int64_t* n_held);
+
+/* Kernel timing with HIP events on the context's stream: enable != 0 starts recording
+ * (and clears the totals). wamct_get_timing synchronizes and returns, per kernel class
+ * (WAMCT_K_*), the summed duration in ms and the launch count (arrays of WAMCT_NK). */
+wamct_status wamct_timing(wamct_ctx* ctx, int32_t enable);
+wamct_status wamct_get_timing(wamct_ctx* ctx, double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

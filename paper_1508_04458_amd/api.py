@@ -1,0 +1,189 @@
+"""Python face of the C ABI: a reconstruction context holding one scan on one GPU.
+
+Every method marshals torch tensors (device memory and the current stream) into the
+matching `wamct_*` call; all arithmetic runs in the HIP kernels of libwamct.so."""
+import ctypes
+from typing import Dict, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+_DT = {"f32": (_lib.F32, torch.float32), "f64": (_lib.F64, torch.float64)}
+
+
+def _geometry(g) -> _lib.Geometry:
+    return _lib.Geometry(int(g.kind), int(g.n), float(g.pixel), int(g.n_views), float(g.angle0),
+                         float(g.angle_span), int(g.n_bins), float(g.bin_pitch), float(g.sod), float(g.sdd))
+
+
+def _options(levels, dtype, geometry):
+    return _lib.Options(int(levels), _DT[dtype][0] if dtype in _DT else 99,
+                        _DT[geometry][0] if geometry in _DT else 99)
+
+
+def validate(g, levels: int, dtype: str = "f32", geometry: str = "f64") -> Optional[str]:
+    """Host-only check of geometry and options; returns None when valid, else the message."""
+    buf = ctypes.create_string_buffer(512)
+    opt = _options(levels, dtype, geometry)
+    st = lib.wamct_validate(ctypes.byref(_geometry(g)), ctypes.byref(opt), buf, 512)
+    return None if st == _lib.OK else buf.value.decode()
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One scan (geometry, counts, I0) and the state of Algorithm 1 (beta, tree)."""
+
+    def __init__(self, geom, levels: int, dtype: str = "f32", device="cuda", geometry: str = "f64"):
+        if dtype not in _DT:
+            raise ValueError("dtype must be 'f32' or 'f64'")
+        self.geom = geom
+        self.levels = int(levels)
+        self.dtype_name = dtype
+        self.dtype = _DT[dtype][1]
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the reconstruction runs on a HIP device only")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.n = int(geom.n)
+        self.n_rays = int(geom.n_views) * int(geom.n_bins)
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            opt = _options(self.levels, dtype, geometry)
+            check(lib.wamct_create(ctypes.byref(_geometry(geom)), ctypes.byref(opt),
+                                   ctypes.c_void_p(stream), ctypes.byref(self._h)))
+
+    # ------------------------------------------------------------------ plumbing
+    def close(self):
+        if self._h:
+            lib.wamct_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, fn, *args):
+        check(fn(self._h, *args), self._h)
+
+    def _arr(self, t: torch.Tensor, numel: int, name: str, dtype=None) -> torch.Tensor:
+        dtype = dtype or self.dtype
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device != self.device or t.dtype != dtype or t.numel() != numel or not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous {dtype} tensor of {numel} elements on {self.device}")
+        return t
+
+    def _new(self, numel: int, dtype=None, shape=None):
+        t = torch.empty(numel, dtype=dtype or self.dtype, device=self.device)
+        return t if shape is None else t.view(*shape)
+
+    # ------------------------------------------------------------------ data and state
+    def set_data(self, d: torch.Tensor, i0) -> None:
+        self._arr(d, self.n_rays, "d")
+        if isinstance(i0, torch.Tensor):
+            self._arr(i0, self.n_rays, "i0")
+            self._call(lib.wamct_set_data, _ptr(d), _ptr(i0), 0.0)
+        else:
+            self._call(lib.wamct_set_data, _ptr(d), None, float(i0))
+
+    def reset(self) -> None:
+        self._call(lib.wamct_reset)
+
+    def set_state(self, beta: torch.Tensor, mask: torch.Tensor) -> None:
+        self._arr(beta, self.n * self.n, "beta")
+        self._arr(mask, self.n * self.n, "mask", torch.uint8)
+        self._call(lib.wamct_set_state, _ptr(beta), _ptr(mask))
+
+    def get_state(self):
+        beta = self._new(self.n * self.n, shape=(self.n, self.n))
+        mask = self._new(self.n * self.n, torch.uint8, (self.n, self.n))
+        it = ctypes.c_int32()
+        self._call(lib.wamct_get_state, _ptr(beta), _ptr(mask), ctypes.byref(it))
+        return beta, mask, it.value
+
+    # ------------------------------------------------------------------ Algorithm 1
+    def iterate(self, n_iters: int, idiv: Optional[torch.Tensor] = None) -> Optional[torch.Tensor]:
+        if idiv is not None:
+            self._arr(idiv, n_iters, "idiv", torch.float64)
+        self._call(lib.wamct_iterate, int(n_iters), _ptr(idiv))
+        return idiv
+
+    def expand(self, frac: float = 0.1) -> int:
+        ns = ctypes.c_int32()
+        self._call(lib.wamct_expand, float(frac), ctypes.byref(ns))
+        return ns.value
+
+    def solve(self, n_iters: int, schedule: Sequence[int] = (), frac: float = 0.1,
+              idiv: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if idiv is None:
+            idiv = self._new(n_iters + 1, torch.float64)
+        self._arr(idiv, n_iters + 1, "idiv", torch.float64)
+        sched = (ctypes.c_int32 * max(1, len(schedule)))(*[int(s) for s in schedule])
+        self._call(lib.wamct_solve, int(n_iters), sched, len(schedule), float(frac), _ptr(idiv))
+        return idiv
+
+    # ------------------------------------------------------------------ operators
+    def synthesize(self) -> torch.Tensor:
+        mu = self._new(self.n * self.n, shape=(self.n, self.n))
+        self._call(lib.wamct_synthesize, _ptr(mu))
+        return mu
+
+    def project(self, mu: torch.Tensor) -> torch.Tensor:
+        self._arr(mu, self.n * self.n, "mu")
+        p = self._new(self.n_rays)
+        self._call(lib.wamct_project, _ptr(mu), _ptr(p))
+        return p
+
+    def backproject(self, y: torch.Tensor) -> torch.Tensor:
+        self._arr(y, self.n_rays, "y")
+        img = self._new(self.n * self.n, shape=(self.n, self.n))
+        self._call(lib.wamct_backproject, _ptr(y), _ptr(img))
+        return img
+
+    def backproject_split(self, y: torch.Tensor):
+        self._arr(y, self.n_rays, "y")
+        bp = self._new(self.n * self.n, shape=(self.n, self.n))
+        bm = self._new(self.n * self.n, shape=(self.n, self.n))
+        self._call(lib.wamct_backproject_split, _ptr(y), _ptr(bp), _ptr(bm))
+        return bp, bm
+
+    def forward(self):
+        q = self._new(self.n_rays)
+        idiv = self._new(1, torch.float64)
+        self._call(lib.wamct_forward, _ptr(q), _ptr(idiv))
+        return q, idiv
+
+    def idiv(self, q: torch.Tensor) -> torch.Tensor:
+        self._arr(q, self.n_rays, "q")
+        out = self._new(1, torch.float64)
+        self._call(lib.wamct_idiv, _ptr(q), _ptr(out))
+        return out
+
+    def b(self) -> torch.Tensor:
+        out = self._new(self.n * self.n, shape=(self.n, self.n))
+        self._call(lib.wamct_get_b, _ptr(out))
+        return out
+
+    def tree_stats(self) -> Dict[str, float]:
+        z0, w, na, nh = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._call(lib.wamct_tree_stats, ctypes.byref(z0), ctypes.byref(w), ctypes.byref(na), ctypes.byref(nh))
+        return dict(z0=z0.value, w=w.value, n_active=na.value, n_held=nh.value)
+
+    # ------------------------------------------------------------------ timing
+    def timing(self, enable: bool) -> None:
+        self._call(lib.wamct_timing, 1 if enable else 0)
+
+    def get_timing(self) -> Dict[str, Dict[str, float]]:
+        ms = (ctypes.c_double * _lib.NK)()
+        cnt = (ctypes.c_int64 * _lib.NK)()
+        self._call(lib.wamct_get_timing, ms, cnt)
+        return {k: dict(ms=ms[i], launches=cnt[i]) for i, k in enumerate(_lib.KERNEL_CLASSES)}

@@ -1,0 +1,100 @@
+// Internal interface between the C ABI (wamct_api.hip) and the kernels (wamct_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wamct {
+
+constexpr int kMaxLevels = 8;
+
+// Scan geometry as the kernels see it (see include/wamct.h for the conventions).
+struct DevGeom {
+  int kind;    // 0 parallel, 1 fan (flat detector)
+  int n;       // image n x n
+  int nv, nb;  // views, bins
+  int L;       // Haar levels
+  double pixel, pitch, sod, sdd;
+};
+
+// Work item of the node-driven backprojection: one tree node or one box.
+//   bit 31     : 1 = node with quadrant chords (three details, plus the approximation
+//                when the node is a root), 0 = single box (root approximation or pixel)
+//   bits 27-30 : level l
+//   bits 13-25 : node row i
+//   bits  0-12 : node column j
+__host__ __device__ inline uint32_t item_pack(int quad, int l, int i, int j) {
+  return (uint32_t(quad) << 31) | (uint32_t(l) << 27) | (uint32_t(i) << 13) | uint32_t(j);
+}
+
+enum GatherMode { kPlain = 0, kSplit = 1, kUpdate = 2 };
+
+// A run of work items of one level, processed with its views split into `chunks` ranges
+// of `vpc` views (chunks = 1: one lane per item over all views).
+struct Segment {
+  int start, count, level, chunks, vpc;
+};
+// Lanes one level segment should occupy (about 16 wave64 per CU on 256 CUs).
+constexpr int kTargetLanes = 1 << 18;
+
+// Launchers. T is float or double. Every pointer is device memory unless noted.
+template <typename T>
+struct Launch {
+  // mu = Omega beta (inactive coefficients are zero by invariant)
+  static void synth(const DevGeom& g, const T* beta, T* mu, hipStream_t s);
+  // per-pixel leaf level from the tree mask
+  static void levmap(const DevGeom& g, const uint8_t* mask, uint8_t* lev, hipStream_t s);
+  // I-divergence terms of a given q -> per-block partials. Returns the number of blocks.
+  static int idiv_terms(const DevGeom& g, const T* q, const T* d, double* part, hipStream_t s);
+  // b = Omega^T g for every coefficient (FP64 accumulation)
+  static void analysis(const DevGeom& g, const T* img, T* coef, hipStream_t s);
+  // FP64 synthesis of the current beta and per-block maxima. Returns the number of blocks.
+  static int mu64(const DevGeom& g, const T* beta, double* mu64, double* part, hipStream_t s);
+  // zero beta outside the mask
+  static void apply_mask(const DevGeom& g, T* beta, const uint8_t* mask, hipStream_t s);
+  // count non-finite or negative entries of x into *bad (int, accumulated)
+  static void check(const T* x, int64_t len, bool allow_negative, int* bad, hipStream_t s);
+  static void fill(T* x, int64_t len, T v, hipStream_t s);
+};
+
+// Kernels whose ray arithmetic runs in R (float or double, R at least as wide as T).
+template <typename T, typename R>
+struct Geo {
+  // per-ray table in R: A = (ox, oy, 1/ex, 1/ey), B = (ex, ey, 0, 0); origin = the point of
+  // the ray closest to the image centre; views = per-view (cos a, sin a) in double.
+  static void ray_table(const DevGeom& g, const double2* views, void* A, void* B, hipStream_t s);
+  // per-view (cos a, sin a) in float, used only for the detector footprint of a box
+  static void view_table(const DevGeom& g, const double2* views, void* vF, hipStream_t s);
+  // ray-driven projection; tree = traverse leaves with `lev`, else pixels. If q != null:
+  // q = I0 exp(-p) and per-block FP64 partial sums of the I-divergence terms in `part`.
+  // If p != null the line integrals are stored. Returns the number of blocks.
+  static int forward(const DevGeom& g, bool tree, const void* A, const void* B, const T* mu,
+                     const uint8_t* lev, const T* d, const T* i0v, double i0s, T* q, T* p,
+                     double* part, hipStream_t s);
+  // node-driven backprojection of y over the segments of `items` (items null: every pixel
+  // as a level-0 box); `part` holds 7 * chunks * count values of R for chunked segments
+  static void gather(const DevGeom& g, int mode, const void* vF, const void* A, const T* y,
+                     const uint32_t* items, const Segment* segs, int n_segs, void* part, T* beta,
+                     const T* b, const double* z0, int* held, T* bp, T* bm, T* out, hipStream_t s);
+};
+
+// Z0 and W of the current tree: per-ray FP64 sums of |phi| over active coefficients and
+// counts of phi != 0; per-block partial max / sum. Returns the number of blocks.
+int z0_partials(const DevGeom& g, const double2* views, const uint8_t* lev, double* part_max,
+                double* part_cnt, hipStream_t s);
+// Deterministic single-block reductions of per-block partials: out[0] = sum or max.
+void reduce_sum(const double* part, int n, double* out, hipStream_t s);
+void reduce_max(const double* part, int n, double* out, hipStream_t s);
+// Work list of the node-driven backprojection (roots, then split nodes level by level,
+// Morton order within a level), compacted with wave ballots; counts[0] = number of items,
+// counts[1 + k] = items of level L - k (k = 0..L; level 0 only when L = 0).
+void build_items(const DevGeom& g, const uint8_t* mask, uint32_t* items, int* counts, hipStream_t s);
+// Tree rule: split every leaf (level >= 1) of mask_old whose FP64 value exceeds frac * max.
+void expand(const DevGeom& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64,
+            const double* maxv, double frac, int* n_split, hipStream_t s);
+// Validity of a tree mask: *bad = number of violated constraints.
+void check_mask(const DevGeom& g, const uint8_t* mask, int* bad, hipStream_t s);
+void fill_u8(uint8_t* x, int64_t len, uint8_t v, hipStream_t s);
+void fill_i32(int* x, int64_t len, int v, hipStream_t s);
+void approx_mask(const DevGeom& g, uint8_t* mask, hipStream_t s);
+
+}  // namespace wamct

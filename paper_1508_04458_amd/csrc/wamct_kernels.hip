@@ -1,0 +1,858 @@
+// HIP kernels of wavelet-tree alternating minimization for gfx950 (wave64).
+//
+// Method: Degirmenci, O'Sullivan, Politte, arXiv 1508.04458, Introduction (eqs. 1.2-1.10,
+// Algorithm 1) and Results (tree rule). The system matrix is never stored: chord lengths
+// h(y|x) (ray-pixel intersection lengths, Introduction) are recomputed on the fly, so the
+// kernels are bound by vector ALU and cache gathers, not by streaming a matrix.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "wamct_internal.h"
+#include "wamct_geom.h"
+
+namespace wamct {
+namespace {
+
+template <typename T> struct V4;
+template <> struct V4<float> { using t = float4; };
+template <> struct V4<double> { using t = double4; };
+template <typename T> struct V2;
+template <> struct V2<float> { using t = float2; };
+template <> struct V2<double> { using t = double2; };
+
+constexpr int kBlock = 256;
+
+inline int blocks_for(int64_t n, int b = kBlock) { return int((n + b - 1) / b); }
+
+// ------------------------------------------------------------------ reductions (wave64)
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// block of kBlock threads -> value in thread 0
+template <bool MAX>
+__device__ inline double block_reduce(double v) {
+  __shared__ double sh[kBlock / 64];
+  v = MAX ? wave_max(v) : wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int k = 1; k < kBlock / 64; ++k) r = MAX ? fmax(r, sh[k]) : r + sh[k];
+    v = r;
+  }
+  return v;
+}
+
+template <bool MAX>
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ part, int n,
+                                                   double* __restrict__ out) {
+  // fixed assignment and order -> deterministic result
+  double v = MAX ? -INFINITY : 0.0;
+  for (int k = threadIdx.x; k < n; k += kBlock) v = MAX ? fmax(v, part[k]) : v + part[k];
+  v = block_reduce<MAX>(v);
+  if (threadIdx.x == 0) out[0] = v;
+}
+
+// ------------------------------------------------------------------ geometry
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ray_table(DevGeom g, const double2* __restrict__ views,
+                                                      typename V4<T>::t* __restrict__ A,
+                                                      typename V4<T>::t* __restrict__ B) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= g.nv * g.nb) return;
+  const int v = r / g.nb, b = r - v * g.nb;
+  double ox, oy, ex, ey;
+  ray_of(g, views[v], b, ox, oy, ex, ey);
+  typename V4<T>::t a, bb;
+  a.x = T(ox); a.y = T(oy); a.z = T(1.0 / ex); a.w = T(1.0 / ey);
+  bb.x = T(ex); bb.y = T(ey); bb.z = T(0); bb.w = T(0);
+  A[r] = a;
+  B[r] = bb;
+}
+
+template <typename T>
+__global__ void k_view_table(int nv, const double2* __restrict__ views, typename V2<T>::t* __restrict__ out) {
+  const int v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= nv) return;
+  typename V2<T>::t o;
+  o.x = T(views[v].x); o.y = T(views[v].y);
+  out[v] = o;
+}
+
+// ------------------------------------------------------------------ tree helpers
+
+// node (l, i, j) split <=> its D1 detail is active (mask[i][m + j], m = n >> l)
+__device__ inline bool is_split(const uint8_t* __restrict__ mask, int n, int l, int i, int j) {
+  const int m = n >> l;
+  return mask[i * n + (m + j)] != 0;
+}
+
+__device__ inline uint32_t morton_compact(uint32_t x) {
+  x &= 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0f0f0f0fu;
+  x = (x | (x >> 4)) & 0x00ff00ffu;
+  x = (x | (x >> 8)) & 0x0000ffffu;
+  return x;
+}
+
+// ------------------------------------------------------------------ synthesis (eq. 1.2)
+
+// mu(r, c) = 2^-L beta_LL(root) + sum_l 2^-l (s1 D1 + s2 D2 + s3 D3) of the node at level l
+// containing the pixel; inactive coefficients are zero, so this is Omega beta on Z_s.
+template <typename T, typename R>
+__device__ inline R synth_pixel(const T* __restrict__ beta, int n, int L, int r, int c) {
+  R v = R(beta[(r >> L) * n + (c >> L)]) * R(1.0 / double(1 << L));
+  for (int l = L; l >= 1; --l) {
+    const int m = n >> l, i = r >> l, j = c >> l;
+    const R d1 = R(beta[i * n + m + j]);
+    const R d2 = R(beta[(m + i) * n + j]);
+    const R d3 = R(beta[(m + i) * n + m + j]);
+    const bool right = (c >> (l - 1)) & 1, bottom = (r >> (l - 1)) & 1;
+    const R s1d1 = right ? -d1 : d1;
+    const R s2d2 = bottom ? -d2 : d2;
+    const R s3d3 = (right != bottom) ? -d3 : d3;
+    v += (s1d1 + s2d2 + s3d3) * R(1.0 / double(1 << l));
+  }
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_synth(int n, int L, const T* __restrict__ beta, T* __restrict__ mu) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n * n) return;
+  mu[p] = synth_pixel<T, T>(beta, n, L, p / n, p % n);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mu64(int n, int L, const T* __restrict__ beta,
+                                                 double* __restrict__ mu64, double* __restrict__ part) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  double v = -INFINITY;
+  if (p < n * n) {
+    v = synth_pixel<T, double>(beta, n, L, p / n, p % n);
+    mu64[p] = v;
+  }
+  v = block_reduce<true>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_levmap(int n, int L, const uint8_t* __restrict__ mask,
+                                                   uint8_t* __restrict__ lev) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n * n) return;
+  const int r = p / n, c = p % n;
+  int l = L;
+  while (l >= 1 && is_split(mask, n, l, r >> l, c >> l)) --l;
+  lev[p] = uint8_t(l);
+}
+
+// ------------------------------------------------------------------ leaf traversal
+
+// Storage type T (mu, q, beta), geometry and accumulation type R (chords are differences
+// of ray parameters whose magnitude reaches the image half-diagonal, so FP64 R keeps
+// chords exact to ~1e-13 mm; FP64 FMA runs at the non-packed FP32 rate on CDNA4).
+template <typename T, typename R>
+struct SumVisitor {
+  const T* __restrict__ mu;
+  int n;
+  R acc;
+  __device__ inline void operator()(int ix, int iy, int, R chord) { acc += chord * R(mu[iy * n + ix]); }
+};
+
+// ------------------------------------------------------------------ forward + Beer's law
+
+// One lane per ray: p = sum over leaves of chord * mu_leaf (= sum_z phi(y|z) beta(z) on
+// Z_s), q-hat = I0 exp(-p) (Introduction; Algorithm 1 first step), and the FP64 term
+// d log(d / q) - d + q of the I-divergence (0 log 0 = 0) with log q = log I0 - p.
+template <typename T, typename R, bool TREE>
+__global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4<R>::t* __restrict__ A,
+                                                    const typename V4<R>::t* __restrict__ B,
+                                                    const T* __restrict__ mu, const uint8_t* __restrict__ lev,
+                                                    const T* __restrict__ d, const T* __restrict__ i0v,
+                                                    double i0s, T* __restrict__ q, T* __restrict__ pout,
+                                                    double* __restrict__ part) {
+  const int M = g.nv * g.nb;
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  double term = 0.0;
+  if (r < M) {
+    const typename V4<R>::t a = A[r];
+    const typename V4<R>::t b = B[r];
+    SumVisitor<T, R> vis{mu, g.n, R(0)};
+    walk<R, TREE>(g, a.x, a.y, b.x, b.y, a.z, a.w, lev, vis);
+    const R p = vis.acc;
+    if (pout) pout[r] = T(p);
+    if (q) {
+      const double i0 = i0v ? double(i0v[r]) : i0s;
+      const double pd = double(p);
+      const double qd = i0 * exp(-pd);
+      q[r] = T(qd);
+      const double dv = double(d[r]);
+      term = qd - dv;
+      if (dv > 0.0) term += dv * (log(dv) - (log(i0) - pd));
+    }
+  }
+  if (part) {
+    term = block_reduce<false>(term);
+    if (threadIdx.x == 0) part[blockIdx.x] = term;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_idiv_terms(int M, const T* __restrict__ q, const T* __restrict__ d,
+                                                       double* __restrict__ part) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  double term = 0.0;
+  if (r < M) {
+    const double qd = double(q[r]), dv = double(d[r]);
+    term = qd - dv;
+    if (dv > 0.0) term += dv * log(dv / qd);
+  }
+  term = block_reduce<false>(term);
+  if (threadIdx.x == 0) part[blockIdx.x] = term;
+}
+
+// ------------------------------------------------------------------ node-driven gather
+
+// Positive root t of bp t^2 - b t + bm = 0 (eq. 1.9 with t = exp(-Z0 (beta - beta_hat)))
+// -> delta = -ln(t) / Z0. Cases (bp >= 0 >= bm): bp > 0 uses the cancellation-free form
+// of the quadratic root; bp = 0 > bm is linear (t = bm / b); bp = bm = 0 means no ray sees
+// the coefficient (delta = 0). No finite minimizer (t <= 0): hold and count.
+template <typename R>
+__device__ inline R am_delta(R b, R bp, R bm, R z0, int* held) {
+  R t;
+  if (bp > R(0)) {
+    const R s = sqrt(fmax(b * b - R(4) * bp * bm, R(0)));
+    t = b >= R(0) ? (b + s) / (R(2) * bp) : (R(2) * bm) / (b - s);
+  } else if (bm < R(0)) {
+    t = bm / b;
+  } else {
+    return R(0);
+  }
+  if (t > R(0) && isfinite(t)) return -log(t) / z0;
+  atomicAdd(held, 1);
+  return R(0);
+}
+
+// Sums of one work item over a range of views. For every view the item's box is projected
+// onto the detector (its four corners bound the bins whose rays can hit it; FP32 suffices
+// for this bound, which is widened by 1e-3 bin), and for each such ray the chord through
+// the box, or through its four quadrants, is computed in R by slab clipping with the same
+// ray table as the forward pass. Details of node (l, i, j) have phi = 2^-l sum_q s_k(q)
+// chord(q); an approximation has 2^-L chord(box). The sign split of eq. 1.10 is taken per
+// (ray, coefficient), so b-hat+ and b-hat- need no atomics.
+template <typename R>
+struct ItemSums {
+  R acc, pos0, pos1, pos2, neg0, neg1, neg2;
+};
+
+template <typename T, typename R>
+__device__ inline ItemSums<R> item_sums(const DevGeom& g, const float2* __restrict__ vf,
+                                        const typename V4<R>::t* __restrict__ A, const T* __restrict__ y,
+                                        bool quad, int l, int i, int j, int v0, int v1) {
+  const int n = g.n, s = 1 << l, nb = g.nb;
+  const R pix = R(g.pixel), hn = R(0.5 * n);
+  const R X0 = (R(j * s) - hn) * pix, X2 = (R((j + 1) * s) - hn) * pix;
+  const R Y0 = (R(i * s) - hn) * pix, Y2 = (R((i + 1) * s) - hn) * pix;
+  const R X1 = R(0.5) * (X0 + X2), Y1 = R(0.5) * (Y0 + Y2);
+  const float fx0 = float(X0), fx2 = float(X2), fy0 = float(Y0), fy2 = float(Y2);
+  const float ipitch = float(1.0 / g.pitch), ctr = float(0.5 * (nb - 1));
+  const float sod = float(g.sod), sdd = float(g.sdd);
+  ItemSums<R> r{R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
+  for (int v = v0; v < v1; ++v) {
+    const float2 cs = vf[v];
+    const float c = cs.x, sn = cs.y;
+    float u00, u01, u10, u11;
+    if (g.kind == 0) {
+      u00 = fx0 * c + fy0 * sn; u01 = fx2 * c + fy0 * sn; u10 = fx0 * c + fy2 * sn; u11 = fx2 * c + fy2 * sn;
+    } else {
+      u00 = sdd * (-fx0 * sn + fy0 * c) / (sod - (fx0 * c + fy0 * sn));
+      u01 = sdd * (-fx2 * sn + fy0 * c) / (sod - (fx2 * c + fy0 * sn));
+      u10 = sdd * (-fx0 * sn + fy2 * c) / (sod - (fx0 * c + fy2 * sn));
+      u11 = sdd * (-fx2 * sn + fy2 * c) / (sod - (fx2 * c + fy2 * sn));
+    }
+    const float umin = fminf(fminf(u00, u01), fminf(u10, u11));
+    const float umax = fmaxf(fmaxf(u00, u01), fmaxf(u10, u11));
+    // bins whose centre lies in [umin, umax] widened by 1e-3 bin; clamped in floating
+    // point first so the integer conversion can never overflow
+    const float flo = fminf(fmaxf(umin * ipitch + ctr - 1e-3f, -1.f), float(nb));
+    const float fhi = fminf(fmaxf(umax * ipitch + ctr + 1e-3f, -1.f), float(nb));
+    const int blo = max(int(ceilf(flo)), 0);
+    const int bhi = min(int(floorf(fhi)), nb - 1);
+    const int base = v * nb;
+    for (int bb = blo; bb <= bhi; ++bb) {
+      const typename V4<R>::t a = A[base + bb];
+      const R yv = R(y[base + bb]);
+      const R tx0 = (X0 - a.x) * a.z, tx2 = (X2 - a.x) * a.z;
+      const R ty0 = (Y0 - a.y) * a.w, ty2 = (Y2 - a.y) * a.w;
+      if (!quad) {
+        const R lo = fmax(fmin(tx0, tx2), fmin(ty0, ty2));
+        const R hi = fmin(fmax(tx0, tx2), fmax(ty0, ty2));
+        r.acc += yv * fmax(hi - lo, R(0));
+      } else {
+        const R tx1 = (X1 - a.x) * a.z, ty1 = (Y1 - a.y) * a.w;
+        const R xl0 = fmin(tx0, tx1), xh0 = fmax(tx0, tx1), xl1 = fmin(tx1, tx2), xh1 = fmax(tx1, tx2);
+        const R yl0 = fmin(ty0, ty1), yh0 = fmax(ty0, ty1), yl1 = fmin(ty1, ty2), yh1 = fmax(ty1, ty2);
+        const R cTL = fmax(fmin(xh0, yh0) - fmax(xl0, yl0), R(0));
+        const R cTR = fmax(fmin(xh1, yh0) - fmax(xl1, yl0), R(0));
+        const R cBL = fmax(fmin(xh0, yh1) - fmax(xl0, yl1), R(0));
+        const R cBR = fmax(fmin(xh1, yh1) - fmax(xl1, yl1), R(0));
+        const R u1 = cTL - cTR, u2 = cBL - cBR, w1v = cTL + cTR, w2v = cBL + cBR;
+        const R w1 = yv * (u1 + u2), w2 = yv * (w1v - w2v), w3 = yv * (u1 - u2);
+        r.acc += yv * (w1v + w2v);
+        r.pos0 += fmax(w1, R(0)); r.neg0 += fmin(w1, R(0));
+        r.pos1 += fmax(w2, R(0)); r.neg1 += fmin(w2, R(0));
+        r.pos2 += fmax(w3, R(0)); r.neg2 += fmin(w3, R(0));
+      }
+    }
+  }
+  return r;
+}
+
+__device__ inline uint32_t item_word(const uint32_t* __restrict__ items, int it, int n) {
+  return items ? items[it] : item_pack(0, 0, it / n, it % n);
+}
+
+// Final write of one item's sums (scaled by 2^-l): H^T y (plain), b-hat+/- (split), or the
+// closed-form zero of eq. 1.9 applied to beta (update).
+template <typename T, typename R, int MODE>
+__device__ inline void item_finish(const DevGeom& g, uint32_t w, const ItemSums<R>& r, T* __restrict__ beta,
+                                   const T* __restrict__ bvec, const double* __restrict__ z0p, int* held,
+                                   T* __restrict__ bp_out, T* __restrict__ bm_out, T* __restrict__ out) {
+  const int n = g.n;
+  const bool quad = (w >> 31) != 0;
+  const int l = int((w >> 27) & 15u);
+  const int i = int((w >> 13) & 0x1fffu);
+  const int j = int(w & 0x1fffu);
+  const R sc = R(1.0 / double(1 << l));
+  const int m = n >> l;
+  if (MODE == kPlain) {
+    out[i * n + j] = T(r.acc * sc);
+    return;
+  }
+  const bool root = (l == g.L);
+  if (MODE == kSplit) {
+    if (root) {
+      bp_out[i * n + j] = T(r.acc * sc);
+      bm_out[i * n + j] = T(0);
+    }
+    if (quad) {
+      bp_out[i * n + m + j] = T(r.pos0 * sc);
+      bm_out[i * n + m + j] = T(r.neg0 * sc);
+      bp_out[(m + i) * n + j] = T(r.pos1 * sc);
+      bm_out[(m + i) * n + j] = T(r.neg1 * sc);
+      bp_out[(m + i) * n + m + j] = T(r.pos2 * sc);
+      bm_out[(m + i) * n + m + j] = T(r.neg2 * sc);
+    }
+    return;
+  }
+  const R z0 = R(*z0p);
+  if (root) {
+    const int z = i * n + j;
+    beta[z] = T(R(beta[z]) + am_delta<R>(R(bvec[z]), r.acc * sc, R(0), z0, held));
+  }
+  if (quad) {
+    const int z1 = i * n + m + j, z2 = (m + i) * n + j, z3 = (m + i) * n + m + j;
+    beta[z1] = T(R(beta[z1]) + am_delta<R>(R(bvec[z1]), r.pos0 * sc, r.neg0 * sc, z0, held));
+    beta[z2] = T(R(beta[z2]) + am_delta<R>(R(bvec[z2]), r.pos1 * sc, r.neg1 * sc, z0, held));
+    beta[z3] = T(R(beta[z3]) + am_delta<R>(R(bvec[z3]), r.pos2 * sc, r.neg2 * sc, z0, held));
+  }
+}
+
+// One lane per item of a level segment, all views (used when the segment alone fills the GPU).
+template <typename T, typename R, int MODE>
+__global__ __launch_bounds__(kBlock) void k_gather(DevGeom g, const float2* __restrict__ vf,
+                                                   const typename V4<R>::t* __restrict__ A,
+                                                   const T* __restrict__ y, const uint32_t* __restrict__ items,
+                                                   int start, int count, T* __restrict__ beta,
+                                                   const T* __restrict__ bvec, const double* __restrict__ z0p,
+                                                   int* __restrict__ held, T* __restrict__ bp_out,
+                                                   T* __restrict__ bm_out, T* __restrict__ out) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= count) return;
+  const uint32_t w = item_word(items, start + k, g.n);
+  const ItemSums<R> r = item_sums<T, R>(g, vf, A, y, (w >> 31) != 0, int((w >> 27) & 15u),
+                                        int((w >> 13) & 0x1fffu), int(w & 0x1fffu), 0, g.nv);
+  item_finish<T, R, MODE>(g, w, r, beta, bvec, z0p, held, bp_out, bm_out, out);
+}
+
+// One lane per (item, view chunk) of a level segment whose item count alone would leave
+// the GPU idle: consecutive lanes take consecutive (spatially adjacent) items of the same
+// chunk; the seven partial sums go to part[chunk][slot][count] (coalesced).
+template <typename T, typename R>
+__global__ __launch_bounds__(kBlock) void k_gather_part(DevGeom g, const float2* __restrict__ vf,
+                                                        const typename V4<R>::t* __restrict__ A,
+                                                        const T* __restrict__ y, const uint32_t* __restrict__ items,
+                                                        int start, int count, int chunks, int vpc,
+                                                        R* __restrict__ part) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= count * chunks) return;
+  const int chunk = k / count, idx = k - chunk * count;
+  const uint32_t w = item_word(items, start + idx, g.n);
+  const bool quad = (w >> 31) != 0;
+  const int v0 = chunk * vpc, v1 = min(g.nv, v0 + vpc);
+  const ItemSums<R> r = item_sums<T, R>(g, vf, A, y, quad, int((w >> 27) & 15u), int((w >> 13) & 0x1fffu),
+                                        int(w & 0x1fffu), v0, v1);
+  R* p = part + size_t(chunk) * 7 * count + idx;
+  p[0] = r.acc;
+  if (quad) {
+    p[1 * count] = r.pos0; p[2 * count] = r.pos1; p[3 * count] = r.pos2;
+    p[4 * count] = r.neg0; p[5 * count] = r.neg1; p[6 * count] = r.neg2;
+  }
+}
+
+// Sum the chunks of each item in chunk order (deterministic) and finish the item.
+template <typename T, typename R, int MODE>
+__global__ __launch_bounds__(kBlock) void k_gather_finish(DevGeom g, const uint32_t* __restrict__ items, int start,
+                                                          int count, int chunks, const R* __restrict__ part,
+                                                          T* __restrict__ beta, const T* __restrict__ bvec,
+                                                          const double* __restrict__ z0p, int* __restrict__ held,
+                                                          T* __restrict__ bp_out, T* __restrict__ bm_out,
+                                                          T* __restrict__ out) {
+  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= count) return;
+  const uint32_t w = item_word(items, start + idx, g.n);
+  const bool quad = (w >> 31) != 0;
+  ItemSums<R> r{R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
+  for (int c = 0; c < chunks; ++c) {
+    const R* p = part + size_t(c) * 7 * count + idx;
+    r.acc += p[0];
+    if (quad) {
+      r.pos0 += p[1 * count]; r.pos1 += p[2 * count]; r.pos2 += p[3 * count];
+      r.neg0 += p[4 * count]; r.neg1 += p[5 * count]; r.neg2 += p[6 * count];
+    }
+  }
+  item_finish<T, R, MODE>(g, w, r, beta, bvec, z0p, held, bp_out, bm_out, out);
+}
+
+// ------------------------------------------------------------------ Haar analysis
+
+// coef(z) = sum over the support of basis function z of its value times img (Omega^T img),
+// FP64 accumulation; Mallat position -> (level, band, node).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_analysis(int n, int L, const T* __restrict__ img, T* __restrict__ coef) {
+  const int z = blockIdx.x * kBlock + threadIdx.x;
+  if (z >= n * n) return;
+  const int r = z / n, c = z % n;
+  const int k = max(r, c);
+  int l = 0;
+  for (int t = 1; t <= L; ++t) {
+    if (k >= (n >> t)) { l = t; break; }
+  }
+  double acc = 0.0;
+  if (l == 0) {  // approximation of root (r, c)
+    const int s = 1 << L;
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b < s; ++b) acc += double(img[(r * s + a) * n + c * s + b]);
+    acc *= 1.0 / double(s);
+  } else {
+    const int m = n >> l, s = 1 << l, h = s >> 1;
+    const int band = (r < m) ? 1 : (c < m ? 2 : 3);
+    const int i = r % m, j = c % m;
+    for (int a = 0; a < s; ++a) {
+      for (int b = 0; b < s; ++b) {
+        const bool right = b >= h, bottom = a >= h;
+        const bool neg = band == 1 ? right : (band == 2 ? bottom : (right != bottom));
+        const double v = double(img[(i * s + a) * n + j * s + b]);
+        acc += neg ? -v : v;
+      }
+    }
+    acc *= 1.0 / double(s);
+  }
+  coef[z] = T(acc);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_apply_mask(int64_t len, T* __restrict__ beta,
+                                                       const uint8_t* __restrict__ mask) {
+  const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (p < len && mask[p] == 0) beta[p] = T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_check(const T* __restrict__ x, int64_t len, bool allow_neg,
+                                                  int* __restrict__ bad) {
+  const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (p >= len) return;
+  const T v = x[p];
+  if (!isfinite(v) || (!allow_neg && v < T(0))) atomicAdd(bad, 1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ x, int64_t len, T v) {
+  const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (p < len) x[p] = v;
+}
+
+// ------------------------------------------------------------------ Z0 and W (eq. 1.61)
+
+// Per ray in FP64: walk the leaves; every leaf chord adds s_k(quadrant) * chord to the
+// three detail accumulators of each split ancestor (levels above the leaf), and chord to
+// the approximation accumulator of its root. When the ray leaves a node, its |phi| =
+// 2^-m |acc_k| are added to the ray's sum and the non-zero ones counted. Z0 is the
+// maximum of the sums over rays; W the total count.
+template <int LT>
+struct Z0Visitor {
+  double tol;
+  double acc[LT + 1][3];
+  int cur[LT + 1];
+  double accLL;
+  int curLL;
+  double sum, cnt;
+  __device__ inline void flush_level(int m) {
+    const double sc = 1.0 / double(1 << m);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double a = fabs(acc[m][k]) * sc;
+      sum += a;
+      cnt += (a > tol) ? 1.0 : 0.0;
+      acc[m][k] = 0.0;
+    }
+  }
+  __device__ inline void flush_ll() {
+    const double a = fabs(accLL) / double(1 << LT);
+    sum += a;
+    cnt += (a > tol) ? 1.0 : 0.0;
+    accLL = 0.0;
+  }
+  __device__ inline void operator()(int ix, int iy, int l, double chord) {
+#pragma unroll
+    for (int m = 1; m <= LT; ++m) {
+      const int node = ((iy >> m) << 16) | (ix >> m);
+      if (node != cur[m]) {
+        if (cur[m] >= 0) flush_level(m);
+        cur[m] = node;
+      }
+      if (m > l) {
+        const bool right = (ix >> (m - 1)) & 1, bottom = (iy >> (m - 1)) & 1;
+        acc[m][0] += right ? -chord : chord;
+        acc[m][1] += bottom ? -chord : chord;
+        acc[m][2] += (right != bottom) ? -chord : chord;
+      }
+    }
+    const int root = ((iy >> LT) << 16) | (ix >> LT);
+    if (root != curLL) {
+      if (curLL >= 0) flush_ll();
+      curLL = root;
+    }
+    accLL += chord;
+  }
+};
+
+// The level count is a template parameter so the per-level accumulators stay in registers.
+template <int LT>
+__global__ __launch_bounds__(kBlock) void k_z0(DevGeom g, const double2* __restrict__ views,
+                                               const uint8_t* __restrict__ lev, double* __restrict__ part_max,
+                                               double* __restrict__ part_cnt) {
+  const int M = g.nv * g.nb;
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  double sum = 0.0, cnt = 0.0;
+  if (r < M) {
+    const int v = r / g.nb, b = r - v * g.nb;
+    double ox, oy, ex, ey;
+    ray_of(g, views[v], b, ox, oy, ex, ey);
+    Z0Visitor<LT> z;
+    z.tol = 1e-9 * g.pixel;
+#pragma unroll
+    for (int m = 0; m <= LT; ++m) {
+      z.cur[m] = -1;
+      z.acc[m][0] = z.acc[m][1] = z.acc[m][2] = 0.0;
+    }
+    z.accLL = 0.0; z.curLL = -1; z.sum = 0.0; z.cnt = 0.0;
+    walk<double, (LT > 0)>(g, ox, oy, ex, ey, 1.0 / ex, 1.0 / ey, lev, z);
+#pragma unroll
+    for (int m = 1; m <= LT; ++m)
+      if (z.cur[m] >= 0) z.flush_level(m);
+    if (z.curLL >= 0) z.flush_ll();
+    sum = z.sum; cnt = z.cnt;
+  }
+  const double mx = block_reduce<true>(sum);
+  __syncthreads();
+  const double ct = block_reduce<false>(cnt);
+  if (threadIdx.x == 0) { part_max[blockIdx.x] = mx; part_cnt[blockIdx.x] = ct; }
+}
+
+// ------------------------------------------------------------------ tree rule (Results)
+
+__global__ __launch_bounds__(kBlock) void k_expand(DevGeom g, const uint8_t* __restrict__ old,
+                                                   uint8_t* __restrict__ mask, const double* __restrict__ mu64,
+                                                   const double* __restrict__ maxv, double frac,
+                                                   int* __restrict__ n_split) {
+  // flattened node index over levels 1..L
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  const int n = g.n;
+  int l = 1;
+  for (; l <= g.L; ++l) {
+    const int m = n >> l;
+    if (k < m * m) break;
+    k -= m * m;
+  }
+  if (l > g.L) return;
+  const double top = *maxv;
+  if (!(top > 0.0)) return;
+  const int m = n >> l, i = k / m, j = k % m;
+  if (is_split(old, n, l, i, j)) return;
+  if (l < g.L && !is_split(old, n, l + 1, i >> 1, j >> 1)) return;
+  const int s = 1 << l;
+  const double val = mu64[(i * s) * n + j * s];   // leaf-constant: any pixel of the block
+  if (val > frac * top) {
+    mask[i * n + m + j] = 1;
+    mask[(m + i) * n + j] = 1;
+    mask[(m + i) * n + m + j] = 1;
+    atomicAdd(n_split, 1);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_mask(DevGeom g, const uint8_t* __restrict__ mask,
+                                                       int* __restrict__ bad) {
+  const int z = blockIdx.x * kBlock + threadIdx.x;
+  const int n = g.n;
+  if (z >= n * n) return;
+  const int r = z / n, c = z % n, L = g.L;
+  const int nL = n >> L;
+  if (L == 0 || (r < nL && c < nL)) {
+    if (mask[z] != 1) atomicAdd(bad, 1);
+    return;
+  }
+  if (mask[z] > 1) { atomicAdd(bad, 1); return; }
+  const int k = max(r, c);
+  int l = 1;
+  for (; l <= L; ++l)
+    if (k >= (n >> l)) break;
+  const int m = n >> l, i = r % m, j = c % m;
+  const uint8_t f = mask[i * n + m + j];
+  if (mask[z] != f) { atomicAdd(bad, 1); return; }
+  if (f && l < L && !is_split(mask, n, l + 1, i >> 1, j >> 1)) atomicAdd(bad, 1);
+}
+
+__global__ void k_approx_mask(int n, int L, uint8_t* __restrict__ mask) {
+  const int z = blockIdx.x * kBlock + threadIdx.x;
+  if (z >= n * n) return;
+  const int nL = n >> L;
+  mask[z] = (L == 0 || ((z / n) < nL && (z % n) < nL)) ? 1 : 0;
+}
+
+// Single work-group compaction of the work list. Levels from L down to 1 (L = 0: pixels);
+// within a level the nodes are visited in Morton order (spatially compact waves). Each
+// wave forms its inclusion mask with a ballot, each lane its offset with mbcnt, and the
+// wave totals are prefix-summed in LDS; order is deterministic.
+__global__ __launch_bounds__(1024) void k_items(DevGeom g, const uint8_t* __restrict__ mask,
+                                                uint32_t* __restrict__ items, int* __restrict__ counts) {
+  __shared__ int wave_tot[16];
+  __shared__ int base_sh;
+  const int n = g.n, L = g.L;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) base_sh = 0;
+  __syncthreads();
+  const int lmin = (L == 0) ? 0 : 1;
+  for (int l = L; l >= lmin; --l) {
+    const int level_start = base_sh;
+    const int m = n >> l;
+    int P = 1;
+    while (P < m) P <<= 1;
+    const int64_t total = int64_t(P) * P;
+    for (int64_t base = 0; base < total; base += 1024) {
+      const int64_t kk = base + threadIdx.x;
+      bool inc = false;
+      uint32_t word = 0;
+      if (kk < total) {
+        const int j = int(morton_compact(uint32_t(kk)));
+        const int i = int(morton_compact(uint32_t(kk >> 1)));
+        if (i < m && j < m) {
+          if (l == L) {
+            inc = true;
+            word = item_pack((L > 0 && is_split(mask, n, L, i, j)) ? 1 : 0, l, i, j);
+          } else if (is_split(mask, n, l, i, j)) {
+            inc = true;
+            word = item_pack(1, l, i, j);
+          }
+        }
+      }
+      const uint64_t bal = __ballot(inc);
+      const int before = __popcll(bal & ((uint64_t(1) << lane) - 1));
+      if (lane == 0) wave_tot[wv] = __popcll(bal);
+      __syncthreads();
+      int off = base_sh;
+      for (int w2 = 0; w2 < wv; ++w2) off += wave_tot[w2];
+      if (inc) items[off + before] = word;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w2 = 0; w2 < 16; ++w2) t += wave_tot[w2];
+        base_sh += t;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[1 + (L - l)] = base_sh - level_start;
+  }
+  if (threadIdx.x == 0) counts[0] = base_sh;
+}
+
+__global__ void k_fill_u8(uint8_t* x, int64_t len, uint8_t v) {
+  const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (p < len) x[p] = v;
+}
+__global__ void k_fill_i32(int* x, int64_t len, int v) {
+  const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (p < len) x[p] = v;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+template <typename T>
+void Launch<T>::synth(const DevGeom& g, const T* beta, T* mu, hipStream_t s) {
+  hipLaunchKernelGGL(k_synth<T>, dim3(blocks_for(int64_t(g.n) * g.n)), dim3(kBlock), 0, s, g.n, g.L, beta, mu);
+}
+template <typename T>
+void Launch<T>::levmap(const DevGeom& g, const uint8_t* mask, uint8_t* lev, hipStream_t s) {
+  hipLaunchKernelGGL(k_levmap, dim3(blocks_for(int64_t(g.n) * g.n)), dim3(kBlock), 0, s, g.n, g.L, mask, lev);
+}
+template <typename T>
+int Launch<T>::idiv_terms(const DevGeom& g, const T* q, const T* d, double* part, hipStream_t s) {
+  const int M = g.nv * g.nb, nb = blocks_for(M);
+  hipLaunchKernelGGL(k_idiv_terms<T>, dim3(nb), dim3(kBlock), 0, s, M, q, d, part);
+  return nb;
+}
+template <typename T>
+void Launch<T>::analysis(const DevGeom& g, const T* img, T* coef, hipStream_t s) {
+  hipLaunchKernelGGL(k_analysis<T>, dim3(blocks_for(int64_t(g.n) * g.n)), dim3(kBlock), 0, s, g.n, g.L, img, coef);
+}
+template <typename T>
+int Launch<T>::mu64(const DevGeom& g, const T* beta, double* mu64, double* part, hipStream_t s) {
+  const int nb = blocks_for(int64_t(g.n) * g.n);
+  hipLaunchKernelGGL(k_mu64<T>, dim3(nb), dim3(kBlock), 0, s, g.n, g.L, beta, mu64, part);
+  return nb;
+}
+template <typename T>
+void Launch<T>::apply_mask(const DevGeom& g, T* beta, const uint8_t* mask, hipStream_t s) {
+  const int64_t len = int64_t(g.n) * g.n;
+  hipLaunchKernelGGL(k_apply_mask<T>, dim3(blocks_for(len)), dim3(kBlock), 0, s, len, beta, mask);
+}
+template <typename T>
+void Launch<T>::check(const T* x, int64_t len, bool allow_negative, int* bad, hipStream_t s) {
+  if (len <= 0) return;
+  hipLaunchKernelGGL(k_check<T>, dim3(blocks_for(len)), dim3(kBlock), 0, s, x, len, allow_negative, bad);
+}
+template <typename T>
+void Launch<T>::fill(T* x, int64_t len, T v, hipStream_t s) {
+  if (len <= 0) return;
+  hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(len)), dim3(kBlock), 0, s, x, len, v);
+}
+
+template struct Launch<float>;
+template struct Launch<double>;
+
+template <typename T, typename R>
+void Geo<T, R>::ray_table(const DevGeom& g, const double2* views, void* A, void* B, hipStream_t s) {
+  const int M = g.nv * g.nb;
+  hipLaunchKernelGGL(k_ray_table<R>, dim3(blocks_for(M)), dim3(kBlock), 0, s, g, views,
+                     (typename V4<R>::t*)A, (typename V4<R>::t*)B);
+}
+template <typename T, typename R>
+void Geo<T, R>::view_table(const DevGeom& g, const double2* views, void* vF, hipStream_t s) {
+  hipLaunchKernelGGL(k_view_table<float>, dim3(blocks_for(g.nv)), dim3(kBlock), 0, s, g.nv, views, (float2*)vF);
+}
+template <typename T, typename R>
+int Geo<T, R>::forward(const DevGeom& g, bool tree, const void* A, const void* B, const T* mu,
+                       const uint8_t* lev, const T* d, const T* i0v, double i0s, T* q, T* p,
+                       double* part, hipStream_t s) {
+  const int nb = blocks_for(int64_t(g.nv) * g.nb);
+  auto a = (const typename V4<R>::t*)A;
+  auto b = (const typename V4<R>::t*)B;
+  if (tree)
+    hipLaunchKernelGGL((k_forward<T, R, true>), dim3(nb), dim3(kBlock), 0, s, g, a, b, mu, lev, d, i0v, i0s, q, p, part);
+  else
+    hipLaunchKernelGGL((k_forward<T, R, false>), dim3(nb), dim3(kBlock), 0, s, g, a, b, mu, lev, d, i0v, i0s, q, p, part);
+  return nb;
+}
+template <typename T, typename R>
+void Geo<T, R>::gather(const DevGeom& g, int mode, const void* vF, const void* A, const T* y,
+                       const uint32_t* items, const Segment* segs, int n_segs, void* part, T* beta,
+                       const T* b, const double* z0, int* held, T* bp, T* bm, T* out, hipStream_t s) {
+  auto vf = (const float2*)vF;
+  auto a = (const typename V4<R>::t*)A;
+  auto pt = (R*)part;
+  const dim3 blk(kBlock);
+  for (int k = 0; k < n_segs; ++k) {
+    const Segment& sg = segs[k];
+    if (sg.count <= 0) continue;
+    if (sg.chunks <= 1) {
+      const dim3 grid(blocks_for(sg.count));
+      if (mode == kPlain)
+        hipLaunchKernelGGL((k_gather<T, R, kPlain>), grid, blk, 0, s, g, vf, a, y, items, sg.start, sg.count, beta, b, z0, held, bp, bm, out);
+      else if (mode == kSplit)
+        hipLaunchKernelGGL((k_gather<T, R, kSplit>), grid, blk, 0, s, g, vf, a, y, items, sg.start, sg.count, beta, b, z0, held, bp, bm, out);
+      else
+        hipLaunchKernelGGL((k_gather<T, R, kUpdate>), grid, blk, 0, s, g, vf, a, y, items, sg.start, sg.count, beta, b, z0, held, bp, bm, out);
+      continue;
+    }
+    hipLaunchKernelGGL((k_gather_part<T, R>), dim3(blocks_for(int64_t(sg.count) * sg.chunks)), blk, 0, s, g, vf, a, y,
+                       items, sg.start, sg.count, sg.chunks, sg.vpc, pt);
+    const dim3 grid(blocks_for(sg.count));
+    if (mode == kPlain)
+      hipLaunchKernelGGL((k_gather_finish<T, R, kPlain>), grid, blk, 0, s, g, items, sg.start, sg.count, sg.chunks, pt, beta, b, z0, held, bp, bm, out);
+    else if (mode == kSplit)
+      hipLaunchKernelGGL((k_gather_finish<T, R, kSplit>), grid, blk, 0, s, g, items, sg.start, sg.count, sg.chunks, pt, beta, b, z0, held, bp, bm, out);
+    else
+      hipLaunchKernelGGL((k_gather_finish<T, R, kUpdate>), grid, blk, 0, s, g, items, sg.start, sg.count, sg.chunks, pt, beta, b, z0, held, bp, bm, out);
+  }
+}
+
+template struct Geo<float, float>;
+template struct Geo<float, double>;
+template struct Geo<double, double>;
+
+int z0_partials(const DevGeom& g, const double2* views, const uint8_t* lev, double* part_max,
+                double* part_cnt, hipStream_t s) {
+  const int nb = blocks_for(int64_t(g.nv) * g.nb);
+  switch (g.L) {
+#define Z0_CASE(K) \
+    case K: hipLaunchKernelGGL(k_z0<K>, dim3(nb), dim3(kBlock), 0, s, g, views, lev, part_max, part_cnt); break;
+    Z0_CASE(0) Z0_CASE(1) Z0_CASE(2) Z0_CASE(3) Z0_CASE(4) Z0_CASE(5) Z0_CASE(6) Z0_CASE(7) Z0_CASE(8)
+#undef Z0_CASE
+  }
+  return nb;
+}
+void reduce_sum(const double* part, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce<false>, dim3(1), dim3(kBlock), 0, s, part, n, out);
+}
+void reduce_max(const double* part, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce<true>, dim3(1), dim3(kBlock), 0, s, part, n, out);
+}
+void build_items(const DevGeom& g, const uint8_t* mask, uint32_t* items, int* counts, hipStream_t s) {
+  hipLaunchKernelGGL(k_items, dim3(1), dim3(1024), 0, s, g, mask, items, counts);
+}
+void expand(const DevGeom& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64,
+            const double* maxv, double frac, int* n_split, hipStream_t s) {
+  int64_t nodes = 0;
+  for (int l = 1; l <= g.L; ++l) nodes += int64_t(g.n >> l) * (g.n >> l);
+  if (nodes == 0) return;
+  hipLaunchKernelGGL(k_expand, dim3(blocks_for(nodes)), dim3(kBlock), 0, s, g, mask_old, mask, mu64, maxv,
+                     frac, n_split);
+}
+void check_mask(const DevGeom& g, const uint8_t* mask, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_mask, dim3(blocks_for(int64_t(g.n) * g.n)), dim3(kBlock), 0, s, g, mask, bad);
+}
+void fill_u8(uint8_t* x, int64_t len, uint8_t v, hipStream_t s) {
+  if (len > 0) hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(len)), dim3(kBlock), 0, s, x, len, v);
+}
+void fill_i32(int* x, int64_t len, int v, hipStream_t s) {
+  if (len > 0) hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(len)), dim3(kBlock), 0, s, x, len, v);
+}
+void approx_mask(const DevGeom& g, uint8_t* mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_approx_mask, dim3(blocks_for(int64_t(g.n) * g.n)), dim3(kBlock), 0, s, g.n, g.L, mask);
+}
+
+}  // namespace wamct
