@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full-am", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=36)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the run, copy a MIB-sized buffer 3 times (reference kernel for PMC byte counters)")
     return ap.parse_args()
 
 
@@ -50,17 +52,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_hash, config):
-    """HBM bytes per launch of the update kernel from committed rocprofv3 PMC summaries,
-    only if they were taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_update_{config}.json")
+def measured_traffic(kernel_hash, config, phase):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) of a phase's kernels
+    from the committed rocprofv3 PMC summary, only if taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{config}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("kernel_hash") != kernel_hash:
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_launch", {}).get(phase)
 
 
 def cpu_baseline(P, n_views_sample):
@@ -145,20 +147,30 @@ def main():
     ms_step = dt * 1e3 / args.steps
     it_s = J * args.steps / dt
 
-    # ---- roofline of the dominant kernel (update: sign-split backprojection + eq. 1.9)
+    # ---- roofline of the dominant kernel: the tree walk (forward projection over the leaves
+    # of Z_s, Beer's law, I-divergence term). Algorithmic bytes are those of the same pass
+    # with Phi stored (the paper lists Phi as an input of Algorithm 1): 8 B per (ray, active
+    # coefficient) pair (FP32 value + int32 index), 4 B per active coefficient (beta), 8 B
+    # per ray (d read, q-hat written). The kernel itself recomputes Phi on the fly.
+    M = g.n_rays
+    fw = tim["forward"]
+    fw_ms = fw["ms"] / max(1, fw["launches"])
+    alg_fw = 8.0 * w_update_avg + 4.0 * active_avg + 8.0 * M
+    khash = kernel_source_hash()
+    traffic = measured_traffic(khash, args.config, "forward")
+    roof = {"bound": "hbm", "achieved": round(alg_fw / (fw_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(alg_fw / (fw_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_forward_rec<float,double>", "avg_launch_ms": round(fw_ms, 5), "launches": fw["launches"],
+            "alg_bytes_per_launch": int(alg_fw), "kernel_hash": khash}
+    # the update pass (sign-split backprojection + eq. 1.9 zero; one or two kernels per level)
     up = tim["update"]
     upd_ms = up["ms"] / max(1, up["launches"])
-    M = g.n_rays
-    # stored-Phi equivalent: 8 B per (ray, coefficient) pair (FP32 value + int32 index),
-    # plus q-hat (4 B per ray) and b, beta read + beta written (12 B per active coefficient)
-    alg_bytes = 8.0 * w_update_avg + 4.0 * M + 12.0 * active_avg
-    achieved = alg_bytes / (upd_ms * 1e-3) / 1e9
-    khash = kernel_source_hash()
-    traffic = measured_traffic(khash, args.config)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_gather<float,double,kUpdate>", "avg_launch_ms": round(upd_ms, 5),
-            "launches": up["launches"], "alg_bytes_per_launch": int(alg_bytes), "kernel_hash": khash}
+    alg_up = 8.0 * w_update_avg + 4.0 * M + 12.0 * active_avg
+    roof_up = {"bound": "hbm", "achieved": round(alg_up / (upd_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+               "unit": "GB/s", "frac": round(alg_up / (upd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "traffic": measured_traffic(khash, args.config, "update"),
+               "kernels": "k_gather_part + k_gather_finish (+ k_gather) per tree level",
+               "avg_pass_ms": round(upd_ms, 5), "passes": up["launches"], "alg_bytes_per_pass": int(alg_up)}
     timing_ms = {k: round(v["ms"] / args.steps, 4) for k, v in tim.items()}
 
     out = {"metric": METRIC, "value": round(it_s, 2), "unit": "AM iter/s", "n_gpus": 1,
@@ -174,7 +186,8 @@ def main():
            "final_idiv": float(tr[-1]),
            "trees": seg,
            "time_ms_per_step_by_kernel": timing_ms,
-           "roofline": roof}
+           "roofline": roof,
+           "roofline_update": roof_up}
 
     # ---- full-image AM (levels = 0) on the same GPU: equal-I-div comparison
     if not args.no_full_am:
@@ -208,6 +221,13 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_views)
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = int(src.numel() * 4)
     ctx.close()
     print(json.dumps(out), flush=True)
 

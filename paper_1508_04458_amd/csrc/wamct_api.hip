@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <algorithm>
@@ -107,7 +108,8 @@ struct Ctx final : wamct_ctx {
   void* A = nullptr;
   void* B = nullptr;
   T *d = nullptr, *i0v = nullptr, *q = nullptr;
-  T *beta = nullptr, *b = nullptr, *mu = nullptr, *img = nullptr;
+  T *beta = nullptr, *b = nullptr, *mu = nullptr, *muT = nullptr, *img = nullptr;
+  void *leafR = nullptr, *leafC = nullptr;  // leaf records (value, level) for the tree walk
   uint8_t *mask = nullptr, *mask_old = nullptr, *lev = nullptr;
   uint32_t* items = nullptr;
   double *partd = nullptr, *part2 = nullptr, *mu64 = nullptr, *scal = nullptr;  // scal: [0]=z0 [1]=w [2]=max [3]=tmp
@@ -212,6 +214,10 @@ struct Ctx final : wamct_ctx {
     if ((r = alloc_bytes(A, sizeof(R) * 4 * size_t(M))) || (r = alloc_bytes(B, sizeof(R) * 4 * size_t(M)))) return r;
     if ((r = alloc(d, M)) || (r = alloc(i0v, M)) || (r = alloc(q, M))) return r;
     if ((r = alloc(beta, NN)) || (r = alloc(b, NN)) || (r = alloc(mu, NN)) || (r = alloc(img, NN))) return r;
+    if ((r = alloc(muT, NN))) return r;
+    if (g.L > 0 && ((r = alloc_bytes(leafR, 2 * sizeof(T) * size_t(NN))) ||
+                    (r = alloc_bytes(leafC, 2 * sizeof(T) * size_t(NN)))))
+      return r;
     if ((r = alloc(mask, NN)) || (r = alloc(mask_old, NN)) || (r = alloc(lev, NN))) return r;
     if ((r = alloc(items, max_items)) || (r = alloc(mu64, NN))) return r;
     const int np = std::max(nb_rays, nb_pix) + 1;
@@ -342,12 +348,22 @@ struct Ctx final : wamct_ctx {
 
   // one forward pass of the current state: mu, q-hat and the I-divergence partials
   int forward_pass() {
+    const bool tree = g.L > 0;
+    if (tree) {
+      {
+        Scope sc(this, WAMCT_K_SYNTH);
+        Launch<T>::synth_records(g, beta, lev, leafR, leafC, st);
+      }
+      Scope sc(this, WAMCT_K_FORWARD);
+      return Geo<T, R>::forward_records(g, A, B, leafR, leafC, d, i0v_used ? i0v : nullptr, i0s, q, nullptr, partd,
+                                        st);
+    }
     {
       Scope sc(this, WAMCT_K_SYNTH);
-      Launch<T>::synth(g, beta, mu, st);
+      Launch<T>::synth_layouts(g, beta, mu, muT, st);
     }
     Scope sc(this, WAMCT_K_FORWARD);
-    return Geo<T, R>::forward(g, g.L > 0, A, B, mu, lev, d, i0v_used ? i0v : nullptr, i0s, q, nullptr, partd, st);
+    return Geo<T, R>::forward(g, A, B, mu, muT, d, i0v_used ? i0v : nullptr, i0s, q, nullptr, partd, st);
   }
 
   wamct_status iterate(int32_t n, double* idv) override {
@@ -407,7 +423,8 @@ struct Ctx final : wamct_ctx {
   wamct_status project(const void* m, void* p) override {
     if (!m || !p) return fail(WAMCT_E_INVALID, "mu and p must not be NULL");
     Scope sc(this, WAMCT_K_OTHER);
-    Geo<T, R>::forward(g, false, A, B, (const T*)m, nullptr, nullptr, nullptr, 1.0, nullptr, (T*)p, nullptr, st);
+    Launch<T>::transpose(g.n, (const T*)m, muT, st);
+    Geo<T, R>::forward(g, A, B, (const T*)m, muT, nullptr, nullptr, 1.0, nullptr, (T*)p, nullptr, st);
     LAUNCHED();
     return WAMCT_OK;
   }

@@ -33,14 +33,21 @@ enum GatherMode { kPlain = 0, kSplit = 1, kUpdate = 2 };
 struct Segment {
   int start, count, level, chunks, vpc;
 };
-// Lanes one level segment should occupy (about 16 wave64 per CU on 256 CUs).
-constexpr int kTargetLanes = 1 << 18;
+// Lanes one level segment should occupy (about 64 wave64 per CU on 256 CUs, several
+// rounds of the resident waves, so short and long tasks even out).
+constexpr int kTargetLanes = 1 << 20;
 
 // Launchers. T is float or double. Every pointer is device memory unless noted.
 template <typename T>
 struct Launch {
   // mu = Omega beta (inactive coefficients are zero by invariant)
   static void synth(const DevGeom& g, const T* beta, T* mu, hipStream_t s);
+  // mu = Omega beta in both layouts the forward walk reads (row- and column-major)
+  static void synth_layouts(const DevGeom& g, const T* beta, T* muR, T* muC, hipStream_t s);
+  // leaf records (value, level) of mu = Omega beta, row- and column-major
+  static void synth_records(const DevGeom& g, const T* beta, const uint8_t* lev, void* leafR, void* leafC,
+                            hipStream_t s);
+  static void transpose(int n, const T* in, T* out, hipStream_t s);
   // per-pixel leaf level from the tree mask
   static void levmap(const DevGeom& g, const uint8_t* mask, uint8_t* lev, hipStream_t s);
   // I-divergence terms of a given q -> per-block partials. Returns the number of blocks.
@@ -64,12 +71,14 @@ struct Geo {
   static void ray_table(const DevGeom& g, const double2* views, void* A, void* B, hipStream_t s);
   // per-view (cos a, sin a) in float, used only for the detector footprint of a box
   static void view_table(const DevGeom& g, const double2* views, void* vF, hipStream_t s);
-  // ray-driven projection; tree = traverse leaves with `lev`, else pixels. If q != null:
-  // q = I0 exp(-p) and per-block FP64 partial sums of the I-divergence terms in `part`.
-  // If p != null the line integrals are stored. Returns the number of blocks.
-  static int forward(const DevGeom& g, bool tree, const void* A, const void* B, const T* mu,
-                     const uint8_t* lev, const T* d, const T* i0v, double i0s, T* q, T* p,
-                     double* part, hipStream_t s);
+  // pixel walk projection of muR/muC (row-/column-major copies of one image). If q != null:
+  // q = I0 exp(-p) and per-block FP64 partial sums of the I-divergence terms in `part`. If
+  // p != null the line integrals are stored. Returns the number of blocks.
+  static int forward(const DevGeom& g, const void* A, const void* B, const T* muR, const T* muC, const T* d,
+                     const T* i0v, double i0s, T* q, T* p, double* part, hipStream_t s);
+  // leaf walk over (value, level) records read from global memory
+  static int forward_records(const DevGeom& g, const void* A, const void* B, const void* leafR, const void* leafC,
+                             const T* d, const T* i0v, double i0s, T* q, T* p, double* part, hipStream_t s);
   // node-driven backprojection of y over the segments of `items` (items null: every pixel
   // as a level-0 box); `part` holds 7 * chunks * count values of R for chunked segments
   static void gather(const DevGeom& g, int mode, const void* vF, const void* A, const T* y,

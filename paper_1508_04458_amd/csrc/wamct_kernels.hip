@@ -157,28 +157,90 @@ __global__ __launch_bounds__(kBlock) void k_levmap(int n, int L, const uint8_t* 
   lev[p] = uint8_t(l);
 }
 
-// ------------------------------------------------------------------ leaf traversal
+// ------------------------------------------------------------------ image layouts
 
-// Storage type T (mu, q, beta), geometry and accumulation type R (chords are differences
-// of ray parameters whose magnitude reaches the image half-diagonal, so FP64 R keeps
-// chords exact to ~1e-13 mm; FP64 FMA runs at the non-packed FP32 rate on CDNA4).
-template <typename T, typename R>
-struct SumVisitor {
-  const T* __restrict__ mu;
-  int n;
-  R acc;
-  __device__ inline void operator()(int ix, int iy, int, R chord) { acc += chord * R(mu[iy * n + ix]); }
+// Leaf record of the forward walk: the (leaf-constant) value at a pixel and the level of
+// the tree leaf containing it, read with one load per step.
+template <typename T>
+struct alignas(2 * sizeof(T)) Leaf {
+  T mu;
+  uint32_t lev;
 };
+
+// mu = Omega beta over 32x32 pixel tiles, written twice: row-major and column-major (the
+// copy read by rays travelling mostly along x, whose lanes then step through consecutive
+// addresses instead of one image row each). TREE: leaf records; otherwise plain values.
+template <typename T, bool TREE>
+__global__ __launch_bounds__(256) void k_synth_tiles(int n, int L, const T* __restrict__ beta,
+                                                     const uint8_t* __restrict__ lev, T* __restrict__ muR,
+                                                     T* __restrict__ muC, Leaf<T>* __restrict__ leafR,
+                                                     Leaf<T>* __restrict__ leafC) {
+  __shared__ T tile[32][33];
+  __shared__ uint8_t ltile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = r0 + ty + 8 * k, c = c0 + tx;
+    if (r < n && c < n) {
+      const T v = synth_pixel<T, T>(beta, n, L, r, c);
+      tile[ty + 8 * k][tx] = v;
+      if (TREE) {
+        const uint8_t lv = lev[r * n + c];
+        ltile[ty + 8 * k][tx] = lv;
+        leafR[r * n + c] = Leaf<T>{v, lv};
+      } else {
+        muR[r * n + c] = v;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = c0 + ty + 8 * k, r = r0 + tx;
+    if (r < n && c < n) {
+      const T v = tile[tx][ty + 8 * k];
+      if (TREE)
+        leafC[c * n + r] = Leaf<T>{v, ltile[tx][ty + 8 * k]};
+      else
+        muC[c * n + r] = v;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(int n, const T* __restrict__ in, T* __restrict__ out) {
+  __shared__ T tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = r0 + ty + 8 * k, c = c0 + tx;
+    if (r < n && c < n) tile[ty + 8 * k][tx] = in[r * n + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = c0 + ty + 8 * k, r = r0 + tx;
+    if (r < n && c < n) out[c * n + r] = tile[tx][ty + 8 * k];
+  }
+}
 
 // ------------------------------------------------------------------ forward + Beer's law
 
-// One lane per ray: p = sum over leaves of chord * mu_leaf (= sum_z phi(y|z) beta(z) on
-// Z_s), q-hat = I0 exp(-p) (Introduction; Algorithm 1 first step), and the FP64 term
-// d log(d / q) - d + q of the I-divergence (0 log 0 = 0) with log q = log I0 - p.
-template <typename T, typename R, bool TREE>
+// Pixel walk (image-domain AM and the projection operator). One lane per ray (consecutive
+// lanes = consecutive bins of one view): p = sum_x h(y|x) mu(x) by incremental plane
+// crossings (Siddon's parametric form, in R), then q-hat = I0 exp(-p) (Introduction;
+// Algorithm 1 first step) and the FP64 term d log(d / q) - d + q of the I-divergence
+// (0 log 0 = 0) with log q = log I0 - p. The pixel sequence does not depend on mu, so the
+// walk runs KB steps ahead recording chord and address, then issues the KB loads together
+// (KB loads in flight per lane instead of one dependent load per step). Rays travelling
+// mostly along x read the column-major copy of the image, so neighbouring lanes touch
+// consecutive addresses.
+template <typename T, typename R, int KB>
 __global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4<R>::t* __restrict__ A,
                                                     const typename V4<R>::t* __restrict__ B,
-                                                    const T* __restrict__ mu, const uint8_t* __restrict__ lev,
+                                                    const T* __restrict__ muR, const T* __restrict__ muC,
                                                     const T* __restrict__ d, const T* __restrict__ i0v,
                                                     double i0s, T* __restrict__ q, T* __restrict__ pout,
                                                     double* __restrict__ part) {
@@ -187,10 +249,140 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4
   double term = 0.0;
   if (r < M) {
     const typename V4<R>::t a = A[r];
-    const typename V4<R>::t b = B[r];
-    SumVisitor<T, R> vis{mu, g.n, R(0)};
-    walk<R, TREE>(g, a.x, a.y, b.x, b.y, a.z, a.w, lev, vis);
-    const R p = vis.acc;
+    const typename V4<R>::t bb = B[r];
+    const R ox = a.x, oy = a.y, iex = a.z, iey = a.w, ex = bb.x, ey = bb.y;
+    const int n = g.n;
+    const R pix = R(g.pixel), ipix = R(1.0 / g.pixel), hn = R(0.5 * n), half = R(0.5 * n * g.pixel);
+    const R tx0 = (-half - ox) * iex, tx1 = (half - ox) * iex;
+    const R ty0 = (-half - oy) * iey, ty1 = (half - oy) * iey;
+    const R t_in = fmax(fmin(tx0, tx1), fmin(ty0, ty1));
+    const R t_out = fmin(fmax(tx0, tx1), fmax(ty0, ty1));
+    R acc = R(0);
+    if (t_out > t_in) {
+      int ix = (int)floor(fmin(fmax((ox + t_in * ex) * ipix + hn, R(-1)), R(n)));
+      int iy = (int)floor(fmin(fmax((oy + t_in * ey) * ipix + hn, R(-1)), R(n)));
+      ix = imin(imax(ix, 0), n - 1);
+      iy = imin(imax(iy, 0), n - 1);
+      const bool px = ex > R(0), py = ey > R(0);
+      const bool xmaj = fabs(ex) >= fabs(ey);
+      const T* __restrict__ base = xmaj ? muC : muR;
+      const int sx = px ? 1 : -1, sy = py ? 1 : -1;
+      R t = t_in;
+      bool alive = true;
+      R tX = ((R(px ? ix + 1 : ix) - hn) * pix - ox) * iex;
+      R tY = ((R(py ? iy + 1 : iy) - hn) * pix - oy) * iey;
+      const R dtX = pix * fabs(iex), dtY = pix * fabs(iey);
+      const int max_batches = (2 * n + 4) / KB + 1;
+      for (int batch = 0; batch < max_batches && alive; ++batch) {
+        R ch[KB];
+        int ad[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          ad[k] = xmaj ? ix * n + iy : iy * n + ix;
+          const bool sxs = tX <= tY;
+          const R te = fmin(sxs ? tX : tY, t_out);
+          const int nix = sxs ? ix + sx : ix, niy = sxs ? iy : iy + sy;
+          ch[k] = alive ? fmax(te - t, R(0)) : R(0);
+          const bool go = alive && te < t_out && (unsigned)nix < (unsigned)n && (unsigned)niy < (unsigned)n;
+          if (go) {
+            if (sxs) tX += dtX; else tY += dtY;
+            t = te; ix = nix; iy = niy;
+          }
+          alive = go;
+        }
+        T mv[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) mv[k] = base[ad[k]];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) acc += ch[k] * R(mv[k]);
+      }
+    }
+    const R p = acc;
+    if (pout) pout[r] = T(p);
+    if (q) {
+      const double i0 = i0v ? double(i0v[r]) : i0s;
+      const double pd = double(p);
+      const double qd = i0 * exp(-pd);
+      q[r] = T(qd);
+      const double dv = double(d[r]);
+      term = qd - dv;
+      if (dv > 0.0) term += dv * (log(dv) - (log(i0) - pd));
+    }
+  }
+  if (part) {
+    term = block_reduce<false>(term);
+    if (threadIdx.x == 0) part[blockIdx.x] = term;
+  }
+}
+
+// Leaf walk (wavelet AM): p = sum over the tree leaves crossed of chord * mu_leaf
+// (= sum_z phi(y|z) beta(z) on Z_s), then Beer's law and the I-divergence term as above.
+// One (value, level) record per step; the next record is requested before the current
+// chord is accumulated. From the pixel (ix, iy) inside the current leaf the exit is the
+// nearer of the leaf's two exit planes; the next pixel is the neighbour across that plane,
+// its other coordinate taken from the exit point (FP32 suffices: it is clamped into the old
+// leaf's range and never moves backwards, so rounding at a corner only moves a vanishing
+// chord between neighbours and cannot reverse the walk). Every step enters a new leaf, so
+// at most 2n steps occur (loop bound 4n + 8). x-major rays read the column-major records.
+template <typename T, typename R>
+__global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typename V4<R>::t* __restrict__ A,
+                                                        const typename V4<R>::t* __restrict__ B,
+                                                        const Leaf<T>* __restrict__ leafR,
+                                                        const Leaf<T>* __restrict__ leafC,
+                                                        const T* __restrict__ d, const T* __restrict__ i0v,
+                                                        double i0s, T* __restrict__ q, T* __restrict__ pout,
+                                                        double* __restrict__ part) {
+  const int M = g.nv * g.nb;
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  double term = 0.0;
+  if (r < M) {
+    const typename V4<R>::t a = A[r];
+    const typename V4<R>::t bb = B[r];
+    const R ox = a.x, oy = a.y, iex = a.z, iey = a.w, ex = bb.x, ey = bb.y;
+    const int n = g.n;
+    const R pix = R(g.pixel), ipix = R(1.0 / g.pixel), hn = R(0.5 * n), half = R(0.5 * n * g.pixel);
+    const R tx0 = (-half - ox) * iex, tx1 = (half - ox) * iex;
+    const R ty0 = (-half - oy) * iey, ty1 = (half - oy) * iey;
+    const R t_in = fmax(fmin(tx0, tx1), fmin(ty0, ty1));
+    const R t_out = fmin(fmax(tx0, tx1), fmax(ty0, ty1));
+    R acc = R(0);
+    if (t_out > t_in) {
+      int ix = (int)floor(fmin(fmax((ox + t_in * ex) * ipix + hn, R(-1)), R(n)));
+      int iy = (int)floor(fmin(fmax((oy + t_in * ey) * ipix + hn, R(-1)), R(n)));
+      ix = imin(imax(ix, 0), n - 1);
+      iy = imin(imax(iy, 0), n - 1);
+      const bool px = ex > R(0), py = ey > R(0);
+      const bool xmaj = fabs(ex) >= fabs(ey);
+      const Leaf<T>* __restrict__ base = xmaj ? leafC : leafR;
+      Leaf<T> rec = base[xmaj ? ix * n + iy : iy * n + ix];
+      R t = t_in;
+      for (int step = 0; step < 4 * n + 8; ++step) {
+        const int l = int(rec.lev);
+        const int s = 1 << l;
+        const int bx0 = (ix >> l) << l, by0 = (iy >> l) << l;
+        const R tX = ((R(px ? bx0 + s : bx0) - hn) * pix - ox) * iex;
+        const R tY = ((R(py ? by0 + s : by0) - hn) * pix - oy) * iey;
+        const bool sxs = tX <= tY;
+        const R te = fmax(fmin(sxs ? tX : tY, t_out), t);
+        int nix, niy;
+        if (sxs) {
+          nix = px ? bx0 + s : bx0 - 1;
+          const int rr = (int)floorf(fminf(fmaxf(float((oy + te * ey) * ipix + hn), -1.f), float(n)));
+          niy = py ? imin(imax(rr, iy), by0 + s - 1) : imax(imin(rr, iy), by0);
+        } else {
+          niy = py ? by0 + s : by0 - 1;
+          const int cc = (int)floorf(fminf(fmaxf(float((ox + te * ex) * ipix + hn), -1.f), float(n)));
+          nix = px ? imin(imax(cc, ix), bx0 + s - 1) : imax(imin(cc, ix), bx0);
+        }
+        const bool go = te < t_out && (unsigned)nix < (unsigned)n && (unsigned)niy < (unsigned)n;
+        Leaf<T> nrec = rec;
+        if (go) nrec = base[xmaj ? nix * n + niy : niy * n + nix];
+        acc += (te - t) * R(rec.mu);
+        if (!go) break;
+        t = te; ix = nix; iy = niy; rec = nrec;
+      }
+    }
+    const R p = acc;
     if (pout) pout[r] = T(p);
     if (q) {
       const double i0 = i0v ? double(i0v[r]) : i0s;
@@ -276,10 +468,11 @@ __device__ inline ItemSums<R> item_sums(const DevGeom& g, const float2* __restri
     if (g.kind == 0) {
       u00 = fx0 * c + fy0 * sn; u01 = fx2 * c + fy0 * sn; u10 = fx0 * c + fy2 * sn; u11 = fx2 * c + fy2 * sn;
     } else {
-      u00 = sdd * (-fx0 * sn + fy0 * c) / (sod - (fx0 * c + fy0 * sn));
-      u01 = sdd * (-fx2 * sn + fy0 * c) / (sod - (fx2 * c + fy0 * sn));
-      u10 = sdd * (-fx0 * sn + fy2 * c) / (sod - (fx0 * c + fy2 * sn));
-      u11 = sdd * (-fx2 * sn + fy2 * c) / (sod - (fx2 * c + fy2 * sn));
+      // hardware reciprocal (1 ulp): the bound is widened by 1e-3 bin anyway
+      u00 = sdd * (-fx0 * sn + fy0 * c) * __builtin_amdgcn_rcpf(sod - (fx0 * c + fy0 * sn));
+      u01 = sdd * (-fx2 * sn + fy0 * c) * __builtin_amdgcn_rcpf(sod - (fx2 * c + fy0 * sn));
+      u10 = sdd * (-fx0 * sn + fy2 * c) * __builtin_amdgcn_rcpf(sod - (fx0 * c + fy2 * sn));
+      u11 = sdd * (-fx2 * sn + fy2 * c) * __builtin_amdgcn_rcpf(sod - (fx2 * c + fy2 * sn));
     }
     const float umin = fminf(fminf(u00, u01), fminf(u10, u11));
     const float umax = fmaxf(fmaxf(u00, u01), fmaxf(u10, u11));
@@ -386,52 +579,73 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevGeom g, const float2* __re
   item_finish<T, R, MODE>(g, w, r, beta, bvec, z0p, held, bp_out, bm_out, out);
 }
 
-// One lane per (item, view chunk) of a level segment whose item count alone would leave
-// the GPU idle: consecutive lanes take consecutive (spatially adjacent) items of the same
-// chunk; the seven partial sums go to part[chunk][slot][count] (coalesced).
+// (item, view chunk) tasks for a level segment whose items alone would leave the GPU idle.
+// A block of kChunkWaves waves takes 64 consecutive (spatially adjacent) items; wave w
+// handles view chunk kChunkWaves * group + w for all of them (uniform view range per wave).
+// The chunk sums are added in LDS in wave order (deterministic) and written to
+// part[group][slot][count].
+constexpr int kChunkWaves = 4;
+
 template <typename T, typename R>
-__global__ __launch_bounds__(kBlock) void k_gather_part(DevGeom g, const float2* __restrict__ vf,
-                                                        const typename V4<R>::t* __restrict__ A,
-                                                        const T* __restrict__ y, const uint32_t* __restrict__ items,
-                                                        int start, int count, int chunks, int vpc,
-                                                        R* __restrict__ part) {
-  const int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= count * chunks) return;
-  const int chunk = k / count, idx = k - chunk * count;
-  const uint32_t w = item_word(items, start + idx, g.n);
-  const bool quad = (w >> 31) != 0;
-  const int v0 = chunk * vpc, v1 = min(g.nv, v0 + vpc);
-  const ItemSums<R> r = item_sums<T, R>(g, vf, A, y, quad, int((w >> 27) & 15u), int((w >> 13) & 0x1fffu),
-                                        int(w & 0x1fffu), v0, v1);
-  R* p = part + size_t(chunk) * 7 * count + idx;
-  p[0] = r.acc;
-  if (quad) {
-    p[1 * count] = r.pos0; p[2 * count] = r.pos1; p[3 * count] = r.pos2;
-    p[4 * count] = r.neg0; p[5 * count] = r.neg1; p[6 * count] = r.neg2;
+__global__ __launch_bounds__(64 * kChunkWaves) void k_gather_part(DevGeom g, const float2* __restrict__ vf,
+                                                                  const typename V4<R>::t* __restrict__ A,
+                                                                  const T* __restrict__ y,
+                                                                  const uint32_t* __restrict__ items, int start,
+                                                                  int count, int chunks, int vpc,
+                                                                  R* __restrict__ part) {
+  __shared__ R sh[kChunkWaves][7][64];
+  const int n_item_groups = (count + 63) / 64;
+  const int ig = blockIdx.x % n_item_groups, group = blockIdx.x / n_item_groups;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int idx = ig * 64 + lane;
+  const int chunk = group * kChunkWaves + wv;
+  ItemSums<R> r{R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
+  bool quad = false;
+  if (idx < count && chunk < chunks) {
+    const uint32_t w = item_word(items, start + idx, g.n);
+    quad = (w >> 31) != 0;
+    const int v0 = chunk * vpc, v1 = min(g.nv, v0 + vpc);
+    r = item_sums<T, R>(g, vf, A, y, quad, int((w >> 27) & 15u), int((w >> 13) & 0x1fffu), int(w & 0x1fffu),
+                        v0, v1);
+  }
+  sh[wv][0][lane] = r.acc;
+  sh[wv][1][lane] = r.pos0; sh[wv][2][lane] = r.pos1; sh[wv][3][lane] = r.pos2;
+  sh[wv][4][lane] = r.neg0; sh[wv][5][lane] = r.neg1; sh[wv][6][lane] = r.neg2;
+  __syncthreads();
+  for (int k = threadIdx.x; k < 7 * 64; k += 64 * kChunkWaves) {
+    const int slot = k / 64, l2 = k % 64;
+    const int it = ig * 64 + l2;
+    if (it >= count) continue;
+    R v = R(0);
+#pragma unroll
+    for (int w2 = 0; w2 < kChunkWaves; ++w2) v += sh[w2][slot][l2];
+    part[(size_t(group) * 7 + slot) * count + it] = v;
   }
 }
 
-// Sum the chunks of each item in chunk order (deterministic) and finish the item.
+// Sum the chunk groups of each item in group order (deterministic): 7 waves of a block each
+// add one slot for 64 consecutive items (coalesced), then one wave finishes the items.
 template <typename T, typename R, int MODE>
-__global__ __launch_bounds__(kBlock) void k_gather_finish(DevGeom g, const uint32_t* __restrict__ items, int start,
-                                                          int count, int chunks, const R* __restrict__ part,
-                                                          T* __restrict__ beta, const T* __restrict__ bvec,
-                                                          const double* __restrict__ z0p, int* __restrict__ held,
-                                                          T* __restrict__ bp_out, T* __restrict__ bm_out,
-                                                          T* __restrict__ out) {
-  const int idx = blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= count) return;
-  const uint32_t w = item_word(items, start + idx, g.n);
-  const bool quad = (w >> 31) != 0;
-  ItemSums<R> r{R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
-  for (int c = 0; c < chunks; ++c) {
-    const R* p = part + size_t(c) * 7 * count + idx;
-    r.acc += p[0];
-    if (quad) {
-      r.pos0 += p[1 * count]; r.pos1 += p[2 * count]; r.pos2 += p[3 * count];
-      r.neg0 += p[4 * count]; r.neg1 += p[5 * count]; r.neg2 += p[6 * count];
-    }
+__global__ __launch_bounds__(512) void k_gather_finish(DevGeom g, const uint32_t* __restrict__ items, int start,
+                                                       int count, int chunks, const R* __restrict__ part,
+                                                       T* __restrict__ beta, const T* __restrict__ bvec,
+                                                       const double* __restrict__ z0p, int* __restrict__ held,
+                                                       T* __restrict__ bp_out, T* __restrict__ bm_out,
+                                                       T* __restrict__ out) {
+  __shared__ R sh[7][64];
+  const int lane = threadIdx.x & 63, slot = threadIdx.x >> 6;
+  const int idx = blockIdx.x * 64 + lane;
+  const int groups = (chunks + kChunkWaves - 1) / kChunkWaves;
+  if (slot < 7) {
+    R v = R(0);
+    if (idx < count)
+      for (int c = 0; c < groups; ++c) v += part[(size_t(c) * 7 + slot) * count + idx];
+    sh[slot][lane] = v;
   }
+  __syncthreads();
+  if (slot != 0 || idx >= count) return;
+  const uint32_t w = item_word(items, start + idx, g.n);
+  ItemSums<R> r{sh[0][lane], sh[1][lane], sh[2][lane], sh[3][lane], sh[4][lane], sh[5][lane], sh[6][lane]};
   item_finish<T, R, MODE>(g, w, r, beta, bvec, z0p, held, bp_out, bm_out, out);
 }
 
@@ -720,6 +934,23 @@ void Launch<T>::levmap(const DevGeom& g, const uint8_t* mask, uint8_t* lev, hipS
   hipLaunchKernelGGL(k_levmap, dim3(blocks_for(int64_t(g.n) * g.n)), dim3(kBlock), 0, s, g.n, g.L, mask, lev);
 }
 template <typename T>
+void Launch<T>::synth_layouts(const DevGeom& g, const T* beta, T* muR, T* muC, hipStream_t s) {
+  const dim3 grid((g.n + 31) / 32, (g.n + 31) / 32);
+  hipLaunchKernelGGL((k_synth_tiles<T, false>), grid, dim3(256), 0, s, g.n, g.L, beta, nullptr, muR, muC,
+                     (Leaf<T>*)nullptr, (Leaf<T>*)nullptr);
+}
+template <typename T>
+void Launch<T>::synth_records(const DevGeom& g, const T* beta, const uint8_t* lev, void* leafR, void* leafC,
+                              hipStream_t s) {
+  const dim3 grid((g.n + 31) / 32, (g.n + 31) / 32);
+  hipLaunchKernelGGL((k_synth_tiles<T, true>), grid, dim3(256), 0, s, g.n, g.L, beta, lev, (T*)nullptr, (T*)nullptr,
+                     (Leaf<T>*)leafR, (Leaf<T>*)leafC);
+}
+template <typename T>
+void Launch<T>::transpose(int n, const T* in, T* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose<T>, dim3((n + 31) / 32, (n + 31) / 32), dim3(256), 0, s, n, in, out);
+}
+template <typename T>
 int Launch<T>::idiv_terms(const DevGeom& g, const T* q, const T* d, double* part, hipStream_t s) {
   const int M = g.nv * g.nb, nb = blocks_for(M);
   hipLaunchKernelGGL(k_idiv_terms<T>, dim3(nb), dim3(kBlock), 0, s, M, q, d, part);
@@ -765,16 +996,20 @@ void Geo<T, R>::view_table(const DevGeom& g, const double2* views, void* vF, hip
   hipLaunchKernelGGL(k_view_table<float>, dim3(blocks_for(g.nv)), dim3(kBlock), 0, s, g.nv, views, (float2*)vF);
 }
 template <typename T, typename R>
-int Geo<T, R>::forward(const DevGeom& g, bool tree, const void* A, const void* B, const T* mu,
-                       const uint8_t* lev, const T* d, const T* i0v, double i0s, T* q, T* p,
-                       double* part, hipStream_t s) {
+int Geo<T, R>::forward(const DevGeom& g, const void* A, const void* B, const T* muR, const T* muC, const T* d,
+                       const T* i0v, double i0s, T* q, T* p, double* part, hipStream_t s) {
   const int nb = blocks_for(int64_t(g.nv) * g.nb);
-  auto a = (const typename V4<R>::t*)A;
-  auto b = (const typename V4<R>::t*)B;
-  if (tree)
-    hipLaunchKernelGGL((k_forward<T, R, true>), dim3(nb), dim3(kBlock), 0, s, g, a, b, mu, lev, d, i0v, i0s, q, p, part);
-  else
-    hipLaunchKernelGGL((k_forward<T, R, false>), dim3(nb), dim3(kBlock), 0, s, g, a, b, mu, lev, d, i0v, i0s, q, p, part);
+  hipLaunchKernelGGL((k_forward<T, R, 8>), dim3(nb), dim3(kBlock), 0, s, g, (const typename V4<R>::t*)A,
+                     (const typename V4<R>::t*)B, muR, muC, d, i0v, i0s, q, p, part);
+  return nb;
+}
+template <typename T, typename R>
+int Geo<T, R>::forward_records(const DevGeom& g, const void* A, const void* B, const void* leafR, const void* leafC,
+                               const T* d, const T* i0v, double i0s, T* q, T* p, double* part, hipStream_t s) {
+  const int nb = blocks_for(int64_t(g.nv) * g.nb);
+  hipLaunchKernelGGL((k_forward_rec<T, R>), dim3(nb), dim3(kBlock), 0, s, g, (const typename V4<R>::t*)A,
+                     (const typename V4<R>::t*)B, (const Leaf<T>*)leafR, (const Leaf<T>*)leafC, d, i0v, i0s, q, p,
+                     part);
   return nb;
 }
 template <typename T, typename R>
@@ -798,15 +1033,16 @@ void Geo<T, R>::gather(const DevGeom& g, int mode, const void* vF, const void* A
         hipLaunchKernelGGL((k_gather<T, R, kUpdate>), grid, blk, 0, s, g, vf, a, y, items, sg.start, sg.count, beta, b, z0, held, bp, bm, out);
       continue;
     }
-    hipLaunchKernelGGL((k_gather_part<T, R>), dim3(blocks_for(int64_t(sg.count) * sg.chunks)), blk, 0, s, g, vf, a, y,
-                       items, sg.start, sg.count, sg.chunks, sg.vpc, pt);
-    const dim3 grid(blocks_for(sg.count));
+    const int groups = (sg.chunks + kChunkWaves - 1) / kChunkWaves;
+    hipLaunchKernelGGL((k_gather_part<T, R>), dim3(((sg.count + 63) / 64) * groups), dim3(64 * kChunkWaves), 0, s, g,
+                       vf, a, y, items, sg.start, sg.count, sg.chunks, sg.vpc, pt);
+    const dim3 grid((sg.count + 63) / 64), fblk(512);
     if (mode == kPlain)
-      hipLaunchKernelGGL((k_gather_finish<T, R, kPlain>), grid, blk, 0, s, g, items, sg.start, sg.count, sg.chunks, pt, beta, b, z0, held, bp, bm, out);
+      hipLaunchKernelGGL((k_gather_finish<T, R, kPlain>), grid, fblk, 0, s, g, items, sg.start, sg.count, sg.chunks, pt, beta, b, z0, held, bp, bm, out);
     else if (mode == kSplit)
-      hipLaunchKernelGGL((k_gather_finish<T, R, kSplit>), grid, blk, 0, s, g, items, sg.start, sg.count, sg.chunks, pt, beta, b, z0, held, bp, bm, out);
+      hipLaunchKernelGGL((k_gather_finish<T, R, kSplit>), grid, fblk, 0, s, g, items, sg.start, sg.count, sg.chunks, pt, beta, b, z0, held, bp, bm, out);
     else
-      hipLaunchKernelGGL((k_gather_finish<T, R, kUpdate>), grid, blk, 0, s, g, items, sg.start, sg.count, sg.chunks, pt, beta, b, z0, held, bp, bm, out);
+      hipLaunchKernelGGL((k_gather_finish<T, R, kUpdate>), grid, fblk, 0, s, g, items, sg.start, sg.count, sg.chunks, pt, beta, b, z0, held, bp, bm, out);
   }
 }
 
