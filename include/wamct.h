@@ -171,6 +171,21 @@ wamct_status wamct_get_b(wamct_ctx* ctx, void* b);
 wamct_status wamct_tree_stats(wamct_ctx* ctx, double* z0, int64_t* w, int64_t* n_active,
                               int64_t* n_held);
 
+/* Differentiable coefficient-domain loss (eq. 1.3 with lambda = 0, every coefficient of the
+ * `levels`-level Haar basis free), for a batch of scans that share this geometry:
+ *   loss_b = I(d_b || I0 exp(-H Omega c_b)), b = 0..batch-1.
+ * c: [batch][n*n] Mallat coefficients; d: [batch][n_rays] counts (not copied; the context's
+ * own data are not used); i0: [batch][n_rays] or NULL for the scalar i0_scalar. loss: device
+ * double[batch] (FP64 reduction). q: [batch][n_rays] receives q_b = I0 exp(-H Omega c_b), the
+ * checkpoint the backward pass needs. Does not touch beta or the tree. */
+wamct_status wamct_loss(wamct_ctx* ctx, int32_t batch, const void* c, const void* d, const void* i0,
+                        double i0_scalar, double* loss, void* q);
+/* Adjoint of wamct_loss from its checkpoint: grad_b = s_b Omega^T H^T (d_b - q_b) (the
+ * gradient of loss_b w.r.t. c_b, scaled by s_b = gscale[b], device double[batch], or 1 when
+ * gscale is NULL). q, d as above; grad: [batch][n*n]. */
+wamct_status wamct_loss_backward(wamct_ctx* ctx, int32_t batch, const void* q, const void* d,
+                                 const double* gscale, void* grad);
+
 /* Kernel timing with HIP events on the context's stream: enable != 0 starts recording
  * (and clears the totals). wamct_get_timing synchronizes and returns, per kernel class
  * (WAMCT_K_*), the summed duration in ms and the launch count (arrays of WAMCT_NK). */

@@ -23,7 +23,7 @@ SYMBOLS = (
     "wamct_set_stream", "wamct_set_data", "wamct_reset", "wamct_set_state", "wamct_get_state",
     "wamct_iterate", "wamct_expand", "wamct_solve", "wamct_synthesize", "wamct_project",
     "wamct_backproject", "wamct_backproject_split", "wamct_forward", "wamct_idiv", "wamct_get_b",
-    "wamct_tree_stats", "wamct_timing", "wamct_get_timing",
+    "wamct_tree_stats", "wamct_timing", "wamct_get_timing", "wamct_loss", "wamct_loss_backward",
 )
 
 
@@ -75,6 +75,8 @@ def _load():
         "wamct_tree_stats": (vp, P(f64), P(i64), P(i64), P(i64)),
         "wamct_timing": (vp, i32),
         "wamct_get_timing": (vp, P(f64), P(i64)),
+        "wamct_loss": (vp, i32, vp, vp, vp, f64, vp, vp),
+        "wamct_loss_backward": (vp, i32, vp, vp, vp, vp),
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -178,6 +178,34 @@ class Context:
         self._call(lib.wamct_tree_stats, ctypes.byref(z0), ctypes.byref(w), ctypes.byref(na), ctypes.byref(nh))
         return dict(z0=z0.value, w=w.value, n_active=na.value, n_held=nh.value)
 
+    # ------------------------------------------------------------------ differentiable loss
+    def loss(self, c: torch.Tensor, d: torch.Tensor, i0):
+        """loss_b = I(d_b || I0 exp(-H Omega c_b)) for a batch c [B, n, n], d [B, n_rays].
+        Returns (loss [B] float64, q [B, n_rays]) with q the checkpoint for loss_backward."""
+        B = c.shape[0]
+        self._arr(c, B * self.n * self.n, "c")
+        self._arr(d, B * self.n_rays, "d")
+        q = self._new(B * self.n_rays, shape=(B, self.n_rays))
+        out = self._new(B, torch.float64)
+        if isinstance(i0, torch.Tensor):
+            self._arr(i0, B * self.n_rays, "i0")
+            self._call(lib.wamct_loss, B, _ptr(c), _ptr(d), _ptr(i0), 0.0, _ptr(out), _ptr(q))
+        else:
+            self._call(lib.wamct_loss, B, _ptr(c), _ptr(d), None, float(i0), _ptr(out), _ptr(q))
+        return out, q
+
+    def loss_backward(self, q: torch.Tensor, d: torch.Tensor, gscale: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """grad_b = gscale_b Omega^T H^T (d_b - q_b), [B, n, n] (the adjoint of `loss`)."""
+        B = q.shape[0]
+        self._arr(q, B * self.n_rays, "q")
+        self._arr(d, B * self.n_rays, "d")
+        if gscale is not None:
+            gscale = gscale.to(device=self.device, dtype=torch.float64).contiguous()
+            self._arr(gscale, B, "gscale", torch.float64)
+        grad = self._new(B * self.n * self.n, shape=(B, self.n, self.n))
+        self._call(lib.wamct_loss_backward, B, _ptr(q), _ptr(d), _ptr(gscale), _ptr(grad))
+        return grad
+
     # ------------------------------------------------------------------ timing
     def timing(self, enable: bool) -> None:
         self._call(lib.wamct_timing, 1 if enable else 0)

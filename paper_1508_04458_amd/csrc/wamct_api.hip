@@ -74,6 +74,8 @@ struct wamct_ctx {
   virtual wamct_status idiv(const void*, double*) = 0;
   virtual wamct_status get_b(void*) = 0;
   virtual wamct_status tree_stats(double*, int64_t*, int64_t*, int64_t*) = 0;
+  virtual wamct_status loss(int32_t, const void*, const void*, const void*, double, double*, void*) = 0;
+  virtual wamct_status loss_backward(int32_t, const void*, const void*, const double*, void*) = 0;
   virtual wamct_status timing(int32_t) = 0;
   virtual wamct_status get_timing(double*, int64_t*) = 0;
   wamct_status fail(wamct_status s, const std::string& m) {
@@ -500,6 +502,52 @@ struct Ctx final : wamct_ctx {
     return WAMCT_OK;
   }
 
+  // Coefficient-domain loss (eq. 1.3 with lambda = 0, every coefficient free):
+  // loss_b = I(d_b || I0 exp(-H Omega c_b)) for a batch of scans of this geometry.
+  wamct_status loss(int32_t batch, const void* c, const void* dd, const void* i0p, double i0sc, double* lossd,
+                    void* qout) override {
+    if (batch < 0) return fail(WAMCT_E_INVALID, "batch must be >= 0");
+    if (batch > 0 && (!c || !dd || !lossd || !qout)) return fail(WAMCT_E_INVALID, "c, d, loss and q must not be NULL");
+    if (!i0p && !(i0sc > 0 && std::isfinite(i0sc))) return fail(WAMCT_E_INVALID, "scalar I0 must be finite and > 0");
+    for (int k = 0; k < batch; ++k) {
+      const T* ck = (const T*)c + size_t(k) * NN;
+      const T* dk = (const T*)dd + size_t(k) * M;
+      const T* ik = i0p ? (const T*)i0p + size_t(k) * M : nullptr;
+      T* qk = (T*)qout + size_t(k) * M;
+      {
+        Scope sc(this, WAMCT_K_SYNTH);
+        Launch<T>::synth_layouts(g, ck, mu, muT, st);
+      }
+      int nbk;
+      {
+        Scope sc(this, WAMCT_K_FORWARD);
+        nbk = Geo<T, R>::forward(g, A, B, mu, muT, dk, ik, i0sc, qk, nullptr, partd, st);
+      }
+      Scope sc(this, WAMCT_K_OTHER);
+      reduce_sum(partd, nbk, lossd + k, st);
+    }
+    LAUNCHED();
+    return WAMCT_OK;
+  }
+
+  // Hand-written adjoint: grad_b = s_b Omega^T H^T (d_b - q_b) from the saved q_b (s_b = the
+  // incoming gradient of loss_b, null = 1).
+  wamct_status loss_backward(int32_t batch, const void* qq, const void* dd, const double* gscale,
+                             void* grad) override {
+    if (batch < 0) return fail(WAMCT_E_INVALID, "batch must be >= 0");
+    if (batch > 0 && (!qq || !dd || !grad)) return fail(WAMCT_E_INVALID, "q, d and grad must not be NULL");
+    for (int k = 0; k < batch; ++k) {
+      Scope sc(this, WAMCT_K_UPDATE);
+      Launch<T>::residual((const T*)dd + size_t(k) * M, (const T*)qq + size_t(k) * M, gscale ? gscale + k : nullptr,
+                          q, M, st);
+      Geo<T, R>::gather(g, kPlain, vT, A, q, nullptr, pix_segs.data(), int(pix_segs.size()), part, nullptr, nullptr,
+                        nullptr, nullptr, nullptr, nullptr, img, st);
+      Launch<T>::analysis(g, img, (T*)grad + size_t(k) * NN, st);
+    }
+    LAUNCHED();
+    return WAMCT_OK;
+  }
+
   wamct_status timing(int32_t on) override {
     HIPCHK(hipStreamSynchronize(st));
     harvest();
@@ -586,6 +634,10 @@ wamct_status wamct_idiv(wamct_ctx* ctx, const void* q, double* out) { CTX_CALL(i
 wamct_status wamct_get_b(wamct_ctx* ctx, void* b) { CTX_CALL(get_b(b)); }
 wamct_status wamct_tree_stats(wamct_ctx* ctx, double* z0, int64_t* w, int64_t* na, int64_t* nh) { CTX_CALL(tree_stats(z0, w, na, nh)); }
 wamct_status wamct_timing(wamct_ctx* ctx, int32_t enable) { CTX_CALL(timing(enable)); }
+wamct_status wamct_loss(wamct_ctx* ctx, int32_t batch, const void* c, const void* d, const void* i0, double i0s,
+                        double* loss, void* q) { CTX_CALL(loss(batch, c, d, i0, i0s, loss, q)); }
+wamct_status wamct_loss_backward(wamct_ctx* ctx, int32_t batch, const void* q, const void* d, const double* gscale,
+                                 void* grad) { CTX_CALL(loss_backward(batch, q, d, gscale, grad)); }
 wamct_status wamct_get_timing(wamct_ctx* ctx, double* ms, int64_t* n) { CTX_CALL(get_timing(ms, n)); }
 
 wamct_status wamct_solve(wamct_ctx* ctx, int32_t n_iters, const int32_t* expand_at, int32_t n_expand, double frac,

@@ -61,6 +61,8 @@ struct Launch {
   // count non-finite or negative entries of x into *bad (int, accumulated)
   static void check(const T* x, int64_t len, bool allow_negative, int* bad, hipStream_t s);
   static void fill(T* x, int64_t len, T v, hipStream_t s);
+  // r = gscale (d - q) (gscale: device double, null = 1)
+  static void residual(const T* d, const T* q, const double* gscale, T* r, int64_t len, hipStream_t s);
 };
 
 // Kernels whose ray arithmetic runs in R (float or double, R at least as wide as T).

@@ -702,6 +702,16 @@ __global__ __launch_bounds__(kBlock) void k_check(const T* __restrict__ x, int64
   if (!isfinite(v) || (!allow_neg && v < T(0))) atomicAdd(bad, 1);
 }
 
+// r = g (d - q): the residual backprojected by the adjoint of the coefficient-domain loss
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual(int64_t len, const T* __restrict__ d, const T* __restrict__ q,
+                                                     const double* __restrict__ gscale, T* __restrict__ r) {
+  const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (p >= len) return;
+  const double gs = gscale ? *gscale : 1.0;
+  r[p] = T(gs * (double(d[p]) - double(q[p])));
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ x, int64_t len, T v) {
   const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -975,6 +985,10 @@ template <typename T>
 void Launch<T>::check(const T* x, int64_t len, bool allow_negative, int* bad, hipStream_t s) {
   if (len <= 0) return;
   hipLaunchKernelGGL(k_check<T>, dim3(blocks_for(len)), dim3(kBlock), 0, s, x, len, allow_negative, bad);
+}
+template <typename T>
+void Launch<T>::residual(const T* d, const T* q, const double* gscale, T* r, int64_t len, hipStream_t s) {
+  if (len > 0) hipLaunchKernelGGL(k_residual<T>, dim3(blocks_for(len)), dim3(kBlock), 0, s, len, d, q, gscale, r);
 }
 template <typename T>
 void Launch<T>::fill(T* x, int64_t len, T v, hipStream_t s) {

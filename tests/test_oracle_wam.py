@@ -223,7 +223,7 @@ def test_approximation_tree_equals_coarse_pixel_am():
     gc = synth.Geometry(0, n >> L, 1.0 * (1 << L), 40, 0.0, math.pi, 96, 1.0)
     P = synth.make_problem("parallel64")
     o, e = geometry.rays(g)
-    p = synth.ellipse_line_integrals(P.ellipses, o, e)
+    p = synth.line_integrals(P.ellipses, o, e)
     d = np.random.default_rng(9).poisson(1e4 * np.exp(-p)).astype(float)
     H = siddon.system_matrix(g)
     Hc = siddon.system_matrix(gc)
@@ -298,7 +298,7 @@ def test_loss_gradient_matches_central_differences():
     O = haar.synthesis_matrix(32, 2)
     o, e = geometry.rays(g)
     ell = np.array([[2.0, -1.0, 9.0, 6.0, 0.4, 0.04]])
-    d = np.random.default_rng(3).poisson(5e4 * np.exp(-synth.ellipse_line_integrals(ell, o, e))).astype(float)
+    d = np.random.default_rng(3).poisson(5e4 * np.exp(-synth.line_integrals(ell, o, e))).astype(float)
     c = haar.cascade_analysis(synth.rasterize(ell, 32, 1.0), 2).ravel()
     c += np.random.default_rng(4).normal(0, 1e-3, c.size)
     loss, grad, q = wam.loss_and_grad(H, O, d, 5e4, c)
