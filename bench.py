@@ -41,6 +41,11 @@ def parse():
     ap.add_argument("--cpu-views", type=int, default=36)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized buffer 3 times (reference kernel for PMC byte counters)")
+    ap.add_argument("--problems", type=int, default=256, help="uneven: number of problems")
+    ap.add_argument("--streams", type=int, default=4, help="uneven: streams of the batch")
+    ap.add_argument("--no-graph", action="store_true", help="uneven: launch directly instead of graph replay")
+    ap.add_argument("--autotune", action="store_true", help="uneven: tune the backprojection tiling first")
+    ap.add_argument("--no-sequential", action="store_true", help="uneven: skip the one-context-at-a-time run")
     return ap.parse_args()
 
 
@@ -89,12 +94,137 @@ def cpu_baseline(P, n_views_sample):
             "final_idiv_sample": float(r["idiv"][-1])}
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bench_uneven(args):
+    """Uneven batch: `problems` independent fan-beam scans (image side from {128, 256, 384,
+    512}, views from {360, 540, 720}, 2n bins, I0 in [1e4, 1e5]), each solved with the
+    3-level tree-adaptive AM (100 iterations, expansions 21/43/85). Scans of one geometry
+    form one context (a stack); the contexts run together as one batch whose iterations
+    are replayed from a captured HIP graph. A step solves every problem from beta = 0."""
+    import numpy as np
+    import torch
+    from paper_1508_04458_amd import api, synth
+
+    workers = max(1, min(16, os.cpu_count() or 1))
+    specs = synth.uneven_specs(args.problems)
+    log(f"drawing {len(specs)} problems with {workers} processes")
+    t0 = time.perf_counter()
+    probs = synth.make_uneven_batch(specs, workers=workers)
+    log(f"problems ready in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    classes = {}
+    for P in probs:
+        classes.setdefault((P.geom.n, P.geom.n_views), []).append(P)
+    keys = sorted(classes, key=lambda k: -k[0] * k[0] * k[1] * len(classes[k]))
+    ctxs = []
+    for k in keys:
+        ps = classes[k]
+        c = api.Context(ps[0].geom, ps[0].levels, "f32", device=dev, geometry=args.geometry, batch=len(ps))
+        c.set_data(torch.as_tensor(np.concatenate([P.d for P in ps]), dtype=torch.float32, device=dev),
+                   [P.i0 for P in ps])
+        ctxs.append(c)
+    del probs
+    P0 = classes[keys[0]][0]
+    J, sched = P0.n_iters, list(P0.schedule)
+    batch = api.Batch(ctxs, n_streams=args.streams, graph=not args.no_graph)
+    M = sum(c.S * c.n_rays for c in ctxs)
+    NN = sum(c.S * c.n * c.n for c in ctxs)
+    log(f"{len(ctxs)} contexts, {M / 1e6:.1f} M rays, {NN / 1e6:.1f} M pixels")
+
+    # ---- W_j and |Z_s| per segment (untimed pass through the same schedule)
+    batch.reset()
+    marks = [0] + sched + [J]
+    w_it = 0.0
+    act_it = 0.0
+    for k, (a, b) in enumerate(zip(marks[:-1], marks[1:])):
+        for c in ctxs:
+            if k > 0:
+                c.expand(0.1)
+            st = c.tree_stats()
+            w = st["w"] if c.S > 1 else [st["w"]]
+            na = st["n_active"] if c.S > 1 else [st["n_active"]]
+            w_it += sum(w) * (b - a)
+            act_it += sum(na) * (b - a)
+            c.iterate(b - a)
+    torch.cuda.synchronize()
+    log("tree statistics done")
+
+    def step():
+        batch.reset()
+        return batch.solve(J, sched, 0.1)
+
+    chosen = None
+    for _ in range(args.warmup):
+        step()
+    if args.autotune:
+        chosen = batch.autotune(1)
+        log(f"tiling chosen: {chosen}")
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tr = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt * 1e3 / args.steps
+    n_prob = sum(c.S for c in ctxs)
+    it_s = n_prob * J * args.steps / dt
+    final = [float(t.reshape(-1, J + 1)[:, -1].sum().item()) for t in tr]
+    stats = batch.stats()
+    log(f"batch: {ms_step:.1f} ms per step")
+
+    seq = None
+    if not args.no_sequential:
+        # the same contexts one after another on one stream, no batch (same kernels)
+        for c in ctxs:
+            c.reset()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for c in ctxs:
+            c.reset()
+            c.solve(J, sched, 0.1)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t1
+        seq = {"ms_per_step": round(t_seq * 1e3, 3), "iter_per_s": round(n_prob * J / t_seq, 2),
+               "batch_speedup": round(t_seq * 1e3 / ms_step, 3)}
+        log(f"sequential: {t_seq * 1e3:.1f} ms")
+
+    # whole iteration against the HBM-equivalent roofline: Phi stored would move 8 B per
+    # (ray, active coefficient) pair in each of the two passes, 8 B per ray (d, q-hat) and
+    # 16 B per active coefficient (beta, b, b-hat+-)
+    alg = 16.0 * w_it + 8.0 * M * J + 16.0 * act_it
+    per_step_s = ms_step * 1e-3
+    roof = {"bound": "hbm", "achieved": round(alg / per_step_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(alg / per_step_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "whole batch iteration (graph replay)", "alg_bytes_per_step": int(alg)}
+    out = {"metric": METRIC, "value": round(it_s, 2), "unit": "AM iter/s (problem-iterations)", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if args.geometry == "f32" else "f32 data, f64 ray geometry", "data": "synthetic",
+           "config": {"workload": f"uneven batch: {n_prob} fan-beam problems (n in {{128,256,384,512}}, views in "
+                                  f"{{360,540,720}}, 2n bins, I0 in [1e4,1e5]), {len(ctxs)} geometry classes, "
+                                  f"3-level tree AM, {J} iterations, expansions at {sched}",
+                      "problems": n_prob, "classes": len(ctxs), "rays": M, "pixels": NN,
+                      "streams": args.streams, "graph": not args.no_graph},
+           "gray_voxel_per_s": round(2 * w_it * args.steps / dt / 1e9, 3),
+           "final_idiv_sum": sum(final), "batch_stats": stats, "tiling": chosen, "sequential": seq,
+           "roofline": roof}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the view-sharded "
               "multi-GPU design is described in DESIGN.md and not built.", file=sys.stderr)
         sys.exit(2)
+    if args.config == "uneven":
+        bench_uneven(args)
+        return
     if args.no_cpu_baseline is False:
         # the CPU baseline is a single-threaded oracle
         for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):

@@ -33,6 +33,12 @@
  * ordered on the stream given at creation; calls return after enqueueing unless they
  * return a host value, which synchronizes that stream.
  *
+ * Stacks: a context holds `batch` (options) independent scans of its geometry, solved in
+ * lockstep (same iteration count and expansion schedule; each scan has its own data, I0,
+ * coefficients, tree, Z0 and held counter). Per-scan arrays are stacked scan-major:
+ * "[S]" below is the batch size, so beta is [S][n*n], d is [S][n_views*n_bins] and an
+ * I-divergence trace of n entries per scan is [S][n].
+ *
  * Errors: every call returns a wamct_status and never aborts; wamct_last_error(ctx)
  * gives the message of the last failing call on that context (NULL ctx: the last
  * failure of wamct_create/wamct_validate in this thread).
@@ -80,6 +86,7 @@ typedef struct {
                           chord lengths and per-ray/per-coefficient sums. WAMCT_F64 keeps
                           chords exact to ~1e-13 mm; WAMCT_F32 chords carry an absolute error
                           of about 1e-7 times the image half-diagonal. */
+  int32_t batch;       /* scans in the stack, 1 <= batch <= 65535 */
 } wamct_options;
 
 enum {                 /* kernel classes reported by wamct_get_timing */
@@ -111,16 +118,17 @@ const char* wamct_version(void);
 wamct_status wamct_set_stream(wamct_ctx* ctx, void* stream);
 
 /* Measured data of the Beer's-law model q(y) = I0(y) exp(-sum_x h(y|x) mu(x))
- * (Introduction). d: counts, [n_views * n_bins], finite and >= 0. i0: per-ray incident
- * counts of the same shape, or NULL to use the scalar i0_scalar (> 0). Both are COPIED
- * into the context. Also precomputes b(z) = sum_y d(y) phi(y|z) for every coefficient
- * (eq. 1.6; Algorithm 1 "Precompute") as Omega^T (H^T d). Synchronizes (validation). */
-wamct_status wamct_set_data(wamct_ctx* ctx, const void* d, const void* i0, double i0_scalar);
+ * (Introduction). d: counts, [S][n_views * n_bins], finite and >= 0. i0: per-ray incident
+ * counts of the same shape, or NULL to use one scalar per scan, i0_scalar (HOST double[S],
+ * each finite and > 0; ignored when i0 is given). Both are COPIED into the context. Also
+ * precomputes b(z) = sum_y d(y) phi(y|z) for every coefficient (eq. 1.6; Algorithm 1
+ * "Precompute") as Omega^T (H^T d). Synchronizes (validation). */
+wamct_status wamct_set_data(wamct_ctx* ctx, const void* d, const void* i0, const double* i0_scalar);
 
 /* beta = 0 and the approximation-only tree. */
 wamct_status wamct_reset(wamct_ctx* ctx);
-/* Set beta (Mallat, n*n) and the tree mask (uint8 device array, n*n). The mask must be a
- * valid tree (checked; E_INVALID otherwise); beta is zeroed outside it (inactive
+/* Set beta (Mallat, [S][n*n]) and the tree masks (uint8 device array, [S][n*n]). Every mask
+ * must be a valid tree (checked; E_INVALID otherwise); beta is zeroed outside it (inactive
  * coefficients are zero). Synchronizes. */
 wamct_status wamct_set_state(wamct_ctx* ctx, const void* beta, const uint8_t* mask);
 /* Copy beta and the mask out (either may be NULL); *iter_host (nullable) receives the
@@ -130,44 +138,45 @@ wamct_status wamct_get_state(wamct_ctx* ctx, void* beta, uint8_t* mask, int32_t*
 /* n_iters iterations of Algorithm 1 on the current tree: q-hat = I0 exp(-Phi beta),
  * b-hat+/- (eq. 1.10), Z0 (eq. 1.61, recomputed only when the tree changed) and the
  * closed-form zero of eq. 1.9 for every active coefficient. idiv (nullable, device
- * double[n_iters]) receives I(d || q-hat^(j)) before each update (footnote to the
+ * double[S][n_iters]) receives I(d || q-hat^(j)) before each update (footnote to the
  * Introduction). Coefficients whose surrogate has no finite minimizer are held and
  * counted (wamct_tree_stats). E_STATE before wamct_set_data. */
 wamct_status wamct_iterate(wamct_ctx* ctx, int32_t n_iters, double* idiv);
 
 /* Tree rule of the Results section: synthesize mu, threshold = frac * max(mu) (FP64);
  * every leaf at level >= 1 with a pixel above the threshold (strict) gets its three
- * details activated at zero; one level per call; nothing if max(mu) <= 0.
- * *n_split_host (nullable) receives the number of split nodes. Synchronizes. */
+ * details activated at zero; one level per call; nothing if max(mu) <= 0. Per scan.
+ * n_split_host (nullable, HOST int32[S]) receives the number of split nodes. Synchronizes. */
 wamct_status wamct_expand(wamct_ctx* ctx, double frac, int32_t* n_split_host);
 
 /* Algorithm 1 with the tree schedule: for j in [0, n_iters): expand (frac) first if j is
  * listed in expand_at (host int32[n_expand], ascending), then iterate once. idiv
- * (nullable, device double[n_iters + 1]) gets I(d || q-hat^(j)) for every j and after the
- * last update. Synchronizes once per expansion. */
+ * (nullable, device double[S][n_iters + 1]) gets I(d || q-hat^(j)) for every j and after
+ * the last update. Synchronizes once per expansion. */
 wamct_status wamct_solve(wamct_ctx* ctx, int32_t n_iters, const int32_t* expand_at,
                          int32_t n_expand, double frac, double* idiv);
 
-/* mu = Omega beta for the current state (eq. 1.2), mu: [n*n]. */
+/* mu = Omega beta for the current state (eq. 1.2), mu: [S][n*n]. */
 wamct_status wamct_synthesize(wamct_ctx* ctx, void* mu);
-/* p = H mu for an arbitrary image mu [n*n] (pixel-level ray tracing), p: [n_rays]. */
+/* p = H mu for one arbitrary image mu [n*n] (pixel-level ray tracing), p: [n_rays]. */
 wamct_status wamct_project(wamct_ctx* ctx, const void* mu, void* p);
-/* img = H^T y, y: [n_rays], img: [n*n]. */
+/* img = H^T y for one sinogram, y: [n_rays], img: [n*n]. */
 wamct_status wamct_backproject(wamct_ctx* ctx, const void* y, void* img);
 /* Sign-split coefficient backprojections over the current tree (eq. 1.10):
  * bp(z) = sum_{phi(y|z) > 0} y phi(y|z) and bm(z) = sum_{phi(y|z) < 0} y phi(y|z) for
- * active z, 0 elsewhere; bp, bm: [n*n] Mallat. */
+ * active z, 0 elsewhere; per scan over its own tree: y [S][n_rays], bp, bm: [S][n*n]. */
 wamct_status wamct_backproject_split(wamct_ctx* ctx, const void* y, void* bp, void* bm);
-/* q-hat = I0 exp(-Phi beta) of the current state into q [n_rays] (nullable), and
- * I(d || q-hat) into *idiv (device double, nullable). E_STATE before set_data. */
+/* q-hat = I0 exp(-Phi beta) of the current state into q [S][n_rays] (nullable), and
+ * I(d || q-hat) into idiv (device double[S], nullable). E_STATE before set_data. */
 wamct_status wamct_forward(wamct_ctx* ctx, void* q, double* idiv);
-/* I(d || q) for q [n_rays] into *out (device double). */
+/* I(d || q) for q [S][n_rays] into out (device double[S]). */
 wamct_status wamct_idiv(wamct_ctx* ctx, const void* q, double* out);
-/* The precomputed b (eq. 1.6) for every coefficient, [n*n] Mallat. */
+/* The precomputed b (eq. 1.6) for every coefficient, [S][n*n] Mallat. */
 wamct_status wamct_get_b(wamct_ctx* ctx, void* b);
-/* Host copies of the current tree's Z0 (eq. 1.61), W = number of (ray, active
- * coefficient) pairs with phi != 0, the number of active coefficients, and the number of
- * coefficient updates held since the last reset (any pointer may be NULL). Synchronizes. */
+/* Host copies, per scan (HOST arrays of S), of the current tree's Z0 (eq. 1.61), W =
+ * number of (ray, active coefficient) pairs with phi != 0, the number of active
+ * coefficients, and the number of coefficient updates held since the last reset (any
+ * pointer may be NULL). Synchronizes. */
 wamct_status wamct_tree_stats(wamct_ctx* ctx, double* z0, int64_t* w, int64_t* n_active,
                               int64_t* n_held);
 
@@ -177,12 +186,14 @@ wamct_status wamct_tree_stats(wamct_ctx* ctx, double* z0, int64_t* w, int64_t* n
  * c: [batch][n*n] Mallat coefficients; d: [batch][n_rays] counts (not copied; the context's
  * own data are not used); i0: [batch][n_rays] or NULL for the scalar i0_scalar. loss: device
  * double[batch] (FP64 reduction). q: [batch][n_rays] receives q_b = I0 exp(-H Omega c_b), the
- * checkpoint the backward pass needs. Does not touch beta or the tree. */
+ * checkpoint the backward pass needs. Independent of the stack: does not touch beta, the
+ * tree or the context's data. */
 wamct_status wamct_loss(wamct_ctx* ctx, int32_t batch, const void* c, const void* d, const void* i0,
                         double i0_scalar, double* loss, void* q);
 /* Adjoint of wamct_loss from its checkpoint: grad_b = s_b Omega^T H^T (d_b - q_b) (the
  * gradient of loss_b w.r.t. c_b, scaled by s_b = gscale[b], device double[batch], or 1 when
- * gscale is NULL). q, d as above; grad: [batch][n*n]. */
+ * gscale is NULL). q, d as above; grad: [batch][n*n]. The residual d_b - q_b is staged in
+ * the context's q-hat buffer, so a later wamct_forward must be called again to read q-hat. */
 wamct_status wamct_loss_backward(wamct_ctx* ctx, int32_t batch, const void* q, const void* d,
                                  const double* gscale, void* grad);
 
@@ -191,6 +202,50 @@ wamct_status wamct_loss_backward(wamct_ctx* ctx, int32_t batch, const void* q, c
  * (WAMCT_K_*), the summed duration in ms and the launch count (arrays of WAMCT_NK). */
 wamct_status wamct_timing(wamct_ctx* ctx, int32_t enable);
 wamct_status wamct_get_timing(wamct_ctx* ctx, double* ms, int64_t* launches);
+
+/* Tiling of the node-driven backprojection: a level segment whose items (over the whole
+ * stack) number fewer than `lanes` has its views split into chunks so that about `lanes`
+ * (item, view chunk) tasks run; 2^12 <= lanes <= 2^24, default 2^20. A larger value may
+ * reallocate the context's partial-sum buffer (synchronizes). Results do not depend on the
+ * tiling beyond floating-point summation order. */
+wamct_status wamct_set_tiling(wamct_ctx* ctx, int32_t lanes);
+wamct_status wamct_get_tiling(wamct_ctx* ctx, int32_t* lanes);
+
+/* ---------------------------------------------------------------- batches
+ * Uneven batches: several contexts (different geometries, image sizes and view counts,
+ * each a stack of scans) solved together. Each context is bound to one of n_streams
+ * streams of the batch (longest processing time first by rays x image side x scans). With
+ * use_graph != 0 one iteration of every context is captured into a HIP graph and replayed
+ * for every iteration between two tree expansions; otherwise the iterations are launched
+ * directly on the streams. The contexts stay owned by the caller, must outlive the batch
+ * and must not be used concurrently with a batch call; `stream` (hipStream_t, NULL =
+ * default) orders the batch after earlier work on it and later work after the batch, as do
+ * the contexts' own streams. */
+typedef struct wamct_batch wamct_batch;
+wamct_status wamct_batch_create(int32_t n_ctx, wamct_ctx* const* ctxs, int32_t n_streams, int32_t use_graph,
+                                void* stream, wamct_batch** out);
+wamct_status wamct_batch_destroy(wamct_batch* batch);
+/* Message of the last failing call on the batch (NULL batch: of wamct_batch_create). */
+const char* wamct_batch_last_error(const wamct_batch* batch);
+/* wamct_reset of every context, one host synchronization for the whole batch. */
+wamct_status wamct_batch_reset(wamct_batch* batch);
+/* wamct_solve of every context with the same schedule (n_iters, expand_at, frac).
+ * idiv: HOST array of n_ctx device pointers (the array or any entry may be NULL); entry i
+ * is double[S_i][n_iters + 1] for context i. Results equal those of wamct_solve on each
+ * context alone. Synchronizes once per expansion. */
+wamct_status wamct_batch_solve(wamct_batch* batch, int32_t n_iters, const int32_t* expand_at, int32_t n_expand,
+                               double frac, double* const* idiv);
+/* Autotuner of the backprojection tiling: for every context, n_trial iterations (after
+ * one untimed) are timed with HIP events at each candidate (HOST int32[n_candidates];
+ * NULL = 2^18 .. 2^22) on the context's own stream, its state restored after every trial,
+ * and the fastest is kept (wamct_set_tiling). chosen: HOST int32[n_ctx] (nullable). Tunes
+ * on each context's current tree. Synchronizes; may allocate. */
+wamct_status wamct_batch_autotune(wamct_batch* batch, int32_t n_trial, const int32_t* candidates,
+                                  int32_t n_candidates, int32_t* chosen);
+/* Stream index of each context (HOST int32[n_ctx]), graph launches so far, nodes of the
+ * last captured graph and the number of captures (any pointer may be NULL). */
+wamct_status wamct_batch_stats(wamct_batch* batch, int32_t* stream_of_ctx, int64_t* graph_launches,
+                               int64_t* graph_nodes, int64_t* captures);
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,9 @@ SYMBOLS = (
     "wamct_iterate", "wamct_expand", "wamct_solve", "wamct_synthesize", "wamct_project",
     "wamct_backproject", "wamct_backproject_split", "wamct_forward", "wamct_idiv", "wamct_get_b",
     "wamct_tree_stats", "wamct_timing", "wamct_get_timing", "wamct_loss", "wamct_loss_backward",
+    "wamct_set_tiling", "wamct_get_tiling", "wamct_batch_create", "wamct_batch_destroy",
+    "wamct_batch_last_error", "wamct_batch_reset", "wamct_batch_solve", "wamct_batch_autotune",
+    "wamct_batch_stats",
 )
 
 
@@ -35,7 +38,8 @@ class Geometry(ctypes.Structure):
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("levels", ctypes.c_int32), ("dtype", ctypes.c_int32), ("geometry", ctypes.c_int32)]
+    _fields_ = [("levels", ctypes.c_int32), ("dtype", ctypes.c_int32), ("geometry", ctypes.c_int32),
+                ("batch", ctypes.c_int32)]
 
 
 class WamctError(RuntimeError):
@@ -58,7 +62,7 @@ def _load():
         "wamct_create": (P(Geometry), P(Options), vp, P(vp)),
         "wamct_destroy": (vp,),
         "wamct_set_stream": (vp, vp),
-        "wamct_set_data": (vp, vp, vp, f64),
+        "wamct_set_data": (vp, vp, vp, P(f64)),
         "wamct_reset": (vp,),
         "wamct_set_state": (vp, vp, vp),
         "wamct_get_state": (vp, vp, vp, P(i32)),
@@ -77,6 +81,14 @@ def _load():
         "wamct_get_timing": (vp, P(f64), P(i64)),
         "wamct_loss": (vp, i32, vp, vp, vp, f64, vp, vp),
         "wamct_loss_backward": (vp, i32, vp, vp, vp, vp),
+        "wamct_set_tiling": (vp, i32),
+        "wamct_get_tiling": (vp, P(i32)),
+        "wamct_batch_create": (i32, P(vp), i32, i32, vp, P(vp)),
+        "wamct_batch_destroy": (vp,),
+        "wamct_batch_reset": (vp,),
+        "wamct_batch_solve": (vp, i32, P(i32), i32, f64, P(vp)),
+        "wamct_batch_autotune": (vp, i32, P(i32), i32, P(i32)),
+        "wamct_batch_stats": (vp, P(i32), P(i64), P(i64), P(i64)),
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -86,6 +98,8 @@ def _load():
     lib.wamct_last_error.restype = ctypes.c_char_p
     lib.wamct_version.argtypes = []
     lib.wamct_version.restype = ctypes.c_char_p
+    lib.wamct_batch_last_error.argtypes = [vp]
+    lib.wamct_batch_last_error.restype = ctypes.c_char_p
     return lib
 
 
@@ -95,4 +109,10 @@ lib = _load()
 def check(status, ctx=None):
     if status != OK:
         msg = lib.wamct_last_error(ctx)
+        raise WamctError(status, msg.decode() if msg else "")
+
+
+def check_batch(status, batch=None):
+    if status != OK:
+        msg = lib.wamct_batch_last_error(batch)
         raise WamctError(status, msg.decode() if msg else "")

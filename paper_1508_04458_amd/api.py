@@ -1,4 +1,5 @@
-"""Python face of the C ABI: a reconstruction context holding one scan on one GPU.
+"""Python face of the C ABI: reconstruction contexts (a stack of scans of one geometry on
+one GPU) and batches of contexts of different geometries.
 
 Every method marshals torch tensors (device memory and the current stream) into the
 matching `wamct_*` call; all arithmetic runs in the HIP kernels of libwamct.so."""
@@ -18,15 +19,15 @@ def _geometry(g) -> _lib.Geometry:
                          float(g.angle_span), int(g.n_bins), float(g.bin_pitch), float(g.sod), float(g.sdd))
 
 
-def _options(levels, dtype, geometry):
+def _options(levels, dtype, geometry, batch=1):
     return _lib.Options(int(levels), _DT[dtype][0] if dtype in _DT else 99,
-                        _DT[geometry][0] if geometry in _DT else 99)
+                        _DT[geometry][0] if geometry in _DT else 99, int(batch))
 
 
-def validate(g, levels: int, dtype: str = "f32", geometry: str = "f64") -> Optional[str]:
+def validate(g, levels: int, dtype: str = "f32", geometry: str = "f64", batch: int = 1) -> Optional[str]:
     """Host-only check of geometry and options; returns None when valid, else the message."""
     buf = ctypes.create_string_buffer(512)
-    opt = _options(levels, dtype, geometry)
+    opt = _options(levels, dtype, geometry, batch)
     st = lib.wamct_validate(ctypes.byref(_geometry(g)), ctypes.byref(opt), buf, 512)
     return None if st == _lib.OK else buf.value.decode()
 
@@ -36,9 +37,12 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 class Context:
-    """One scan (geometry, counts, I0) and the state of Algorithm 1 (beta, tree)."""
+    """A stack of `batch` scans of one geometry (counts, I0 each) and the state of
+    Algorithm 1 (beta, tree) of every scan, solved in lockstep. With batch = 1 the
+    per-scan leading dimension is left out of every returned tensor."""
 
-    def __init__(self, geom, levels: int, dtype: str = "f32", device="cuda", geometry: str = "f64"):
+    def __init__(self, geom, levels: int, dtype: str = "f32", device="cuda", geometry: str = "f64",
+                 batch: int = 1):
         if dtype not in _DT:
             raise ValueError("dtype must be 'f32' or 'f64'")
         self.geom = geom
@@ -52,10 +56,11 @@ class Context:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.n = int(geom.n)
         self.n_rays = int(geom.n_views) * int(geom.n_bins)
+        self.S = int(batch)
         self._h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
-            opt = _options(self.levels, dtype, geometry)
+            opt = _options(self.levels, dtype, geometry, self.S)
             check(lib.wamct_create(ctypes.byref(_geometry(geom)), ctypes.byref(opt),
                                    ctypes.c_void_p(stream), ctypes.byref(self._h)))
 
@@ -82,30 +87,42 @@ class Context:
             raise ValueError(f"{name}: expected a contiguous {dtype} tensor of {numel} elements on {self.device}")
         return t
 
+    def _shape(self, *dims):
+        return dims if self.S == 1 else (self.S, *dims)
+
     def _new(self, numel: int, dtype=None, shape=None):
         t = torch.empty(numel, dtype=dtype or self.dtype, device=self.device)
         return t if shape is None else t.view(*shape)
 
+    def _per_scan(self, values):
+        return values[0] if self.S == 1 else list(values)
+
     # ------------------------------------------------------------------ data and state
     def set_data(self, d: torch.Tensor, i0) -> None:
-        self._arr(d, self.n_rays, "d")
+        """d: [S, n_rays] counts; i0: a tensor of the same shape, one number for every scan,
+        or a sequence of S numbers."""
+        self._arr(d, self.S * self.n_rays, "d")
         if isinstance(i0, torch.Tensor):
-            self._arr(i0, self.n_rays, "i0")
-            self._call(lib.wamct_set_data, _ptr(d), _ptr(i0), 0.0)
-        else:
-            self._call(lib.wamct_set_data, _ptr(d), None, float(i0))
+            self._arr(i0, self.S * self.n_rays, "i0")
+            self._call(lib.wamct_set_data, _ptr(d), _ptr(i0), None)
+            return
+        vals = [float(v) for v in i0] if isinstance(i0, (list, tuple)) else [float(i0)] * self.S
+        if len(vals) != self.S:
+            raise ValueError(f"expected {self.S} scalar I0 values")
+        self._call(lib.wamct_set_data, _ptr(d), None, (ctypes.c_double * self.S)(*vals))
 
     def reset(self) -> None:
         self._call(lib.wamct_reset)
 
     def set_state(self, beta: torch.Tensor, mask: torch.Tensor) -> None:
-        self._arr(beta, self.n * self.n, "beta")
-        self._arr(mask, self.n * self.n, "mask", torch.uint8)
+        self._arr(beta, self.S * self.n * self.n, "beta")
+        self._arr(mask, self.S * self.n * self.n, "mask", torch.uint8)
         self._call(lib.wamct_set_state, _ptr(beta), _ptr(mask))
 
     def get_state(self):
-        beta = self._new(self.n * self.n, shape=(self.n, self.n))
-        mask = self._new(self.n * self.n, torch.uint8, (self.n, self.n))
+        nn = self.S * self.n * self.n
+        beta = self._new(nn, shape=self._shape(self.n, self.n))
+        mask = self._new(nn, torch.uint8, self._shape(self.n, self.n))
         it = ctypes.c_int32()
         self._call(lib.wamct_get_state, _ptr(beta), _ptr(mask), ctypes.byref(it))
         return beta, mask, it.value
@@ -113,27 +130,35 @@ class Context:
     # ------------------------------------------------------------------ Algorithm 1
     def iterate(self, n_iters: int, idiv: Optional[torch.Tensor] = None) -> Optional[torch.Tensor]:
         if idiv is not None:
-            self._arr(idiv, n_iters, "idiv", torch.float64)
+            self._arr(idiv, self.S * n_iters, "idiv", torch.float64)
         self._call(lib.wamct_iterate, int(n_iters), _ptr(idiv))
         return idiv
 
-    def expand(self, frac: float = 0.1) -> int:
-        ns = ctypes.c_int32()
-        self._call(lib.wamct_expand, float(frac), ctypes.byref(ns))
-        return ns.value
+    def expand(self, frac: float = 0.1):
+        ns = (ctypes.c_int32 * self.S)()
+        self._call(lib.wamct_expand, float(frac), ns)
+        return self._per_scan(ns)
 
     def solve(self, n_iters: int, schedule: Sequence[int] = (), frac: float = 0.1,
               idiv: Optional[torch.Tensor] = None) -> torch.Tensor:
         if idiv is None:
-            idiv = self._new(n_iters + 1, torch.float64)
-        self._arr(idiv, n_iters + 1, "idiv", torch.float64)
+            idiv = self._new(self.S * (n_iters + 1), torch.float64, self._shape(n_iters + 1))
+        self._arr(idiv, self.S * (n_iters + 1), "idiv", torch.float64)
         sched = (ctypes.c_int32 * max(1, len(schedule)))(*[int(s) for s in schedule])
         self._call(lib.wamct_solve, int(n_iters), sched, len(schedule), float(frac), _ptr(idiv))
         return idiv
 
+    def set_tiling(self, lanes: int) -> None:
+        self._call(lib.wamct_set_tiling, int(lanes))
+
+    def tiling(self) -> int:
+        v = ctypes.c_int32()
+        self._call(lib.wamct_get_tiling, ctypes.byref(v))
+        return v.value
+
     # ------------------------------------------------------------------ operators
     def synthesize(self) -> torch.Tensor:
-        mu = self._new(self.n * self.n, shape=(self.n, self.n))
+        mu = self._new(self.S * self.n * self.n, shape=self._shape(self.n, self.n))
         self._call(lib.wamct_synthesize, _ptr(mu))
         return mu
 
@@ -150,33 +175,36 @@ class Context:
         return img
 
     def backproject_split(self, y: torch.Tensor):
-        self._arr(y, self.n_rays, "y")
-        bp = self._new(self.n * self.n, shape=(self.n, self.n))
-        bm = self._new(self.n * self.n, shape=(self.n, self.n))
+        self._arr(y, self.S * self.n_rays, "y")
+        bp = self._new(self.S * self.n * self.n, shape=self._shape(self.n, self.n))
+        bm = self._new(self.S * self.n * self.n, shape=self._shape(self.n, self.n))
         self._call(lib.wamct_backproject_split, _ptr(y), _ptr(bp), _ptr(bm))
         return bp, bm
 
     def forward(self):
-        q = self._new(self.n_rays)
-        idiv = self._new(1, torch.float64)
+        q = self._new(self.S * self.n_rays, shape=self._shape(self.n_rays))
+        idiv = self._new(self.S, torch.float64)
         self._call(lib.wamct_forward, _ptr(q), _ptr(idiv))
         return q, idiv
 
     def idiv(self, q: torch.Tensor) -> torch.Tensor:
-        self._arr(q, self.n_rays, "q")
-        out = self._new(1, torch.float64)
+        self._arr(q, self.S * self.n_rays, "q")
+        out = self._new(self.S, torch.float64)
         self._call(lib.wamct_idiv, _ptr(q), _ptr(out))
         return out
 
     def b(self) -> torch.Tensor:
-        out = self._new(self.n * self.n, shape=(self.n, self.n))
+        out = self._new(self.S * self.n * self.n, shape=self._shape(self.n, self.n))
         self._call(lib.wamct_get_b, _ptr(out))
         return out
 
     def tree_stats(self) -> Dict[str, float]:
-        z0, w, na, nh = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-        self._call(lib.wamct_tree_stats, ctypes.byref(z0), ctypes.byref(w), ctypes.byref(na), ctypes.byref(nh))
-        return dict(z0=z0.value, w=w.value, n_active=na.value, n_held=nh.value)
+        """Per scan: Z0, W, active coefficients, held updates (lists when S > 1)."""
+        z0, w = (ctypes.c_double * self.S)(), (ctypes.c_int64 * self.S)()
+        na, nh = (ctypes.c_int64 * self.S)(), (ctypes.c_int64 * self.S)()
+        self._call(lib.wamct_tree_stats, z0, w, na, nh)
+        return dict(z0=self._per_scan(z0), w=self._per_scan(w), n_active=self._per_scan(na),
+                    n_held=self._per_scan(nh))
 
     # ------------------------------------------------------------------ differentiable loss
     def loss(self, c: torch.Tensor, d: torch.Tensor, i0):
@@ -215,3 +243,68 @@ class Context:
         cnt = (ctypes.c_int64 * _lib.NK)()
         self._call(lib.wamct_get_timing, ms, cnt)
         return {k: dict(ms=ms[i], launches=cnt[i]) for i, k in enumerate(_lib.KERNEL_CLASSES)}
+
+
+class Batch:
+    """Contexts of different geometries solved together: one iteration of all of them is
+    captured into a HIP graph (graph=True) and replayed between tree expansions, the
+    contexts spread over `n_streams` streams. The contexts must outlive the batch."""
+
+    def __init__(self, contexts: Sequence[Context], n_streams: int = 4, graph: bool = True):
+        self.contexts = list(contexts)
+        if not self.contexts:
+            raise ValueError("a batch needs at least one context")
+        dev = self.contexts[0].device
+        if any(c.device != dev for c in self.contexts):
+            raise ValueError("all contexts of a batch must be on one device")
+        self.device = dev
+        self._h = ctypes.c_void_p()
+        handles = (ctypes.c_void_p * len(self.contexts))(*[c._h.value for c in self.contexts])
+        with torch.cuda.device(dev):
+            stream = torch.cuda.current_stream(dev).cuda_stream
+            _lib.check_batch(lib.wamct_batch_create(len(self.contexts), handles, int(n_streams),
+                                                    1 if graph else 0, ctypes.c_void_p(stream),
+                                                    ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib.wamct_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, fn, *args):
+        _lib.check_batch(fn(self._h, *args), self._h)
+
+    def reset(self) -> None:
+        self._call(lib.wamct_batch_reset)
+
+    def solve(self, n_iters: int, schedule: Sequence[int] = (), frac: float = 0.1):
+        """Returns the I-divergence traces, one tensor per context ([S, n_iters + 1], or
+        [n_iters + 1] for a single-scan context)."""
+        out = [c._new(c.S * (n_iters + 1), torch.float64, c._shape(n_iters + 1)) for c in self.contexts]
+        ptrs = (ctypes.c_void_p * len(out))(*[t.data_ptr() for t in out])
+        sched = (ctypes.c_int32 * max(1, len(schedule)))(*[int(s) for s in schedule])
+        self._call(lib.wamct_batch_solve, int(n_iters), sched, len(schedule), float(frac), ptrs)
+        return out
+
+    def autotune(self, n_trial: int = 2, candidates: Optional[Sequence[int]] = None):
+        """Backprojection tiling per context, chosen by timing; returns the choices."""
+        chosen = (ctypes.c_int32 * len(self.contexts))()
+        if candidates is None:
+            self._call(lib.wamct_batch_autotune, int(n_trial), None, 0, chosen)
+        else:
+            cand = (ctypes.c_int32 * len(candidates))(*[int(c) for c in candidates])
+            self._call(lib.wamct_batch_autotune, int(n_trial), cand, len(candidates), chosen)
+        return list(chosen)
+
+    def stats(self) -> Dict[str, object]:
+        lanes = (ctypes.c_int32 * len(self.contexts))()
+        gl, gn, cap = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._call(lib.wamct_batch_stats, lanes, ctypes.byref(gl), ctypes.byref(gn), ctypes.byref(cap))
+        return dict(stream_of_context=list(lanes), graph_launches=gl.value, graph_nodes=gn.value,
+                    captures=cap.value)

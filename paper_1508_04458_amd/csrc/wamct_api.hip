@@ -1,6 +1,9 @@
 // C ABI of wavelet-tree AM (include/wamct.h): validation, buffers, and the order of
 // kernel launches for Algorithm 1 and the tree rule (arXiv 1508.04458, Introduction and
-// Results). Device memory is allocated only in wamct_create; iterating allocates nothing.
+// Results). Device memory is allocated only in wamct_create (and when a larger gather
+// tiling is requested); iterating allocates nothing. A context holds a stack of scans of
+// one geometry, solved in lockstep; a batch runs several contexts concurrently, one
+// iteration of all of them captured in a HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -51,6 +54,7 @@ std::string validate(const wamct_geometry* g, const wamct_options* o) {
   if (o->dtype != WAMCT_F32 && o->dtype != WAMCT_F64) return fmt("unknown dtype %d", o->dtype);
   if (o->geometry != WAMCT_F32 && o->geometry != WAMCT_F64) return fmt("unknown geometry precision %d", o->geometry);
   if (o->geometry == WAMCT_F32 && o->dtype == WAMCT_F64) return "geometry precision must be at least dtype";
+  if (o->batch < 1 || o->batch > 65535) return fmt("batch = %d outside [1, 65535]", o->batch);
   return "";
 }
 }  // namespace
@@ -60,12 +64,13 @@ struct wamct_ctx {
   virtual ~wamct_ctx() {}
   virtual wamct_status init(const wamct_geometry&, const wamct_options&, hipStream_t) = 0;
   virtual wamct_status set_stream(hipStream_t) = 0;
-  virtual wamct_status set_data(const void*, const void*, double) = 0;
+  virtual wamct_status set_data(const void*, const void*, const double*) = 0;
   virtual wamct_status reset() = 0;
   virtual wamct_status set_state(const void*, const uint8_t*) = 0;
   virtual wamct_status get_state(void*, uint8_t*, int32_t*) = 0;
   virtual wamct_status iterate(int32_t, double*) = 0;
   virtual wamct_status expand_tree(double, int32_t*) = 0;
+  virtual wamct_status solve(int32_t, const int32_t*, int32_t, double, double*) = 0;
   virtual wamct_status synthesize(void*) = 0;
   virtual wamct_status project(const void*, void*) = 0;
   virtual wamct_status backproject(const void*, void*) = 0;
@@ -78,6 +83,24 @@ struct wamct_ctx {
   virtual wamct_status loss_backward(int32_t, const void*, const void*, const double*, void*) = 0;
   virtual wamct_status timing(int32_t) = 0;
   virtual wamct_status get_timing(double*, int64_t*) = 0;
+  virtual wamct_status set_tiling(int32_t) = 0;
+  virtual int32_t tiling() const = 0;
+  // stream-ordered pieces used by batches (no host synchronization inside)
+  virtual int n_scans() const = 0;
+  virtual hipStream_t stream() const = 0;
+  virtual double work() const = 0;
+  virtual bool has_data_() const = 0;
+  virtual bool tree_dirty_() const = 0;
+  virtual wamct_status enq_tree(hipStream_t) = 0;
+  virtual wamct_status finish_tree(int32_t*) = 0;
+  virtual wamct_status enq_reset(hipStream_t) = 0;
+  virtual wamct_status enq_expand(hipStream_t, double) = 0;
+  virtual wamct_status enq_begin(hipStream_t) = 0;
+  virtual wamct_status enq_iteration(hipStream_t, double*, int64_t, bool) = 0;
+  virtual wamct_status enq_final(hipStream_t, double*, int64_t, bool) = 0;
+  virtual wamct_status save_state(hipStream_t) = 0;
+  virtual wamct_status restore_state(hipStream_t) = 0;
+  virtual void count_iters(int) = 0;
   wamct_status fail(wamct_status s, const std::string& m) {
     err = m;
     return s;
@@ -95,6 +118,11 @@ struct wamct_ctx {
     hipError_t e_ = hipGetLastError();                                                 \
     if (e_ != hipSuccess) return fail(WAMCT_E_HIP, fmt("kernel launch: %s", hipGetErrorString(e_))); \
   } while (0)
+#define CHECKED(expr)                                                                  \
+  do {                                                                                 \
+    wamct_status r_ = (expr);                                                          \
+    if (r_ != WAMCT_OK) return r_;                                                     \
+  } while (0)
 
 namespace {
 
@@ -102,28 +130,37 @@ template <typename T, typename R>
 struct Ctx final : wamct_ctx {
   DevGeom g{};
   hipStream_t st = nullptr;
-  int64_t M = 0, NN = 0;
-  int max_items = 0, nb_rays = 0, nb_pix = 0;
-  // device buffers
-  double2* views = nullptr;
-  void* vT = nullptr;
-  void* A = nullptr;
+  int P = 1;                  // scans in the stack
+  int64_t M = 0, NN = 0;      // rays and pixels per scan
+  int nb_rays = 0, nb_pix = 0, np = 0;
+  // device buffers ([P][...] per scan unless noted)
+  double2* views = nullptr;   // shared
+  void* vT = nullptr;         // shared
+  void* A = nullptr;          // shared ray table
   void* B = nullptr;
   T *d = nullptr, *i0v = nullptr, *q = nullptr;
-  T *beta = nullptr, *b = nullptr, *mu = nullptr, *muT = nullptr, *img = nullptr;
+  T *beta = nullptr, *b = nullptr, *mu = nullptr, *muT = nullptr;
+  T* img = nullptr;           // one image (operators, precompute)
   void *leafR = nullptr, *leafC = nullptr;  // leaf records (value, level) for the tree walk
   uint8_t *mask = nullptr, *mask_old = nullptr, *lev = nullptr;
   uint32_t* items = nullptr;
-  double *partd = nullptr, *part2 = nullptr, *mu64 = nullptr, *scal = nullptr;  // scal: [0]=z0 [1]=w [2]=max [3]=tmp
-  int* ints = nullptr;  // [0]=held [1]=bad [2]=n_split; [8] = item count, [9 + k] = items of level L - k
-  void* part = nullptr;  // chunked gather partial sums
+  double *partd = nullptr, *part2 = nullptr, *mu64 = nullptr;
+  double* scal = nullptr;     // [P][kScal]
+  int* ints = nullptr;        // [P][kInts]
+  double* i0one = nullptr;    // scalar I0 of the loss path
+  T* beta_save = nullptr;     // tiling trials
+  int* ints_save = nullptr;
+  int32_t iters_save = 0;
+  void* part = nullptr;       // chunked gather partial sums
+  int64_t part_cap = 0;       // elements of R
+  int* h_ints = nullptr;      // pinned host copies read after a tree rebuild
+  double* h_scal = nullptr;
   std::vector<Segment> segs, pix_segs;
   std::vector<void*> allocs;
   // host state
-  double i0s = 1.0;
-  bool has_data = false, tree_dirty = true;
-  int n_items = 0;
+  bool has_data = false, tree_dirty = true, i0v_used = false;
   int32_t iters = 0;
+  int target_lanes = kTargetLanes;
   // timing
   bool timing_on = false;
   struct Rec { int kind; hipEvent_t a, b; };
@@ -134,16 +171,28 @@ struct Ctx final : wamct_ctx {
 
   ~Ctx() override {
     if (st) hipStreamSynchronize(st);
+    hipDeviceSynchronize();
     for (auto& r : recs) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
     for (auto e : pool) hipEventDestroy(e);
     for (void* p : allocs) hipFree(p);
+    if (part) hipFree(part);
+    if (h_ints) hipHostFree(h_ints);
+    if (h_scal) hipHostFree(h_scal);
   }
 
-  template <typename P>
-  wamct_status alloc(P*& p, int64_t count) {
+  int n_scans() const override { return P; }
+  hipStream_t stream() const override { return st; }
+  double work() const override { return double(P) * double(M) * double(g.n); }
+  bool has_data_() const override { return has_data; }
+  bool tree_dirty_() const override { return tree_dirty; }
+  int32_t tiling() const override { return target_lanes; }
+  void count_iters(int k) override { iters += k; }
+
+  template <typename Q>
+  wamct_status alloc(Q*& p, int64_t count) {
     void* v = nullptr;
-    wamct_status r = alloc_bytes(v, size_t(count > 0 ? count : 1) * sizeof(P));
-    p = static_cast<P*>(v);
+    wamct_status r = alloc_bytes(v, size_t(count > 0 ? count : 1) * sizeof(Q));
+    p = static_cast<Q*>(v);
     return r;
   }
   wamct_status alloc_bytes(void*& v, size_t bytes) {
@@ -172,26 +221,31 @@ struct Ctx final : wamct_ctx {
     }
     recs.clear();
   }
+  // Records the kernels of its lifetime under `kind` when timing is on and the work runs on
+  // the context's own stream (batch streams are not timed per kernel class).
   struct Scope {
-    Ctx* c; int kind; hipEvent_t a = nullptr;
-    Scope(Ctx* c_, int k) : c(c_), kind(k) {
-      if (c->timing_on) { a = c->ev(); hipEventRecord(a, c->st); }
+    Ctx* c; int kind; hipStream_t s; hipEvent_t a = nullptr;
+    Scope(Ctx* c_, int k, hipStream_t s_) : c(c_), kind(k), s(s_) {
+      if (c->timing_on && s == c->st) { a = c->ev(); hipEventRecord(a, s); }
     }
     ~Scope() {
       if (a) {
         hipEvent_t b = c->ev();
-        hipEventRecord(b, c->st);
+        hipEventRecord(b, s);
         c->recs.push_back({kind, a, b});
         if (c->recs.size() > 4096) { hipEventSynchronize(b); c->harvest(); }
       }
     }
   };
 
-  // Split the views of a level segment into chunks when its items alone cannot fill the GPU.
-  Segment make_segment(int start, int count, int level) const {
-    Segment sg{start, count, level, 1, g.nv};
-    if (count < kTargetLanes) {
-      int chunks = std::min(g.nv, (kTargetLanes + count - 1) / count);
+  // ---------------------------------------------------------------- tiling of the gather
+  // Split the views of a level segment into chunks when its items (over the S scans of
+  // one launch) alone cannot fill the GPU.
+  Segment make_segment(int kseg, int start, int count, int level, int S) const {
+    Segment sg{kseg, start, count, level, 1, g.nv};
+    const int64_t lanes = int64_t(count) * S;
+    if (count > 0 && lanes < target_lanes) {
+      int chunks = int(std::min<int64_t>(g.nv, (target_lanes + lanes - 1) / lanes));
       const int vpc = (g.nv + chunks - 1) / chunks;
       chunks = (g.nv + vpc - 1) / vpc;
       sg.chunks = chunks;
@@ -199,34 +253,97 @@ struct Ctx final : wamct_ctx {
     }
     return sg;
   }
+  // Partial sums any segment can need at a given target: 7 (target / 4 + lanes) with
+  // lanes = count * S < target (chunk groups of four waves, rounded up).
+  int64_t part_need(int target) const {
+    return 7 * (int64_t(target) / 4 + 1 + std::min<int64_t>(int64_t(P) * NN, target));
+  }
+  wamct_status ensure_part(int target) {
+    const int64_t need = part_need(target);
+    if (need <= part_cap) return WAMCT_OK;
+    if (part) {
+      HIPCHK(hipDeviceSynchronize());
+      HIPCHK(hipFree(part));
+      part = nullptr;
+      part_cap = 0;
+    }
+    hipError_t e = hipMalloc(&part, size_t(need) * sizeof(R));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      part = nullptr;
+      return fail(WAMCT_E_OOM, fmt("hipMalloc(%zu bytes): %s", size_t(need) * sizeof(R), hipGetErrorString(e)));
+    }
+    part_cap = need;
+    return WAMCT_OK;
+  }
+  void build_segs() {
+    segs.clear();
+    const int n_levels = g.L == 0 ? 1 : g.L;
+    for (int k = 0; k < n_levels; ++k) {
+      int mx = 0;
+      for (int p = 0; p < P; ++p) mx = std::max(mx, h_ints[p * kInts + 9 + k]);
+      if (mx > 0) segs.push_back(make_segment(k, 0, mx, g.L - k, P));
+    }
+    pix_segs = {make_segment(-1, 0, int(NN), 0, 1)};
+  }
+  wamct_status set_tiling(int32_t t) override {
+    if (t < kMinTargetLanes || t > kMaxTargetLanes)
+      return fail(WAMCT_E_INVALID, fmt("tiling %d outside [%d, %d]", t, kMinTargetLanes, kMaxTargetLanes));
+    HIPCHK(hipStreamSynchronize(st));
+    CHECKED(ensure_part(t));
+    target_lanes = t;
+    if (!tree_dirty) build_segs();
+    else pix_segs = {make_segment(-1, 0, int(NN), 0, 1)};
+    return WAMCT_OK;
+  }
+  // gather over segments with a host check that their partial sums fit
+  wamct_status gather(int mode, const T* y, const std::vector<Segment>& sg, int S, T* bt, int* held, T* bp, T* bm,
+                      T* out, hipStream_t s) {
+    for (const Segment& x : sg)
+      if (segment_part_elems(x, S) > part_cap)
+        return fail(WAMCT_E_HIP, "internal: gather partial buffer too small for its tiling");
+    const bool tree = &sg == &segs;
+    Geo<T, R>::gather(g, mode, vT, A, y, tree ? items : nullptr, tree ? ints + 9 : nullptr, sg.data(),
+                      int(sg.size()), part, bt, b, scal + 0, held, bp, bm, out, S, s);
+    return WAMCT_OK;
+  }
 
   // ---------------------------------------------------------------- setup
   wamct_status init(const wamct_geometry& G, const wamct_options& O, hipStream_t s) override {
     st = s;
+    P = O.batch;
     g.kind = G.kind; g.n = G.n; g.nv = G.n_views; g.nb = G.n_bins; g.L = O.levels;
     g.pixel = G.pixel; g.pitch = G.bin_pitch; g.sod = G.sod; g.sdd = G.sdd;
     M = int64_t(g.nv) * g.nb;
     NN = int64_t(g.n) * g.n;
     nb_rays = int((M + 255) / 256);
     nb_pix = int((NN + 255) / 256);
-    max_items = int(NN);
-    wamct_status r;
-    if ((r = alloc(views, g.nv))) return r;
-    if ((r = alloc_bytes(vT, sizeof(float) * 2 * size_t(g.nv)))) return r;
-    if ((r = alloc_bytes(A, sizeof(R) * 4 * size_t(M))) || (r = alloc_bytes(B, sizeof(R) * 4 * size_t(M)))) return r;
-    if ((r = alloc(d, M)) || (r = alloc(i0v, M)) || (r = alloc(q, M))) return r;
-    if ((r = alloc(beta, NN)) || (r = alloc(b, NN)) || (r = alloc(mu, NN)) || (r = alloc(img, NN))) return r;
-    if ((r = alloc(muT, NN))) return r;
-    if (g.L > 0 && ((r = alloc_bytes(leafR, 2 * sizeof(T) * size_t(NN))) ||
-                    (r = alloc_bytes(leafC, 2 * sizeof(T) * size_t(NN)))))
-      return r;
-    if ((r = alloc(mask, NN)) || (r = alloc(mask_old, NN)) || (r = alloc(lev, NN))) return r;
-    if ((r = alloc(items, max_items)) || (r = alloc(mu64, NN))) return r;
-    const int np = std::max(nb_rays, nb_pix) + 1;
-    if ((r = alloc(partd, np)) || (r = alloc(part2, np)) || (r = alloc(scal, 8)) || (r = alloc(ints, 32))) return r;
-    if ((r = alloc_bytes(part, sizeof(R) * 7 * 2 * size_t(kTargetLanes)))) return r;
-    pix_segs = {make_segment(0, int(NN), 0)};
-    i0v_used = false;
+    np = std::max(nb_rays, nb_pix) + 1;
+    if (hipHostMalloc((void**)&h_ints, sizeof(int) * kInts * P, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h_scal, sizeof(double) * kScal * P, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(WAMCT_E_OOM, "hipHostMalloc of the readback buffers failed");
+    }
+    std::memset(h_ints, 0, sizeof(int) * kInts * P);
+    std::memset(h_scal, 0, sizeof(double) * kScal * P);
+    CHECKED(alloc(views, g.nv));
+    CHECKED(alloc_bytes(vT, sizeof(float) * 2 * size_t(g.nv)));
+    CHECKED(alloc_bytes(A, sizeof(R) * 4 * size_t(M)));
+    CHECKED(alloc_bytes(B, sizeof(R) * 4 * size_t(M)));
+    CHECKED(alloc(d, M * P)); CHECKED(alloc(i0v, M * P)); CHECKED(alloc(q, M * P));
+    CHECKED(alloc(beta, NN * P)); CHECKED(alloc(b, NN * P));
+    CHECKED(alloc(mu, NN * P)); CHECKED(alloc(muT, NN * P)); CHECKED(alloc(img, NN));
+    if (g.L > 0) {
+      CHECKED(alloc_bytes(leafR, 2 * sizeof(T) * size_t(NN * P)));
+      CHECKED(alloc_bytes(leafC, 2 * sizeof(T) * size_t(NN * P)));
+    }
+    CHECKED(alloc(mask, NN * P)); CHECKED(alloc(mask_old, NN * P)); CHECKED(alloc(lev, NN * P));
+    CHECKED(alloc(items, NN * P)); CHECKED(alloc(mu64, NN * P));
+    CHECKED(alloc(partd, int64_t(np) * P)); CHECKED(alloc(part2, int64_t(np) * P));
+    CHECKED(alloc(scal, int64_t(kScal) * P)); CHECKED(alloc(ints, int64_t(kInts) * P));
+    CHECKED(alloc(i0one, 1));
+    CHECKED(ensure_part(target_lanes));
+    pix_segs = {make_segment(-1, 0, int(NN), 0, 1)};
     std::vector<double2> hv(g.nv);
     for (int v = 0; v < g.nv; ++v) {
       const double a = G.angle0 + v * (G.angle_span / G.n_views);
@@ -235,13 +352,13 @@ struct Ctx final : wamct_ctx {
     HIPCHK(hipMemcpyAsync(views, hv.data(), sizeof(double2) * g.nv, hipMemcpyHostToDevice, st));
     Geo<T, R>::view_table(g, views, vT, st);
     Geo<T, R>::ray_table(g, views, A, B, st);
-    fill_i32(ints, 32, 0, st);
-    Launch<T>::fill(q, M, T(0), st);
+    fill_i32(ints, int64_t(kInts) * P, 0, st);
+    Launch<double>::fill(scal, int64_t(kScal) * P, 0.0, st);
+    Launch<T>::fill(q, M * P, T(0), st);
     LAUNCHED();
     HIPCHK(hipStreamSynchronize(st));
     return reset();
   }
-  bool i0v_used = false;
 
   wamct_status set_stream(hipStream_t s) override {
     HIPCHK(hipStreamSynchronize(st));
@@ -249,215 +366,292 @@ struct Ctx final : wamct_ctx {
     return WAMCT_OK;
   }
 
-  wamct_status set_data(const void* dd, const void* ii, double i0) override {
+  wamct_status set_data(const void* dd, const void* ii, const double* i0h) override {
     if (!dd) return fail(WAMCT_E_INVALID, "d must not be NULL");
-    if (!ii && !(i0 > 0 && std::isfinite(i0))) return fail(WAMCT_E_INVALID, "scalar I0 must be finite and > 0");
-    HIPCHK(hipMemcpyAsync(d, dd, sizeof(T) * M, hipMemcpyDeviceToDevice, st));
-    if (ii) HIPCHK(hipMemcpyAsync(i0v, ii, sizeof(T) * M, hipMemcpyDeviceToDevice, st));
+    std::vector<double> i0s(P, 1.0);
+    if (!ii) {
+      if (!i0h) return fail(WAMCT_E_INVALID, "scalar I0 values must be given when i0 is NULL");
+      for (int p = 0; p < P; ++p) {
+        if (!(i0h[p] > 0) || !std::isfinite(i0h[p]))
+          return fail(WAMCT_E_INVALID, fmt("scalar I0 of scan %d must be finite and > 0", p));
+        i0s[p] = i0h[p];
+      }
+    }
+    HIPCHK(hipMemcpyAsync(d, dd, sizeof(T) * M * P, hipMemcpyDeviceToDevice, st));
+    if (ii) HIPCHK(hipMemcpyAsync(i0v, ii, sizeof(T) * M * P, hipMemcpyDeviceToDevice, st));
+    for (int p = 0; p < P; ++p) h_scal[p * kScal + 4] = i0s[p];
+    HIPCHK(hipMemcpy2DAsync(scal + 4, sizeof(double) * kScal, h_scal + 4, sizeof(double) * kScal, sizeof(double),
+                            P, hipMemcpyHostToDevice, st));
     fill_i32(ints + 1, 1, 0, st);
-    Launch<T>::check(d, M, false, ints + 1, st);
+    Launch<T>::check(d, M * P, false, ints + 1, st);
     int bad_d = 0, bad_i = 0;
-    HIPCHK(hipMemcpyAsync(&bad_d, ints + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_ints + 1, ints + 1, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    bad_d = h_ints[1];
     if (bad_d) return fail(WAMCT_E_INVALID, fmt("%d counts are negative or not finite", bad_d));
     if (ii) {
       fill_i32(ints + 1, 1, 0, st);
-      Launch<T>::check(i0v, M, false, ints + 1, st);
-      HIPCHK(hipMemcpyAsync(&bad_i, ints + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+      Launch<T>::check(i0v, M * P, false, ints + 1, st);
+      HIPCHK(hipMemcpyAsync(h_ints + 1, ints + 1, sizeof(int), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
+      bad_i = h_ints[1];
       if (bad_i) return fail(WAMCT_E_INVALID, fmt("%d I0 values are negative or not finite", bad_i));
     }
     i0v_used = ii != nullptr;
-    i0s = ii ? 1.0 : i0;
-    // eq. 1.6: b = Phi^T d = Omega^T (H^T d) for every coefficient
+    // eq. 1.6: b = Phi^T d = Omega^T (H^T d) for every coefficient of every scan
     {
-      Scope sc(this, WAMCT_K_OTHER);
-      Geo<T, R>::gather(g, kPlain, vT, A, d, nullptr, pix_segs.data(), int(pix_segs.size()), part, nullptr,
-                        nullptr, nullptr, nullptr, nullptr, nullptr, img, st);
-      Launch<T>::analysis(g, img, b, st);
+      Scope sc(this, WAMCT_K_OTHER, st);
+      for (int p = 0; p < P; ++p) {
+        CHECKED(gather(kPlain, d + p * M, pix_segs, 1, nullptr, nullptr, nullptr, nullptr, img, st));
+        Launch<T>::analysis(g, img, b + p * NN, st);
+      }
     }
     LAUNCHED();
     has_data = true;
     return WAMCT_OK;
   }
 
-  wamct_status rebuild_tree() {
+  // ---------------------------------------------------------------- tree (stream-ordered)
+  // Work list, leaf levels, Z0 and W of every scan's tree, then a copy of the per-scan
+  // counters and scalars to pinned host memory (read by finish_tree once s has finished).
+  wamct_status enq_tree(hipStream_t s) override {
     {
-      Scope sc(this, WAMCT_K_TREE);
-      build_items(g, mask, items, ints + 8, st);
-      Launch<T>::levmap(g, mask, lev, st);
-      const int nbk = z0_partials(g, views, lev, partd, part2, st);
-      reduce_max(partd, nbk, scal + 0, st);
-      reduce_sum(part2, nbk, scal + 1, st);
+      Scope sc(this, WAMCT_K_TREE, s);
+      build_items(g, mask, items, ints + 8, P, s);
+      Launch<T>::levmap(g, mask, lev, P, s);
+      const int nbk = z0_partials(g, views, lev, partd, part2, P, s);
+      reduce_stack(true, partd, nbk, nbk, scal + 0, kScal, nullptr, P, s);
+      reduce_stack(false, part2, nbk, nbk, scal + 1, kScal, nullptr, P, s);
     }
     LAUNCHED();
-    int cnt[2 + kMaxLevels] = {0};
-    HIPCHK(hipMemcpyAsync(cnt, ints + 8, sizeof cnt, hipMemcpyDeviceToHost, st));
-    double z0 = 0;
-    HIPCHK(hipMemcpyAsync(&z0, scal + 0, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    n_items = cnt[0];
-    segs.clear();
-    int start = 0;
-    const int n_levels = g.L == 0 ? 1 : g.L;
-    for (int k = 0; k < n_levels; ++k) {
-      const int c = cnt[1 + k];
-      if (c > 0) segs.push_back(make_segment(start, c, g.L - k));
-      start += c;
+    HIPCHK(hipMemcpyAsync(h_ints, ints, sizeof(int) * kInts * P, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h_scal, scal, sizeof(double) * kScal * P, hipMemcpyDeviceToHost, s));
+    tree_dirty = true;
+    return WAMCT_OK;
+  }
+  wamct_status finish_tree(int32_t* n_split) override {
+    build_segs();
+    for (int p = 0; p < P; ++p) {
+      const double z0 = h_scal[p * kScal + 0];
+      if (!(z0 > 0) || !std::isfinite(z0))
+        return fail(WAMCT_E_INVALID, fmt("Z0 = 0 in scan %d: no ray crosses the image", p));
+      if (n_split) n_split[p] = h_ints[p * kInts + 2];
     }
-    if (!(z0 > 0) || !std::isfinite(z0)) return fail(WAMCT_E_INVALID, "Z0 = 0: no ray crosses the image");
     tree_dirty = false;
     return WAMCT_OK;
   }
+  wamct_status rebuild_tree() {
+    CHECKED(enq_tree(st));
+    HIPCHK(hipStreamSynchronize(st));
+    return finish_tree(nullptr);
+  }
 
-  wamct_status reset() override {
-    Launch<T>::fill(beta, NN, T(0), st);
-    approx_mask(g, mask, st);
-    fill_i32(ints, 1, 0, st);
+  wamct_status enq_reset(hipStream_t s) override {
+    Launch<T>::fill(beta, NN * P, T(0), s);
+    approx_mask(g, mask, P, s);
+    fill_i32_strided(ints + 0, P, kInts, 0, s);
+    fill_i32_strided(ints + 2, P, kInts, 0, s);
     LAUNCHED();
     iters = 0;
-    tree_dirty = true;
-    return rebuild_tree();
+    return enq_tree(s);
+  }
+  wamct_status reset() override {
+    CHECKED(enq_reset(st));
+    HIPCHK(hipStreamSynchronize(st));
+    return finish_tree(nullptr);
   }
 
   wamct_status set_state(const void* bt, const uint8_t* mk) override {
     if (!bt || !mk) return fail(WAMCT_E_INVALID, "beta and mask must not be NULL");
-    HIPCHK(hipMemcpyAsync(mask_old, mk, NN, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(mask_old, mk, NN * P, hipMemcpyDeviceToDevice, st));
     fill_i32(ints + 1, 1, 0, st);
-    check_mask(g, mask_old, ints + 1, st);
-    Launch<T>::check((const T*)bt, NN, true, ints + 1, st);
+    check_mask(g, mask_old, ints + 1, P, st);
+    Launch<T>::check((const T*)bt, NN * P, true, ints + 1, st);
     LAUNCHED();
-    int bad = 0;
-    HIPCHK(hipMemcpyAsync(&bad, ints + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_ints + 1, ints + 1, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    const int bad = h_ints[1];
     if (bad) return fail(WAMCT_E_INVALID, fmt("state rejected: %d invalid tree entries or non-finite coefficients", bad));
-    HIPCHK(hipMemcpyAsync(mask, mask_old, NN, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(beta, bt, sizeof(T) * NN, hipMemcpyDeviceToDevice, st));
-    Launch<T>::apply_mask(g, beta, mask, st);
-    fill_i32(ints, 1, 0, st);
+    HIPCHK(hipMemcpyAsync(mask, mask_old, NN * P, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(beta, bt, sizeof(T) * NN * P, hipMemcpyDeviceToDevice, st));
+    Launch<T>::apply_mask(g, beta, mask, P, st);
+    fill_i32_strided(ints + 0, P, kInts, 0, st);
     LAUNCHED();
     iters = 0;
-    tree_dirty = true;
     return rebuild_tree();
   }
 
   wamct_status get_state(void* bt, uint8_t* mk, int32_t* it) override {
-    if (bt) HIPCHK(hipMemcpyAsync(bt, beta, sizeof(T) * NN, hipMemcpyDeviceToDevice, st));
-    if (mk) HIPCHK(hipMemcpyAsync(mk, mask, NN, hipMemcpyDeviceToDevice, st));
+    if (bt) HIPCHK(hipMemcpyAsync(bt, beta, sizeof(T) * NN * P, hipMemcpyDeviceToDevice, st));
+    if (mk) HIPCHK(hipMemcpyAsync(mk, mask, NN * P, hipMemcpyDeviceToDevice, st));
     if (it) *it = iters;
     return WAMCT_OK;
   }
 
-  // one forward pass of the current state: mu, q-hat and the I-divergence partials
-  int forward_pass() {
-    const bool tree = g.L > 0;
-    if (tree) {
+  // ---------------------------------------------------------------- iteration (stream-ordered)
+  // One forward pass of the current state: mu, q-hat and the I-divergence partials.
+  int forward_pass(hipStream_t s) {
+    const T* iv = i0v_used ? i0v : nullptr;
+    if (g.L > 0) {
       {
-        Scope sc(this, WAMCT_K_SYNTH);
-        Launch<T>::synth_records(g, beta, lev, leafR, leafC, st);
+        Scope sc(this, WAMCT_K_SYNTH, s);
+        Launch<T>::synth_records(g, beta, lev, leafR, leafC, P, s);
       }
-      Scope sc(this, WAMCT_K_FORWARD);
-      return Geo<T, R>::forward_records(g, A, B, leafR, leafC, d, i0v_used ? i0v : nullptr, i0s, q, nullptr, partd,
-                                        st);
+      Scope sc(this, WAMCT_K_FORWARD, s);
+      return Geo<T, R>::forward_records(g, A, B, leafR, leafC, d, iv, scal + 4, q, nullptr, partd, P, s);
     }
     {
-      Scope sc(this, WAMCT_K_SYNTH);
-      Launch<T>::synth_layouts(g, beta, mu, muT, st);
+      Scope sc(this, WAMCT_K_SYNTH, s);
+      Launch<T>::synth_layouts(g, beta, mu, muT, P, s);
     }
-    Scope sc(this, WAMCT_K_FORWARD);
-    return Geo<T, R>::forward(g, A, B, mu, muT, d, i0v_used ? i0v : nullptr, i0s, q, nullptr, partd, st);
+    Scope sc(this, WAMCT_K_FORWARD, s);
+    return Geo<T, R>::forward(g, A, B, mu, muT, d, iv, scal + 4, q, nullptr, partd, P, s);
+  }
+  // I-divergence of scan p -> out[p * ostride] (or out[p * ostride + counter] with the
+  // device counters; out null: the scratch slot)
+  void store_idiv(int nbk, double* out, int64_t ostride, bool counted, hipStream_t s) {
+    Scope sc(this, WAMCT_K_OTHER, s);
+    if (out)
+      reduce_stack(false, partd, nbk, nbk, out, ostride, counted ? ints + 3 : nullptr, P, s);
+    else
+      reduce_stack(false, partd, nbk, nbk, scal + 3, kScal, nullptr, P, s);
+  }
+  wamct_status enq_iteration(hipStream_t s, double* out, int64_t ostride, bool counted) override {
+    const int nbk = forward_pass(s);
+    store_idiv(nbk, out, ostride, counted, s);
+    {
+      Scope sc(this, WAMCT_K_UPDATE, s);
+      CHECKED(gather(kUpdate, q, segs, P, beta, ints + 0, nullptr, nullptr, nullptr, s));
+    }
+    ++iters;
+    LAUNCHED();
+    return WAMCT_OK;
+  }
+  wamct_status enq_final(hipStream_t s, double* out, int64_t ostride, bool counted) override {
+    const int nbk = forward_pass(s);
+    store_idiv(nbk, out, ostride, counted, s);
+    LAUNCHED();
+    return WAMCT_OK;
+  }
+  wamct_status enq_begin(hipStream_t s) override {
+    fill_i32_strided(ints + 3, P, kInts, 0, s);
+    LAUNCHED();
+    return WAMCT_OK;
   }
 
   wamct_status iterate(int32_t n, double* idv) override {
     if (!has_data) return fail(WAMCT_E_STATE, "iterate before set_data");
     if (n < 0) return fail(WAMCT_E_INVALID, "n_iters must be >= 0");
-    if (tree_dirty) { wamct_status r = rebuild_tree(); if (r) return r; }
-    for (int k = 0; k < n; ++k) {
-      const int nbk = forward_pass();
-      {
-        Scope sc(this, WAMCT_K_OTHER);
-        reduce_sum(partd, nbk, idv ? idv + k : scal + 3, st);
-      }
-      {
-        Scope sc(this, WAMCT_K_UPDATE);
-        Geo<T, R>::gather(g, kUpdate, vT, A, q, items, segs.data(), int(segs.size()), part, beta, b, scal + 0,
-                          ints + 0, nullptr, nullptr, nullptr, st);
-      }
-      ++iters;
-    }
-    LAUNCHED();
+    if (tree_dirty) CHECKED(rebuild_tree());
+    for (int k = 0; k < n; ++k) CHECKED(enq_iteration(st, idv ? idv + k : nullptr, n, false));
     return WAMCT_OK;
   }
 
-  wamct_status expand_tree(double frac, int32_t* n_split) override {
-    if (!(frac >= 0) || !std::isfinite(frac)) return fail(WAMCT_E_INVALID, "frac must be finite and >= 0");
-    int ns = 0;
+  // Tree rule (Results): FP64 synthesis, per-scan maximum, split, then the new tree.
+  wamct_status enq_expand(hipStream_t s, double frac) override {
     if (g.L > 0) {
       {
-        Scope sc(this, WAMCT_K_TREE);
-        const int nbk = Launch<T>::mu64(g, beta, mu64, partd, st);
-        reduce_max(partd, nbk, scal + 2, st);
-        HIPCHK(hipMemcpyAsync(mask_old, mask, NN, hipMemcpyDeviceToDevice, st));
-        fill_i32(ints + 2, 1, 0, st);
-        expand(g, mask_old, mask, mu64, scal + 2, frac, ints + 2, st);
+        Scope sc(this, WAMCT_K_TREE, s);
+        const int nbk = Launch<T>::mu64(g, beta, mu64, partd, P, s);
+        reduce_stack(true, partd, nbk, nbk, scal + 2, kScal, nullptr, P, s);
+        HIPCHK(hipMemcpyAsync(mask_old, mask, NN * P, hipMemcpyDeviceToDevice, s));
+        fill_i32_strided(ints + 2, P, kInts, 0, s);
+        expand(g, mask_old, mask, mu64, scal + 2, frac, ints + 2, P, s);
       }
       LAUNCHED();
-      HIPCHK(hipMemcpyAsync(&ns, ints + 2, sizeof(int), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      if (ns > 0) {
-        tree_dirty = true;
-        wamct_status r = rebuild_tree();
-        if (r) return r;
-      }
+    } else {
+      fill_i32_strided(ints + 2, P, kInts, 0, s);
+      LAUNCHED();
     }
-    if (n_split) *n_split = ns;
+    return enq_tree(s);
+  }
+  wamct_status expand_tree(double frac, int32_t* n_split) override {
+    if (!(frac >= 0) || !std::isfinite(frac)) return fail(WAMCT_E_INVALID, "frac must be finite and >= 0");
+    CHECKED(enq_expand(st, frac));
+    HIPCHK(hipStreamSynchronize(st));
+    return finish_tree(n_split);
+  }
+
+  wamct_status solve(int32_t n_iters, const int32_t* expand_at, int32_t n_expand, double frac,
+                     double* idv) override {
+    if (!has_data) return fail(WAMCT_E_STATE, "solve before set_data");
+    if (!(frac >= 0) || !std::isfinite(frac)) return fail(WAMCT_E_INVALID, "frac must be finite and >= 0");
+    if (tree_dirty) CHECKED(rebuild_tree());
+    const int64_t os = int64_t(n_iters) + 1;
+    int e = 0;
+    for (int j = 0; j < n_iters; ++j) {
+      while (e < n_expand && expand_at[e] < j) ++e;
+      if (e < n_expand && expand_at[e] == j) {
+        CHECKED(expand_tree(frac, nullptr));
+        ++e;
+      }
+      CHECKED(enq_iteration(st, idv ? idv + j : nullptr, os, false));
+    }
+    return enq_final(st, idv ? idv + n_iters : nullptr, os, false);
+  }
+
+  // ---------------------------------------------------------------- tiling trials
+  wamct_status save_state(hipStream_t s) override {
+    if (!beta_save) {
+      CHECKED(alloc(beta_save, NN * P));
+      CHECKED(alloc(ints_save, int64_t(kInts) * P));
+    }
+    HIPCHK(hipMemcpyAsync(beta_save, beta, sizeof(T) * NN * P, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ints_save, ints, sizeof(int) * kInts * P, hipMemcpyDeviceToDevice, s));
+    iters_save = iters;
+    return WAMCT_OK;
+  }
+  wamct_status restore_state(hipStream_t s) override {
+    if (!beta_save) return fail(WAMCT_E_STATE, "no saved state");
+    HIPCHK(hipMemcpyAsync(beta, beta_save, sizeof(T) * NN * P, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ints, ints_save, sizeof(int) * kInts * P, hipMemcpyDeviceToDevice, s));
+    iters = iters_save;
     return WAMCT_OK;
   }
 
+  // ---------------------------------------------------------------- operators
   wamct_status synthesize(void* out) override {
     if (!out) return fail(WAMCT_E_INVALID, "mu must not be NULL");
-    Scope sc(this, WAMCT_K_SYNTH);
-    Launch<T>::synth(g, beta, (T*)out, st);
+    Scope sc(this, WAMCT_K_SYNTH, st);
+    Launch<T>::synth(g, beta, (T*)out, P, st);
     LAUNCHED();
     return WAMCT_OK;
   }
 
   wamct_status project(const void* m, void* p) override {
     if (!m || !p) return fail(WAMCT_E_INVALID, "mu and p must not be NULL");
-    Scope sc(this, WAMCT_K_OTHER);
+    Scope sc(this, WAMCT_K_OTHER, st);
     Launch<T>::transpose(g.n, (const T*)m, muT, st);
-    Geo<T, R>::forward(g, A, B, (const T*)m, muT, nullptr, nullptr, 1.0, nullptr, (T*)p, nullptr, st);
+    Geo<T, R>::forward(g, A, B, (const T*)m, muT, nullptr, nullptr, nullptr, nullptr, (T*)p, nullptr, 1, st);
     LAUNCHED();
     return WAMCT_OK;
   }
 
   wamct_status backproject(const void* y, void* out) override {
     if (!y || !out) return fail(WAMCT_E_INVALID, "y and img must not be NULL");
-    Scope sc(this, WAMCT_K_OTHER);
-    Geo<T, R>::gather(g, kPlain, vT, A, (const T*)y, nullptr, pix_segs.data(), int(pix_segs.size()), part,
-                      nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, (T*)out, st);
+    Scope sc(this, WAMCT_K_OTHER, st);
+    CHECKED(gather(kPlain, (const T*)y, pix_segs, 1, nullptr, nullptr, nullptr, nullptr, (T*)out, st));
     LAUNCHED();
     return WAMCT_OK;
   }
 
   wamct_status backproject_split(const void* y, void* bp, void* bm) override {
     if (!y || !bp || !bm) return fail(WAMCT_E_INVALID, "y, bp and bm must not be NULL");
-    if (tree_dirty) { wamct_status r = rebuild_tree(); if (r) return r; }
-    Scope sc(this, WAMCT_K_OTHER);
-    Launch<T>::fill((T*)bp, NN, T(0), st);
-    Launch<T>::fill((T*)bm, NN, T(0), st);
-    Geo<T, R>::gather(g, kSplit, vT, A, (const T*)y, items, segs.data(), int(segs.size()), part, nullptr,
-                      nullptr, nullptr, nullptr, (T*)bp, (T*)bm, nullptr, st);
+    if (tree_dirty) CHECKED(rebuild_tree());
+    Scope sc(this, WAMCT_K_OTHER, st);
+    Launch<T>::fill((T*)bp, NN * P, T(0), st);
+    Launch<T>::fill((T*)bm, NN * P, T(0), st);
+    CHECKED(gather(kSplit, (const T*)y, segs, P, nullptr, nullptr, (T*)bp, (T*)bm, nullptr, st));
     LAUNCHED();
     return WAMCT_OK;
   }
 
   wamct_status forward(void* qo, double* idv) override {
     if (!has_data) return fail(WAMCT_E_STATE, "forward before set_data");
-    if (tree_dirty) { wamct_status r = rebuild_tree(); if (r) return r; }
-    const int nbk = forward_pass();
-    if (idv) reduce_sum(partd, nbk, idv, st);
-    if (qo) HIPCHK(hipMemcpyAsync(qo, q, sizeof(T) * M, hipMemcpyDeviceToDevice, st));
+    if (tree_dirty) CHECKED(rebuild_tree());
+    const int nbk = forward_pass(st);
+    if (idv) reduce_stack(false, partd, nbk, nbk, idv, 1, nullptr, P, st);
+    if (qo) HIPCHK(hipMemcpyAsync(qo, q, sizeof(T) * M * P, hipMemcpyDeviceToDevice, st));
     LAUNCHED();
     return WAMCT_OK;
   }
@@ -465,9 +659,9 @@ struct Ctx final : wamct_ctx {
   wamct_status idiv(const void* qq, double* out) override {
     if (!has_data) return fail(WAMCT_E_STATE, "idiv before set_data");
     if (!qq || !out) return fail(WAMCT_E_INVALID, "q and out must not be NULL");
-    Scope sc(this, WAMCT_K_OTHER);
-    const int nbk = Launch<T>::idiv_terms(g, (const T*)qq, d, partd, st);
-    reduce_sum(partd, nbk, out, st);
+    Scope sc(this, WAMCT_K_OTHER, st);
+    const int nbk = Launch<T>::idiv_terms(g, (const T*)qq, d, partd, P, st);
+    reduce_stack(false, partd, nbk, nbk, out, 1, nullptr, P, st);
     LAUNCHED();
     return WAMCT_OK;
   }
@@ -475,29 +669,32 @@ struct Ctx final : wamct_ctx {
   wamct_status get_b(void* out) override {
     if (!has_data) return fail(WAMCT_E_STATE, "get_b before set_data");
     if (!out) return fail(WAMCT_E_INVALID, "b must not be NULL");
-    HIPCHK(hipMemcpyAsync(out, b, sizeof(T) * NN, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(out, b, sizeof(T) * NN * P, hipMemcpyDeviceToDevice, st));
     return WAMCT_OK;
   }
 
   wamct_status tree_stats(double* z0, int64_t* w, int64_t* n_active, int64_t* n_held) override {
-    if (tree_dirty) { wamct_status r = rebuild_tree(); if (r) return r; }
-    double sc[2] = {0, 0};
-    int held = 0;
-    HIPCHK(hipMemcpyAsync(sc, scal, sizeof sc, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&held, ints, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (tree_dirty) CHECKED(rebuild_tree());
+    std::vector<double> sc(size_t(kScal) * P);
+    std::vector<int> in(size_t(kInts) * P);
+    HIPCHK(hipMemcpyAsync(sc.data(), scal, sizeof(double) * kScal * P, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(in.data(), ints, sizeof(int) * kInts * P, hipMemcpyDeviceToHost, st));
     std::vector<uint8_t> hm;
     if (n_active) {
-      hm.resize(NN);
-      HIPCHK(hipMemcpyAsync(hm.data(), mask, NN, hipMemcpyDeviceToHost, st));
+      hm.resize(size_t(NN) * P);
+      HIPCHK(hipMemcpyAsync(hm.data(), mask, NN * P, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipStreamSynchronize(st));
-    if (z0) *z0 = sc[0];
-    if (w) *w = int64_t(llround(sc[1]));
-    if (n_held) *n_held = held;
-    if (n_active) {
-      int64_t c = 0;
-      for (uint8_t v : hm) c += v;
-      *n_active = c;
+    for (int p = 0; p < P; ++p) {
+      if (z0) z0[p] = sc[p * kScal + 0];
+      if (w) w[p] = int64_t(llround(sc[p * kScal + 1]));
+      if (n_held) n_held[p] = in[p * kInts + 0];
+      if (n_active) {
+        int64_t c = 0;
+        const uint8_t* m = hm.data() + size_t(p) * NN;
+        for (int64_t k = 0; k < NN; ++k) c += m[k];
+        n_active[p] = c;
+      }
     }
     return WAMCT_OK;
   }
@@ -509,21 +706,22 @@ struct Ctx final : wamct_ctx {
     if (batch < 0) return fail(WAMCT_E_INVALID, "batch must be >= 0");
     if (batch > 0 && (!c || !dd || !lossd || !qout)) return fail(WAMCT_E_INVALID, "c, d, loss and q must not be NULL");
     if (!i0p && !(i0sc > 0 && std::isfinite(i0sc))) return fail(WAMCT_E_INVALID, "scalar I0 must be finite and > 0");
+    Launch<double>::fill(i0one, 1, i0p ? 1.0 : i0sc, st);
     for (int k = 0; k < batch; ++k) {
       const T* ck = (const T*)c + size_t(k) * NN;
       const T* dk = (const T*)dd + size_t(k) * M;
       const T* ik = i0p ? (const T*)i0p + size_t(k) * M : nullptr;
       T* qk = (T*)qout + size_t(k) * M;
       {
-        Scope sc(this, WAMCT_K_SYNTH);
-        Launch<T>::synth_layouts(g, ck, mu, muT, st);
+        Scope sc(this, WAMCT_K_SYNTH, st);
+        Launch<T>::synth_layouts(g, ck, mu, muT, 1, st);
       }
       int nbk;
       {
-        Scope sc(this, WAMCT_K_FORWARD);
-        nbk = Geo<T, R>::forward(g, A, B, mu, muT, dk, ik, i0sc, qk, nullptr, partd, st);
+        Scope sc(this, WAMCT_K_FORWARD, st);
+        nbk = Geo<T, R>::forward(g, A, B, mu, muT, dk, ik, i0one, qk, nullptr, partd, 1, st);
       }
-      Scope sc(this, WAMCT_K_OTHER);
+      Scope sc(this, WAMCT_K_OTHER, st);
       reduce_sum(partd, nbk, lossd + k, st);
     }
     LAUNCHED();
@@ -531,17 +729,17 @@ struct Ctx final : wamct_ctx {
   }
 
   // Hand-written adjoint: grad_b = s_b Omega^T H^T (d_b - q_b) from the saved q_b (s_b = the
-  // incoming gradient of loss_b, null = 1).
+  // incoming gradient of loss_b, null = 1). The residual is staged in the context's q-hat
+  // buffer, so the solver's q-hat is overwritten.
   wamct_status loss_backward(int32_t batch, const void* qq, const void* dd, const double* gscale,
                              void* grad) override {
     if (batch < 0) return fail(WAMCT_E_INVALID, "batch must be >= 0");
     if (batch > 0 && (!qq || !dd || !grad)) return fail(WAMCT_E_INVALID, "q, d and grad must not be NULL");
     for (int k = 0; k < batch; ++k) {
-      Scope sc(this, WAMCT_K_UPDATE);
+      Scope sc(this, WAMCT_K_UPDATE, st);
       Launch<T>::residual((const T*)dd + size_t(k) * M, (const T*)qq + size_t(k) * M, gscale ? gscale + k : nullptr,
                           q, M, st);
-      Geo<T, R>::gather(g, kPlain, vT, A, q, nullptr, pix_segs.data(), int(pix_segs.size()), part, nullptr, nullptr,
-                        nullptr, nullptr, nullptr, nullptr, img, st);
+      CHECKED(gather(kPlain, q, pix_segs, 1, nullptr, nullptr, nullptr, nullptr, img, st));
       Launch<T>::analysis(g, img, (T*)grad + size_t(k) * NN, st);
     }
     LAUNCHED();
@@ -568,6 +766,272 @@ struct Ctx final : wamct_ctx {
 };
 
 }  // namespace
+
+// ------------------------------------------------------------------ batches
+
+// Several contexts (stacks of scans of different geometries) solved together. Each context
+// is bound to one of the batch's streams (longest-processing-time-first by its work
+// estimate); one iteration of every context is captured into a HIP graph (fork from the
+// batch's main stream, one chain per stream, join) that is replayed for every iteration
+// between two tree expansions. The expansions run on the same streams with one host
+// synchronization for the whole batch. Per-scan I-divergence slots come from device
+// counters, so every replay of the same graph writes the next slot.
+struct wamct_batch {
+  std::string err;
+  std::vector<wamct_ctx*> ctx;
+  std::vector<int> lane;
+  std::vector<hipStream_t> streams;
+  hipStream_t main = nullptr, caller = nullptr;
+  hipEvent_t ev_main = nullptr, ev_in = nullptr;
+  std::vector<hipEvent_t> ev_s;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool use_graph = true;
+  int64_t graph_launches = 0, graph_nodes = 0, captures = 0;
+
+  wamct_status fail(wamct_status s, const std::string& m) {
+    err = m;
+    return s;
+  }
+  wamct_status from(wamct_ctx* c, wamct_status s) {
+    err = c->err;
+    return s;
+  }
+  void drop_graph() {
+    if (exec || graph) hipStreamSynchronize(main);
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~wamct_batch() {
+    if (main) hipStreamSynchronize(main);
+    for (auto s : streams) hipStreamSynchronize(s);
+    drop_graph();
+    for (auto s : streams) hipStreamDestroy(s);
+    if (main) hipStreamDestroy(main);
+    for (auto e : ev_s) hipEventDestroy(e);
+    if (ev_main) hipEventDestroy(ev_main);
+    if (ev_in) hipEventDestroy(ev_in);
+  }
+  hipStream_t sof(size_t i) const { return streams[lane[i]]; }
+
+  wamct_status init(int n, wamct_ctx* const* cs, int n_streams, int graph_on, hipStream_t s) {
+    caller = s;
+    use_graph = graph_on != 0;
+    ctx.assign(cs, cs + n);
+    HIPCHK(hipStreamCreateWithFlags(&main, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ev_main, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+    streams.resize(n_streams, nullptr);
+    ev_s.resize(n_streams, nullptr);
+    for (int k = 0; k < n_streams; ++k) {
+      HIPCHK(hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&ev_s[k], hipEventDisableTiming));
+    }
+    // longest processing time first
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ctx[a]->work() > ctx[b]->work(); });
+    std::vector<double> load(n_streams, 0.0);
+    lane.assign(n, 0);
+    for (int i : order) {
+      const int k = int(std::min_element(load.begin(), load.end()) - load.begin());
+      lane[i] = k;
+      load[k] += ctx[i]->work();
+    }
+    return WAMCT_OK;
+  }
+  // main waits for the caller's stream and every context's own stream
+  wamct_status enter() {
+    HIPCHK(hipEventRecord(ev_in, caller));
+    HIPCHK(hipStreamWaitEvent(main, ev_in, 0));
+    for (wamct_ctx* c : ctx) {
+      HIPCHK(hipEventRecord(ev_in, c->stream()));
+      HIPCHK(hipStreamWaitEvent(main, ev_in, 0));
+    }
+    return fork();
+  }
+  wamct_status fork() {
+    HIPCHK(hipEventRecord(ev_main, main));
+    for (auto s : streams) HIPCHK(hipStreamWaitEvent(s, ev_main, 0));
+    return WAMCT_OK;
+  }
+  wamct_status join() {
+    for (size_t k = 0; k < streams.size(); ++k) {
+      HIPCHK(hipEventRecord(ev_s[k], streams[k]));
+      HIPCHK(hipStreamWaitEvent(main, ev_s[k], 0));
+    }
+    return WAMCT_OK;
+  }
+  // the caller's stream and every context's stream wait for the batch's work
+  wamct_status leave() {
+    CHECKED(join());
+    HIPCHK(hipEventRecord(ev_main, main));
+    HIPCHK(hipStreamWaitEvent(caller, ev_main, 0));
+    for (wamct_ctx* c : ctx) HIPCHK(hipStreamWaitEvent(c->stream(), ev_main, 0));
+    return WAMCT_OK;
+  }
+  wamct_status sync_streams() {
+    for (auto s : streams) HIPCHK(hipStreamSynchronize(s));
+    return WAMCT_OK;
+  }
+  // tree work already enqueued on the streams: wait, then every context reads its counts
+  wamct_status finish_trees() {
+    CHECKED(sync_streams());
+    for (wamct_ctx* c : ctx) {
+      wamct_status r = c->finish_tree(nullptr);
+      if (r) return from(c, r);
+    }
+    return WAMCT_OK;
+  }
+
+  wamct_status reset() {
+    CHECKED(enter());
+    for (size_t i = 0; i < ctx.size(); ++i) {
+      wamct_status r = ctx[i]->enq_reset(sof(i));
+      if (r) return from(ctx[i], r);
+    }
+    CHECKED(finish_trees());
+    return leave();
+  }
+
+  wamct_status capture(double* const* idiv, int64_t os) {
+    drop_graph();
+    HIPCHK(hipStreamBeginCapture(main, hipStreamCaptureModeThreadLocal));
+    wamct_status r = fork();
+    for (size_t i = 0; i < ctx.size() && r == WAMCT_OK; ++i) {
+      double* out = idiv ? idiv[i] : nullptr;
+      wamct_status rc = ctx[i]->enq_iteration(sof(i), out, os, out != nullptr);
+      if (rc) r = from(ctx[i], rc);
+    }
+    if (r == WAMCT_OK) r = join();
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(main, &gr);
+    if (r != WAMCT_OK) {
+      if (gr) hipGraphDestroy(gr);
+      return r;
+    }
+    if (e != hipSuccess) return fail(WAMCT_E_HIP, fmt("hipStreamEndCapture: %s", hipGetErrorString(e)));
+    graph = gr;
+    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    size_t nodes = 0;
+    HIPCHK(hipGraphGetNodes(graph, nullptr, &nodes));
+    graph_nodes = int64_t(nodes);
+    ++captures;
+    return WAMCT_OK;
+  }
+
+  wamct_status run(int k, double* const* idiv, int64_t os) {
+    if (k <= 0) return WAMCT_OK;
+    if (use_graph) {
+      CHECKED(capture(idiv, os));  // counts one iteration per context
+      CHECKED(join());
+      for (int it = 0; it < k; ++it) {
+        HIPCHK(hipGraphLaunch(exec, main));
+        ++graph_launches;
+      }
+      for (wamct_ctx* c : ctx) c->count_iters(k - 1);
+      return fork();
+    }
+    for (int it = 0; it < k; ++it)
+      for (size_t i = 0; i < ctx.size(); ++i) {
+        double* out = idiv ? idiv[i] : nullptr;
+        wamct_status r = ctx[i]->enq_iteration(sof(i), out, os, out != nullptr);
+        if (r) return from(ctx[i], r);
+      }
+    return WAMCT_OK;
+  }
+
+  wamct_status solve(int n_iters, const int32_t* at, int n_expand, double frac, double* const* idiv) {
+    for (wamct_ctx* c : ctx)
+      if (!c->has_data_()) return fail(WAMCT_E_STATE, "batch solve before set_data on every context");
+    CHECKED(enter());
+    bool dirty = false;
+    for (size_t i = 0; i < ctx.size(); ++i)
+      if (ctx[i]->tree_dirty_()) {
+        wamct_status r = ctx[i]->enq_tree(sof(i));
+        if (r) return from(ctx[i], r);
+        dirty = true;
+      }
+    if (dirty) CHECKED(finish_trees());
+    for (size_t i = 0; i < ctx.size(); ++i) {
+      wamct_status r = ctx[i]->enq_begin(sof(i));
+      if (r) return from(ctx[i], r);
+    }
+    const int64_t os = int64_t(n_iters) + 1;
+    int e = 0, j = 0;
+    while (j < n_iters) {
+      while (e < n_expand && at[e] < j) ++e;
+      if (e < n_expand && at[e] == j) {
+        for (size_t i = 0; i < ctx.size(); ++i) {
+          wamct_status r = ctx[i]->enq_expand(sof(i), frac);
+          if (r) return from(ctx[i], r);
+        }
+        CHECKED(finish_trees());
+        ++e;
+      }
+      int stop = n_iters;
+      if (e < n_expand && at[e] < stop) stop = at[e];
+      CHECKED(run(stop - j, idiv, os));
+      j = stop;
+    }
+    for (size_t i = 0; i < ctx.size(); ++i) {
+      double* out = idiv ? idiv[i] : nullptr;
+      wamct_status r = ctx[i]->enq_final(sof(i), out, os, out != nullptr);
+      if (r) return from(ctx[i], r);
+    }
+    drop_graph();
+    return leave();
+  }
+
+  // Per context: time n_trial iterations (after one untimed) at each candidate tiling on
+  // the context's own stream, restoring its state after every trial; keep the fastest.
+  wamct_status autotune(int n_trial, const int32_t* cand, int n_cand, int32_t* chosen) {
+    err.clear();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    wamct_status res = WAMCT_OK;
+    for (size_t i = 0; i < ctx.size() && res == WAMCT_OK; ++i) {
+      wamct_ctx* c = ctx[i];
+      const hipStream_t s = c->stream();
+      int32_t best = c->tiling();
+      float best_ms = -1.f;
+      for (int k = 0; k < n_cand && res == WAMCT_OK; ++k) {
+        wamct_status r = c->set_tiling(cand[k]);
+        if (!r && c->tree_dirty_()) {
+          r = c->enq_tree(s);
+          if (!r && hipStreamSynchronize(s) != hipSuccess) r = fail(WAMCT_E_HIP, "synchronize");
+          if (!r) r = c->finish_tree(nullptr);
+        }
+        if (!r) r = c->save_state(s);
+        if (!r) r = c->enq_iteration(s, nullptr, 0, false);
+        if (!r && hipEventRecord(e0, s) != hipSuccess) r = fail(WAMCT_E_HIP, "hipEventRecord");
+        for (int t = 0; t < n_trial && !r; ++t) r = c->enq_iteration(s, nullptr, 0, false);
+        if (!r && hipEventRecord(e1, s) != hipSuccess) r = fail(WAMCT_E_HIP, "hipEventRecord");
+        if (!r) r = c->restore_state(s);
+        float ms = 0.f;
+        if (!r && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          r = fail(WAMCT_E_HIP, "trial timing failed");
+        if (r) {
+          if (err.empty()) err = c->err;
+          res = r;
+          break;
+        }
+        if (best_ms < 0 || ms < best_ms) { best_ms = ms; best = cand[k]; }
+      }
+      if (res == WAMCT_OK) {
+        wamct_status r = c->set_tiling(best);
+        if (r) res = from(c, r);
+      }
+      if (chosen) chosen[i] = best;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return res;
+  }
+};
 
 // ------------------------------------------------------------------ C ABI
 
@@ -619,7 +1083,7 @@ const char* wamct_version(void) { return kVersion; }
   } while (0)
 
 wamct_status wamct_set_stream(wamct_ctx* ctx, void* stream) { CTX_CALL(set_stream(static_cast<hipStream_t>(stream))); }
-wamct_status wamct_set_data(wamct_ctx* ctx, const void* d, const void* i0, double i0s) { CTX_CALL(set_data(d, i0, i0s)); }
+wamct_status wamct_set_data(wamct_ctx* ctx, const void* d, const void* i0, const double* i0s) { CTX_CALL(set_data(d, i0, i0s)); }
 wamct_status wamct_reset(wamct_ctx* ctx) { CTX_CALL(reset()); }
 wamct_status wamct_set_state(wamct_ctx* ctx, const void* beta, const uint8_t* mask) { CTX_CALL(set_state(beta, mask)); }
 wamct_status wamct_get_state(wamct_ctx* ctx, void* beta, uint8_t* mask, int32_t* it) { CTX_CALL(get_state(beta, mask, it)); }
@@ -639,31 +1103,107 @@ wamct_status wamct_loss(wamct_ctx* ctx, int32_t batch, const void* c, const void
 wamct_status wamct_loss_backward(wamct_ctx* ctx, int32_t batch, const void* q, const void* d, const double* gscale,
                                  void* grad) { CTX_CALL(loss_backward(batch, q, d, gscale, grad)); }
 wamct_status wamct_get_timing(wamct_ctx* ctx, double* ms, int64_t* n) { CTX_CALL(get_timing(ms, n)); }
+wamct_status wamct_set_tiling(wamct_ctx* ctx, int32_t lanes) { CTX_CALL(set_tiling(lanes)); }
+wamct_status wamct_get_tiling(wamct_ctx* ctx, int32_t* lanes) {
+  if (!ctx) { g_last_error = "ctx is NULL"; return WAMCT_E_INVALID; }
+  if (!lanes) return ctx->fail(WAMCT_E_INVALID, "lanes must not be NULL");
+  *lanes = ctx->tiling();
+  return WAMCT_OK;
+}
+
+static std::string check_schedule(int32_t n_iters, const int32_t* expand_at, int32_t n_expand, double frac) {
+  if (n_iters < 0 || n_expand < 0 || (n_expand > 0 && !expand_at)) return "bad iteration count or expansion schedule";
+  for (int k = 1; k < n_expand; ++k)
+    if (expand_at[k] <= expand_at[k - 1]) return "expansion schedule must ascend";
+  if (!(frac >= 0) || !std::isfinite(frac)) return "frac must be finite and >= 0";
+  return "";
+}
 
 wamct_status wamct_solve(wamct_ctx* ctx, int32_t n_iters, const int32_t* expand_at, int32_t n_expand, double frac,
                          double* idiv) {
   if (!ctx) { g_last_error = "ctx is NULL"; return WAMCT_E_INVALID; }
-  if (n_iters < 0 || n_expand < 0 || (n_expand > 0 && !expand_at))
-    return ctx->fail(WAMCT_E_INVALID, "bad iteration count or expansion schedule");
-  for (int k = 1; k < n_expand; ++k)
-    if (expand_at[k] <= expand_at[k - 1]) return ctx->fail(WAMCT_E_INVALID, "expansion schedule must ascend");
-  int e = 0;
-  int j = 0;
-  while (j < n_iters) {
-    while (e < n_expand && expand_at[e] < j) ++e;
-    if (e < n_expand && expand_at[e] == j) {
-      wamct_status s = ctx->expand_tree(frac, nullptr);
-      if (s) return s;
-      ++e;
-    }
-    // run up to the next scheduled expansion in one call
-    int stop = n_iters;
-    if (e < n_expand && expand_at[e] < stop) stop = expand_at[e];
-    wamct_status s = ctx->iterate(stop - j, idiv ? idiv + j : nullptr);
-    if (s) return s;
-    j = stop;
+  std::string e = check_schedule(n_iters, expand_at, n_expand, frac);
+  if (!e.empty()) return ctx->fail(WAMCT_E_INVALID, e);
+  return ctx->solve(n_iters, expand_at, n_expand, frac, idiv);
+}
+
+wamct_status wamct_batch_create(int32_t n_ctx, wamct_ctx* const* ctxs, int32_t n_streams, int32_t use_graph,
+                                void* stream, wamct_batch** out) {
+  if (!out) { g_last_error = "out must not be NULL"; return WAMCT_E_INVALID; }
+  *out = nullptr;
+  if (n_ctx < 1 || !ctxs) { g_last_error = "a batch needs at least one context"; return WAMCT_E_INVALID; }
+  if (n_streams < 1 || n_streams > 64) { g_last_error = "n_streams outside [1, 64]"; return WAMCT_E_INVALID; }
+  for (int i = 0; i < n_ctx; ++i) {
+    if (!ctxs[i]) { g_last_error = fmt("context %d is NULL", i); return WAMCT_E_INVALID; }
+    for (int k = 0; k < i; ++k)
+      if (ctxs[k] == ctxs[i]) { g_last_error = fmt("context %d appears twice", i); return WAMCT_E_INVALID; }
   }
-  return ctx->forward(nullptr, idiv ? idiv + n_iters : nullptr);
+  wamct_batch* b = new wamct_batch();
+  wamct_status s = b->init(n_ctx, ctxs, n_streams, use_graph, static_cast<hipStream_t>(stream));
+  if (s != WAMCT_OK) {
+    g_last_error = b->err;
+    delete b;
+    return s;
+  }
+  *out = b;
+  return WAMCT_OK;
+}
+
+wamct_status wamct_batch_destroy(wamct_batch* batch) {
+  delete batch;
+  return WAMCT_OK;
+}
+
+const char* wamct_batch_last_error(const wamct_batch* batch) {
+  return batch ? batch->err.c_str() : g_last_error.c_str();
+}
+
+#define BATCH_CHECK()                                                      \
+  do {                                                                     \
+    if (!batch) { g_last_error = "batch is NULL"; return WAMCT_E_INVALID; } \
+  } while (0)
+
+wamct_status wamct_batch_reset(wamct_batch* batch) {
+  BATCH_CHECK();
+  return batch->reset();
+}
+
+wamct_status wamct_batch_solve(wamct_batch* batch, int32_t n_iters, const int32_t* expand_at, int32_t n_expand,
+                               double frac, double* const* idiv) {
+  BATCH_CHECK();
+  std::string e = check_schedule(n_iters, expand_at, n_expand, frac);
+  if (!e.empty()) return batch->fail(WAMCT_E_INVALID, e);
+  return batch->solve(n_iters, expand_at, n_expand, frac, idiv);
+}
+
+wamct_status wamct_batch_autotune(wamct_batch* batch, int32_t n_trial, const int32_t* candidates,
+                                  int32_t n_candidates, int32_t* chosen) {
+  BATCH_CHECK();
+  static const int32_t kDefault[] = {1 << 18, 1 << 19, 1 << 20, 1 << 21, 1 << 22};
+  if (n_trial < 1) return batch->fail(WAMCT_E_INVALID, "n_trial must be >= 1");
+  if (!candidates) {
+    candidates = kDefault;
+    n_candidates = int32_t(sizeof kDefault / sizeof kDefault[0]);
+  }
+  if (n_candidates < 1) return batch->fail(WAMCT_E_INVALID, "no candidate tilings");
+  for (int k = 0; k < n_candidates; ++k)
+    if (candidates[k] < kMinTargetLanes || candidates[k] > kMaxTargetLanes)
+      return batch->fail(WAMCT_E_INVALID, fmt("candidate tiling %d outside [%d, %d]", candidates[k],
+                                              kMinTargetLanes, kMaxTargetLanes));
+  for (wamct_ctx* c : batch->ctx)
+    if (!c->has_data_()) return batch->fail(WAMCT_E_STATE, "autotune before set_data on every context");
+  return batch->autotune(n_trial, candidates, n_candidates, chosen);
+}
+
+wamct_status wamct_batch_stats(wamct_batch* batch, int32_t* stream_of_ctx, int64_t* graph_launches,
+                               int64_t* graph_nodes, int64_t* captures) {
+  BATCH_CHECK();
+  if (stream_of_ctx)
+    for (size_t i = 0; i < batch->ctx.size(); ++i) stream_of_ctx[i] = batch->lane[i];
+  if (graph_launches) *graph_launches = batch->graph_launches;
+  if (graph_nodes) *graph_nodes = batch->graph_nodes;
+  if (captures) *captures = batch->captures;
+  return WAMCT_OK;
 }
 
 }  // extern "C"

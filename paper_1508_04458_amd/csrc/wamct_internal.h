@@ -6,6 +6,10 @@
 namespace wamct {
 
 constexpr int kMaxLevels = 8;
+// Per-scan slots of the small device arrays of a context holding a stack of scans.
+constexpr int kScal = 8;   // doubles: [0] Z0, [1] W, [2] max mu, [3] scratch, [4] scalar I0
+constexpr int kInts = 32;  // ints: [0] held, [1] bad, [2] n_split, [3] iteration counter,
+                           // [8] work items, [9 + k] items of level L - k
 
 // Scan geometry as the kernels see it (see include/wamct.h for the conventions).
 struct DevGeom {
@@ -29,35 +33,49 @@ __host__ __device__ inline uint32_t item_pack(int quad, int l, int i, int j) {
 enum GatherMode { kPlain = 0, kSplit = 1, kUpdate = 2 };
 
 // A run of work items of one level, processed with its views split into `chunks` ranges
-// of `vpc` views (chunks = 1: one lane per item over all views).
+// of `vpc` views (chunks = 1: one lane per item over all views). For a stack of scans the
+// run of scan p is level index kseg of its per-scan counts (start and length read on the
+// device) and `count` is the largest length over the stack; kseg < 0 means the fixed range
+// [start, start + count) in every scan.
 struct Segment {
-  int start, count, level, chunks, vpc;
+  int kseg, start, count, level, chunks, vpc;
 };
-// Lanes one level segment should occupy (about 64 wave64 per CU on 256 CUs, several
-// rounds of the resident waves, so short and long tasks even out).
+// Default lanes one level segment should occupy over the whole stack (about 64 wave64 per
+// CU on 256 CUs, several rounds of the resident waves, so short and long tasks even out);
+// tunable per context within [kMinTargetLanes, kMaxTargetLanes].
 constexpr int kTargetLanes = 1 << 20;
+constexpr int kMinTargetLanes = 1 << 12;
+constexpr int kMaxTargetLanes = 1 << 24;
+// Partial sums a chunked segment stores: 7 values of R per (scan, item, chunk group).
+inline int64_t segment_part_elems(const Segment& sg, int n_scans) {
+  if (sg.chunks <= 1) return 0;
+  const int64_t groups = (sg.chunks + 3) / 4;
+  return 7 * groups * int64_t(sg.count) * n_scans;
+}
 
 // Launchers. T is float or double. Every pointer is device memory unless noted.
 template <typename T>
 struct Launch {
+  // Kernels taking S work on a stack of S scans: image-shaped arrays are [S][n*n],
+  // sinogram-shaped arrays [S][n_views*n_bins], per-block partials [S][blocks].
   // mu = Omega beta (inactive coefficients are zero by invariant)
-  static void synth(const DevGeom& g, const T* beta, T* mu, hipStream_t s);
+  static void synth(const DevGeom& g, const T* beta, T* mu, int S, hipStream_t s);
   // mu = Omega beta in both layouts the forward walk reads (row- and column-major)
-  static void synth_layouts(const DevGeom& g, const T* beta, T* muR, T* muC, hipStream_t s);
+  static void synth_layouts(const DevGeom& g, const T* beta, T* muR, T* muC, int S, hipStream_t s);
   // leaf records (value, level) of mu = Omega beta, row- and column-major
-  static void synth_records(const DevGeom& g, const T* beta, const uint8_t* lev, void* leafR, void* leafC,
+  static void synth_records(const DevGeom& g, const T* beta, const uint8_t* lev, void* leafR, void* leafC, int S,
                             hipStream_t s);
   static void transpose(int n, const T* in, T* out, hipStream_t s);
   // per-pixel leaf level from the tree mask
-  static void levmap(const DevGeom& g, const uint8_t* mask, uint8_t* lev, hipStream_t s);
-  // I-divergence terms of a given q -> per-block partials. Returns the number of blocks.
-  static int idiv_terms(const DevGeom& g, const T* q, const T* d, double* part, hipStream_t s);
-  // b = Omega^T g for every coefficient (FP64 accumulation)
+  static void levmap(const DevGeom& g, const uint8_t* mask, uint8_t* lev, int S, hipStream_t s);
+  // I-divergence terms of a given q -> per-block partials. Returns the blocks per scan.
+  static int idiv_terms(const DevGeom& g, const T* q, const T* d, double* part, int S, hipStream_t s);
+  // b = Omega^T g for every coefficient (FP64 accumulation), one scan
   static void analysis(const DevGeom& g, const T* img, T* coef, hipStream_t s);
-  // FP64 synthesis of the current beta and per-block maxima. Returns the number of blocks.
-  static int mu64(const DevGeom& g, const T* beta, double* mu64, double* part, hipStream_t s);
+  // FP64 synthesis of the current beta and per-block maxima. Returns the blocks per scan.
+  static int mu64(const DevGeom& g, const T* beta, double* mu64, double* part, int S, hipStream_t s);
   // zero beta outside the mask
-  static void apply_mask(const DevGeom& g, T* beta, const uint8_t* mask, hipStream_t s);
+  static void apply_mask(const DevGeom& g, T* beta, const uint8_t* mask, int S, hipStream_t s);
   // count non-finite or negative entries of x into *bad (int, accumulated)
   static void check(const T* x, int64_t len, bool allow_negative, int* bad, hipStream_t s);
   static void fill(T* x, int64_t len, T v, hipStream_t s);
@@ -73,39 +91,52 @@ struct Geo {
   static void ray_table(const DevGeom& g, const double2* views, void* A, void* B, hipStream_t s);
   // per-view (cos a, sin a) in float, used only for the detector footprint of a box
   static void view_table(const DevGeom& g, const double2* views, void* vF, hipStream_t s);
-  // pixel walk projection of muR/muC (row-/column-major copies of one image). If q != null:
-  // q = I0 exp(-p) and per-block FP64 partial sums of the I-divergence terms in `part`. If
-  // p != null the line integrals are stored. Returns the number of blocks.
+  // pixel walk projection of muR/muC (row-/column-major copies of one image per scan). If
+  // q != null: q = I0 exp(-p) (I0 = i0v per ray, else the scan's scalar i0s[scan * kScal])
+  // and per-block FP64 partial sums of the I-divergence terms in `part`. If p != null the
+  // line integrals are stored. Returns the blocks per scan.
   static int forward(const DevGeom& g, const void* A, const void* B, const T* muR, const T* muC, const T* d,
-                     const T* i0v, double i0s, T* q, T* p, double* part, hipStream_t s);
+                     const T* i0v, const double* i0s, T* q, T* p, double* part, int S, hipStream_t s);
   // leaf walk over (value, level) records read from global memory
   static int forward_records(const DevGeom& g, const void* A, const void* B, const void* leafR, const void* leafC,
-                             const T* d, const T* i0v, double i0s, T* q, T* p, double* part, hipStream_t s);
+                             const T* d, const T* i0v, const double* i0s, T* q, T* p, double* part, int S,
+                             hipStream_t s);
   // node-driven backprojection of y over the segments of `items` (items null: every pixel
-  // as a level-0 box); `part` holds 7 * chunks * count values of R for chunked segments
+  // as a level-0 box). counts: per-scan level counts (stride kInts; null for fixed ranges);
+  // z0 per scan at stride kScal, held at stride kInts; `part` holds segment_part_elems.
   static void gather(const DevGeom& g, int mode, const void* vF, const void* A, const T* y,
-                     const uint32_t* items, const Segment* segs, int n_segs, void* part, T* beta,
-                     const T* b, const double* z0, int* held, T* bp, T* bm, T* out, hipStream_t s);
+                     const uint32_t* items, const int* counts, const Segment* segs, int n_segs, void* part,
+                     T* beta, const T* b, const double* z0, int* held, T* bp, T* bm, T* out, int S,
+                     hipStream_t s);
 };
 
 // Z0 and W of the current tree: per-ray FP64 sums of |phi| over active coefficients and
-// counts of phi != 0; per-block partial max / sum. Returns the number of blocks.
+// counts of phi != 0; per-block partial max / sum. Returns the blocks per scan.
 int z0_partials(const DevGeom& g, const double2* views, const uint8_t* lev, double* part_max,
-                double* part_cnt, hipStream_t s);
+                double* part_cnt, int S, hipStream_t s);
 // Deterministic single-block reductions of per-block partials: out[0] = sum or max.
 void reduce_sum(const double* part, int n, double* out, hipStream_t s);
 void reduce_max(const double* part, int n, double* out, hipStream_t s);
+// The same for a stack of S scans, one block per scan: scan p reduces part[p * pstride ..
+// + n) into out[p * ostride + c], c = 0, or c = ctr[p * kInts] when ctr is not null (the
+// counter is then incremented: the slot of the next call).
+void reduce_stack(bool max, const double* part, int n, int64_t pstride, double* out, int64_t ostride, int* ctr,
+                  int S, hipStream_t s);
 // Work list of the node-driven backprojection (roots, then split nodes level by level,
-// Morton order within a level), compacted with wave ballots; counts[0] = number of items,
-// counts[1 + k] = items of level L - k (k = 0..L; level 0 only when L = 0).
-void build_items(const DevGeom& g, const uint8_t* mask, uint32_t* items, int* counts, hipStream_t s);
-// Tree rule: split every leaf (level >= 1) of mask_old whose FP64 value exceeds frac * max.
+// Morton order within a level), compacted with wave ballots; per scan counts[0] = number
+// of items, counts[1 + k] = items of level L - k (k = 0..L; level 0 only when L = 0);
+// counts at stride kInts, items at stride n*n.
+void build_items(const DevGeom& g, const uint8_t* mask, uint32_t* items, int* counts, int S, hipStream_t s);
+// Tree rule: split every leaf (level >= 1) of mask_old whose FP64 value exceeds frac * max
+// (maxv at stride kScal, n_split at stride kInts).
 void expand(const DevGeom& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64,
-            const double* maxv, double frac, int* n_split, hipStream_t s);
-// Validity of a tree mask: *bad = number of violated constraints.
-void check_mask(const DevGeom& g, const uint8_t* mask, int* bad, hipStream_t s);
+            const double* maxv, double frac, int* n_split, int S, hipStream_t s);
+// Validity of S tree masks: *bad = number of violated constraints.
+void check_mask(const DevGeom& g, const uint8_t* mask, int* bad, int S, hipStream_t s);
 void fill_u8(uint8_t* x, int64_t len, uint8_t v, hipStream_t s);
 void fill_i32(int* x, int64_t len, int v, hipStream_t s);
-void approx_mask(const DevGeom& g, uint8_t* mask, hipStream_t s);
+// x[k * stride] = v for k < count
+void fill_i32_strided(int* x, int count, int stride, int v, hipStream_t s);
+void approx_mask(const DevGeom& g, uint8_t* mask, int S, hipStream_t s);
 
 }  // namespace wamct

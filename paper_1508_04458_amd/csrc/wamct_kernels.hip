@@ -24,6 +24,10 @@ constexpr int kBlock = 256;
 
 inline int blocks_for(int64_t n, int b = kBlock) { return int((n + b - 1) / b); }
 
+// Slice of scan `off / size` of a stacked array (a null pointer stays null).
+template <typename P>
+__device__ inline P* at(P* x, int64_t off) { return x ? x + off : x; }
+
 // ------------------------------------------------------------------ reductions (wave64)
 
 __device__ inline double wave_sum(double v) {
@@ -52,14 +56,26 @@ __device__ inline double block_reduce(double v) {
   return v;
 }
 
+// One block per scan; fixed assignment and order -> deterministic result. With a counter
+// the result goes to slot ctr[scan] of the scan's row, and the counter moves on.
 template <bool MAX>
-__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ part, int n,
-                                                   double* __restrict__ out) {
-  // fixed assignment and order -> deterministic result
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ part, int n, int64_t pstride,
+                                                   double* __restrict__ out, int64_t ostride,
+                                                   int* __restrict__ ctr) {
+  const int p = blockIdx.x;
+  part += p * pstride;
   double v = MAX ? -INFINITY : 0.0;
   for (int k = threadIdx.x; k < n; k += kBlock) v = MAX ? fmax(v, part[k]) : v + part[k];
   v = block_reduce<MAX>(v);
-  if (threadIdx.x == 0) out[0] = v;
+  if (threadIdx.x == 0) {
+    int64_t o = p * ostride;
+    if (ctr) {
+      const int c = ctr[p * kInts];
+      o += c;
+      ctr[p * kInts] = c + 1;
+    }
+    out[o] = v;
+  }
 }
 
 // ------------------------------------------------------------------ geometry
@@ -129,6 +145,9 @@ __device__ inline R synth_pixel(const T* __restrict__ beta, int n, int L, int r,
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_synth(int n, int L, const T* __restrict__ beta, T* __restrict__ mu) {
+  const int64_t off = int64_t(blockIdx.y) * n * n;
+  beta += off;
+  mu += off;
   const int p = blockIdx.x * kBlock + threadIdx.x;
   if (p >= n * n) return;
   mu[p] = synth_pixel<T, T>(beta, n, L, p / n, p % n);
@@ -137,6 +156,9 @@ __global__ __launch_bounds__(kBlock) void k_synth(int n, int L, const T* __restr
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mu64(int n, int L, const T* __restrict__ beta,
                                                  double* __restrict__ mu64, double* __restrict__ part) {
+  const int64_t off = int64_t(blockIdx.y) * n * n;
+  beta += off;
+  mu64 += off;
   const int p = blockIdx.x * kBlock + threadIdx.x;
   double v = -INFINITY;
   if (p < n * n) {
@@ -144,11 +166,14 @@ __global__ __launch_bounds__(kBlock) void k_mu64(int n, int L, const T* __restri
     mu64[p] = v;
   }
   v = block_reduce<true>(v);
-  if (threadIdx.x == 0) part[blockIdx.x] = v;
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = v;
 }
 
 __global__ __launch_bounds__(kBlock) void k_levmap(int n, int L, const uint8_t* __restrict__ mask,
                                                    uint8_t* __restrict__ lev) {
+  const int64_t off = int64_t(blockIdx.y) * n * n;
+  mask += off;
+  lev += off;
   const int p = blockIdx.x * kBlock + threadIdx.x;
   if (p >= n * n) return;
   const int r = p / n, c = p % n;
@@ -177,6 +202,13 @@ __global__ __launch_bounds__(256) void k_synth_tiles(int n, int L, const T* __re
                                                      Leaf<T>* __restrict__ leafC) {
   __shared__ T tile[32][33];
   __shared__ uint8_t ltile[32][33];
+  const int64_t off = int64_t(blockIdx.z) * n * n;
+  beta += off;
+  lev = at(lev, off);
+  muR = at(muR, off);
+  muC = at(muC, off);
+  leafR = at(leafR, off);
+  leafC = at(leafC, off);
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
 #pragma unroll
@@ -242,9 +274,15 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4
                                                     const typename V4<R>::t* __restrict__ B,
                                                     const T* __restrict__ muR, const T* __restrict__ muC,
                                                     const T* __restrict__ d, const T* __restrict__ i0v,
-                                                    double i0s, T* __restrict__ q, T* __restrict__ pout,
-                                                    double* __restrict__ part) {
+                                                    const double* __restrict__ i0s, T* __restrict__ q,
+                                                    T* __restrict__ pout, double* __restrict__ part) {
   const int M = g.nv * g.nb;
+  const int sc = blockIdx.y;
+  {
+    const int64_t oi = int64_t(sc) * g.n * g.n, orr = int64_t(sc) * M;
+    muR += oi; muC += oi;
+    d = at(d, orr); i0v = at(i0v, orr); q = at(q, orr); pout = at(pout, orr);
+  }
   const int r = blockIdx.x * kBlock + threadIdx.x;
   double term = 0.0;
   if (r < M) {
@@ -300,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4
     const R p = acc;
     if (pout) pout[r] = T(p);
     if (q) {
-      const double i0 = i0v ? double(i0v[r]) : i0s;
+      const double i0 = i0v ? double(i0v[r]) : i0s[sc * kScal];
       const double pd = double(p);
       const double qd = i0 * exp(-pd);
       q[r] = T(qd);
@@ -311,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4
   }
   if (part) {
     term = block_reduce<false>(term);
-    if (threadIdx.x == 0) part[blockIdx.x] = term;
+    if (threadIdx.x == 0) part[sc * gridDim.x + blockIdx.x] = term;
   }
 }
 
@@ -330,9 +368,15 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
                                                         const Leaf<T>* __restrict__ leafR,
                                                         const Leaf<T>* __restrict__ leafC,
                                                         const T* __restrict__ d, const T* __restrict__ i0v,
-                                                        double i0s, T* __restrict__ q, T* __restrict__ pout,
-                                                        double* __restrict__ part) {
+                                                        const double* __restrict__ i0s, T* __restrict__ q,
+                                                        T* __restrict__ pout, double* __restrict__ part) {
   const int M = g.nv * g.nb;
+  const int sc = blockIdx.y;
+  {
+    const int64_t oi = int64_t(sc) * g.n * g.n, orr = int64_t(sc) * M;
+    leafR += oi; leafC += oi;
+    d = at(d, orr); i0v = at(i0v, orr); q = at(q, orr); pout = at(pout, orr);
+  }
   const int r = blockIdx.x * kBlock + threadIdx.x;
   double term = 0.0;
   if (r < M) {
@@ -385,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
     const R p = acc;
     if (pout) pout[r] = T(p);
     if (q) {
-      const double i0 = i0v ? double(i0v[r]) : i0s;
+      const double i0 = i0v ? double(i0v[r]) : i0s[sc * kScal];
       const double pd = double(p);
       const double qd = i0 * exp(-pd);
       q[r] = T(qd);
@@ -396,13 +440,15 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
   }
   if (part) {
     term = block_reduce<false>(term);
-    if (threadIdx.x == 0) part[blockIdx.x] = term;
+    if (threadIdx.x == 0) part[sc * gridDim.x + blockIdx.x] = term;
   }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_idiv_terms(int M, const T* __restrict__ q, const T* __restrict__ d,
                                                        double* __restrict__ part) {
+  q += int64_t(blockIdx.y) * M;
+  d += int64_t(blockIdx.y) * M;
   const int r = blockIdx.x * kBlock + threadIdx.x;
   double term = 0.0;
   if (r < M) {
@@ -411,7 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_idiv_terms(int M, const T* __restric
     if (dv > 0.0) term += dv * log(dv / qd);
   }
   term = block_reduce<false>(term);
-  if (threadIdx.x == 0) part[blockIdx.x] = term;
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = term;
 }
 
 // ------------------------------------------------------------------ node-driven gather
@@ -562,51 +608,103 @@ __device__ inline void item_finish(const DevGeom& g, uint32_t w, const ItemSums<
   }
 }
 
+// Arguments of the gather kernels. Scan p = blockIdx.y of a stack: its rays at y + p M,
+// its items, coefficients and outputs at + p n^2, Z0 at z0 + p kScal, held counter at
+// held + p kInts, partial sums at part + p pstride. The segment of scan p is level index
+// kseg of its counts (start = sum of the earlier levels) or, with counts null, the fixed
+// range [start, start + count); `count` is the largest segment length of the stack.
+template <typename T, typename R>
+struct GatherArgs {
+  DevGeom g;
+  const float2* vf;
+  const typename V4<R>::t* A;
+  const T* y;
+  const uint32_t* items;
+  const int* counts;
+  int kseg, start, count, chunks, vpc;
+  int64_t pstride;
+  R* part;
+  T* beta;
+  const T* b;
+  const double* z0;
+  int* held;
+  T *bp, *bm, *out;
+};
+
+template <typename T, typename R>
+struct ScanView {
+  const T* y;
+  const uint32_t* items;
+  T* beta;
+  const T* b;
+  const double* z0;
+  int* held;
+  T *bp, *bm, *out;
+  R* part;
+  int start, count;
+};
+
+template <typename T, typename R>
+__device__ inline ScanView<T, R> scan_view(const GatherArgs<T, R>& a) {
+  const int p = blockIdx.y;
+  const int64_t M = int64_t(a.g.nv) * a.g.nb, NN = int64_t(a.g.n) * a.g.n;
+  ScanView<T, R> v;
+  v.y = a.y + p * M;
+  v.items = at(a.items, p * NN);
+  v.beta = at(a.beta, p * NN);
+  v.b = at(a.b, p * NN);
+  v.z0 = at(a.z0, int64_t(p) * kScal);
+  v.held = at(a.held, int64_t(p) * kInts);
+  v.bp = at(a.bp, p * NN);
+  v.bm = at(a.bm, p * NN);
+  v.out = at(a.out, p * NN);
+  v.part = at(a.part, p * a.pstride);
+  v.start = a.start;
+  v.count = a.count;
+  if (a.counts) {
+    const int* c = a.counts + p * kInts;
+    int st = 0;
+    for (int k = 0; k < a.kseg; ++k) st += c[k];
+    v.start = st;
+    v.count = c[a.kseg];
+  }
+  return v;
+}
+
 // One lane per item of a level segment, all views (used when the segment alone fills the GPU).
 template <typename T, typename R, int MODE>
-__global__ __launch_bounds__(kBlock) void k_gather(DevGeom g, const float2* __restrict__ vf,
-                                                   const typename V4<R>::t* __restrict__ A,
-                                                   const T* __restrict__ y, const uint32_t* __restrict__ items,
-                                                   int start, int count, T* __restrict__ beta,
-                                                   const T* __restrict__ bvec, const double* __restrict__ z0p,
-                                                   int* __restrict__ held, T* __restrict__ bp_out,
-                                                   T* __restrict__ bm_out, T* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_gather(GatherArgs<T, R> a) {
+  const ScanView<T, R> v = scan_view(a);
   const int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= count) return;
-  const uint32_t w = item_word(items, start + k, g.n);
-  const ItemSums<R> r = item_sums<T, R>(g, vf, A, y, (w >> 31) != 0, int((w >> 27) & 15u),
-                                        int((w >> 13) & 0x1fffu), int(w & 0x1fffu), 0, g.nv);
-  item_finish<T, R, MODE>(g, w, r, beta, bvec, z0p, held, bp_out, bm_out, out);
+  if (k >= v.count) return;
+  const uint32_t w = item_word(v.items, v.start + k, a.g.n);
+  const ItemSums<R> r = item_sums<T, R>(a.g, a.vf, a.A, v.y, (w >> 31) != 0, int((w >> 27) & 15u),
+                                        int((w >> 13) & 0x1fffu), int(w & 0x1fffu), 0, a.g.nv);
+  item_finish<T, R, MODE>(a.g, w, r, v.beta, v.b, v.z0, v.held, v.bp, v.bm, v.out);
 }
 
 // (item, view chunk) tasks for a level segment whose items alone would leave the GPU idle.
 // A block of kChunkWaves waves takes 64 consecutive (spatially adjacent) items; wave w
 // handles view chunk kChunkWaves * group + w for all of them (uniform view range per wave).
 // The chunk sums are added in LDS in wave order (deterministic) and written to
-// part[group][slot][count].
+// part[group][slot][count] (count = the stack's largest segment length).
 constexpr int kChunkWaves = 4;
 
 template <typename T, typename R>
-__global__ __launch_bounds__(64 * kChunkWaves) void k_gather_part(DevGeom g, const float2* __restrict__ vf,
-                                                                  const typename V4<R>::t* __restrict__ A,
-                                                                  const T* __restrict__ y,
-                                                                  const uint32_t* __restrict__ items, int start,
-                                                                  int count, int chunks, int vpc,
-                                                                  R* __restrict__ part) {
+__global__ __launch_bounds__(64 * kChunkWaves) void k_gather_part(GatherArgs<T, R> a) {
   __shared__ R sh[kChunkWaves][7][64];
-  const int n_item_groups = (count + 63) / 64;
+  const ScanView<T, R> v = scan_view(a);
+  const int n_item_groups = (a.count + 63) / 64;
   const int ig = blockIdx.x % n_item_groups, group = blockIdx.x / n_item_groups;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int idx = ig * 64 + lane;
   const int chunk = group * kChunkWaves + wv;
   ItemSums<R> r{R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
-  bool quad = false;
-  if (idx < count && chunk < chunks) {
-    const uint32_t w = item_word(items, start + idx, g.n);
-    quad = (w >> 31) != 0;
-    const int v0 = chunk * vpc, v1 = min(g.nv, v0 + vpc);
-    r = item_sums<T, R>(g, vf, A, y, quad, int((w >> 27) & 15u), int((w >> 13) & 0x1fffu), int(w & 0x1fffu),
-                        v0, v1);
+  if (idx < v.count && chunk < a.chunks) {
+    const uint32_t w = item_word(v.items, v.start + idx, a.g.n);
+    const int v0 = chunk * a.vpc, v1 = min(a.g.nv, v0 + a.vpc);
+    r = item_sums<T, R>(a.g, a.vf, a.A, v.y, (w >> 31) != 0, int((w >> 27) & 15u), int((w >> 13) & 0x1fffu),
+                        int(w & 0x1fffu), v0, v1);
   }
   sh[wv][0][lane] = r.acc;
   sh[wv][1][lane] = r.pos0; sh[wv][2][lane] = r.pos1; sh[wv][3][lane] = r.pos2;
@@ -615,38 +713,34 @@ __global__ __launch_bounds__(64 * kChunkWaves) void k_gather_part(DevGeom g, con
   for (int k = threadIdx.x; k < 7 * 64; k += 64 * kChunkWaves) {
     const int slot = k / 64, l2 = k % 64;
     const int it = ig * 64 + l2;
-    if (it >= count) continue;
-    R v = R(0);
+    if (it >= v.count) continue;
+    R s = R(0);
 #pragma unroll
-    for (int w2 = 0; w2 < kChunkWaves; ++w2) v += sh[w2][slot][l2];
-    part[(size_t(group) * 7 + slot) * count + it] = v;
+    for (int w2 = 0; w2 < kChunkWaves; ++w2) s += sh[w2][slot][l2];
+    v.part[(size_t(group) * 7 + slot) * a.count + it] = s;
   }
 }
 
 // Sum the chunk groups of each item in group order (deterministic): 7 waves of a block each
 // add one slot for 64 consecutive items (coalesced), then one wave finishes the items.
 template <typename T, typename R, int MODE>
-__global__ __launch_bounds__(512) void k_gather_finish(DevGeom g, const uint32_t* __restrict__ items, int start,
-                                                       int count, int chunks, const R* __restrict__ part,
-                                                       T* __restrict__ beta, const T* __restrict__ bvec,
-                                                       const double* __restrict__ z0p, int* __restrict__ held,
-                                                       T* __restrict__ bp_out, T* __restrict__ bm_out,
-                                                       T* __restrict__ out) {
+__global__ __launch_bounds__(512) void k_gather_finish(GatherArgs<T, R> a) {
   __shared__ R sh[7][64];
+  const ScanView<T, R> v = scan_view(a);
   const int lane = threadIdx.x & 63, slot = threadIdx.x >> 6;
   const int idx = blockIdx.x * 64 + lane;
-  const int groups = (chunks + kChunkWaves - 1) / kChunkWaves;
+  const int groups = (a.chunks + kChunkWaves - 1) / kChunkWaves;
   if (slot < 7) {
-    R v = R(0);
-    if (idx < count)
-      for (int c = 0; c < groups; ++c) v += part[(size_t(c) * 7 + slot) * count + idx];
-    sh[slot][lane] = v;
+    R s = R(0);
+    if (idx < v.count)
+      for (int c = 0; c < groups; ++c) s += v.part[(size_t(c) * 7 + slot) * a.count + idx];
+    sh[slot][lane] = s;
   }
   __syncthreads();
-  if (slot != 0 || idx >= count) return;
-  const uint32_t w = item_word(items, start + idx, g.n);
+  if (slot != 0 || idx >= v.count) return;
+  const uint32_t w = item_word(v.items, v.start + idx, a.g.n);
   ItemSums<R> r{sh[0][lane], sh[1][lane], sh[2][lane], sh[3][lane], sh[4][lane], sh[5][lane], sh[6][lane]};
-  item_finish<T, R, MODE>(g, w, r, beta, bvec, z0p, held, bp_out, bm_out, out);
+  item_finish<T, R, MODE>(a.g, w, r, v.beta, v.b, v.z0, v.held, v.bp, v.bm, v.out);
 }
 
 // ------------------------------------------------------------------ Haar analysis
@@ -779,6 +873,7 @@ __global__ __launch_bounds__(kBlock) void k_z0(DevGeom g, const double2* __restr
                                                const uint8_t* __restrict__ lev, double* __restrict__ part_max,
                                                double* __restrict__ part_cnt) {
   const int M = g.nv * g.nb;
+  lev += int64_t(blockIdx.y) * g.n * g.n;
   const int r = blockIdx.x * kBlock + threadIdx.x;
   double sum = 0.0, cnt = 0.0;
   if (r < M) {
@@ -803,7 +898,11 @@ __global__ __launch_bounds__(kBlock) void k_z0(DevGeom g, const double2* __restr
   const double mx = block_reduce<true>(sum);
   __syncthreads();
   const double ct = block_reduce<false>(cnt);
-  if (threadIdx.x == 0) { part_max[blockIdx.x] = mx; part_cnt[blockIdx.x] = ct; }
+  if (threadIdx.x == 0) {
+    const int o = blockIdx.y * gridDim.x + blockIdx.x;
+    part_max[o] = mx;
+    part_cnt[o] = ct;
+  }
 }
 
 // ------------------------------------------------------------------ tree rule (Results)
@@ -812,9 +911,16 @@ __global__ __launch_bounds__(kBlock) void k_expand(DevGeom g, const uint8_t* __r
                                                    uint8_t* __restrict__ mask, const double* __restrict__ mu64,
                                                    const double* __restrict__ maxv, double frac,
                                                    int* __restrict__ n_split) {
+  const int n = g.n;
+  {
+    const int p = blockIdx.y;
+    const int64_t off = int64_t(p) * n * n;
+    old += off; mask += off; mu64 += off;
+    maxv += p * kScal;
+    n_split += p * kInts;
+  }
   // flattened node index over levels 1..L
   int k = blockIdx.x * kBlock + threadIdx.x;
-  const int n = g.n;
   int l = 1;
   for (; l <= g.L; ++l) {
     const int m = n >> l;
@@ -841,6 +947,7 @@ __global__ __launch_bounds__(kBlock) void k_check_mask(DevGeom g, const uint8_t*
                                                        int* __restrict__ bad) {
   const int z = blockIdx.x * kBlock + threadIdx.x;
   const int n = g.n;
+  mask += int64_t(blockIdx.y) * n * n;
   if (z >= n * n) return;
   const int r = z / n, c = z % n, L = g.L;
   const int nL = n >> L;
@@ -860,6 +967,7 @@ __global__ __launch_bounds__(kBlock) void k_check_mask(DevGeom g, const uint8_t*
 }
 
 __global__ void k_approx_mask(int n, int L, uint8_t* __restrict__ mask) {
+  mask += int64_t(blockIdx.y) * n * n;
   const int z = blockIdx.x * kBlock + threadIdx.x;
   if (z >= n * n) return;
   const int nL = n >> L;
@@ -875,6 +983,12 @@ __global__ __launch_bounds__(1024) void k_items(DevGeom g, const uint8_t* __rest
   __shared__ int wave_tot[16];
   __shared__ int base_sh;
   const int n = g.n, L = g.L;
+  {
+    const int64_t off = int64_t(blockIdx.x) * n * n;
+    mask += off;
+    items += off;
+    counts += blockIdx.x * kInts;
+  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (threadIdx.x == 0) base_sh = 0;
   __syncthreads();
@@ -882,9 +996,9 @@ __global__ __launch_bounds__(1024) void k_items(DevGeom g, const uint8_t* __rest
   for (int l = L; l >= lmin; --l) {
     const int level_start = base_sh;
     const int m = n >> l;
-    int P = 1;
-    while (P < m) P <<= 1;
-    const int64_t total = int64_t(P) * P;
+    int pw = 1;
+    while (pw < m) pw <<= 1;
+    const int64_t total = int64_t(pw) * pw;
     for (int64_t base = 0; base < total; base += 1024) {
       const int64_t kk = base + threadIdx.x;
       bool inc = false;
@@ -930,29 +1044,33 @@ __global__ void k_fill_i32(int* x, int64_t len, int v) {
   const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (p < len) x[p] = v;
 }
+__global__ void k_fill_i32_strided(int* x, int count, int stride, int v) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k < count) x[int64_t(k) * stride] = v;
+}
 
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
 
 template <typename T>
-void Launch<T>::synth(const DevGeom& g, const T* beta, T* mu, hipStream_t s) {
-  hipLaunchKernelGGL(k_synth<T>, dim3(blocks_for(int64_t(g.n) * g.n)), dim3(kBlock), 0, s, g.n, g.L, beta, mu);
+void Launch<T>::synth(const DevGeom& g, const T* beta, T* mu, int S, hipStream_t s) {
+  hipLaunchKernelGGL(k_synth<T>, dim3(blocks_for(int64_t(g.n) * g.n), S), dim3(kBlock), 0, s, g.n, g.L, beta, mu);
 }
 template <typename T>
-void Launch<T>::levmap(const DevGeom& g, const uint8_t* mask, uint8_t* lev, hipStream_t s) {
-  hipLaunchKernelGGL(k_levmap, dim3(blocks_for(int64_t(g.n) * g.n)), dim3(kBlock), 0, s, g.n, g.L, mask, lev);
+void Launch<T>::levmap(const DevGeom& g, const uint8_t* mask, uint8_t* lev, int S, hipStream_t s) {
+  hipLaunchKernelGGL(k_levmap, dim3(blocks_for(int64_t(g.n) * g.n), S), dim3(kBlock), 0, s, g.n, g.L, mask, lev);
 }
 template <typename T>
-void Launch<T>::synth_layouts(const DevGeom& g, const T* beta, T* muR, T* muC, hipStream_t s) {
-  const dim3 grid((g.n + 31) / 32, (g.n + 31) / 32);
+void Launch<T>::synth_layouts(const DevGeom& g, const T* beta, T* muR, T* muC, int S, hipStream_t s) {
+  const dim3 grid((g.n + 31) / 32, (g.n + 31) / 32, S);
   hipLaunchKernelGGL((k_synth_tiles<T, false>), grid, dim3(256), 0, s, g.n, g.L, beta, nullptr, muR, muC,
                      (Leaf<T>*)nullptr, (Leaf<T>*)nullptr);
 }
 template <typename T>
-void Launch<T>::synth_records(const DevGeom& g, const T* beta, const uint8_t* lev, void* leafR, void* leafC,
+void Launch<T>::synth_records(const DevGeom& g, const T* beta, const uint8_t* lev, void* leafR, void* leafC, int S,
                               hipStream_t s) {
-  const dim3 grid((g.n + 31) / 32, (g.n + 31) / 32);
+  const dim3 grid((g.n + 31) / 32, (g.n + 31) / 32, S);
   hipLaunchKernelGGL((k_synth_tiles<T, true>), grid, dim3(256), 0, s, g.n, g.L, beta, lev, (T*)nullptr, (T*)nullptr,
                      (Leaf<T>*)leafR, (Leaf<T>*)leafC);
 }
@@ -961,9 +1079,9 @@ void Launch<T>::transpose(int n, const T* in, T* out, hipStream_t s) {
   hipLaunchKernelGGL(k_transpose<T>, dim3((n + 31) / 32, (n + 31) / 32), dim3(256), 0, s, n, in, out);
 }
 template <typename T>
-int Launch<T>::idiv_terms(const DevGeom& g, const T* q, const T* d, double* part, hipStream_t s) {
+int Launch<T>::idiv_terms(const DevGeom& g, const T* q, const T* d, double* part, int S, hipStream_t s) {
   const int M = g.nv * g.nb, nb = blocks_for(M);
-  hipLaunchKernelGGL(k_idiv_terms<T>, dim3(nb), dim3(kBlock), 0, s, M, q, d, part);
+  hipLaunchKernelGGL(k_idiv_terms<T>, dim3(nb, S), dim3(kBlock), 0, s, M, q, d, part);
   return nb;
 }
 template <typename T>
@@ -971,14 +1089,14 @@ void Launch<T>::analysis(const DevGeom& g, const T* img, T* coef, hipStream_t s)
   hipLaunchKernelGGL(k_analysis<T>, dim3(blocks_for(int64_t(g.n) * g.n)), dim3(kBlock), 0, s, g.n, g.L, img, coef);
 }
 template <typename T>
-int Launch<T>::mu64(const DevGeom& g, const T* beta, double* mu64, double* part, hipStream_t s) {
+int Launch<T>::mu64(const DevGeom& g, const T* beta, double* mu64, double* part, int S, hipStream_t s) {
   const int nb = blocks_for(int64_t(g.n) * g.n);
-  hipLaunchKernelGGL(k_mu64<T>, dim3(nb), dim3(kBlock), 0, s, g.n, g.L, beta, mu64, part);
+  hipLaunchKernelGGL(k_mu64<T>, dim3(nb, S), dim3(kBlock), 0, s, g.n, g.L, beta, mu64, part);
   return nb;
 }
 template <typename T>
-void Launch<T>::apply_mask(const DevGeom& g, T* beta, const uint8_t* mask, hipStream_t s) {
-  const int64_t len = int64_t(g.n) * g.n;
+void Launch<T>::apply_mask(const DevGeom& g, T* beta, const uint8_t* mask, int S, hipStream_t s) {
+  const int64_t len = int64_t(g.n) * g.n * S;
   hipLaunchKernelGGL(k_apply_mask<T>, dim3(blocks_for(len)), dim3(kBlock), 0, s, len, beta, mask);
 }
 template <typename T>
@@ -1011,52 +1129,69 @@ void Geo<T, R>::view_table(const DevGeom& g, const double2* views, void* vF, hip
 }
 template <typename T, typename R>
 int Geo<T, R>::forward(const DevGeom& g, const void* A, const void* B, const T* muR, const T* muC, const T* d,
-                       const T* i0v, double i0s, T* q, T* p, double* part, hipStream_t s) {
+                       const T* i0v, const double* i0s, T* q, T* p, double* part, int S, hipStream_t s) {
   const int nb = blocks_for(int64_t(g.nv) * g.nb);
-  hipLaunchKernelGGL((k_forward<T, R, 8>), dim3(nb), dim3(kBlock), 0, s, g, (const typename V4<R>::t*)A,
+  hipLaunchKernelGGL((k_forward<T, R, 8>), dim3(nb, S), dim3(kBlock), 0, s, g, (const typename V4<R>::t*)A,
                      (const typename V4<R>::t*)B, muR, muC, d, i0v, i0s, q, p, part);
   return nb;
 }
 template <typename T, typename R>
 int Geo<T, R>::forward_records(const DevGeom& g, const void* A, const void* B, const void* leafR, const void* leafC,
-                               const T* d, const T* i0v, double i0s, T* q, T* p, double* part, hipStream_t s) {
+                               const T* d, const T* i0v, const double* i0s, T* q, T* p, double* part, int S,
+                               hipStream_t s) {
   const int nb = blocks_for(int64_t(g.nv) * g.nb);
-  hipLaunchKernelGGL((k_forward_rec<T, R>), dim3(nb), dim3(kBlock), 0, s, g, (const typename V4<R>::t*)A,
+  hipLaunchKernelGGL((k_forward_rec<T, R>), dim3(nb, S), dim3(kBlock), 0, s, g, (const typename V4<R>::t*)A,
                      (const typename V4<R>::t*)B, (const Leaf<T>*)leafR, (const Leaf<T>*)leafC, d, i0v, i0s, q, p,
                      part);
   return nb;
 }
+
+namespace {
+template <typename T, typename R, int MODE>
+void launch_segment(const GatherArgs<T, R>& a, int S, hipStream_t s) {
+  if (a.chunks <= 1) {
+    hipLaunchKernelGGL((k_gather<T, R, MODE>), dim3(blocks_for(a.count), S), dim3(kBlock), 0, s, a);
+    return;
+  }
+  const int groups = (a.chunks + kChunkWaves - 1) / kChunkWaves;
+  hipLaunchKernelGGL((k_gather_part<T, R>), dim3(((a.count + 63) / 64) * groups, S), dim3(64 * kChunkWaves), 0, s,
+                     a);
+  hipLaunchKernelGGL((k_gather_finish<T, R, MODE>), dim3((a.count + 63) / 64, S), dim3(512), 0, s, a);
+}
+}  // namespace
+
 template <typename T, typename R>
 void Geo<T, R>::gather(const DevGeom& g, int mode, const void* vF, const void* A, const T* y,
-                       const uint32_t* items, const Segment* segs, int n_segs, void* part, T* beta,
-                       const T* b, const double* z0, int* held, T* bp, T* bm, T* out, hipStream_t s) {
-  auto vf = (const float2*)vF;
-  auto a = (const typename V4<R>::t*)A;
-  auto pt = (R*)part;
-  const dim3 blk(kBlock);
+                       const uint32_t* items, const int* counts, const Segment* segs, int n_segs, void* part,
+                       T* beta, const T* b, const double* z0, int* held, T* bp, T* bm, T* out, int S,
+                       hipStream_t s) {
+  GatherArgs<T, R> a;
+  a.g = g;
+  a.vf = (const float2*)vF;
+  a.A = (const typename V4<R>::t*)A;
+  a.y = y;
+  a.items = items;
+  a.counts = counts;
+  a.part = (R*)part;
+  a.beta = beta;
+  a.b = b;
+  a.z0 = z0;
+  a.held = held;
+  a.bp = bp;
+  a.bm = bm;
+  a.out = out;
   for (int k = 0; k < n_segs; ++k) {
     const Segment& sg = segs[k];
     if (sg.count <= 0) continue;
-    if (sg.chunks <= 1) {
-      const dim3 grid(blocks_for(sg.count));
-      if (mode == kPlain)
-        hipLaunchKernelGGL((k_gather<T, R, kPlain>), grid, blk, 0, s, g, vf, a, y, items, sg.start, sg.count, beta, b, z0, held, bp, bm, out);
-      else if (mode == kSplit)
-        hipLaunchKernelGGL((k_gather<T, R, kSplit>), grid, blk, 0, s, g, vf, a, y, items, sg.start, sg.count, beta, b, z0, held, bp, bm, out);
-      else
-        hipLaunchKernelGGL((k_gather<T, R, kUpdate>), grid, blk, 0, s, g, vf, a, y, items, sg.start, sg.count, beta, b, z0, held, bp, bm, out);
-      continue;
-    }
-    const int groups = (sg.chunks + kChunkWaves - 1) / kChunkWaves;
-    hipLaunchKernelGGL((k_gather_part<T, R>), dim3(((sg.count + 63) / 64) * groups), dim3(64 * kChunkWaves), 0, s, g,
-                       vf, a, y, items, sg.start, sg.count, sg.chunks, sg.vpc, pt);
-    const dim3 grid((sg.count + 63) / 64), fblk(512);
-    if (mode == kPlain)
-      hipLaunchKernelGGL((k_gather_finish<T, R, kPlain>), grid, fblk, 0, s, g, items, sg.start, sg.count, sg.chunks, pt, beta, b, z0, held, bp, bm, out);
-    else if (mode == kSplit)
-      hipLaunchKernelGGL((k_gather_finish<T, R, kSplit>), grid, fblk, 0, s, g, items, sg.start, sg.count, sg.chunks, pt, beta, b, z0, held, bp, bm, out);
-    else
-      hipLaunchKernelGGL((k_gather_finish<T, R, kUpdate>), grid, fblk, 0, s, g, items, sg.start, sg.count, sg.chunks, pt, beta, b, z0, held, bp, bm, out);
+    a.kseg = sg.kseg;
+    a.start = sg.start;
+    a.count = sg.count;
+    a.chunks = sg.chunks;
+    a.vpc = sg.vpc;
+    a.pstride = segment_part_elems(sg, 1);
+    if (mode == kPlain) launch_segment<T, R, kPlain>(a, S, s);
+    else if (mode == kSplit) launch_segment<T, R, kSplit>(a, S, s);
+    else launch_segment<T, R, kUpdate>(a, S, s);
   }
 }
 
@@ -1065,35 +1200,44 @@ template struct Geo<float, double>;
 template struct Geo<double, double>;
 
 int z0_partials(const DevGeom& g, const double2* views, const uint8_t* lev, double* part_max,
-                double* part_cnt, hipStream_t s) {
+                double* part_cnt, int S, hipStream_t s) {
   const int nb = blocks_for(int64_t(g.nv) * g.nb);
   switch (g.L) {
 #define Z0_CASE(K) \
-    case K: hipLaunchKernelGGL(k_z0<K>, dim3(nb), dim3(kBlock), 0, s, g, views, lev, part_max, part_cnt); break;
+    case K: hipLaunchKernelGGL(k_z0<K>, dim3(nb, S), dim3(kBlock), 0, s, g, views, lev, part_max, part_cnt); break;
     Z0_CASE(0) Z0_CASE(1) Z0_CASE(2) Z0_CASE(3) Z0_CASE(4) Z0_CASE(5) Z0_CASE(6) Z0_CASE(7) Z0_CASE(8)
 #undef Z0_CASE
   }
   return nb;
 }
 void reduce_sum(const double* part, int n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce<false>, dim3(1), dim3(kBlock), 0, s, part, n, out);
+  hipLaunchKernelGGL(k_reduce<false>, dim3(1), dim3(kBlock), 0, s, part, n, int64_t(0), out, int64_t(0),
+                     (int*)nullptr);
 }
 void reduce_max(const double* part, int n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce<true>, dim3(1), dim3(kBlock), 0, s, part, n, out);
+  hipLaunchKernelGGL(k_reduce<true>, dim3(1), dim3(kBlock), 0, s, part, n, int64_t(0), out, int64_t(0),
+                     (int*)nullptr);
 }
-void build_items(const DevGeom& g, const uint8_t* mask, uint32_t* items, int* counts, hipStream_t s) {
-  hipLaunchKernelGGL(k_items, dim3(1), dim3(1024), 0, s, g, mask, items, counts);
+void reduce_stack(bool max, const double* part, int n, int64_t pstride, double* out, int64_t ostride, int* ctr,
+                  int S, hipStream_t s) {
+  if (max)
+    hipLaunchKernelGGL(k_reduce<true>, dim3(S), dim3(kBlock), 0, s, part, n, pstride, out, ostride, ctr);
+  else
+    hipLaunchKernelGGL(k_reduce<false>, dim3(S), dim3(kBlock), 0, s, part, n, pstride, out, ostride, ctr);
+}
+void build_items(const DevGeom& g, const uint8_t* mask, uint32_t* items, int* counts, int S, hipStream_t s) {
+  hipLaunchKernelGGL(k_items, dim3(S), dim3(1024), 0, s, g, mask, items, counts);
 }
 void expand(const DevGeom& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64,
-            const double* maxv, double frac, int* n_split, hipStream_t s) {
+            const double* maxv, double frac, int* n_split, int S, hipStream_t s) {
   int64_t nodes = 0;
   for (int l = 1; l <= g.L; ++l) nodes += int64_t(g.n >> l) * (g.n >> l);
   if (nodes == 0) return;
-  hipLaunchKernelGGL(k_expand, dim3(blocks_for(nodes)), dim3(kBlock), 0, s, g, mask_old, mask, mu64, maxv,
+  hipLaunchKernelGGL(k_expand, dim3(blocks_for(nodes), S), dim3(kBlock), 0, s, g, mask_old, mask, mu64, maxv,
                      frac, n_split);
 }
-void check_mask(const DevGeom& g, const uint8_t* mask, int* bad, hipStream_t s) {
-  hipLaunchKernelGGL(k_check_mask, dim3(blocks_for(int64_t(g.n) * g.n)), dim3(kBlock), 0, s, g, mask, bad);
+void check_mask(const DevGeom& g, const uint8_t* mask, int* bad, int S, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_mask, dim3(blocks_for(int64_t(g.n) * g.n), S), dim3(kBlock), 0, s, g, mask, bad);
 }
 void fill_u8(uint8_t* x, int64_t len, uint8_t v, hipStream_t s) {
   if (len > 0) hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(len)), dim3(kBlock), 0, s, x, len, v);
@@ -1101,8 +1245,11 @@ void fill_u8(uint8_t* x, int64_t len, uint8_t v, hipStream_t s) {
 void fill_i32(int* x, int64_t len, int v, hipStream_t s) {
   if (len > 0) hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(len)), dim3(kBlock), 0, s, x, len, v);
 }
-void approx_mask(const DevGeom& g, uint8_t* mask, hipStream_t s) {
-  hipLaunchKernelGGL(k_approx_mask, dim3(blocks_for(int64_t(g.n) * g.n)), dim3(kBlock), 0, s, g.n, g.L, mask);
+void fill_i32_strided(int* x, int count, int stride, int v, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_fill_i32_strided, dim3(blocks_for(count)), dim3(kBlock), 0, s, x, count, stride, v);
+}
+void approx_mask(const DevGeom& g, uint8_t* mask, int S, hipStream_t s) {
+  hipLaunchKernelGGL(k_approx_mask, dim3(blocks_for(int64_t(g.n) * g.n), S), dim3(kBlock), 0, s, g.n, g.L, mask);
 }
 
 }  // namespace wamct
