@@ -1,4 +1,4 @@
-"""Benchmark: tree-adaptive wavelet AM on one MI355X (fan512 workload).
+"""Benchmark: tree-adaptive wavelet AM on one MI355X (fan512 workload by default).
 
 A step is one complete reconstruction of Algorithm 1 with the tree rule: 100 iterations
 from beta = 0 on the approximation-only 3-level tree, expanding at iterations 21, 43 and 85
@@ -9,9 +9,13 @@ Extra fields:
   gray_voxel_per_s  sum_j 2 W_j / time, W_j = (ray, active coefficient) pairs with phi != 0
   full_am           image-domain AM (levels = 0) on the same GPU: it/s, and the time it
                     needs to reach the tree run's final I-divergence (equal-objective)
-  roofline          the update kernel (sign-split backprojection + eq. 1.9 zero), timed with
-                    HIP events on the library's stream over the timed steps
+  roofline          the tree walk (forward projection over the leaves, Beer's law, I-div
+                    term), timed with HIP events on the library's stream over the timed steps;
+                    roofline_update: the update pass, likewise
   cpu_baseline      the FP64 CPU oracle on a bounded sample of the same workload
+
+Other workloads: --config uneven (256 independent problems of uneven size solved as one
+batch, graph-replayed) and --config loss16 (differentiable loss + adjoint, 16 slices).
 """
 import argparse
 import hashlib
@@ -216,6 +220,74 @@ def bench_uneven(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_loss(args):
+    """Differentiable path: loss_b = I(d_b || I0 exp(-H Omega c_b)) and its hand-written
+    adjoint for a batch of 16 slices of the 256x256 fan-beam scan (360 views, 512 bins,
+    2-level Haar, every coefficient free, I0 = 5e4). A step is one loss + gradient
+    evaluation of the whole batch through the autograd function."""
+    import numpy as np
+    import torch
+    from paper_1508_04458_amd import api, synth
+    from paper_1508_04458_amd.autograd import wam_loss
+
+    B = 16
+    probs = [synth.make_problem("fan256", problem_idx=k) for k in range(B)]
+    g = probs[0].geom
+    L = probs[0].levels
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ctx = api.Context(g, L, "f32", device=dev, geometry=args.geometry)
+    d = torch.as_tensor(np.stack([P.d for P in probs]), dtype=torch.float32, device=dev)
+    # coefficients: random small values (the work does not depend on them)
+    c0 = np.stack([synth.random_image(g.n, 100 + k, 0.0, 0.004) for k in range(B)])
+    c = torch.as_tensor(c0, dtype=torch.float32, device=dev).requires_grad_(True)
+    i0 = probs[0].i0
+
+    def step():
+        c.grad = None
+        loss = wam_loss(c, d, i0, ctx)
+        loss.sum().backward()
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing(True, ("forward", "update"))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tim = ctx.get_timing()
+    ctx.timing(False)
+    full = api.Context(g, 0, "f32", device=dev, geometry=args.geometry)
+    nnz = full.tree_stats()["w"]                       # nonzeros of H (every pixel active)
+    full.close()
+    M = g.n_rays
+    ms_step = dt * 1e3 / args.steps
+    # forward pixel walk: 8 B per nonzero of H (stored-matrix equivalent) + d, q per ray
+    fw = tim["forward"]
+    fw_ms = fw["ms"] / max(1, fw["launches"])
+    alg_fw = 8.0 * nnz + 12.0 * M
+    roof = {"bound": "hbm", "achieved": round(alg_fw / (fw_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(alg_fw / (fw_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_forward<float,double,8>", "avg_launch_ms": round(fw_ms, 5), "launches": fw["launches"],
+            "alg_bytes_per_launch": int(alg_fw)}
+    out = {"metric": METRIC, "value": round(args.steps / dt, 3), "unit": "loss+grad evals/s (16-slice batch)",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 data, f64 ray geometry, f64 loss", "data": "synthetic",
+           "config": {"workload": f"differentiable loss: {B} fan-beam slices {g.n}x{g.n}, {g.n_views} views x "
+                                  f"{g.n_bins} bins, {L}-level Haar (all coefficients), I0 = {i0:g}",
+                      "batch": B, "rays": M, "pixels": g.n * g.n},
+           "slice_evals_per_s": round(B * args.steps / dt, 2),
+           "gray_voxel_per_s": round(2 * nnz * B * args.steps / dt / 1e9, 3),
+           "time_ms_per_step_by_kernel": {k: round(v["ms"] / args.steps, 4) for k, v in tim.items()
+                                          if k in ("forward", "update")},
+           "roofline": roof}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -224,6 +296,9 @@ def main():
         sys.exit(2)
     if args.config == "uneven":
         bench_uneven(args)
+        return
+    if args.config == "loss16":
+        bench_loss(args)
         return
     if args.no_cpu_baseline is False:
         # the CPU baseline is a single-threaded oracle
@@ -264,7 +339,8 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ctx.timing(True)
+    # HIP events around the two kernel classes whose rooflines are reported
+    ctx.timing(True, ("forward", "update"))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -301,7 +377,7 @@ def main():
                "traffic": measured_traffic(khash, args.config, "update"),
                "kernels": "k_gather_part + k_gather_finish (+ k_gather) per tree level",
                "avg_pass_ms": round(upd_ms, 5), "passes": up["launches"], "alg_bytes_per_pass": int(alg_up)}
-    timing_ms = {k: round(v["ms"] / args.steps, 4) for k, v in tim.items()}
+    timing_ms = {k: round(v["ms"] / args.steps, 4) for k, v in tim.items() if k in ("forward", "update")}
 
     out = {"metric": METRIC, "value": round(it_s, 2), "unit": "AM iter/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),

@@ -197,10 +197,14 @@ wamct_status wamct_loss(wamct_ctx* ctx, int32_t batch, const void* c, const void
 wamct_status wamct_loss_backward(wamct_ctx* ctx, int32_t batch, const void* q, const void* d,
                                  const double* gscale, void* grad);
 
-/* Kernel timing with HIP events on the context's stream: enable != 0 starts recording
- * (and clears the totals). wamct_get_timing synchronizes and returns, per kernel class
- * (WAMCT_K_*), the summed duration in ms and the launch count (arrays of WAMCT_NK). */
-wamct_status wamct_timing(wamct_ctx* ctx, int32_t enable);
+/* Kernel timing with HIP events on the context's stream. classes: bit k set = record the
+ * launches of kernel class k (WAMCT_K_*), each bracketed by two events; 0 stops recording;
+ * WAMCT_TIME_ALL records every class; values outside [0, WAMCT_TIME_ALL] give E_INVALID.
+ * The call synchronizes and clears the totals. Events add a few microseconds per recorded
+ * launch, so record only the classes needed. wamct_get_timing synchronizes and returns, per
+ * kernel class, the summed duration in ms and the launch count (arrays of WAMCT_NK). */
+#define WAMCT_TIME_ALL ((1 << WAMCT_NK) - 1)
+wamct_status wamct_timing(wamct_ctx* ctx, int32_t classes);
 wamct_status wamct_get_timing(wamct_ctx* ctx, double* ms, int64_t* launches);
 
 /* Tiling of the node-driven backprojection: a level segment whose items (over the whole

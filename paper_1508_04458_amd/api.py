@@ -235,8 +235,15 @@ class Context:
         return grad
 
     # ------------------------------------------------------------------ timing
-    def timing(self, enable: bool) -> None:
-        self._call(lib.wamct_timing, 1 if enable else 0)
+    def timing(self, enable: bool, classes: Optional[Sequence[str]] = None) -> None:
+        """Record kernel durations with HIP events (all classes, or the named ones of
+        "synth", "forward", "update", "tree", "other"); enable=False stops."""
+        mask = 0
+        if enable:
+            names = _lib.KERNEL_CLASSES if classes is None else classes
+            for c in names:
+                mask |= 1 << _lib.KERNEL_CLASSES.index(c)
+        self._call(lib.wamct_timing, mask)
 
     def get_timing(self) -> Dict[str, Dict[str, float]]:
         ms = (ctypes.c_double * _lib.NK)()

@@ -141,7 +141,7 @@ struct Ctx final : wamct_ctx {
   T *d = nullptr, *i0v = nullptr, *q = nullptr;
   T *beta = nullptr, *b = nullptr, *mu = nullptr, *muT = nullptr;
   T* img = nullptr;           // one image (operators, precompute)
-  void *leafR = nullptr, *leafC = nullptr;  // leaf records (value, level) for the tree walk
+  void *leafR = nullptr, *leafC = nullptr;  // leaf records (value | level) for the tree walk
   uint8_t *mask = nullptr, *mask_old = nullptr, *lev = nullptr;
   uint32_t* items = nullptr;
   double *partd = nullptr, *part2 = nullptr, *mu64 = nullptr;
@@ -162,7 +162,7 @@ struct Ctx final : wamct_ctx {
   int32_t iters = 0;
   int target_lanes = kTargetLanes;
   // timing
-  bool timing_on = false;
+  uint32_t timing_mask = 0;   // bit k: record kernel class k
   struct Rec { int kind; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
@@ -226,7 +226,7 @@ struct Ctx final : wamct_ctx {
   struct Scope {
     Ctx* c; int kind; hipStream_t s; hipEvent_t a = nullptr;
     Scope(Ctx* c_, int k, hipStream_t s_) : c(c_), kind(k), s(s_) {
-      if (c->timing_on && s == c->st) { a = c->ev(); hipEventRecord(a, s); }
+      if (((c->timing_mask >> kind) & 1u) && s == c->st) { a = c->ev(); hipEventRecord(a, s); }
     }
     ~Scope() {
       if (a) {
@@ -334,8 +334,8 @@ struct Ctx final : wamct_ctx {
     CHECKED(alloc(beta, NN * P)); CHECKED(alloc(b, NN * P));
     CHECKED(alloc(mu, NN * P)); CHECKED(alloc(muT, NN * P)); CHECKED(alloc(img, NN));
     if (g.L > 0) {
-      CHECKED(alloc_bytes(leafR, 2 * sizeof(T) * size_t(NN * P)));
-      CHECKED(alloc_bytes(leafC, 2 * sizeof(T) * size_t(NN * P)));
+      CHECKED(alloc_bytes(leafR, sizeof(T) * size_t(NN * P)));
+      CHECKED(alloc_bytes(leafC, sizeof(T) * size_t(NN * P)));
     }
     CHECKED(alloc(mask, NN * P)); CHECKED(alloc(mask_old, NN * P)); CHECKED(alloc(lev, NN * P));
     CHECKED(alloc(items, NN * P)); CHECKED(alloc(mu64, NN * P));
@@ -750,7 +750,8 @@ struct Ctx final : wamct_ctx {
     HIPCHK(hipStreamSynchronize(st));
     harvest();
     for (int k = 0; k < WAMCT_NK; ++k) { tot_ms[k] = 0; tot_n[k] = 0; }
-    timing_on = on != 0;
+    if (on < 0 || on >= (1 << WAMCT_NK)) return fail(WAMCT_E_INVALID, fmt("timing mask %d outside [0, %d]", on, (1 << WAMCT_NK) - 1));
+    timing_mask = uint32_t(on);
     return WAMCT_OK;
   }
 

@@ -184,12 +184,28 @@ __global__ __launch_bounds__(kBlock) void k_levmap(int n, int L, const uint8_t* 
 
 // ------------------------------------------------------------------ image layouts
 
-// Leaf record of the forward walk: the (leaf-constant) value at a pixel and the level of
-// the tree leaf containing it, read with one load per step.
+// Leaf record of the forward walk, one word per pixel read with one load per step: the
+// (leaf-constant) value at the pixel rounded to the nearest value whose 4 low mantissa
+// bits are zero (relative rounding <= 2^-20 in FP32, 2^-49 in FP64), with the level of the
+// tree leaf containing the pixel (0..8) stored in those 4 bits. Half the bytes of a
+// (value, level) pair, so a wave's scattered loads touch fewer cache lines.
 template <typename T>
-struct alignas(2 * sizeof(T)) Leaf {
-  T mu;
-  uint32_t lev;
+struct Leaf;
+template <>
+struct Leaf<float> {
+  uint32_t w;
+  __device__ static Leaf make(float v, uint32_t lev) { return Leaf{((__float_as_uint(v) + 8u) & ~15u) | lev}; }
+  __device__ float mu() const { return __uint_as_float(w & ~15u); }
+  __device__ uint32_t lev() const { return w & 15u; }
+};
+template <>
+struct Leaf<double> {
+  uint64_t w;
+  __device__ static Leaf make(double v, uint32_t lev) {
+    return Leaf{((uint64_t(__double_as_longlong(v)) + 8u) & ~uint64_t(15)) | lev};
+  }
+  __device__ double mu() const { return __longlong_as_double((long long)(w & ~uint64_t(15))); }
+  __device__ uint32_t lev() const { return uint32_t(w & 15u); }
 };
 
 // mu = Omega beta over 32x32 pixel tiles, written twice: row-major and column-major (the
@@ -220,7 +236,7 @@ __global__ __launch_bounds__(256) void k_synth_tiles(int n, int L, const T* __re
       if (TREE) {
         const uint8_t lv = lev[r * n + c];
         ltile[ty + 8 * k][tx] = lv;
-        leafR[r * n + c] = Leaf<T>{v, lv};
+        leafR[r * n + c] = Leaf<T>::make(v, lv);
       } else {
         muR[r * n + c] = v;
       }
@@ -233,7 +249,7 @@ __global__ __launch_bounds__(256) void k_synth_tiles(int n, int L, const T* __re
     if (r < n && c < n) {
       const T v = tile[tx][ty + 8 * k];
       if (TREE)
-        leafC[c * n + r] = Leaf<T>{v, ltile[tx][ty + 8 * k]};
+        leafC[c * n + r] = Leaf<T>::make(v, ltile[tx][ty + 8 * k]);
       else
         muC[c * n + r] = v;
     }
@@ -401,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
       Leaf<T> rec = base[xmaj ? ix * n + iy : iy * n + ix];
       R t = t_in;
       for (int step = 0; step < 4 * n + 8; ++step) {
-        const int l = int(rec.lev);
+        const int l = int(rec.lev());
         const int s = 1 << l;
         const int bx0 = (ix >> l) << l, by0 = (iy >> l) << l;
         const R tX = ((R(px ? bx0 + s : bx0) - hn) * pix - ox) * iex;
@@ -421,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
         const bool go = te < t_out && (unsigned)nix < (unsigned)n && (unsigned)niy < (unsigned)n;
         Leaf<T> nrec = rec;
         if (go) nrec = base[xmaj ? nix * n + niy : niy * n + nix];
-        acc += (te - t) * R(rec.mu);
+        acc += (te - t) * R(rec.mu());
         if (!go) break;
         t = te; ix = nix; iy = niy; rec = nrec;
       }
