@@ -19,8 +19,9 @@ Iterative Image Reconstruction for X-Ray Imaging for Security Applications"
   wam.py       Phi = H Omega, b (eq. 1.6), Z0 (eq. 1.61), b-hat+/- (eq. 1.10), the
                closed-form zero of eq. 1.9, Algorithm 1, the tree-expansion rule of the
                Results section, unregularized pixel AM (Omega = I), the I-divergence,
-               the surrogate of eq. 1.8, and the loss/gradient of the coefficient-domain
-               problem (eq. 1.3 with lambda = 0)
+               the surrogate of eq. 1.8, the loss/gradient of the coefficient-domain
+               problem (eq. 1.3 with lambda = 0), and wavelet AM combined with ordered
+               subsets of views (Conclusion)
 
 Parity status: every function is pinned by the `-m "not gpu"` tests in
 tests/test_oracle_*.py (closed forms, brute force, invariants, a hand-computed golden

@@ -198,6 +198,76 @@ def wam_solve(H, n, levels, d, i0, n_iters, pixel, schedule=(), frac=0.1, masks=
     return out
 
 
+def subset_rows(n_views, n_bins, n_subsets):
+    """Rays of each ordered subset: subset s holds the views v with v mod S = s (interleaved
+    views, each subset spanning the whole angular range), in view-major ray order."""
+    if not 1 <= n_subsets <= n_views:
+        raise ValueError("need 1 <= n_subsets <= n_views")
+    return [(np.arange(s, n_views, n_subsets)[:, None] * n_bins + np.arange(n_bins)[None, :]).ravel()
+            for s in range(n_subsets)]
+
+
+def os_wam_solve(H, n, levels, d, i0, n_iters, pixel, n_views, n_subsets, schedule=(), frac=0.1,
+                 Omega=None, record_sub=False, beta0=None, mask0=None):
+    """Wavelet AM combined with ordered subsets (the combination the Conclusion names).
+
+    The views are split into S interleaved subsets (`subset_rows`). Pass j applies the tree
+    rule first when j is in `schedule`, then S sub-iterations; sub-iteration s is the update
+    of Algorithm 1 with the data term restricted to the rays Y_s of subset s:
+      q-hat = I0 exp(-Phi_s beta) on Y_s, b_s(z) = sum_{y in Y_s} d(y) phi(y|z) (eq. 1.6 on
+      Y_s), b-hat+/- over Y_s (eq. 1.10), Z0_s = max_{y in Y_s} sum_z |phi(y|z)| (eq. 1.61
+      on Y_s), and the zero of eq. 1.9 with these sums.
+    Each sub-iteration is an exact AM step for I(d_s || q_s), so it cannot increase that
+    subset's I-divergence; the full I-divergence is not guaranteed to fall.
+    Returns beta, mu, idiv (n_iters + 1 values: I(d||q-hat) over all rays before each pass
+    and after the last), trees, z0 (per tree: the S values Z0_s), the per-subset b_s, the
+    held count and, with record_sub, (I(d_s||q_s) before, after) for every sub-iteration.
+    beta0/mask0: starting coefficients and tree (default 0 and the approximation-only tree)."""
+    if Omega is None:
+        Omega = haar.synthesis_matrix(n, levels)
+    d = np.asarray(d, np.float64)
+    i0 = np.asarray(i0, np.float64)
+    rows = subset_rows(n_views, H.shape[0] // n_views, n_subsets)
+    i0_of = [i0 if i0.ndim == 0 else i0[r] for r in rows]
+    b_sub = [Omega.T @ (H[r].T @ d[r]) for r in rows]
+    beta = np.zeros(n * n) if beta0 is None else np.array(beta0, np.float64).ravel()
+    mask = haar.approx_mask(n, levels) if mask0 is None else np.array(mask0, np.uint8)
+    trace, trees, z0s, sub, held_total = [], [], [], [], 0
+    Phi = None
+    for j in range(n_iters):
+        changed = False
+        if j in schedule:
+            mask, _ = expand_tree(beta, mask, levels, frac, Omega)
+            changed = True
+        if Phi is None or changed:
+            Phi, act = phi_matrix(H, Omega, mask, pixel)
+            parts = []
+            for r in rows:
+                Ps = Phi[r]
+                Psp, Psm = split_phi(Ps)
+                z = float(np.max(np.asarray(abs(Ps).sum(axis=1)).ravel()))
+                if not z > 0:
+                    raise ValueError("a subset has no ray crossing the image (Z0_s = 0)")
+                parts.append((Ps, Psp, Psm, z))
+            trees.append((j, mask.copy()))
+            z0s.append([p[3] for p in parts])
+        trace.append(idiv(d, beer_mean(i0, Phi @ beta[act])))
+        for s, (Ps, Psp, Psm, z) in enumerate(parts):
+            q_s = beer_mean(i0_of[s], Ps @ beta[act])
+            before = idiv(d[rows[s]], q_s) if record_sub else None
+            delta, held = closed_form_update(b_sub[s][act], Psp.T @ q_s, Psm.T @ q_s, z)
+            held_total += int(held.sum())
+            beta[act] += delta
+            if record_sub:
+                sub.append((before, idiv(d[rows[s]], beer_mean(i0_of[s], Ps @ beta[act]))))
+    trace.append(idiv(d, beer_mean(i0, H @ (Omega @ beta))))
+    out = dict(beta=beta.reshape(n, n), mu=(Omega @ beta).reshape(n, n), idiv=np.array(trace), trees=trees,
+               z0=z0s, b_sub=[b.reshape(n, n) for b in b_sub], held=held_total, mask=mask)
+    if record_sub:
+        out["sub"] = sub
+    return out
+
+
 def am_solve(H, n, d, i0, n_iters, pixel, mu0=None):
     """Unregularized image-domain AM (O'Sullivan-Benac): Algorithm 1 with Omega = I."""
     return wam_solve(H, n, 0, d, i0, n_iters, pixel, beta0=mu0)
