@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--cpu-views", type=int, default=36)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized buffer 3 times (reference kernel for PMC byte counters)")
+    ap.add_argument("--os-subsets", type=int, default=8, help="fan512: ordered-subsets comparison (0 = skip)")
     ap.add_argument("--problems", type=int, default=256, help="uneven: number of problems")
     ap.add_argument("--streams", type=int, default=4, help="uneven: streams of the batch")
     ap.add_argument("--no-graph", action="store_true", help="uneven: launch directly instead of graph replay")
@@ -424,6 +425,31 @@ def main():
         out["pixel_equiv_gray_voxel_per_s"] = round(2 * w_pix * it_s / 1e9, 3)
         out["equal_idiv"] = eq
         full.close()
+
+    # ---- wavelet AM with ordered subsets of views (same tree schedule, passes of S updates)
+    if args.os_subsets > 1:
+        S = args.os_subsets
+        osc = api.Context(g, P.levels, "f32", device=dev, geometry=args.geometry)
+        osc.set_subsets(S)
+        osc.set_data(d, P.i0)
+        osc.reset()
+        otr = osc.solve(J, sched, 0.1).cpu().numpy()          # traced run (untimed)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(2):
+            osc.reset()
+            osc.solve(J, sched, 0.1, trace=False)
+        torch.cuda.synchronize()
+        t_os = (time.perf_counter() - t2) / 2
+        target = tr[-1]
+        hit = np.nonzero(otr <= target)[0]
+        k_os = int(hit[0]) if hit.size else None
+        out["ordered_subsets"] = {
+            "subsets": S, "passes": J, "ms_per_solve": round(t_os * 1e3, 3), "pass_per_s": round(J / t_os, 2),
+            "final_idiv": float(otr[-1]), "passes_to_tree_final_idiv": k_os,
+            "time_to_tree_final_idiv_ms": None if k_os is None else round(k_os * t_os / J * 1e3, 3),
+            "idiv_at_pass": {str(k): float(otr[k]) for k in (1, 2, 5, 10, 21, 43, 85) if k <= J}}
+        osc.close()
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_views)

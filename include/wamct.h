@@ -215,6 +215,20 @@ wamct_status wamct_get_timing(wamct_ctx* ctx, double* ms, int64_t* launches);
 wamct_status wamct_set_tiling(wamct_ctx* ctx, int32_t lanes);
 wamct_status wamct_get_tiling(wamct_ctx* ctx, int32_t* lanes);
 
+/* Ordered subsets of views (the combination with ordered subsets that the Conclusion names;
+ * 1 <= n_subsets <= n_views, default 1 = Algorithm 1 as written). Subset k holds the views
+ * v with v mod n_subsets = k. With n_subsets > 1 every iteration of wamct_iterate,
+ * wamct_solve and batches becomes a pass of n_subsets updates; update k is the Algorithm 1
+ * update with q-hat, b (eq. 1.6), b-hat+/- (eq. 1.10) and Z0 (eq. 1.61) all taken over the
+ * rays of subset k, so it cannot increase that subset's I-divergence (the full I-divergence
+ * is not guaranteed to fall). The idiv entries are I(d || q-hat) over all rays before each
+ * pass (an extra full forward pass per iteration when idiv is not NULL) and after the last.
+ * Precomputes b of every subset (now if data are set, else in wamct_set_data: [n_subsets]
+ * extra coefficient arrays per scan) and a Z0 per subset at every tree change; E_INVALID if
+ * a subset has no ray crossing the image. Synchronizes; may allocate. */
+wamct_status wamct_set_subsets(wamct_ctx* ctx, int32_t n_subsets);
+wamct_status wamct_get_subsets(wamct_ctx* ctx, int32_t* n_subsets);
+
 /* ---------------------------------------------------------------- batches
  * Uneven batches: several contexts (different geometries, image sizes and view counts,
  * each a stack of scans) solved together. Each context is bound to one of n_streams

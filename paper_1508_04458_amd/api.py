@@ -140,13 +140,26 @@ class Context:
         return self._per_scan(ns)
 
     def solve(self, n_iters: int, schedule: Sequence[int] = (), frac: float = 0.1,
-              idiv: Optional[torch.Tensor] = None) -> torch.Tensor:
-        if idiv is None:
+              idiv: Optional[torch.Tensor] = None, trace: bool = True) -> Optional[torch.Tensor]:
+        """Algorithm 1 with the tree schedule; returns the I-divergence trace [S, n_iters + 1]
+        (None with trace=False, which also skips the extra full forward pass per iteration
+        of ordered subsets)."""
+        if idiv is None and trace:
             idiv = self._new(self.S * (n_iters + 1), torch.float64, self._shape(n_iters + 1))
-        self._arr(idiv, self.S * (n_iters + 1), "idiv", torch.float64)
+        if idiv is not None:
+            self._arr(idiv, self.S * (n_iters + 1), "idiv", torch.float64)
         sched = (ctypes.c_int32 * max(1, len(schedule)))(*[int(s) for s in schedule])
         self._call(lib.wamct_solve, int(n_iters), sched, len(schedule), float(frac), _ptr(idiv))
         return idiv
+
+    def set_subsets(self, n_subsets: int) -> None:
+        """Ordered subsets of views: every iteration becomes a pass of n_subsets updates."""
+        self._call(lib.wamct_set_subsets, int(n_subsets))
+
+    def subsets(self) -> int:
+        v = ctypes.c_int32()
+        self._call(lib.wamct_get_subsets, ctypes.byref(v))
+        return v.value
 
     def set_tiling(self, lanes: int) -> None:
         self._call(lib.wamct_set_tiling, int(lanes))

@@ -85,6 +85,8 @@ struct wamct_ctx {
   virtual wamct_status get_timing(double*, int64_t*) = 0;
   virtual wamct_status set_tiling(int32_t) = 0;
   virtual int32_t tiling() const = 0;
+  virtual wamct_status set_subsets(int32_t) = 0;
+  virtual int32_t subsets() const = 0;
   // stream-ordered pieces used by batches (no host synchronization inside)
   virtual int n_scans() const = 0;
   virtual hipStream_t stream() const = 0;
@@ -155,7 +157,12 @@ struct Ctx final : wamct_ctx {
   int64_t part_cap = 0;       // elements of R
   int* h_ints = nullptr;      // pinned host copies read after a tree rebuild
   double* h_scal = nullptr;
-  std::vector<Segment> segs, pix_segs;
+  // ordered subsets of views (n_sub > 1): b and Z0 of every subset, [n_sub][P][...]
+  int n_sub = 1;
+  T* bsub = nullptr;
+  double* z0s = nullptr;
+  double* h_z0s = nullptr;
+  std::vector<Segment> segs, pix_segs, segs_sub, pix_segs_sub;
   std::vector<void*> allocs;
   // host state
   bool has_data = false, tree_dirty = true, i0v_used = false;
@@ -176,6 +183,7 @@ struct Ctx final : wamct_ctx {
     for (auto e : pool) hipEventDestroy(e);
     for (void* p : allocs) hipFree(p);
     if (part) hipFree(part);
+    free_subsets();
     if (h_ints) hipHostFree(h_ints);
     if (h_scal) hipHostFree(h_scal);
   }
@@ -239,15 +247,15 @@ struct Ctx final : wamct_ctx {
   };
 
   // ---------------------------------------------------------------- tiling of the gather
-  // Split the views of a level segment into chunks when its items (over the S scans of
+  // Split the nv views of a level segment into chunks when its items (over the S scans of
   // one launch) alone cannot fill the GPU.
-  Segment make_segment(int kseg, int start, int count, int level, int S) const {
-    Segment sg{kseg, start, count, level, 1, g.nv};
+  Segment make_segment(int kseg, int start, int count, int level, int S, int nv) const {
+    Segment sg{kseg, start, count, level, 1, nv};
     const int64_t lanes = int64_t(count) * S;
     if (count > 0 && lanes < target_lanes) {
-      int chunks = int(std::min<int64_t>(g.nv, (target_lanes + lanes - 1) / lanes));
-      const int vpc = (g.nv + chunks - 1) / chunks;
-      chunks = (g.nv + vpc - 1) / vpc;
+      int chunks = int(std::min<int64_t>(nv, (target_lanes + lanes - 1) / lanes));
+      const int vpc = (nv + chunks - 1) / chunks;
+      chunks = (nv + vpc - 1) / vpc;
       sg.chunks = chunks;
       sg.vpc = vpc;
     }
@@ -278,13 +286,21 @@ struct Ctx final : wamct_ctx {
   }
   void build_segs() {
     segs.clear();
+    segs_sub.clear();
     const int n_levels = g.L == 0 ? 1 : g.L;
     for (int k = 0; k < n_levels; ++k) {
       int mx = 0;
       for (int p = 0; p < P; ++p) mx = std::max(mx, h_ints[p * kInts + 9 + k]);
-      if (mx > 0) segs.push_back(make_segment(k, 0, mx, g.L - k, P));
+      if (mx > 0) {
+        segs.push_back(make_segment(k, 0, mx, g.L - k, P, g.nv));
+        segs_sub.push_back(make_segment(k, 0, mx, g.L - k, P, sub_views(0)));
+      }
     }
-    pix_segs = {make_segment(-1, 0, int(NN), 0, 1)};
+    build_pix_segs();
+  }
+  void build_pix_segs() {
+    pix_segs = {make_segment(-1, 0, int(NN), 0, 1, g.nv)};
+    pix_segs_sub = {make_segment(-1, 0, int(NN), 0, 1, sub_views(0))};
   }
   wamct_status set_tiling(int32_t t) override {
     if (t < kMinTargetLanes || t > kMaxTargetLanes)
@@ -293,19 +309,90 @@ struct Ctx final : wamct_ctx {
     CHECKED(ensure_part(t));
     target_lanes = t;
     if (!tree_dirty) build_segs();
-    else pix_segs = {make_segment(-1, 0, int(NN), 0, 1)};
+    else build_pix_segs();
     return WAMCT_OK;
   }
-  // gather over segments with a host check that their partial sums fit
+
+  // ---------------------------------------------------------------- ordered subsets
+  // Subset k holds the views v = k mod n_sub: geometry, b and Z0 of subset k (k < 0: all
+  // views, the context's own b and Z0).
+  struct Sel {
+    DevGeom g;
+    const T* b;
+    const double* z0;
+    int z0stride;
+  };
+  int sub_views(int k) const { return (g.nv - k + n_sub - 1) / n_sub; }
+  Sel sel(int k) const {
+    if (k < 0) return Sel{g, b, scal + 0, kScal};
+    DevGeom gs = g;
+    gs.vs0 = k;
+    gs.vss = n_sub;
+    gs.nvs = sub_views(k);
+    return Sel{gs, bsub + size_t(k) * P * NN, z0s + size_t(k) * P, 1};
+  }
+  void free_subsets() {
+    if (bsub) hipFree(bsub);
+    if (z0s) hipFree(z0s);
+    if (h_z0s) hipHostFree(h_z0s);
+    bsub = nullptr;
+    z0s = nullptr;
+    h_z0s = nullptr;
+  }
+  // b of every subset (eq. 1.6 over the subset's rays), for every scan
+  wamct_status precompute_bsub(hipStream_t s) {
+    for (int k = 0; k < n_sub; ++k)
+      for (int p = 0; p < P; ++p) {
+        CHECKED(gather(kPlain, d + p * M, pix_segs_sub, 1, nullptr, nullptr, nullptr, nullptr, img, s, sel(k)));
+        Launch<T>::analysis(g, img, bsub + (size_t(k) * P + p) * NN, s);
+      }
+    LAUNCHED();
+    return WAMCT_OK;
+  }
+  wamct_status set_subsets(int32_t ns) override {
+    if (ns < 1 || ns > g.nv) return fail(WAMCT_E_INVALID, fmt("n_subsets = %d outside [1, n_views = %d]", ns, g.nv));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipDeviceSynchronize());
+    free_subsets();
+    n_sub = ns;
+    if (ns > 1) {
+      void* v = nullptr;
+      hipError_t e1 = hipMalloc(&v, sizeof(T) * size_t(ns) * P * NN);
+      bsub = static_cast<T*>(v);
+      hipError_t e2 = hipMalloc(&v, sizeof(double) * size_t(ns) * P);
+      z0s = static_cast<double*>(v);
+      hipError_t e3 = hipHostMalloc((void**)&h_z0s, sizeof(double) * size_t(ns) * P, hipHostMallocDefault);
+      if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        (void)hipGetLastError();
+        if (e2 != hipSuccess) z0s = nullptr;
+        if (e3 != hipSuccess) h_z0s = nullptr;
+        if (e1 != hipSuccess) bsub = nullptr;
+        free_subsets();
+        n_sub = 1;
+        return fail(WAMCT_E_OOM, "allocation of the ordered-subset buffers failed");
+      }
+    }
+    build_pix_segs();
+    if (has_data && ns > 1) CHECKED(precompute_bsub(st));
+    tree_dirty = true;
+    return WAMCT_OK;
+  }
+  int32_t subsets() const override { return n_sub; }
+  // gather over segments (of the tree, or of every pixel) with a host check that their
+  // partial sums fit; views, b and Z0 of the selection
   wamct_status gather(int mode, const T* y, const std::vector<Segment>& sg, int S, T* bt, int* held, T* bp, T* bm,
-                      T* out, hipStream_t s) {
+                      T* out, hipStream_t s, const Sel& v) {
     for (const Segment& x : sg)
       if (segment_part_elems(x, S) > part_cap)
         return fail(WAMCT_E_HIP, "internal: gather partial buffer too small for its tiling");
-    const bool tree = &sg == &segs;
-    Geo<T, R>::gather(g, mode, vT, A, y, tree ? items : nullptr, tree ? ints + 9 : nullptr, sg.data(),
-                      int(sg.size()), part, bt, b, scal + 0, held, bp, bm, out, S, s);
+    const bool tree = &sg == &segs || &sg == &segs_sub;
+    Geo<T, R>::gather(v.g, mode, vT, A, y, tree ? items : nullptr, tree ? ints + 9 : nullptr, sg.data(),
+                      int(sg.size()), part, bt, v.b, v.z0, v.z0stride, held, bp, bm, out, S, s);
     return WAMCT_OK;
+  }
+  wamct_status gather(int mode, const T* y, const std::vector<Segment>& sg, int S, T* bt, int* held, T* bp, T* bm,
+                      T* out, hipStream_t s) {
+    return gather(mode, y, sg, S, bt, held, bp, bm, out, s, sel(-1));
   }
 
   // ---------------------------------------------------------------- setup
@@ -314,6 +401,7 @@ struct Ctx final : wamct_ctx {
     P = O.batch;
     g.kind = G.kind; g.n = G.n; g.nv = G.n_views; g.nb = G.n_bins; g.L = O.levels;
     g.pixel = G.pixel; g.pitch = G.bin_pitch; g.sod = G.sod; g.sdd = G.sdd;
+    g.vs0 = 0; g.vss = 1; g.nvs = g.nv;
     M = int64_t(g.nv) * g.nb;
     NN = int64_t(g.n) * g.n;
     nb_rays = int((M + 255) / 256);
@@ -343,7 +431,7 @@ struct Ctx final : wamct_ctx {
     CHECKED(alloc(scal, int64_t(kScal) * P)); CHECKED(alloc(ints, int64_t(kInts) * P));
     CHECKED(alloc(i0one, 1));
     CHECKED(ensure_part(target_lanes));
-    pix_segs = {make_segment(-1, 0, int(NN), 0, 1)};
+    build_pix_segs();
     std::vector<double2> hv(g.nv);
     for (int v = 0; v < g.nv; ++v) {
       const double a = G.angle0 + v * (G.angle_span / G.n_views);
@@ -405,6 +493,7 @@ struct Ctx final : wamct_ctx {
         CHECKED(gather(kPlain, d + p * M, pix_segs, 1, nullptr, nullptr, nullptr, nullptr, img, st));
         Launch<T>::analysis(g, img, b + p * NN, st);
       }
+      if (n_sub > 1) CHECKED(precompute_bsub(st));
     }
     LAUNCHED();
     has_data = true;
@@ -422,8 +511,16 @@ struct Ctx final : wamct_ctx {
       const int nbk = z0_partials(g, views, lev, partd, part2, P, s);
       reduce_stack(true, partd, nbk, nbk, scal + 0, kScal, nullptr, P, s);
       reduce_stack(false, part2, nbk, nbk, scal + 1, kScal, nullptr, P, s);
+      if (n_sub > 1)
+        for (int k = 0; k < n_sub; ++k) {   // Z0 of every view subset
+          const Sel v = sel(k);
+          const int nbs = z0_partials(v.g, views, lev, partd, part2, P, s);
+          reduce_stack(true, partd, nbs, nbs, z0s + size_t(k) * P, 1, nullptr, P, s);
+        }
     }
     LAUNCHED();
+    if (n_sub > 1)
+      HIPCHK(hipMemcpyAsync(h_z0s, z0s, sizeof(double) * n_sub * P, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(h_ints, ints, sizeof(int) * kInts * P, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(h_scal, scal, sizeof(double) * kScal * P, hipMemcpyDeviceToHost, s));
     tree_dirty = true;
@@ -437,6 +534,10 @@ struct Ctx final : wamct_ctx {
         return fail(WAMCT_E_INVALID, fmt("Z0 = 0 in scan %d: no ray crosses the image", p));
       if (n_split) n_split[p] = h_ints[p * kInts + 2];
     }
+    for (int k = 0; n_sub > 1 && k < n_sub * P; ++k)
+      if (!(h_z0s[k] > 0) || !std::isfinite(h_z0s[k]))
+        return fail(WAMCT_E_INVALID, fmt("Z0 = 0 for view subset %d of scan %d: none of its rays crosses the image",
+                                         k / P, k % P));
     tree_dirty = false;
     return WAMCT_OK;
   }
@@ -490,7 +591,8 @@ struct Ctx final : wamct_ctx {
 
   // ---------------------------------------------------------------- iteration (stream-ordered)
   // One forward pass of the current state: mu, q-hat and the I-divergence partials.
-  int forward_pass(hipStream_t s) {
+  // (over the views of gg; partials of the I-divergence only when `pd` is not null)
+  int forward_pass(hipStream_t s, const DevGeom& gg, double* pd) {
     const T* iv = i0v_used ? i0v : nullptr;
     if (g.L > 0) {
       {
@@ -498,15 +600,16 @@ struct Ctx final : wamct_ctx {
         Launch<T>::synth_records(g, beta, lev, leafR, leafC, P, s);
       }
       Scope sc(this, WAMCT_K_FORWARD, s);
-      return Geo<T, R>::forward_records(g, A, B, leafR, leafC, d, iv, scal + 4, q, nullptr, partd, P, s);
+      return Geo<T, R>::forward_records(gg, A, B, leafR, leafC, d, iv, scal + 4, q, nullptr, pd, P, s);
     }
     {
       Scope sc(this, WAMCT_K_SYNTH, s);
       Launch<T>::synth_layouts(g, beta, mu, muT, P, s);
     }
     Scope sc(this, WAMCT_K_FORWARD, s);
-    return Geo<T, R>::forward(g, A, B, mu, muT, d, iv, scal + 4, q, nullptr, partd, P, s);
+    return Geo<T, R>::forward(gg, A, B, mu, muT, d, iv, scal + 4, q, nullptr, pd, P, s);
   }
+  int forward_pass(hipStream_t s) { return forward_pass(s, g, partd); }
   // I-divergence of scan p -> out[p * ostride] (or out[p * ostride + counter] with the
   // device counters; out null: the scratch slot)
   void store_idiv(int nbk, double* out, int64_t ostride, bool counted, hipStream_t s) {
@@ -517,6 +620,20 @@ struct Ctx final : wamct_ctx {
       reduce_stack(false, partd, nbk, nbk, scal + 3, kScal, nullptr, P, s);
   }
   wamct_status enq_iteration(hipStream_t s, double* out, int64_t ostride, bool counted) override {
+    if (n_sub > 1) {
+      // a pass of ordered subsets: the full I-divergence before the pass (when asked for),
+      // then one update per subset with q-hat, b, b-hat+/- and Z0 of its rays
+      if (out) store_idiv(forward_pass(s), out, ostride, counted, s);
+      for (int k = 0; k < n_sub; ++k) {
+        const Sel v = sel(k);
+        forward_pass(s, v.g, nullptr);
+        Scope sc(this, WAMCT_K_UPDATE, s);
+        CHECKED(gather(kUpdate, q, segs_sub, P, beta, ints + 0, nullptr, nullptr, nullptr, s, v));
+      }
+      ++iters;
+      LAUNCHED();
+      return WAMCT_OK;
+    }
     const int nbk = forward_pass(s);
     store_idiv(nbk, out, ostride, counted, s);
     {
@@ -1105,6 +1222,13 @@ wamct_status wamct_loss_backward(wamct_ctx* ctx, int32_t batch, const void* q, c
                                  void* grad) { CTX_CALL(loss_backward(batch, q, d, gscale, grad)); }
 wamct_status wamct_get_timing(wamct_ctx* ctx, double* ms, int64_t* n) { CTX_CALL(get_timing(ms, n)); }
 wamct_status wamct_set_tiling(wamct_ctx* ctx, int32_t lanes) { CTX_CALL(set_tiling(lanes)); }
+wamct_status wamct_set_subsets(wamct_ctx* ctx, int32_t n_subsets) { CTX_CALL(set_subsets(n_subsets)); }
+wamct_status wamct_get_subsets(wamct_ctx* ctx, int32_t* n_subsets) {
+  if (!ctx) { g_last_error = "ctx is NULL"; return WAMCT_E_INVALID; }
+  if (!n_subsets) return ctx->fail(WAMCT_E_INVALID, "n_subsets must not be NULL");
+  *n_subsets = ctx->subsets();
+  return WAMCT_OK;
+}
 wamct_status wamct_get_tiling(wamct_ctx* ctx, int32_t* lanes) {
   if (!ctx) { g_last_error = "ctx is NULL"; return WAMCT_E_INVALID; }
   if (!lanes) return ctx->fail(WAMCT_E_INVALID, "lanes must not be NULL");

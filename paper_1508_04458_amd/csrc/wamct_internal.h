@@ -18,6 +18,9 @@ struct DevGeom {
   int nv, nb;  // views, bins
   int L;       // Haar levels
   double pixel, pitch, sod, sdd;
+  // views a launch works on: vs0 + vss k for k < nvs (every view: 0, 1, nv); ray arrays
+  // stay indexed by the full [view][bin] layout
+  int vs0, vss, nvs;
 };
 
 // Work item of the node-driven backprojection: one tree node or one box.
@@ -102,12 +105,13 @@ struct Geo {
                              const T* d, const T* i0v, const double* i0s, T* q, T* p, double* part, int S,
                              hipStream_t s);
   // node-driven backprojection of y over the segments of `items` (items null: every pixel
-  // as a level-0 box). counts: per-scan level counts (stride kInts; null for fixed ranges);
-  // z0 per scan at stride kScal, held at stride kInts; `part` holds segment_part_elems.
+  // as a level-0 box), over the views of g's subset. counts: per-scan level counts (stride
+  // kInts; null for fixed ranges); z0 per scan at stride z0stride, held at stride kInts;
+  // `part` holds segment_part_elems.
   static void gather(const DevGeom& g, int mode, const void* vF, const void* A, const T* y,
                      const uint32_t* items, const int* counts, const Segment* segs, int n_segs, void* part,
-                     T* beta, const T* b, const double* z0, int* held, T* bp, T* bm, T* out, int S,
-                     hipStream_t s);
+                     T* beta, const T* b, const double* z0, int z0stride, int* held, T* bp, T* bm, T* out,
+                     int S, hipStream_t s);
 };
 
 // Z0 and W of the current tree: per-ray FP64 sums of |phi| over active coefficients and

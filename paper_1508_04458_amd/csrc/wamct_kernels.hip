@@ -28,6 +28,12 @@ inline int blocks_for(int64_t n, int b = kBlock) { return int((n + b - 1) / b); 
 template <typename P>
 __device__ inline P* at(P* x, int64_t off) { return x ? x + off : x; }
 
+// Ray (index into the full [view][bin] layout) of the k-th ray of the launch's views.
+__device__ inline int subset_ray(const DevGeom& g, int k) {
+  const int j = k / g.nb;
+  return (g.vs0 + g.vss * j) * g.nb + (k - j * g.nb);
+}
+
 // ------------------------------------------------------------------ reductions (wave64)
 
 __device__ inline double wave_sum(double v) {
@@ -299,9 +305,10 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4
     muR += oi; muC += oi;
     d = at(d, orr); i0v = at(i0v, orr); q = at(q, orr); pout = at(pout, orr);
   }
-  const int r = blockIdx.x * kBlock + threadIdx.x;
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  const int r = subset_ray(g, k);
   double term = 0.0;
-  if (r < M) {
+  if (k < g.nvs * g.nb) {
     const typename V4<R>::t a = A[r];
     const typename V4<R>::t bb = B[r];
     const R ox = a.x, oy = a.y, iex = a.z, iey = a.w, ex = bb.x, ey = bb.y;
@@ -393,9 +400,10 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
     leafR += oi; leafC += oi;
     d = at(d, orr); i0v = at(i0v, orr); q = at(q, orr); pout = at(pout, orr);
   }
-  const int r = blockIdx.x * kBlock + threadIdx.x;
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  const int r = subset_ray(g, k);
   double term = 0.0;
-  if (r < M) {
+  if (k < g.nvs * g.nb) {
     const typename V4<R>::t a = A[r];
     const typename V4<R>::t bb = B[r];
     const R ox = a.x, oy = a.y, iex = a.z, iey = a.w, ex = bb.x, ey = bb.y;
@@ -523,7 +531,8 @@ __device__ inline ItemSums<R> item_sums(const DevGeom& g, const float2* __restri
   const float ipitch = float(1.0 / g.pitch), ctr = float(0.5 * (nb - 1));
   const float sod = float(g.sod), sdd = float(g.sdd);
   ItemSums<R> r{R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
-  for (int v = v0; v < v1; ++v) {
+  for (int k = v0; k < v1; ++k) {
+    const int v = g.vs0 + g.vss * k;   // k-th view of the launch's subset
     const float2 cs = vf[v];
     const float c = cs.x, sn = cs.y;
     float u00, u01, u10, u11;
@@ -628,7 +637,8 @@ __device__ inline void item_finish(const DevGeom& g, uint32_t w, const ItemSums<
 // its items, coefficients and outputs at + p n^2, Z0 at z0 + p kScal, held counter at
 // held + p kInts, partial sums at part + p pstride. The segment of scan p is level index
 // kseg of its counts (start = sum of the earlier levels) or, with counts null, the fixed
-// range [start, start + count); `count` is the largest segment length of the stack.
+// range [start, start + count); `count` is the largest segment length of the stack. Views
+// are those of the launch's subset (g.vs0 + g.vss k, k < g.nvs), chunks count within them.
 template <typename T, typename R>
 struct GatherArgs {
   DevGeom g;
@@ -643,6 +653,7 @@ struct GatherArgs {
   T* beta;
   const T* b;
   const double* z0;
+  int z0stride;
   int* held;
   T *bp, *bm, *out;
 };
@@ -669,7 +680,7 @@ __device__ inline ScanView<T, R> scan_view(const GatherArgs<T, R>& a) {
   v.items = at(a.items, p * NN);
   v.beta = at(a.beta, p * NN);
   v.b = at(a.b, p * NN);
-  v.z0 = at(a.z0, int64_t(p) * kScal);
+  v.z0 = at(a.z0, int64_t(p) * a.z0stride);
   v.held = at(a.held, int64_t(p) * kInts);
   v.bp = at(a.bp, p * NN);
   v.bm = at(a.bm, p * NN);
@@ -695,7 +706,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs<T, R> a) {
   if (k >= v.count) return;
   const uint32_t w = item_word(v.items, v.start + k, a.g.n);
   const ItemSums<R> r = item_sums<T, R>(a.g, a.vf, a.A, v.y, (w >> 31) != 0, int((w >> 27) & 15u),
-                                        int((w >> 13) & 0x1fffu), int(w & 0x1fffu), 0, a.g.nv);
+                                        int((w >> 13) & 0x1fffu), int(w & 0x1fffu), 0, a.g.nvs);
   item_finish<T, R, MODE>(a.g, w, r, v.beta, v.b, v.z0, v.held, v.bp, v.bm, v.out);
 }
 
@@ -718,7 +729,7 @@ __global__ __launch_bounds__(64 * kChunkWaves) void k_gather_part(GatherArgs<T, 
   ItemSums<R> r{R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
   if (idx < v.count && chunk < a.chunks) {
     const uint32_t w = item_word(v.items, v.start + idx, a.g.n);
-    const int v0 = chunk * a.vpc, v1 = min(a.g.nv, v0 + a.vpc);
+    const int v0 = chunk * a.vpc, v1 = min(a.g.nvs, v0 + a.vpc);
     r = item_sums<T, R>(a.g, a.vf, a.A, v.y, (w >> 31) != 0, int((w >> 27) & 15u), int((w >> 13) & 0x1fffu),
                         int(w & 0x1fffu), v0, v1);
   }
@@ -888,11 +899,11 @@ template <int LT>
 __global__ __launch_bounds__(kBlock) void k_z0(DevGeom g, const double2* __restrict__ views,
                                                const uint8_t* __restrict__ lev, double* __restrict__ part_max,
                                                double* __restrict__ part_cnt) {
-  const int M = g.nv * g.nb;
   lev += int64_t(blockIdx.y) * g.n * g.n;
-  const int r = blockIdx.x * kBlock + threadIdx.x;
+  const int k = blockIdx.x * kBlock + threadIdx.x;
   double sum = 0.0, cnt = 0.0;
-  if (r < M) {
+  if (k < g.nvs * g.nb) {
+    const int r = subset_ray(g, k);
     const int v = r / g.nb, b = r - v * g.nb;
     double ox, oy, ex, ey;
     ray_of(g, views[v], b, ox, oy, ex, ey);
@@ -1146,7 +1157,7 @@ void Geo<T, R>::view_table(const DevGeom& g, const double2* views, void* vF, hip
 template <typename T, typename R>
 int Geo<T, R>::forward(const DevGeom& g, const void* A, const void* B, const T* muR, const T* muC, const T* d,
                        const T* i0v, const double* i0s, T* q, T* p, double* part, int S, hipStream_t s) {
-  const int nb = blocks_for(int64_t(g.nv) * g.nb);
+  const int nb = blocks_for(int64_t(g.nvs) * g.nb);
   hipLaunchKernelGGL((k_forward<T, R, 8>), dim3(nb, S), dim3(kBlock), 0, s, g, (const typename V4<R>::t*)A,
                      (const typename V4<R>::t*)B, muR, muC, d, i0v, i0s, q, p, part);
   return nb;
@@ -1155,7 +1166,7 @@ template <typename T, typename R>
 int Geo<T, R>::forward_records(const DevGeom& g, const void* A, const void* B, const void* leafR, const void* leafC,
                                const T* d, const T* i0v, const double* i0s, T* q, T* p, double* part, int S,
                                hipStream_t s) {
-  const int nb = blocks_for(int64_t(g.nv) * g.nb);
+  const int nb = blocks_for(int64_t(g.nvs) * g.nb);
   hipLaunchKernelGGL((k_forward_rec<T, R>), dim3(nb, S), dim3(kBlock), 0, s, g, (const typename V4<R>::t*)A,
                      (const typename V4<R>::t*)B, (const Leaf<T>*)leafR, (const Leaf<T>*)leafC, d, i0v, i0s, q, p,
                      part);
@@ -1179,8 +1190,8 @@ void launch_segment(const GatherArgs<T, R>& a, int S, hipStream_t s) {
 template <typename T, typename R>
 void Geo<T, R>::gather(const DevGeom& g, int mode, const void* vF, const void* A, const T* y,
                        const uint32_t* items, const int* counts, const Segment* segs, int n_segs, void* part,
-                       T* beta, const T* b, const double* z0, int* held, T* bp, T* bm, T* out, int S,
-                       hipStream_t s) {
+                       T* beta, const T* b, const double* z0, int z0stride, int* held, T* bp, T* bm, T* out,
+                       int S, hipStream_t s) {
   GatherArgs<T, R> a;
   a.g = g;
   a.vf = (const float2*)vF;
@@ -1192,6 +1203,7 @@ void Geo<T, R>::gather(const DevGeom& g, int mode, const void* vF, const void* A
   a.beta = beta;
   a.b = b;
   a.z0 = z0;
+  a.z0stride = z0stride;
   a.held = held;
   a.bp = bp;
   a.bm = bm;
@@ -1217,7 +1229,7 @@ template struct Geo<double, double>;
 
 int z0_partials(const DevGeom& g, const double2* views, const uint8_t* lev, double* part_max,
                 double* part_cnt, int S, hipStream_t s) {
-  const int nb = blocks_for(int64_t(g.nv) * g.nb);
+  const int nb = blocks_for(int64_t(g.nvs) * g.nb);
   switch (g.L) {
 #define Z0_CASE(K) \
     case K: hipLaunchKernelGGL(k_z0<K>, dim3(nb, S), dim3(kBlock), 0, s, g, views, lev, part_max, part_cnt); break;
