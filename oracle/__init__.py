@@ -20,8 +20,9 @@ Iterative Image Reconstruction for X-Ray Imaging for Security Applications"
                closed-form zero of eq. 1.9, Algorithm 1, the tree-expansion rule of the
                Results section, unregularized pixel AM (Omega = I), the I-divergence,
                the surrogate of eq. 1.8, the loss/gradient of the coefficient-domain
-               problem (eq. 1.3 with lambda = 0), and wavelet AM combined with ordered
-               subsets of views (Conclusion)
+               problem (eq. 1.3 with lambda = 0), wavelet AM combined with ordered
+               subsets of views (Conclusion), and z-slices sharing one tree chosen on
+               the slice-summed image (Results)
 
 Parity status: every function is pinned by the `-m "not gpu"` tests in
 tests/test_oracle_*.py (closed forms, brute force, invariants, a hand-computed golden

@@ -268,6 +268,49 @@ def os_wam_solve(H, n, levels, d, i0, n_iters, pixel, n_views, n_subsets, schedu
     return out
 
 
+def volume_wam_solve(H, n, levels, ds, i0s, n_iters, pixel, schedule=(), frac=0.1, Omega=None,
+                     betas0=None, mask0=None):
+    """Algorithm 1 on a stack of z-slices that share one tree (Results: each z-slice is
+    represented by a 2-D Haar transform, and the tree is expanded where the image summed
+    over the slices exceeds frac times its maximum). Every slice has the 2-D scan H (rays
+    stay in their slice), its own counts ds[p] and incident counts i0s[p]. Z0 is the
+    maximum over all rays of the volume; with one tree and one geometry it is the same for
+    every slice. Returns betas [P, n, n], the shared mask, idiv [P, n_iters + 1] per slice
+    (before each update and after the last), trees, z0 per tree, held count."""
+    if Omega is None:
+        Omega = haar.synthesis_matrix(n, levels)
+    P = len(ds)
+    ds = [np.asarray(d, np.float64) for d in ds]
+    betas = np.zeros((P, n * n)) if betas0 is None else np.array(betas0, np.float64).reshape(P, n * n)
+    mask = haar.approx_mask(n, levels) if mask0 is None else np.array(mask0, np.uint8)
+    b_all = [Omega.T @ (H.T @ d) for d in ds]
+    trace = [[] for _ in range(P)]
+    trees, z0s, held_total = [], [], 0
+    Phi = None
+    for j in range(n_iters):
+        changed = False
+        if j in schedule:
+            # the image summed over slices is Omega applied to the summed coefficients
+            mask, _ = expand_tree(betas.sum(axis=0), mask, levels, frac, Omega)
+            changed = True
+        if Phi is None or changed:
+            Phi, act = phi_matrix(H, Omega, mask, pixel)
+            Php, Phm = split_phi(Phi)
+            z0 = z0_of(Phi)
+            trees.append((j, mask.copy()))
+            z0s.append(z0)
+        for p in range(P):
+            q_hat = beer_mean(i0s[p], Phi @ betas[p][act])
+            trace[p].append(idiv(ds[p], q_hat))
+            delta, held = closed_form_update(b_all[p][act], Php.T @ q_hat, Phm.T @ q_hat, z0)
+            held_total += int(held.sum())
+            betas[p][act] += delta
+    for p in range(P):
+        trace[p].append(idiv(ds[p], beer_mean(i0s[p], H @ (Omega @ betas[p]))))
+    return dict(betas=betas.reshape(P, n, n), mask=mask, idiv=np.array(trace), trees=trees, z0=z0s,
+                held=held_total)
+
+
 def am_solve(H, n, d, i0, n_iters, pixel, mu0=None):
     """Unregularized image-domain AM (O'Sullivan-Benac): Algorithm 1 with Omega = I."""
     return wam_solve(H, n, 0, d, i0, n_iters, pixel, beta0=mu0)

@@ -90,3 +90,45 @@ def test_consistent_data_is_a_fixed_point():
     assert np.max(np.abs(r["beta"].ravel() - beta)) <= 1e-10
     assert r["held"] == 0
     assert abs(r["idiv"][-1]) <= 1e-8
+
+
+# ------------------------------------------------------------------ slices sharing one tree
+
+def test_single_slice_volume_is_algorithm_1(fan64):
+    g, H, d = fan64
+    ref = wam.wam_solve(H, g.n, 2, d, 3e4, 8, g.pixel, schedule=[3, 6])
+    vol = wam.volume_wam_solve(H, g.n, 2, [d], [3e4], 8, g.pixel, schedule=[3, 6])
+    np.testing.assert_allclose(vol["betas"][0], ref["beta"], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(vol["idiv"][0], ref["idiv"], rtol=1e-13)
+    np.testing.assert_array_equal(vol["mask"], ref["mask"])
+
+
+def test_identical_slices_reproduce_one_slice(fan64):
+    """Two identical slices: the summed image is twice each slice (exact), so the tree and
+    every slice's iterates equal those of one slice alone."""
+    g, H, d = fan64
+    ref = wam.wam_solve(H, g.n, 2, d, 3e4, 8, g.pixel, schedule=[3, 6])
+    vol = wam.volume_wam_solve(H, g.n, 2, [d, d], [3e4, 3e4], 8, g.pixel, schedule=[3, 6])
+    np.testing.assert_array_equal(vol["mask"], ref["mask"])
+    for p in range(2):
+        np.testing.assert_array_equal(vol["betas"][p], ref["beta"])
+
+
+def test_tree_follows_the_slice_sum():
+    """Hand-made coefficients (approximation only, 2 levels, 16x16): slice 0 bright in root
+    (0, 0), slice 1 in root (3, 3) at the same value -> the summed image splits both roots;
+    with slice 1 at 5 % of that value only root (0, 0) splits (5 % < 10 % of the maximum)."""
+    g = synth.parallel_geometry(16, 12, 24, 1.0)
+    H = siddon.system_matrix(g)
+    L = 2
+    d = [np.zeros(g.n_rays)] * 2
+    for v1, split_33 in ((1.0, True), (0.05, False)):
+        betas = np.zeros((2, 16, 16))
+        betas[0, 0, 0] = 4.0            # approximation of root (0, 0): mu = 1 on its block
+        betas[1, 3, 3] = 4.0 * v1
+        vol = wam.volume_wam_solve(H, 16, L, d, [1.0, 1.0], 1, g.pixel, schedule=[0], betas0=betas)
+        split = haar.split_flags(vol["mask"], L)
+        expect = np.zeros((4, 4), bool)
+        expect[0, 0] = True
+        expect[3, 3] = split_33
+        np.testing.assert_array_equal(split, expect)
