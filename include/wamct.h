@@ -229,6 +229,17 @@ wamct_status wamct_get_tiling(wamct_ctx* ctx, int32_t* lanes);
 wamct_status wamct_set_subsets(wamct_ctx* ctx, int32_t n_subsets);
 wamct_status wamct_get_subsets(wamct_ctx* ctx, int32_t* n_subsets);
 
+/* Slices of one volume (Results: each z-slice has its own 2-D Haar transform and all
+ * slices share one tree). shared = 1: the scans of the stack are slices with one tree,
+ * which the tree rule grows on the FP64 image summed over the slices (every leaf with a
+ * pixel of the summed image above frac times its maximum splits, in every slice); scan 0's
+ * current tree is copied to every slice now and coefficients outside it are zeroed.
+ * Z0 needs no change: with one tree and one geometry it is the same for every slice.
+ * wamct_expand then reports the shared tree's split count for every slice. shared = 0
+ * (default): every scan grows its own tree. */
+wamct_status wamct_set_tree_sharing(wamct_ctx* ctx, int32_t shared);
+wamct_status wamct_get_tree_sharing(wamct_ctx* ctx, int32_t* shared);
+
 /* ---------------------------------------------------------------- batches
  * Uneven batches: several contexts (different geometries, image sizes and view counts,
  * each a stack of scans) solved together. Each context is bound to one of n_streams

@@ -26,7 +26,8 @@ SYMBOLS = (
     "wamct_tree_stats", "wamct_timing", "wamct_get_timing", "wamct_loss", "wamct_loss_backward",
     "wamct_set_tiling", "wamct_get_tiling", "wamct_batch_create", "wamct_batch_destroy",
     "wamct_batch_last_error", "wamct_batch_reset", "wamct_batch_solve", "wamct_batch_autotune",
-    "wamct_batch_stats", "wamct_set_subsets", "wamct_get_subsets",
+    "wamct_batch_stats", "wamct_set_subsets", "wamct_get_subsets", "wamct_set_tree_sharing",
+    "wamct_get_tree_sharing",
 )
 
 
@@ -84,6 +85,8 @@ def _load():
         "wamct_set_tiling": (vp, i32),
         "wamct_get_tiling": (vp, P(i32)),
         "wamct_set_subsets": (vp, i32),
+        "wamct_set_tree_sharing": (vp, i32),
+        "wamct_get_tree_sharing": (vp, P(i32)),
         "wamct_get_subsets": (vp, P(i32)),
         "wamct_batch_create": (i32, P(vp), i32, i32, vp, P(vp)),
         "wamct_batch_destroy": (vp,),

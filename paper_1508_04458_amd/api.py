@@ -152,6 +152,15 @@ class Context:
         self._call(lib.wamct_solve, int(n_iters), sched, len(schedule), float(frac), _ptr(idiv))
         return idiv
 
+    def set_tree_sharing(self, shared: bool) -> None:
+        """Scans as z-slices of one volume sharing one tree grown on the slice-summed image."""
+        self._call(lib.wamct_set_tree_sharing, 1 if shared else 0)
+
+    def tree_sharing(self) -> bool:
+        v = ctypes.c_int32()
+        self._call(lib.wamct_get_tree_sharing, ctypes.byref(v))
+        return bool(v.value)
+
     def set_subsets(self, n_subsets: int) -> None:
         """Ordered subsets of views: every iteration becomes a pass of n_subsets updates."""
         self._call(lib.wamct_set_subsets, int(n_subsets))

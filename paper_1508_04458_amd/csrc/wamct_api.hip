@@ -87,6 +87,8 @@ struct wamct_ctx {
   virtual int32_t tiling() const = 0;
   virtual wamct_status set_subsets(int32_t) = 0;
   virtual int32_t subsets() const = 0;
+  virtual wamct_status set_tree_sharing(int32_t) = 0;
+  virtual int32_t tree_sharing() const = 0;
   // stream-ordered pieces used by batches (no host synchronization inside)
   virtual int n_scans() const = 0;
   virtual hipStream_t stream() const = 0;
@@ -157,6 +159,8 @@ struct Ctx final : wamct_ctx {
   int64_t part_cap = 0;       // elements of R
   int* h_ints = nullptr;      // pinned host copies read after a tree rebuild
   double* h_scal = nullptr;
+  // one tree for the whole stack, grown on the slice-summed image
+  bool shared_tree = false;
   // ordered subsets of views (n_sub > 1): b and Z0 of every subset, [n_sub][P][...]
   int n_sub = 1;
   T* bsub = nullptr;
@@ -378,6 +382,20 @@ struct Ctx final : wamct_ctx {
     return WAMCT_OK;
   }
   int32_t subsets() const override { return n_sub; }
+
+  wamct_status set_tree_sharing(int32_t on) override {
+    if (on != 0 && on != 1) return fail(WAMCT_E_INVALID, "shared must be 0 or 1");
+    shared_tree = on == 1;
+    if (shared_tree && P > 1) {
+      // every slice takes slice 0's tree; coefficients outside it become 0
+      for (int p = 1; p < P; ++p) HIPCHK(hipMemcpyAsync(mask + p * NN, mask, NN, hipMemcpyDeviceToDevice, st));
+      Launch<T>::apply_mask(g, beta, mask, P, st);
+      LAUNCHED();
+      tree_dirty = true;
+    }
+    return WAMCT_OK;
+  }
+  int32_t tree_sharing() const override { return shared_tree ? 1 : 0; }
   // gather over segments (of the tree, or of every pixel) with a host check that their
   // partial sums fit; views, b and Z0 of the selection
   wamct_status gather(int mode, const T* y, const std::vector<Segment>& sg, int S, T* bt, int* held, T* bp, T* bm,
@@ -532,7 +550,7 @@ struct Ctx final : wamct_ctx {
       const double z0 = h_scal[p * kScal + 0];
       if (!(z0 > 0) || !std::isfinite(z0))
         return fail(WAMCT_E_INVALID, fmt("Z0 = 0 in scan %d: no ray crosses the image", p));
-      if (n_split) n_split[p] = h_ints[p * kInts + 2];
+      if (n_split) n_split[p] = h_ints[(shared_tree ? 0 : p) * kInts + 2];
     }
     for (int k = 0; n_sub > 1 && k < n_sub * P; ++k)
       if (!(h_z0s[k] > 0) || !std::isfinite(h_z0s[k]))
@@ -664,8 +682,25 @@ struct Ctx final : wamct_ctx {
     return WAMCT_OK;
   }
 
-  // Tree rule (Results): FP64 synthesis, per-scan maximum, split, then the new tree.
+  // Tree rule (Results): FP64 synthesis, per-scan maximum, split, then the new tree. With
+  // a shared tree the rule runs once, on the image summed over the stack's slices, and the
+  // resulting tree is copied to every slice.
   wamct_status enq_expand(hipStream_t s, double frac) override {
+    if (g.L > 0 && shared_tree && P > 1) {
+      {
+        Scope sc(this, WAMCT_K_TREE, s);
+        Launch<T>::mu64(g, beta, mu64, partd, P, s);
+        const int nbk = sum_slices(g, mu64, partd, P, s);
+        reduce_stack(true, partd, nbk, nbk, scal + 2, kScal, nullptr, 1, s);
+        HIPCHK(hipMemcpyAsync(mask_old, mask, NN, hipMemcpyDeviceToDevice, s));
+        fill_i32_strided(ints + 2, P, kInts, 0, s);
+        expand(g, mask_old, mask, mu64, scal + 2, frac, ints + 2, 1, s);
+        for (int p = 1; p < P; ++p)
+          HIPCHK(hipMemcpyAsync(mask + p * NN, mask, NN, hipMemcpyDeviceToDevice, s));
+      }
+      LAUNCHED();
+      return enq_tree(s);
+    }
     if (g.L > 0) {
       {
         Scope sc(this, WAMCT_K_TREE, s);
@@ -1223,6 +1258,13 @@ wamct_status wamct_loss_backward(wamct_ctx* ctx, int32_t batch, const void* q, c
 wamct_status wamct_get_timing(wamct_ctx* ctx, double* ms, int64_t* n) { CTX_CALL(get_timing(ms, n)); }
 wamct_status wamct_set_tiling(wamct_ctx* ctx, int32_t lanes) { CTX_CALL(set_tiling(lanes)); }
 wamct_status wamct_set_subsets(wamct_ctx* ctx, int32_t n_subsets) { CTX_CALL(set_subsets(n_subsets)); }
+wamct_status wamct_set_tree_sharing(wamct_ctx* ctx, int32_t shared) { CTX_CALL(set_tree_sharing(shared)); }
+wamct_status wamct_get_tree_sharing(wamct_ctx* ctx, int32_t* shared) {
+  if (!ctx) { g_last_error = "ctx is NULL"; return WAMCT_E_INVALID; }
+  if (!shared) return ctx->fail(WAMCT_E_INVALID, "shared must not be NULL");
+  *shared = ctx->tree_sharing();
+  return WAMCT_OK;
+}
 wamct_status wamct_get_subsets(wamct_ctx* ctx, int32_t* n_subsets) {
   if (!ctx) { g_last_error = "ctx is NULL"; return WAMCT_E_INVALID; }
   if (!n_subsets) return ctx->fail(WAMCT_E_INVALID, "n_subsets must not be NULL");

@@ -135,6 +135,9 @@ void build_items(const DevGeom& g, const uint8_t* mask, uint32_t* items, int* co
 // (maxv at stride kScal, n_split at stride kInts).
 void expand(const DevGeom& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64,
             const double* maxv, double frac, int* n_split, int S, hipStream_t s);
+// Sum of the FP64 images of S slices into slice 0 (slice order) and per-block maxima of the
+// sum. Returns the number of blocks.
+int sum_slices(const DevGeom& g, double* mu64, double* part, int S, hipStream_t s);
 // Validity of S tree masks: *bad = number of violated constraints.
 void check_mask(const DevGeom& g, const uint8_t* mask, int* bad, int S, hipStream_t s);
 void fill_u8(uint8_t* x, int64_t len, uint8_t v, hipStream_t s);

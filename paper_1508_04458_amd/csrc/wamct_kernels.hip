@@ -175,6 +175,22 @@ __global__ __launch_bounds__(kBlock) void k_mu64(int n, int L, const T* __restri
   if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = v;
 }
 
+// Slices sharing one tree (Results: the tree rule thresholds the image summed over the
+// z-slices): mu64[i] = sum over the S slices of mu64[p][i] in slice order (FP64), written to
+// slice 0, with per-block maxima of the sum.
+__global__ __launch_bounds__(kBlock) void k_sum_slices(int64_t nn, int S, double* __restrict__ mu64,
+                                                       double* __restrict__ part) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  double v = -INFINITY;
+  if (i < nn) {
+    v = 0.0;
+    for (int p = 0; p < S; ++p) v += mu64[p * nn + i];
+    mu64[i] = v;
+  }
+  v = block_reduce<true>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
 __global__ __launch_bounds__(kBlock) void k_levmap(int n, int L, const uint8_t* __restrict__ mask,
                                                    uint8_t* __restrict__ lev) {
   const int64_t off = int64_t(blockIdx.y) * n * n;
@@ -1119,6 +1135,12 @@ template <typename T>
 int Launch<T>::mu64(const DevGeom& g, const T* beta, double* mu64, double* part, int S, hipStream_t s) {
   const int nb = blocks_for(int64_t(g.n) * g.n);
   hipLaunchKernelGGL(k_mu64<T>, dim3(nb, S), dim3(kBlock), 0, s, g.n, g.L, beta, mu64, part);
+  return nb;
+}
+int sum_slices(const DevGeom& g, double* mu64, double* part, int S, hipStream_t s) {
+  const int64_t nn = int64_t(g.n) * g.n;
+  const int nb = blocks_for(nn);
+  hipLaunchKernelGGL(k_sum_slices, dim3(nb), dim3(kBlock), 0, s, nn, S, mu64, part);
   return nb;
 }
 template <typename T>

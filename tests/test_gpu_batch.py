@@ -159,3 +159,43 @@ def test_tiling_changes_only_summation_order():
     for idv, beta in out[1:]:
         np.testing.assert_allclose(idv, out[0][0], rtol=1e-12)
         assert rel_l2(beta, out[0][1]) <= 1e-11
+
+
+# ------------------------------------------------------------------ slices sharing one tree
+
+def test_shared_tree_slices_match_oracle_fp64():
+    """Three z-slices (own phantoms and I0) sharing one tree grown on the slice-summed image:
+    every slice's solve equals the oracle's (shared mask exact, beta 1e-9, I-div 1e-10)."""
+    probs = [synth.make_problem("fan96", problem_idx=k, i0=i0) for k, i0 in enumerate((5e4, 2e4, 8e4))]
+    g = probs[0].geom
+    P0 = probs[0]
+    c = _stack_ctx(probs, "f64")
+    c.set_tree_sharing(True)
+    assert c.tree_sharing()
+    idv = host(c.solve(P0.n_iters, P0.schedule, 0.1))
+    beta, mask, _ = c.get_state()
+    beta, mask = host(beta), host(mask)
+    ref = wam.volume_wam_solve(siddon.system_matrix(g), g.n, P0.levels, [P.d for P in probs],
+                               [P.i0 for P in probs], P0.n_iters, g.pixel, schedule=P0.schedule)
+    for k in range(len(probs)):
+        np.testing.assert_array_equal(mask[k], ref["mask"])
+        assert rel_l2(beta[k].ravel(), ref["betas"][k].ravel()) <= 1e-9, k
+        np.testing.assert_allclose(idv[k], ref["idiv"][k], rtol=1e-10)
+    assert sum(c.tree_stats()["n_held"]) == ref["held"]
+
+
+def test_shared_tree_of_identical_slices_is_the_single_tree():
+    P = synth.make_problem("fan96")
+    g = P.geom
+    one = _api().Context(g, P.levels, "f64")
+    one.set_data(dev(P.d, "f64"), P.i0)
+    i1 = host(one.solve(P.n_iters, P.schedule, 0.1))
+    two = _stack_ctx([P, P], "f64")
+    two.set_tree_sharing(True)
+    i2 = host(two.solve(P.n_iters, P.schedule, 0.1))
+    b2, m2, _ = two.get_state()
+    b1, m1, _ = one.get_state()
+    for k in range(2):
+        np.testing.assert_array_equal(host(m2)[k], host(m1))
+        np.testing.assert_allclose(i2[k], i1, rtol=1e-12)
+        assert rel_l2(host(b2)[k], host(b1)) <= 1e-12
