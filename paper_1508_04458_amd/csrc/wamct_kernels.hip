@@ -435,35 +435,43 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
       int iy = (int)floor(fmin(fmax((oy + t_in * ey) * ipix + hn, R(-1)), R(n)));
       ix = imin(imax(ix, 0), n - 1);
       iy = imin(imax(iy, 0), n - 1);
-      const bool px = ex > R(0), py = ey > R(0);
+      // major axis u (the one the ray travels along more; its records are contiguous in
+      // the minor axis w) and minor axis w: the record of pixel (u, w) is base[u n + w]
       const bool xmaj = fabs(ex) >= fabs(ey);
       const Leaf<T>* __restrict__ base = xmaj ? leafC : leafR;
-      Leaf<T> rec = base[xmaj ? ix * n + iy : iy * n + ix];
+      const bool pu = (xmaj ? ex : ey) > R(0), pw = (xmaj ? ey : ex) > R(0);
+      // plane k of an axis (at -half + k pix) is crossed at t = t0 + k dt; the pixel
+      // coordinate along an axis at parameter t is c0 + t ce
+      const R tu0 = xmaj ? tx0 : ty0, tw0 = xmaj ? ty0 : tx0;
+      const R dtu = pix * (xmaj ? iex : iey), dtw = pix * (xmaj ? iey : iex);
+      const R cu0 = (xmaj ? ox : oy) * ipix + hn, cue = (xmaj ? ex : ey) * ipix;
+      const R cw0 = (xmaj ? oy : ox) * ipix + hn, cwe = (xmaj ? ey : ex) * ipix;
+      int iu = xmaj ? ix : iy, iw = xmaj ? iy : ix;
+      Leaf<T> rec = base[iu * n + iw];
       R t = t_in;
       for (int step = 0; step < 4 * n + 8; ++step) {
         const int l = int(rec.lev());
         const int s = 1 << l;
-        const int bx0 = (ix >> l) << l, by0 = (iy >> l) << l;
-        const R tX = ((R(px ? bx0 + s : bx0) - hn) * pix - ox) * iex;
-        const R tY = ((R(py ? by0 + s : by0) - hn) * pix - oy) * iey;
-        const bool sxs = tX <= tY;
-        const R te = fmax(fmin(sxs ? tX : tY, t_out), t);
-        int nix, niy;
-        if (sxs) {
-          nix = px ? bx0 + s : bx0 - 1;
-          const int rr = (int)floorf(fminf(fmaxf(float((oy + te * ey) * ipix + hn), -1.f), float(n)));
-          niy = py ? imin(imax(rr, iy), by0 + s - 1) : imax(imin(rr, iy), by0);
-        } else {
-          niy = py ? by0 + s : by0 - 1;
-          const int cc = (int)floorf(fminf(fmaxf(float((ox + te * ex) * ipix + hn), -1.f), float(n)));
-          nix = px ? imin(imax(cc, ix), bx0 + s - 1) : imax(imin(cc, ix), bx0);
-        }
-        const bool go = te < t_out && (unsigned)nix < (unsigned)n && (unsigned)niy < (unsigned)n;
+        const int bu0 = iu & -s, bw0 = iw & -s;
+        const R tU = fma(R(pu ? bu0 + s : bu0), dtu, tu0);
+        const R tW = fma(R(pw ? bw0 + s : bw0), dtw, tw0);
+        const bool cu = tU <= tW;   // the leaf is left through a u plane
+        const R te = fmax(fmin(cu ? tU : tW, t_out), t);
+        // the axis not crossed takes the exit point's pixel, clamped into the old leaf's
+        // range and never moving backwards; the crossed axis steps to the neighbour leaf
+        const int o = (int)floorf(fminf(fmaxf(float(fma(te, cu ? cwe : cue, cu ? cw0 : cu0)), -1.f), float(n)));
+        const int cur = cu ? iw : iu, b0 = cu ? bw0 : bu0;
+        const bool pos = cu ? pw : pu;
+        const int lo = pos ? cur : b0, hi = pos ? b0 + s - 1 : cur;
+        const int oth = imin(imax(o, lo), hi);
+        const int nu = pu ? bu0 + s : bu0 - 1, nw = pw ? bw0 + s : bw0 - 1;
+        const int niu = cu ? nu : oth, niw = cu ? oth : nw;
+        const bool go = te < t_out && (unsigned)niu < (unsigned)n && (unsigned)niw < (unsigned)n;
         Leaf<T> nrec = rec;
-        if (go) nrec = base[xmaj ? nix * n + niy : niy * n + nix];
+        if (go) nrec = base[niu * n + niw];
         acc += (te - t) * R(rec.mu());
         if (!go) break;
-        t = te; ix = nix; iy = niy; rec = nrec;
+        t = te; iu = niu; iw = niw; rec = nrec;
       }
     }
     const R p = acc;
