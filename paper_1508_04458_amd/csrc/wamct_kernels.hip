@@ -722,11 +722,21 @@ __device__ inline ScanView<T, R> scan_view(const GatherArgs<T, R>& a) {
   return v;
 }
 
+// Work blocks are dealt to the chip's 8 XCDs (each with its own L2) round-robin by block
+// index. A block index b is mapped to work unit w so that each XCD gets one contiguous slice
+// of the units, n_pad / 8 of them (n_pad = units rounded up to a multiple of 8; w >= units:
+// an idle block): units close in the list (the same views, neighbouring items) then share
+// one L2 instead of being fetched by all eight.
+constexpr int kXcds = 8;
+__device__ inline int xcd_unit(int b, int n_pad) { return (b % kXcds) * (n_pad / kXcds) + b / kXcds; }
+inline int xcd_pad(int units) { return (units + kXcds - 1) / kXcds * kXcds; }
+
 // One lane per item of a level segment, all views (used when the segment alone fills the GPU).
 template <typename T, typename R, int MODE>
 __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs<T, R> a) {
   const ScanView<T, R> v = scan_view(a);
-  const int k = blockIdx.x * kBlock + threadIdx.x;
+  const int blk = xcd_unit(blockIdx.x, gridDim.x);
+  const int k = blk * kBlock + threadIdx.x;
   if (k >= v.count) return;
   const uint32_t w = item_word(v.items, v.start + k, a.g.n);
   const ItemSums<R> r = item_sums<T, R>(a.g, a.vf, a.A, v.y, (w >> 31) != 0, int((w >> 27) & 15u),
@@ -746,7 +756,10 @@ __global__ __launch_bounds__(64 * kChunkWaves) void k_gather_part(GatherArgs<T, 
   __shared__ R sh[kChunkWaves][7][64];
   const ScanView<T, R> v = scan_view(a);
   const int n_item_groups = (a.count + 63) / 64;
-  const int ig = blockIdx.x % n_item_groups, group = blockIdx.x / n_item_groups;
+  const int groups = (a.chunks + kChunkWaves - 1) / kChunkWaves;
+  const int unit = xcd_unit(blockIdx.x, gridDim.x);   // unit = group * n_item_groups + ig
+  if (unit >= groups * n_item_groups) return;
+  const int ig = unit % n_item_groups, group = unit / n_item_groups;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int idx = ig * 64 + lane;
   const int chunk = group * kChunkWaves + wv;
@@ -1207,12 +1220,12 @@ namespace {
 template <typename T, typename R, int MODE>
 void launch_segment(const GatherArgs<T, R>& a, int S, hipStream_t s) {
   if (a.chunks <= 1) {
-    hipLaunchKernelGGL((k_gather<T, R, MODE>), dim3(blocks_for(a.count), S), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_gather<T, R, MODE>), dim3(xcd_pad(blocks_for(a.count)), S), dim3(kBlock), 0, s, a);
     return;
   }
   const int groups = (a.chunks + kChunkWaves - 1) / kChunkWaves;
-  hipLaunchKernelGGL((k_gather_part<T, R>), dim3(((a.count + 63) / 64) * groups, S), dim3(64 * kChunkWaves), 0, s,
-                     a);
+  hipLaunchKernelGGL((k_gather_part<T, R>), dim3(xcd_pad(((a.count + 63) / 64) * groups), S),
+                     dim3(64 * kChunkWaves), 0, s, a);
   hipLaunchKernelGGL((k_gather_finish<T, R, MODE>), dim3((a.count + 63) / 64, S), dim3(512), 0, s, a);
 }
 }  // namespace
