@@ -401,7 +401,11 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4
 // leaf's range and never moves backwards, so rounding at a corner only moves a vanishing
 // chord between neighbours and cannot reverse the walk). Every step enters a new leaf, so
 // at most 2n steps occur (loop bound 4n + 8). x-major rays read the column-major records.
-template <typename T, typename R>
+// With K > 1, K adjacent lanes share a ray (for launches with too few rays to fill the
+// GPU): lane k walks the k-th of K equal parameter pieces of the ray's path through the
+// image from the pixel holding the piece's first point, and the K sums are added across
+// the lanes.
+template <typename T, typename R, int K>
 __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typename V4<R>::t* __restrict__ A,
                                                         const typename V4<R>::t* __restrict__ B,
                                                         const Leaf<T>* __restrict__ leafR,
@@ -416,9 +420,11 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
     leafR += oi; leafC += oi;
     d = at(d, orr); i0v = at(i0v, orr); q = at(q, orr); pout = at(pout, orr);
   }
-  const int k = blockIdx.x * kBlock + threadIdx.x;
+  const int lane_id = blockIdx.x * kBlock + threadIdx.x;
+  const int k = lane_id / K, piece = lane_id % K;
   const int r = subset_ray(g, k);
   double term = 0.0;
+  R acc = R(0);
   if (k < g.nvs * g.nb) {
     const typename V4<R>::t a = A[r];
     const typename V4<R>::t bb = B[r];
@@ -428,11 +434,13 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
     const R tx0 = (-half - ox) * iex, tx1 = (half - ox) * iex;
     const R ty0 = (-half - oy) * iey, ty1 = (half - oy) * iey;
     const R t_in = fmax(fmin(tx0, tx1), fmin(ty0, ty1));
-    const R t_out = fmin(fmax(tx0, tx1), fmax(ty0, ty1));
-    R acc = R(0);
-    if (t_out > t_in) {
-      int ix = (int)floor(fmin(fmax((ox + t_in * ex) * ipix + hn, R(-1)), R(n)));
-      int iy = (int)floor(fmin(fmax((oy + t_in * ey) * ipix + hn, R(-1)), R(n)));
+    const R t_end = fmin(fmax(tx0, tx1), fmax(ty0, ty1));
+    if (t_end > t_in) {
+      // this lane's piece [t_s, t_out) of the path
+      const R t_s = piece == 0 ? t_in : t_in + (t_end - t_in) * (R(piece) / R(K));
+      const R t_out = piece == K - 1 ? t_end : t_in + (t_end - t_in) * (R(piece + 1) / R(K));
+      int ix = (int)floor(fmin(fmax((ox + t_s * ex) * ipix + hn, R(-1)), R(n)));
+      int iy = (int)floor(fmin(fmax((oy + t_s * ey) * ipix + hn, R(-1)), R(n)));
       ix = imin(imax(ix, 0), n - 1);
       iy = imin(imax(iy, 0), n - 1);
       // major axis u (the one the ray travels along more; its records are contiguous in
@@ -448,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
       const R cw0 = (xmaj ? oy : ox) * ipix + hn, cwe = (xmaj ? ey : ex) * ipix;
       int iu = xmaj ? ix : iy, iw = xmaj ? iy : ix;
       Leaf<T> rec = base[iu * n + iw];
-      R t = t_in;
+      R t = t_s;
       for (int step = 0; step < 4 * n + 8; ++step) {
         const int l = int(rec.lev());
         const int s = 1 << l;
@@ -474,6 +482,10 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
         t = te; iu = niu; iw = niw; rec = nrec;
       }
     }
+  }
+#pragma unroll
+  for (int o = 1; o < K; o <<= 1) acc += __shfl_xor(acc, o, 64);
+  if (k < g.nvs * g.nb && piece == 0) {
     const R p = acc;
     if (pout) pout[r] = T(p);
     if (q) {
@@ -1209,10 +1221,21 @@ template <typename T, typename R>
 int Geo<T, R>::forward_records(const DevGeom& g, const void* A, const void* B, const void* leafR, const void* leafC,
                                const T* d, const T* i0v, const double* i0s, T* q, T* p, double* part, int S,
                                hipStream_t s) {
-  const int nb = blocks_for(int64_t(g.nvs) * g.nb);
-  hipLaunchKernelGGL((k_forward_rec<T, R>), dim3(nb, S), dim3(kBlock), 0, s, g, (const typename V4<R>::t*)A,
-                     (const typename V4<R>::t*)B, (const Leaf<T>*)leafR, (const Leaf<T>*)leafC, d, i0v, i0s, q, p,
-                     part);
+  // rays per lane group: a launch with fewer rays than ~2^19 (the GPU holds 2^19 lanes at
+  // 8 waves per SIMD) splits each ray over 2 or 4 lanes
+  const int64_t rays = int64_t(g.nvs) * g.nb * S;
+  const int k = rays >= (int64_t(1) << 19) ? 1 : (rays >= (int64_t(1) << 17) ? 2 : 4);
+  const int nb = blocks_for(int64_t(g.nvs) * g.nb * k);
+  auto a = (const typename V4<R>::t*)A;
+  auto b = (const typename V4<R>::t*)B;
+  auto lr = (const Leaf<T>*)leafR;
+  auto lc = (const Leaf<T>*)leafC;
+  if (k == 1)
+    hipLaunchKernelGGL((k_forward_rec<T, R, 1>), dim3(nb, S), dim3(kBlock), 0, s, g, a, b, lr, lc, d, i0v, i0s, q, p, part);
+  else if (k == 2)
+    hipLaunchKernelGGL((k_forward_rec<T, R, 2>), dim3(nb, S), dim3(kBlock), 0, s, g, a, b, lr, lc, d, i0v, i0s, q, p, part);
+  else
+    hipLaunchKernelGGL((k_forward_rec<T, R, 4>), dim3(nb, S), dim3(kBlock), 0, s, g, a, b, lr, lc, d, i0v, i0s, q, p, part);
   return nb;
 }
 
