@@ -1,0 +1,131 @@
+"""Pins of the 3-D cone-beam oracle (oracle/vol3d.py), CPU only.
+
+  * 3-D Siddon H equals brute-force box clipping of every (ray, voxel) pair, and for rays
+    in the mid-plane z = 0 each row sum equals the closed-form chord of the square;
+  * 3-D Haar: orthonormal; Omega^T equals an independent recursive 2x2x2 analysis; a
+    hand-computed 2x2x2 example;
+  * Z0 of the approximation-only octree = 2^(-3L/2) max chord through the volume;
+  * approximation-only 3-D wavelet AM equals voxel AM on the 2^L-coarser grid (exact);
+  * the I-divergence decreases at every iteration, across octree expansions;
+  * noise-free data are a fixed point; the octree rule splits exactly the leaves holding
+    a voxel above the threshold (hand-made case).
+"""
+import numpy as np
+import pytest
+
+from oracle import vol3d, wam
+from paper_1508_04458_amd import synth
+from test_oracle_siddon import square_chord_closed_form
+
+
+def tiny_geom(n=8, nz=4, views=5, rows=6, cols=12):
+    return synth.cone_geometry(n, nz, views, rows, cols, sod=40.0, sdd=70.0)
+
+
+def test_siddon3_equals_box_clipping():
+    for g in (tiny_geom(), tiny_geom(8, 8, 3, 7, 9)):
+        o, e = vol3d.rays3(g)
+        H = vol3d.system_matrix3(g).toarray()
+        exy, ez = vol3d.edges3(g)
+        s, r, c = np.meshgrid(np.arange(g.nz), np.arange(g.n), np.arange(g.n), indexing="ij")
+        lo = np.stack([exy[c.ravel()], exy[r.ravel()], ez[s.ravel()]], axis=1)
+        hi = np.stack([exy[c.ravel() + 1], exy[r.ravel() + 1], ez[s.ravel() + 1]], axis=1)
+        dense = vol3d.box_chord3(o[:, None, :], e[:, None, :], lo[None], hi[None])
+        np.testing.assert_allclose(H, dense, atol=1e-12)
+
+
+def test_mid_plane_rays_match_square_closed_form():
+    g = synth.cone_geometry(16, 4, 7, 1, 40, sod=60.0, sdd=100.0)   # one row: the z = 0 plane
+    o, e = vol3d.rays3(g)
+    assert np.all(e[:, 2] == 0)
+    H = vol3d.system_matrix3(g)
+    ref = square_chord_closed_form(o[:, :2], e[:, :2] / np.linalg.norm(e[:, :2], axis=1, keepdims=True),
+                                   0.5 * g.n * g.pixel)
+    np.testing.assert_allclose(np.asarray(H.sum(axis=1)).ravel(), ref, rtol=1e-12, atol=1e-12)
+
+
+def test_haar3_orthonormal_and_cascade():
+    n, nz, L = 8, 4, 2
+    O = vol3d.synthesis_matrix3(n, nz, L)
+    I = (O.T @ O).toarray()
+    np.testing.assert_allclose(I, np.eye(n * n * nz), atol=1e-13)
+    vol = np.random.default_rng(1).normal(size=(nz, n, n))
+    np.testing.assert_allclose((O.T @ vol.ravel()).reshape(nz, n, n), vol3d.cascade_analysis3(vol, L), atol=1e-12)
+
+
+def test_haar3_hand_example():
+    # one level on a 2x2x2 volume: approximation = sum / (2 sqrt 2); detail (tz, ty, tx) =
+    # sum of +-v / (2 sqrt 2) with - on the upper half of each flagged axis
+    v = np.arange(1.0, 9.0).reshape(2, 2, 2)          # v[z][y][x] = 1..8
+    c = (vol3d.synthesis_matrix3(2, 2, 1).T @ v.ravel()).reshape(2, 2, 2)
+    k = 2 * np.sqrt(2)
+    assert abs(c[0, 0, 0] - 36 / k) < 1e-12
+    assert abs(c[0, 0, 1] - (1 - 2 + 3 - 4 + 5 - 6 + 7 - 8) / k) < 1e-12      # tx
+    assert abs(c[0, 1, 0] - (1 + 2 - 3 - 4 + 5 + 6 - 7 - 8) / k) < 1e-12      # ty
+    assert abs(c[1, 0, 0] - (1 + 2 + 3 + 4 - 5 - 6 - 7 - 8) / k) < 1e-12      # tz
+    assert abs(c[1, 1, 1] - (1 - 2 - 3 + 4 - 5 + 6 + 7 - 8) / k) < 1e-12      # tz ty tx
+
+
+def test_z0_closed_form_and_coarse_grid_reduction():
+    """Approximation-only octree: Z0 = 2^(-3L/2) max chord through the volume, and the
+    whole solve equals voxel AM on the grid of root blocks."""
+    g = synth.cone_geometry(16, 8, 9, 8, 30, sod=60.0, sdd=100.0)
+    L = 1
+    H = vol3d.system_matrix3(g)
+    shapes = synth.make_ellipsoids(np.random.default_rng(3), g.n, g.nz, g.pixel, 4, 0.06, 0)
+    o, e = vol3d.rays3(g)
+    d = np.random.default_rng(4).poisson(2e4 * np.exp(-synth.line_integrals3(shapes, o, e))).astype(float)
+    r = vol3d.wam_solve3(H, g.n, g.nz, L, d, 2e4, 5, g.pixel)
+    lo = np.array([-8.0, -8.0, -4.0])
+    chord = vol3d.box_chord3(o, e, lo, -lo)
+    assert abs(r["z0"][0] - 2 ** (-1.5 * L) * chord.max()) <= 1e-12 * r["z0"][0]
+    gc = synth.cone_geometry(8, 4, 9, 8, 30, sod=60.0, sdd=100.0, pixel=2.0)
+    gc = synth.Geometry3(**{**gc.__dict__, "col_pitch": g.col_pitch, "row_pitch": g.row_pitch})
+    Hc = vol3d.system_matrix3(gc)
+    # pixel AM on the coarse grid (Omega = I), written with the generic 3-D solver (levels 0)
+    rc = vol3d.wam_solve3(Hc, gc.n, gc.nz, 0, d, 2e4, 5, gc.pixel)
+    mu = r["mu"][::2, ::2, ::2]
+    np.testing.assert_allclose(mu, rc["mu"], rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(r["idiv"], rc["idiv"], rtol=1e-11)
+
+
+@pytest.fixture(scope="module")
+def cone32():
+    P = synth.make_cone_problem("cone32")
+    return P, vol3d.system_matrix3(P.geom)
+
+
+def test_monotone_across_expansions(cone32):
+    P, H = cone32
+    g = P.geom
+    r = vol3d.wam_solve3(H, g.n, g.nz, P.levels, P.d, P.i0, P.n_iters, g.pixel, schedule=P.schedule)
+    tr = r["idiv"]
+    assert np.all(np.diff(tr) <= 1e-12 * np.abs(tr[:-1])), np.diff(tr)
+    assert len(r["trees"]) == len(P.schedule) + 1
+    assert vol3d.valid_mask3(r["mask"], P.levels)
+    assert r["mask"].sum() > (g.n >> P.levels) ** 2 * (g.nz >> P.levels)
+
+
+def test_fixed_point_and_tree_rule():
+    g = synth.cone_geometry(8, 8, 6, 6, 14, sod=40.0, sdd=70.0)
+    L = 2
+    H = vol3d.system_matrix3(g)
+    O = vol3d.synthesis_matrix3(g.n, g.nz, L)
+    mask = vol3d.approx_mask3(g.n, g.nz, L)
+    beta = np.zeros((g.nz, g.n, g.n))
+    beta[:2, :2, :2] = np.random.default_rng(5).uniform(0.05, 0.2, (2, 2, 2)) * 2 ** (1.5 * L)
+    # octree rule: only root (1, 0, 1) holds a value above 0.1 of the maximum
+    beta2 = np.zeros_like(beta)
+    beta2[1, 0, 1] = 1.0
+    beta2[0, 1, 1] = 0.05
+    new, count = vol3d.expand_tree3(beta2.ravel(), mask, L, 0.1, O)
+    split = vol3d.split_flags3(new, L)
+    expect = np.zeros((2, 2, 2), bool)
+    expect[1, 0, 1] = True
+    np.testing.assert_array_equal(split, expect)
+    assert count == 1 and vol3d.valid_mask3(new, L)
+    # noise-free data of beta on the tree: a fixed point
+    d = 3e4 * np.exp(-(H @ (O @ beta.ravel())))
+    r = vol3d.wam_solve3(H, g.n, g.nz, L, d, 3e4, 2, g.pixel, beta0=beta, mask0=mask)
+    assert np.max(np.abs(r["beta"] - beta)) <= 1e-10
+    assert abs(r["idiv"][-1]) <= 1e-8
