@@ -22,6 +22,18 @@
  *            detail k = 2^-l s_k on the node block with quadrant signs over (top-left,
  *            top-right, bottom-left, bottom-right) s1 = (+,-,+,-), s2 = (+,+,-,-),
  *            s3 = (+,-,-,+), "top" = smaller row index.
+ *   volume   (WAMCT_CONE) n x n x nz voxels of edge `pixel`, centred, layout [z][y][x], voxel
+ *            (s, r, c) covering z in [(s - nz/2) pixel, (s + 1 - nz/2) pixel) (x, y as above).
+ *            Circular orbit: source sod (cos a, sin a, 0); flat detector centred at
+ *            -(sdd - sod)(cos a, sin a, 0), column axis (-sin a, cos a, 0), row axis (0, 0, 1);
+ *            element (row rr, column cc) at (cc - (n_bins - 1)/2) bin_pitch,
+ *            (rr - (n_rows - 1)/2) row_pitch; ray y = (view n_rows + rr) n_bins + cc.
+ *            3-D Haar: orthonormal, separable, 3-D Mallat layout; node (l, k, i, j) covers
+ *            the voxel block [k 2^l, (k+1) 2^l) x [i 2^l, ...) x [j 2^l, ...) (z, y, x); its
+ *            seven details t = (tz, ty, tx) != 0 sit at [k + tz mz][i + ty m][j + tx m]
+ *            (m = n >> l, mz = nz >> l), basis 2^(-3l/2) times, per flagged axis, +1 on the
+ *            lower and -1 on the upper half; the approximation of root (k, i, j) sits at
+ *            [k][i][j], basis 2^(-3L/2). A node splits into its seven details together.
  *   tree     the active set Z_s (footnote to eq. 1.61) is a uint8 n x n mask in Mallat
  *            layout: approximations always active; a node's three details are active
  *            together ("split"), and only if its parent is split or it is a root.
@@ -62,7 +74,7 @@ typedef enum {
   WAMCT_E_STATE = 6        /* call out of order (e.g. iterate before set_data) */
 } wamct_status;
 
-enum { WAMCT_PARALLEL = 0, WAMCT_FAN = 1 };
+enum { WAMCT_PARALLEL = 0, WAMCT_FAN = 1, WAMCT_CONE = 2 };
 enum { WAMCT_F32 = 0, WAMCT_F64 = 1 };
 
 /* Scan geometry (the paper gives none; see the conventions above). */
@@ -75,8 +87,11 @@ typedef struct {
   double angle_span;   /* [rad]; view v at angle0 + v * angle_span / n_views */
   int32_t n_bins;      /* >= 1 */
   double bin_pitch;    /* [mm] at the detector, > 0 */
-  double sod;          /* fan: source to isocentre [mm], > image circumradius */
-  double sdd;          /* fan: source to detector [mm], > sod */
+  double sod;          /* fan, cone: source to isocentre [mm], > image circumradius */
+  double sdd;          /* fan, cone: source to detector [mm], > sod */
+  int32_t nz;          /* cone: slices of the n x n x nz volume (1 <= nz <= 512); else ignored */
+  int32_t n_rows;      /* cone: detector rows (>= 1); else ignored */
+  double row_pitch;    /* cone: detector row pitch [mm] (> 0); else ignored */
 } wamct_geometry;
 
 typedef struct {

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwamct.so")
 
 OK, E_INVALID, E_UNSUPPORTED, E_OOM, E_HIP, E_NUMERIC, E_STATE = range(7)
-PARALLEL, FAN = 0, 1
+PARALLEL, FAN, CONE = 0, 1, 2
 F32, F64 = 0, 1
 K_SYNTH, K_FORWARD, K_UPDATE, K_TREE, K_OTHER, NK = range(6)
 KERNEL_CLASSES = ("synth", "forward", "update", "tree", "other")
@@ -35,7 +35,8 @@ class Geometry(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32), ("pixel", ctypes.c_double),
                 ("n_views", ctypes.c_int32), ("angle0", ctypes.c_double), ("angle_span", ctypes.c_double),
                 ("n_bins", ctypes.c_int32), ("bin_pitch", ctypes.c_double), ("sod", ctypes.c_double),
-                ("sdd", ctypes.c_double)]
+                ("sdd", ctypes.c_double), ("nz", ctypes.c_int32), ("n_rows", ctypes.c_int32),
+                ("row_pitch", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):

@@ -6,6 +6,7 @@ matching `wamct_*` call; all arithmetic runs in the HIP kernels of libwamct.so."
 import ctypes
 from typing import Dict, Optional, Sequence
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -15,8 +16,13 @@ _DT = {"f32": (_lib.F32, torch.float32), "f64": (_lib.F64, torch.float64)}
 
 
 def _geometry(g) -> _lib.Geometry:
+    if int(g.kind) == _lib.CONE:   # 3-D cone beam: detector columns are the "bins"
+        return _lib.Geometry(int(g.kind), int(g.n), float(g.pixel), int(g.n_views), float(g.angle0),
+                             float(g.angle_span), int(g.n_cols), float(g.col_pitch), float(g.sod), float(g.sdd),
+                             int(g.nz), int(g.n_rows), float(g.row_pitch))
     return _lib.Geometry(int(g.kind), int(g.n), float(g.pixel), int(g.n_views), float(g.angle0),
-                         float(g.angle_span), int(g.n_bins), float(g.bin_pitch), float(g.sod), float(g.sdd))
+                         float(g.angle_span), int(g.n_bins), float(g.bin_pitch), float(g.sod), float(g.sdd),
+                         1, 1, 0.0)
 
 
 def _options(levels, dtype, geometry, batch=1):
@@ -55,7 +61,13 @@ class Context:
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.n = int(geom.n)
-        self.n_rays = int(geom.n_views) * int(geom.n_bins)
+        if int(geom.kind) == _lib.CONE:
+            self.n_rays = int(geom.n_views) * int(geom.n_rows) * int(geom.n_cols)
+            self.img_shape = (int(geom.nz), self.n, self.n)
+        else:
+            self.n_rays = int(geom.n_views) * int(geom.n_bins)
+            self.img_shape = (self.n, self.n)
+        self.npix = int(np.prod(self.img_shape))
         self.S = int(batch)
         self._h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -115,14 +127,14 @@ class Context:
         self._call(lib.wamct_reset)
 
     def set_state(self, beta: torch.Tensor, mask: torch.Tensor) -> None:
-        self._arr(beta, self.S * self.n * self.n, "beta")
-        self._arr(mask, self.S * self.n * self.n, "mask", torch.uint8)
+        self._arr(beta, self.S * self.npix, "beta")
+        self._arr(mask, self.S * self.npix, "mask", torch.uint8)
         self._call(lib.wamct_set_state, _ptr(beta), _ptr(mask))
 
     def get_state(self):
-        nn = self.S * self.n * self.n
-        beta = self._new(nn, shape=self._shape(self.n, self.n))
-        mask = self._new(nn, torch.uint8, self._shape(self.n, self.n))
+        nn = self.S * self.npix
+        beta = self._new(nn, shape=self._shape(*self.img_shape))
+        mask = self._new(nn, torch.uint8, self._shape(*self.img_shape))
         it = ctypes.c_int32()
         self._call(lib.wamct_get_state, _ptr(beta), _ptr(mask), ctypes.byref(it))
         return beta, mask, it.value
@@ -180,26 +192,26 @@ class Context:
 
     # ------------------------------------------------------------------ operators
     def synthesize(self) -> torch.Tensor:
-        mu = self._new(self.S * self.n * self.n, shape=self._shape(self.n, self.n))
+        mu = self._new(self.S * self.npix, shape=self._shape(*self.img_shape))
         self._call(lib.wamct_synthesize, _ptr(mu))
         return mu
 
     def project(self, mu: torch.Tensor) -> torch.Tensor:
-        self._arr(mu, self.n * self.n, "mu")
+        self._arr(mu, self.npix, "mu")
         p = self._new(self.n_rays)
         self._call(lib.wamct_project, _ptr(mu), _ptr(p))
         return p
 
     def backproject(self, y: torch.Tensor) -> torch.Tensor:
         self._arr(y, self.n_rays, "y")
-        img = self._new(self.n * self.n, shape=(self.n, self.n))
+        img = self._new(self.npix, shape=self.img_shape)
         self._call(lib.wamct_backproject, _ptr(y), _ptr(img))
         return img
 
     def backproject_split(self, y: torch.Tensor):
         self._arr(y, self.S * self.n_rays, "y")
-        bp = self._new(self.S * self.n * self.n, shape=self._shape(self.n, self.n))
-        bm = self._new(self.S * self.n * self.n, shape=self._shape(self.n, self.n))
+        bp = self._new(self.S * self.npix, shape=self._shape(*self.img_shape))
+        bm = self._new(self.S * self.npix, shape=self._shape(*self.img_shape))
         self._call(lib.wamct_backproject_split, _ptr(y), _ptr(bp), _ptr(bm))
         return bp, bm
 
@@ -216,7 +228,7 @@ class Context:
         return out
 
     def b(self) -> torch.Tensor:
-        out = self._new(self.S * self.n * self.n, shape=self._shape(self.n, self.n))
+        out = self._new(self.S * self.npix, shape=self._shape(*self.img_shape))
         self._call(lib.wamct_get_b, _ptr(out))
         return out
 

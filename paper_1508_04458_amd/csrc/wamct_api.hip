@@ -16,16 +16,12 @@
 #include <vector>
 
 #include "../../include/wamct.h"
+#include "wamct_ctx.h"
 #include "wamct_internal.h"
 
 using namespace wamct;
 
-namespace {
-thread_local std::string g_last_error;
-
-const char* kVersion = "wamct 0.1 (gfx950)";
-
-std::string fmt(const char* f, ...) __attribute__((format(printf, 1, 2)));
+namespace wamct {
 std::string fmt(const char* f, ...) {
   char buf[512];
   va_list ap;
@@ -34,9 +30,16 @@ std::string fmt(const char* f, ...) {
   va_end(ap);
   return buf;
 }
+}  // namespace wamct
+
+namespace {
+thread_local std::string g_last_error;
+
+const char* kVersion = "wamct 0.2 (gfx950)";
 
 std::string validate(const wamct_geometry* g, const wamct_options* o) {
   if (!g || !o) return "geometry and options must not be NULL";
+  if (g->kind == WAMCT_CONE) return validate3(g, o);
   if (g->kind != WAMCT_PARALLEL && g->kind != WAMCT_FAN) return fmt("unknown geometry kind %d", g->kind);
   if (g->n < 2 || g->n > 8192) return fmt("image size n = %d outside [2, 8192]", g->n);
   if (!(g->pixel > 0) || !std::isfinite(g->pixel)) return "pixel size must be finite and > 0";
@@ -58,75 +61,6 @@ std::string validate(const wamct_geometry* g, const wamct_options* o) {
   return "";
 }
 }  // namespace
-
-struct wamct_ctx {
-  std::string err;
-  virtual ~wamct_ctx() {}
-  virtual wamct_status init(const wamct_geometry&, const wamct_options&, hipStream_t) = 0;
-  virtual wamct_status set_stream(hipStream_t) = 0;
-  virtual wamct_status set_data(const void*, const void*, const double*) = 0;
-  virtual wamct_status reset() = 0;
-  virtual wamct_status set_state(const void*, const uint8_t*) = 0;
-  virtual wamct_status get_state(void*, uint8_t*, int32_t*) = 0;
-  virtual wamct_status iterate(int32_t, double*) = 0;
-  virtual wamct_status expand_tree(double, int32_t*) = 0;
-  virtual wamct_status solve(int32_t, const int32_t*, int32_t, double, double*) = 0;
-  virtual wamct_status synthesize(void*) = 0;
-  virtual wamct_status project(const void*, void*) = 0;
-  virtual wamct_status backproject(const void*, void*) = 0;
-  virtual wamct_status backproject_split(const void*, void*, void*) = 0;
-  virtual wamct_status forward(void*, double*) = 0;
-  virtual wamct_status idiv(const void*, double*) = 0;
-  virtual wamct_status get_b(void*) = 0;
-  virtual wamct_status tree_stats(double*, int64_t*, int64_t*, int64_t*) = 0;
-  virtual wamct_status loss(int32_t, const void*, const void*, const void*, double, double*, void*) = 0;
-  virtual wamct_status loss_backward(int32_t, const void*, const void*, const double*, void*) = 0;
-  virtual wamct_status timing(int32_t) = 0;
-  virtual wamct_status get_timing(double*, int64_t*) = 0;
-  virtual wamct_status set_tiling(int32_t) = 0;
-  virtual int32_t tiling() const = 0;
-  virtual wamct_status set_subsets(int32_t) = 0;
-  virtual int32_t subsets() const = 0;
-  virtual wamct_status set_tree_sharing(int32_t) = 0;
-  virtual int32_t tree_sharing() const = 0;
-  // stream-ordered pieces used by batches (no host synchronization inside)
-  virtual int n_scans() const = 0;
-  virtual hipStream_t stream() const = 0;
-  virtual double work() const = 0;
-  virtual bool has_data_() const = 0;
-  virtual bool tree_dirty_() const = 0;
-  virtual wamct_status enq_tree(hipStream_t) = 0;
-  virtual wamct_status finish_tree(int32_t*) = 0;
-  virtual wamct_status enq_reset(hipStream_t) = 0;
-  virtual wamct_status enq_expand(hipStream_t, double) = 0;
-  virtual wamct_status enq_begin(hipStream_t) = 0;
-  virtual wamct_status enq_iteration(hipStream_t, double*, int64_t, bool) = 0;
-  virtual wamct_status enq_final(hipStream_t, double*, int64_t, bool) = 0;
-  virtual wamct_status save_state(hipStream_t) = 0;
-  virtual wamct_status restore_state(hipStream_t) = 0;
-  virtual void count_iters(int) = 0;
-  wamct_status fail(wamct_status s, const std::string& m) {
-    err = m;
-    return s;
-  }
-};
-
-#define HIPCHK(expr)                                                                   \
-  do {                                                                                 \
-    hipError_t e_ = (expr);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      return fail(WAMCT_E_HIP, fmt("%s: %s", #expr, hipGetErrorString(e_)));            \
-  } while (0)
-#define LAUNCHED()                                                                     \
-  do {                                                                                 \
-    hipError_t e_ = hipGetLastError();                                                 \
-    if (e_ != hipSuccess) return fail(WAMCT_E_HIP, fmt("kernel launch: %s", hipGetErrorString(e_))); \
-  } while (0)
-#define CHECKED(expr)                                                                  \
-  do {                                                                                 \
-    wamct_status r_ = (expr);                                                          \
-    if (r_ != WAMCT_OK) return r_;                                                     \
-  } while (0)
 
 namespace {
 
@@ -1208,7 +1142,8 @@ wamct_status wamct_create(const wamct_geometry* geom, const wamct_options* opt, 
   std::string e = validate(geom, opt);
   if (!e.empty()) { g_last_error = e; return WAMCT_E_INVALID; }
   wamct_ctx* c = nullptr;
-  if (opt->dtype == WAMCT_F64) c = new Ctx<double, double>();
+  if (geom->kind == WAMCT_CONE) c = make_ctx3(*opt);
+  else if (opt->dtype == WAMCT_F64) c = new Ctx<double, double>();
   else if (opt->geometry == WAMCT_F32) c = new Ctx<float, float>();
   else c = new Ctx<float, double>();
   wamct_status s = c->init(*geom, *opt, static_cast<hipStream_t>(stream));

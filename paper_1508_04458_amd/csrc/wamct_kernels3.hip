@@ -1,0 +1,910 @@
+// HIP kernels of wavelet-tree AM on a 3-D volume for gfx950: circular cone beam with a flat
+// detector and a 3-D Haar octree (seven details per node).
+//
+// Method: Degirmenci, O'Sullivan, Politte, arXiv 1508.04458, Introduction (eqs. 1.2-1.10,
+// Algorithm 1) and Results (tree rule), applied to voxels and octree nodes. As in 2-D the
+// system matrix is never stored: chords through voxels, leaves and node octants are
+// recomputed from the ray table, so the kernels are bound by vector ALU and cache gathers.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "wamct_internal3.h"
+
+namespace wamct {
+namespace {
+
+constexpr int kB = 256;
+inline int blocks3(int64_t n, int b = kB) { return int((n + b - 1) / b); }
+
+__device__ inline int imin3(int a, int b) { return a < b ? a : b; }
+__device__ inline int imax3(int a, int b) { return a > b ? a : b; }
+
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wmax(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+template <bool MAX>
+__device__ inline double breduce(double v) {
+  __shared__ double sh[kB / 64];
+  v = MAX ? wmax(v) : wsum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int k = 1; k < kB / 64; ++k) r = MAX ? fmax(r, sh[k]) : r + sh[k];
+    v = r;
+  }
+  return v;
+}
+
+// ------------------------------------------------------------------ geometry
+
+// Ray of detector element (row, col) of a view: from the source sod (c, s, 0) to the element
+// centre on the flat detector; origin moved to the point closest to the volume centre. A
+// direction component within 1e-12 of 0 is treated as exactly 0: the line is moved to the
+// centre of the voxel slab that contains it along that axis (chords unchanged; a line on a
+// boundary goes to the + side, half-open voxels) and tilted by 1e-12 so 1/e stays finite.
+__global__ __launch_bounds__(kB) void k3_ray_table(DevGeom3 g, const double2* __restrict__ views,
+                                                   double4* __restrict__ A, double4* __restrict__ B,
+                                                   double* __restrict__ C) {
+  const int64_t r = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int64_t per_view = int64_t(g.nr) * g.nc;
+  if (r >= per_view * g.nv) return;
+  const int v = int(r / per_view);
+  const int rem = int(r - int64_t(v) * per_view);
+  const int row = rem / g.nc, col = rem - row * g.nc;
+  const double c = views[v].x, s = views[v].y;
+  const double u = (col - 0.5 * (g.nc - 1)) * g.cpitch, w = (row - 0.5 * (g.nr - 1)) * g.rpitch;
+  const double sx = g.sod * c, sy = g.sod * s, sz = 0.0;
+  const double dx = -(g.sdd - g.sod) * c - u * s - sx, dy = -(g.sdd - g.sod) * s + u * c - sy, dz = w - sz;
+  const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+  double ex = dx * inv, ey = dy * inv, ez = dz * inv;
+  const double tc = -(sx * ex + sy * ey + sz * ez);
+  double ox = sx + tc * ex, oy = sy + tc * ey, oz = sz + tc * ez;
+  const double hn = 0.5 * g.n, hz = 0.5 * g.nz;
+  if (fabs(ex) < 1e-12) { ox = (floor(ox / g.pixel + hn) + 0.5 - hn) * g.pixel; ex = ex < 0 ? -1e-12 : 1e-12; }
+  if (fabs(ey) < 1e-12) { oy = (floor(oy / g.pixel + hn) + 0.5 - hn) * g.pixel; ey = ey < 0 ? -1e-12 : 1e-12; }
+  if (fabs(ez) < 1e-12) { oz = (floor(oz / g.pixel + hz) + 0.5 - hz) * g.pixel; ez = ez < 0 ? -1e-12 : 1e-12; }
+  A[r] = make_double4(ox, oy, oz, 1.0 / ex);
+  B[r] = make_double4(1.0 / ey, 1.0 / ez, ex, ey);
+  C[r] = ez;
+}
+
+// ------------------------------------------------------------------ octree helpers
+
+// node (l, k, i, j) split <=> its tx detail is active: mask[k][i][m + j], m = n >> l
+__device__ inline bool split3(const uint8_t* __restrict__ mask, int n, int l, int k, int i, int j) {
+  const int m = n >> l;
+  return mask[(int64_t(k) * n + i) * n + m + j] != 0;
+}
+
+__device__ inline uint32_t morton3_compact(uint32_t x) {
+  x &= 0x09249249u;
+  x = (x | (x >> 2)) & 0x030c30c3u;
+  x = (x | (x >> 4)) & 0x0300f00fu;
+  x = (x | (x >> 8)) & 0x030000ffu;
+  x = (x | (x >> 16)) & 0x000003ffu;
+  return x;
+}
+
+// Detail slot d (0..6) has the type t = d + 1 with bits (tz, ty, tx) = (t >> 2, t >> 1, t) & 1,
+// at [k + tz mz][i + ty m][j + tx m]; its basis is 2^(-3l/2) prod over flagged axes of
+// (+1 lower half, -1 upper half).
+__device__ inline int64_t detail_pos(int n, int nz, int l, int d, int k, int i, int j) {
+  const int t = d + 1, m = n >> l, mz = nz >> l;
+  return (int64_t(k + ((t >> 2) & 1) * mz) * n + (i + ((t >> 1) & 1) * m)) * n + (j + (t & 1) * m);
+}
+
+__device__ inline double scale3(int l) { return exp2(-1.5 * double(l)); }
+
+// mu(voxel) = 2^(-3L/2) beta_LL(root) + sum over levels of 2^(-3l/2) sum_d sign_d beta_d
+template <typename T, typename R>
+__device__ inline R synth_voxel(const T* __restrict__ beta, int n, int nz, int L, int s, int r, int c) {
+  R v = R(beta[(int64_t(s >> L) * n + (r >> L)) * n + (c >> L)]) * R(scale3(L));
+  for (int l = L; l >= 1; --l) {
+    const int k = s >> l, i = r >> l, j = c >> l;
+    const int oct = (((s >> (l - 1)) & 1) << 2) | (((r >> (l - 1)) & 1) << 1) | ((c >> (l - 1)) & 1);
+    R acc = R(0);
+#pragma unroll
+    for (int d = 0; d < 7; ++d) {
+      const R b = R(beta[detail_pos(n, nz, l, d, k, i, j)]);
+      acc += (__popc(uint32_t((d + 1) & oct)) & 1) ? -b : b;
+    }
+    v += acc * R(scale3(l));
+  }
+  return v;
+}
+
+// Leaf record: value rounded to 4 free low mantissa bits that hold the leaf level.
+template <typename T> struct Rec3;
+template <> struct Rec3<float> {
+  uint32_t w;
+  __device__ static Rec3 make(float v, uint32_t lev) { return Rec3{((__float_as_uint(v) + 8u) & ~15u) | lev}; }
+  __device__ float mu() const { return __uint_as_float(w & ~15u); }
+  __device__ uint32_t lev() const { return w & 15u; }
+};
+template <> struct Rec3<double> {
+  uint64_t w;
+  __device__ static Rec3 make(double v, uint32_t lev) {
+    return Rec3{((uint64_t(__double_as_longlong(v)) + 8u) & ~uint64_t(15)) | lev};
+  }
+  __device__ double mu() const { return __longlong_as_double((long long)(w & ~uint64_t(15))); }
+  __device__ uint32_t lev() const { return uint32_t(w & 15u); }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kB) void k3_synth_records(DevGeom3 g, const T* __restrict__ beta,
+                                                       const uint8_t* __restrict__ lev, Rec3<T>* __restrict__ recR,
+                                                       Rec3<T>* __restrict__ recC) {
+  const int64_t p = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int n = g.n;
+  if (p >= int64_t(n) * n * g.nz) return;
+  const int s = int(p / (int64_t(n) * n)), r = int((p / n) % n), c = int(p % n);
+  const T v = lev ? synth_voxel<T, T>(beta, n, g.nz, g.L, s, r, c) : beta[p];
+  const uint32_t l = lev ? lev[p] : 0u;
+  recR[p] = Rec3<T>::make(v, l);
+  recC[(int64_t(s) * n + c) * n + r] = Rec3<T>::make(v, l);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kB) void k3_synth(DevGeom3 g, const T* __restrict__ beta, T* __restrict__ mu) {
+  const int64_t p = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int n = g.n;
+  if (p >= int64_t(n) * n * g.nz) return;
+  mu[p] = synth_voxel<T, T>(beta, n, g.nz, g.L, int(p / (int64_t(n) * n)), int((p / n) % n), int(p % n));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kB) void k3_mu64(DevGeom3 g, const T* __restrict__ beta, double* __restrict__ mu64,
+                                              double* __restrict__ part) {
+  const int64_t p = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int n = g.n;
+  double v = -INFINITY;
+  if (p < int64_t(n) * n * g.nz) {
+    v = synth_voxel<T, double>(beta, n, g.nz, g.L, int(p / (int64_t(n) * n)), int((p / n) % n), int(p % n));
+    mu64[p] = v;
+  }
+  v = breduce<true>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kB) void k3_levmap(DevGeom3 g, const uint8_t* __restrict__ mask,
+                                                uint8_t* __restrict__ lev) {
+  const int64_t p = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int n = g.n;
+  if (p >= int64_t(n) * n * g.nz) return;
+  const int s = int(p / (int64_t(n) * n)), r = int((p / n) % n), c = int(p % n);
+  int l = g.L;
+  while (l >= 1 && split3(mask, n, l, s >> l, r >> l, c >> l)) --l;
+  lev[p] = uint8_t(l);
+}
+
+// coef(z) = sum over the support of basis function z of its value times vol (Omega^T vol),
+// FP64; Mallat position -> (level, detail type, node)
+template <typename T>
+__global__ __launch_bounds__(kB) void k3_analysis(DevGeom3 g, const T* __restrict__ vol, T* __restrict__ coef) {
+  const int64_t p = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int n = g.n, nz = g.nz, L = g.L;
+  if (p >= int64_t(n) * n * nz) return;
+  const int z = int(p / (int64_t(n) * n)), y = int((p / n) % n), x = int(p % n);
+  int l = 0, t = 0;
+  for (int lv = L; lv >= 1; --lv) {
+    const int m = n >> lv, mz = nz >> lv;
+    if (z < 2 * mz && y < 2 * m && x < 2 * m) {
+      t = (z >= mz ? 4 : 0) | (y >= m ? 2 : 0) | (x >= m ? 1 : 0);
+      if (t != 0 || lv == L) { l = lv; break; }
+    }
+  }
+  double acc = 0.0;
+  if (t == 0) {  // approximation of root (z, y, x) (or a voxel when L = 0)
+    const int s = 1 << L;
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b < s; ++b)
+        for (int c = 0; c < s; ++c) acc += double(vol[(int64_t(z * s + a) * n + y * s + b) * n + x * s + c]);
+    acc *= scale3(L);
+  } else {
+    const int m = n >> l, mz = nz >> l, s = 1 << l, h = s >> 1;
+    const int k = z % mz, i = y % m, j = x % m;
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b < s; ++b)
+        for (int c = 0; c < s; ++c) {
+          const int oct = ((a >= h) << 2) | ((b >= h) << 1) | (c >= h);
+          const double v = double(vol[(int64_t(k * s + a) * n + i * s + b) * n + j * s + c]);
+          acc += (__popc(uint32_t(t & oct)) & 1) ? -v : v;
+        }
+    acc *= scale3(l);
+  }
+  coef[p] = T(acc);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kB) void k3_apply_mask(int64_t len, T* __restrict__ beta, const uint8_t* __restrict__ m) {
+  const int64_t p = int64_t(blockIdx.x) * kB + threadIdx.x;
+  if (p < len && m[p] == 0) beta[p] = T(0);
+}
+
+// Validity of an octree mask: *bad counts violated constraints (roots active; 0/1 values;
+// a node's seven details equal; a split node's parent split).
+__global__ __launch_bounds__(kB) void k3_check_mask(DevGeom3 g, const uint8_t* __restrict__ mask,
+                                                    int* __restrict__ bad) {
+  const int64_t p = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int n = g.n, nz = g.nz, L = g.L;
+  if (p >= int64_t(n) * n * nz) return;
+  const int z = int(p / (int64_t(n) * n)), y = int((p / n) % n), x = int(p % n);
+  if (z < (nz >> L) && y < (n >> L) && x < (n >> L)) {
+    if (mask[p] != 1) atomicAdd(bad, 1);
+    return;
+  }
+  if (mask[p] > 1) { atomicAdd(bad, 1); return; }
+  int l = 0;
+  for (int lv = L; lv >= 1; --lv)
+    if (z < 2 * (nz >> lv) && y < 2 * (n >> lv) && x < 2 * (n >> lv)) { l = lv; break; }
+  if (l == 0) { atomicAdd(bad, 1); return; }
+  const int m = n >> l, mz = nz >> l;
+  const int k = z % mz, i = y % m, j = x % m;
+  const bool f = split3(mask, n, l, k, i, j);
+  if ((mask[p] != 0) != f) { atomicAdd(bad, 1); return; }
+  if (f && l < L && !split3(mask, n, l + 1, k >> 1, i >> 1, j >> 1)) atomicAdd(bad, 1);
+}
+
+__global__ void k3_approx_mask(DevGeom3 g, uint8_t* __restrict__ mask) {
+  const int64_t p = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int n = g.n;
+  if (p >= int64_t(n) * n * g.nz) return;
+  const int z = int(p / (int64_t(n) * n)), y = int((p / n) % n), x = int(p % n);
+  mask[p] = (z < (g.nz >> g.L) && y < (n >> g.L) && x < (n >> g.L)) ? 1 : 0;
+}
+
+// ------------------------------------------------------------------ forward (leaf walk)
+
+// Per ray: walk the octree leaves (cubes of side 2^l voxels) from the entry point; each leaf
+// is left through the nearest of its three exit planes; the crossed axis steps to the
+// neighbouring leaf, the two others take the exit point's voxel, clamped into the old
+// leaf's range and never moving backwards. p = sum of chord * leaf value; then Beer's law
+// and the FP64 I-divergence term. x-major rays read the [z][x][y] records (neighbouring
+// lanes, neighbouring rays of a detector row, then touch neighbouring addresses).
+template <typename T>
+__global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, const double4* __restrict__ A,
+                                                 const double4* __restrict__ B, const double* __restrict__ C,
+                                                 const Rec3<T>* __restrict__ recR, const Rec3<T>* __restrict__ recC,
+                                                 const T* __restrict__ d, const T* __restrict__ i0v,
+                                                 const double* __restrict__ i0s, T* __restrict__ q,
+                                                 T* __restrict__ pout, double* __restrict__ part) {
+  const int64_t r = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int64_t M = int64_t(g.nv) * g.nr * g.nc;
+  double term = 0.0;
+  if (r < M) {
+    const double4 a = A[r], b = B[r];
+    const double ox = a.x, oy = a.y, oz = a.z, iex = a.w, iey = b.x, iez = b.y, ex = b.z, ey = b.w, ez = C[r];
+    const int n = g.n, nz = g.nz;
+    const double pix = g.pixel, ipix = 1.0 / g.pixel, hn = 0.5 * n, hz = 0.5 * nz;
+    const double tx0 = (-hn * pix - ox) * iex, tx1 = (hn * pix - ox) * iex;
+    const double ty0 = (-hn * pix - oy) * iey, ty1 = (hn * pix - oy) * iey;
+    const double tz0 = (-hz * pix - oz) * iez, tz1 = (hz * pix - oz) * iez;
+    const double t_in = fmax(fmax(fmin(tx0, tx1), fmin(ty0, ty1)), fmin(tz0, tz1));
+    const double t_out = fmin(fmin(fmax(tx0, tx1), fmax(ty0, ty1)), fmax(tz0, tz1));
+    double acc = 0.0;
+    if (t_out > t_in) {
+      int ix = (int)floor(fmin(fmax((ox + t_in * ex) * ipix + hn, -1.0), double(n)));
+      int iy = (int)floor(fmin(fmax((oy + t_in * ey) * ipix + hn, -1.0), double(n)));
+      int iz = (int)floor(fmin(fmax((oz + t_in * ez) * ipix + hz, -1.0), double(nz)));
+      ix = imin3(imax3(ix, 0), n - 1);
+      iy = imin3(imax3(iy, 0), n - 1);
+      iz = imin3(imax3(iz, 0), nz - 1);
+      const bool px = ex > 0, py = ey > 0, pz = ez > 0;
+      const bool xmaj = fabs(ex) >= fabs(ey);
+      const Rec3<T>* __restrict__ base = xmaj ? recC : recR;
+      auto addr = [&](int x, int y, int z) {
+        return xmaj ? (int64_t(z) * n + x) * n + y : (int64_t(z) * n + y) * n + x;
+      };
+      Rec3<T> rec = base[addr(ix, iy, iz)];
+      double t = t_in;
+      for (int step = 0; step < 4 * (2 * n + nz) + 8; ++step) {
+        const int l = int(rec.lev());
+        const int s = 1 << l;
+        const int bx0 = ix & -s, by0 = iy & -s, bz0 = iz & -s;
+        const double tX = ((double(px ? bx0 + s : bx0) - hn) * pix - ox) * iex;
+        const double tY = ((double(py ? by0 + s : by0) - hn) * pix - oy) * iey;
+        const double tZ = ((double(pz ? bz0 + s : bz0) - hz) * pix - oz) * iez;
+        const int ax = (tX <= tY && tX <= tZ) ? 0 : (tY <= tZ ? 1 : 2);
+        const double tmin = ax == 0 ? tX : (ax == 1 ? tY : tZ);
+        const double te = fmax(fmin(tmin, t_out), t);
+        // exit point's voxel along every axis, clamped into the old leaf, never backwards
+        const int cx = (int)floorf(fminf(fmaxf(float((ox + te * ex) * ipix + hn), -1.f), float(n)));
+        const int cy = (int)floorf(fminf(fmaxf(float((oy + te * ey) * ipix + hn), -1.f), float(n)));
+        const int cz = (int)floorf(fminf(fmaxf(float((oz + te * ez) * ipix + hz), -1.f), float(nz)));
+        int nx = px ? imin3(imax3(cx, ix), bx0 + s - 1) : imax3(imin3(cx, ix), bx0);
+        int ny = py ? imin3(imax3(cy, iy), by0 + s - 1) : imax3(imin3(cy, iy), by0);
+        int nzi = pz ? imin3(imax3(cz, iz), bz0 + s - 1) : imax3(imin3(cz, iz), bz0);
+        if (ax == 0) nx = px ? bx0 + s : bx0 - 1;
+        else if (ax == 1) ny = py ? by0 + s : by0 - 1;
+        else nzi = pz ? bz0 + s : bz0 - 1;
+        const bool go = te < t_out && (unsigned)nx < (unsigned)n && (unsigned)ny < (unsigned)n &&
+                        (unsigned)nzi < (unsigned)nz;
+        Rec3<T> nrec = rec;
+        if (go) nrec = base[addr(nx, ny, nzi)];
+        acc += (te - t) * double(rec.mu());
+        if (!go) break;
+        t = te; ix = nx; iy = ny; iz = nzi; rec = nrec;
+      }
+    }
+    if (pout) pout[r] = T(acc);
+    if (q) {
+      const double i0 = i0v ? double(i0v[r]) : *i0s;
+      const double qd = i0 * exp(-acc);
+      q[r] = T(qd);
+      const double dv = double(d[r]);
+      term = qd - dv;
+      if (dv > 0.0) term += dv * (log(dv) - (log(i0) - acc));
+    }
+  }
+  if (part) {
+    term = breduce<false>(term);
+    if (threadIdx.x == 0) part[blockIdx.x] = term;
+  }
+}
+
+// ------------------------------------------------------------------ node-driven gather
+
+template <typename R>
+struct Sums3 {
+  R v[kSlots3];   // [0] plain sum, [1 + d] positive part of detail d, [8 + d] negative part
+};
+
+// Sums of one item over views [v0, v1). Per view the item box's eight corners are projected
+// onto the detector (FP32 with the hardware reciprocal, widened by 1e-3 element) to bound the
+// rows and columns whose rays can cross it; per such ray the chords through the box, or
+// through its eight octants, come from slab clipping in FP64, and the seven detail values
+// from a 2x2x2 Haar butterfly of the octant chords (per (ray, coefficient) sign split).
+template <typename T>
+__device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __restrict__ views,
+                                           const double4* __restrict__ A, const double4* __restrict__ B,
+                                           const T* __restrict__ y, bool split, int l, int k, int i, int j, int v0,
+                                           int v1) {
+  const int n = g.n, nz = g.nz, s = 1 << l;
+  const double pix = g.pixel, hn = 0.5 * n, hz = 0.5 * nz;
+  const double X0 = (double(j * s) - hn) * pix, X2 = (double((j + 1) * s) - hn) * pix;
+  const double Y0 = (double(i * s) - hn) * pix, Y2 = (double((i + 1) * s) - hn) * pix;
+  const double Z0 = (double(k * s) - hz) * pix, Z2 = (double((k + 1) * s) - hz) * pix;
+  const double X1 = 0.5 * (X0 + X2), Y1 = 0.5 * (Y0 + Y2), Z1 = 0.5 * (Z0 + Z2);
+  const float sod = float(g.sod), sdd = float(g.sdd);
+  const float icp = float(1.0 / g.cpitch), irp = float(1.0 / g.rpitch);
+  const float cc0 = float(0.5 * (g.nc - 1)), rc0 = float(0.5 * (g.nr - 1));
+  Sums3<double> r;
+#pragma unroll
+  for (int q = 0; q < kSlots3; ++q) r.v[q] = 0.0;
+  for (int v = v0; v < v1; ++v) {
+    const float c = float(views[v].x), sn = float(views[v].y);
+    float umin = 1e30f, umax = -1e30f, wmin = 1e30f, wmax = -1e30f;
+#pragma unroll
+    for (int corner = 0; corner < 8; ++corner) {
+      const float px = float((corner & 1) ? X2 : X0), py = float((corner & 2) ? Y2 : Y0);
+      const float pz = float((corner & 4) ? Z2 : Z0);
+      const float depth = sod - (px * c + py * sn);                  // distance from the source along the axis
+      const float f = sdd * __builtin_amdgcn_rcpf(depth);
+      const float u = (-px * sn + py * c) * f, w = pz * f;
+      umin = fminf(umin, u); umax = fmaxf(umax, u); wmin = fminf(wmin, w); wmax = fmaxf(wmax, w);
+    }
+    const float fc0 = fminf(fmaxf(umin * icp + cc0 - 1e-3f, -1.f), float(g.nc));
+    const float fc1 = fminf(fmaxf(umax * icp + cc0 + 1e-3f, -1.f), float(g.nc));
+    const float fr0 = fminf(fmaxf(wmin * irp + rc0 - 1e-3f, -1.f), float(g.nr));
+    const float fr1 = fminf(fmaxf(wmax * irp + rc0 + 1e-3f, -1.f), float(g.nr));
+    const int clo = max(int(ceilf(fc0)), 0), chi = min(int(floorf(fc1)), g.nc - 1);
+    const int rlo = max(int(ceilf(fr0)), 0), rhi = min(int(floorf(fr1)), g.nr - 1);
+    for (int row = rlo; row <= rhi; ++row) {
+      const int64_t rowbase = (int64_t(v) * g.nr + row) * g.nc;
+      for (int col = clo; col <= chi; ++col) {
+        const double4 a = A[rowbase + col];
+        const double4 bb = B[rowbase + col];
+        const double yv = double(y[rowbase + col]);
+        const double tx0 = (X0 - a.x) * a.w, tx2 = (X2 - a.x) * a.w;
+        const double ty0 = (Y0 - a.y) * bb.x, ty2 = (Y2 - a.y) * bb.x;
+        const double tz0 = (Z0 - a.z) * bb.y, tz2 = (Z2 - a.z) * bb.y;
+        if (!split) {
+          const double lo = fmax(fmax(fmin(tx0, tx2), fmin(ty0, ty2)), fmin(tz0, tz2));
+          const double hi = fmin(fmin(fmax(tx0, tx2), fmax(ty0, ty2)), fmax(tz0, tz2));
+          r.v[0] += yv * fmax(hi - lo, 0.0);
+          continue;
+        }
+        const double tx1 = (X1 - a.x) * a.w, ty1 = (Y1 - a.y) * bb.x, tz1 = (Z1 - a.z) * bb.y;
+        // per axis the parameter interval of the lower [.0] and upper [.1] half
+        const double xl[2] = {fmin(tx0, tx1), fmin(tx1, tx2)}, xh[2] = {fmax(tx0, tx1), fmax(tx1, tx2)};
+        const double yl[2] = {fmin(ty0, ty1), fmin(ty1, ty2)}, yh[2] = {fmax(ty0, ty1), fmax(ty1, ty2)};
+        const double zl[2] = {fmin(tz0, tz1), fmin(tz1, tz2)}, zh[2] = {fmax(tz0, tz1), fmax(tz1, tz2)};
+        double ch[8];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+          const int bx = o & 1, by = (o >> 1) & 1, bz = (o >> 2) & 1;
+          ch[o] = fmax(fmin(fmin(xh[bx], yh[by]), zh[bz]) - fmax(fmax(xl[bx], yl[by]), zl[bz]), 0.0);
+        }
+        // 2x2x2 butterfly: x, then y, then z (lower half +, upper half -)
+        double s1[4], d1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { s1[q] = ch[2 * q] + ch[2 * q + 1]; d1[q] = ch[2 * q] - ch[2 * q + 1]; }
+        const double ss0 = s1[0] + s1[1], sd0 = s1[0] - s1[1], ds0 = d1[0] + d1[1], dd0 = d1[0] - d1[1];
+        const double ss1 = s1[2] + s1[3], sd1 = s1[2] - s1[3], ds1 = d1[2] + d1[3], dd1 = d1[2] - d1[3];
+        const double det[7] = {ds0 + ds1, sd0 + sd1, dd0 + dd1, ss0 - ss1, ds0 - ds1, sd0 - sd1, dd0 - dd1};
+        r.v[0] += yv * (ss0 + ss1);
+#pragma unroll
+        for (int d = 0; d < 7; ++d) {
+          const double wv = yv * det[d];
+          r.v[1 + d] += fmax(wv, 0.0);
+          r.v[8 + d] += fmin(wv, 0.0);
+        }
+      }
+    }
+  }
+  return r;
+}
+
+// am_delta as in 2-D (eq. 1.9 zero; held when no finite minimizer)
+__device__ inline double am_delta3(double b, double bp, double bm, double z0, int* held) {
+  double t;
+  if (bp > 0.0) {
+    const double sq = sqrt(fmax(b * b - 4.0 * bp * bm, 0.0));
+    t = b >= 0.0 ? (b + sq) / (2.0 * bp) : (2.0 * bm) / (b - sq);
+  } else if (bm < 0.0) {
+    t = bm / b;
+  } else {
+    return 0.0;
+  }
+  if (t > 0.0 && isfinite(t)) return -log(t) / z0;
+  atomicAdd(held, 1);
+  return 0.0;
+}
+
+template <typename T>
+struct GArgs3 {
+  DevGeom3 g;
+  const double2* views;
+  const double4* A;
+  const double4* B;
+  const T* y;
+  const uint32_t* items;
+  const int* counts;
+  int kseg, start, count, chunks, vpc;
+  double* part;
+  T* beta;
+  const T* b;
+  const double* z0;
+  int* held;
+  T *bp, *bm, *out;
+};
+
+__device__ inline uint32_t item3_word(const uint32_t* __restrict__ items, int64_t it, int n) {
+  if (items) return items[it];
+  // every voxel as a level-0 box
+  const int64_t nn = int64_t(n) * n;
+  return item3_pack(0, 0, int(it / nn), int((it / n) % n), int(it % n));
+}
+
+template <typename T>
+__device__ inline void seg_range3(const GArgs3<T>& a, int& start, int& count) {
+  start = a.start;
+  count = a.count;
+  if (a.counts) {
+    start = 0;
+    for (int q = 0; q < a.kseg; ++q) start += a.counts[q];
+    count = a.counts[a.kseg];
+  }
+}
+
+template <typename T, int MODE>
+__device__ inline void item_finish3(const GArgs3<T>& a, uint32_t w, const Sums3<double>& r) {
+  const int n = a.g.n, nz = a.g.nz;
+  const bool split = (w >> 31) != 0;
+  const int l = int((w >> 27) & 15u);
+  const int k = int((w >> 18) & 0x1ffu), i = int((w >> 9) & 0x1ffu), j = int(w & 0x1ffu);
+  const double sc = scale3(l);
+  const int64_t root = (int64_t(k) * n + i) * n + j;
+  if (MODE == kPlain) {
+    a.out[root] = T(r.v[0] * sc);
+    return;
+  }
+  const bool is_root = l == a.g.L;
+  if (MODE == kSplit) {
+    if (is_root) { a.bp[root] = T(r.v[0] * sc); a.bm[root] = T(0); }
+    if (split)
+      for (int d = 0; d < 7; ++d) {
+        const int64_t z = detail_pos(n, nz, l, d, k, i, j);
+        a.bp[z] = T(r.v[1 + d] * sc);
+        a.bm[z] = T(r.v[8 + d] * sc);
+      }
+    return;
+  }
+  const double z0 = *a.z0;
+  if (is_root) a.beta[root] = T(double(a.beta[root]) + am_delta3(double(a.b[root]), r.v[0] * sc, 0.0, z0, a.held));
+  if (split)
+    for (int d = 0; d < 7; ++d) {
+      const int64_t z = detail_pos(n, nz, l, d, k, i, j);
+      a.beta[z] = T(double(a.beta[z]) + am_delta3(double(a.b[z]), r.v[1 + d] * sc, r.v[8 + d] * sc, z0, a.held));
+    }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kB) void k3_gather(GArgs3<T> a) {
+  int start, count;
+  seg_range3(a, start, count);
+  const int it = blockIdx.x * kB + threadIdx.x;
+  if (it >= count) return;
+  const uint32_t w = item3_word(a.items, start + it, a.g.n);
+  const Sums3<double> r = item_sums3<T>(a.g, a.views, a.A, a.B, a.y, (w >> 31) != 0, int((w >> 27) & 15u),
+                                        int((w >> 18) & 0x1ffu), int((w >> 9) & 0x1ffu), int(w & 0x1ffu), 0, a.g.nv);
+  item_finish3<T, MODE>(a, w, r);
+}
+
+// (item, view chunk) tasks: a block of 4 waves takes 64 items; wave w handles view chunk
+// 4 group + w; the four chunk sums are added in LDS in wave order and stored per group.
+template <typename T>
+__global__ __launch_bounds__(256) void k3_gather_part(GArgs3<T> a) {
+  __shared__ double sh[4][kSlots3][64];
+  int start, count;
+  seg_range3(a, start, count);
+  const int n_ig = (a.count + 63) / 64;
+  const int ig = blockIdx.x % n_ig, group = blockIdx.x / n_ig;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int idx = ig * 64 + lane, chunk = group * 4 + wv;
+  Sums3<double> r;
+#pragma unroll
+  for (int q = 0; q < kSlots3; ++q) r.v[q] = 0.0;
+  if (idx < count && chunk < a.chunks) {
+    const uint32_t w = item3_word(a.items, start + idx, a.g.n);
+    const int v0 = chunk * a.vpc, v1 = min(a.g.nv, v0 + a.vpc);
+    r = item_sums3<T>(a.g, a.views, a.A, a.B, a.y, (w >> 31) != 0, int((w >> 27) & 15u), int((w >> 18) & 0x1ffu),
+                      int((w >> 9) & 0x1ffu), int(w & 0x1ffu), v0, v1);
+  }
+#pragma unroll
+  for (int q = 0; q < kSlots3; ++q) sh[wv][q][lane] = r.v[q];
+  __syncthreads();
+  for (int t = threadIdx.x; t < kSlots3 * 64; t += 256) {
+    const int slot = t / 64, l2 = t % 64;
+    const int it = ig * 64 + l2;
+    if (it >= count) continue;
+    a.part[(size_t(group) * kSlots3 + slot) * a.count + it] = sh[0][slot][l2] + sh[1][slot][l2] + sh[2][slot][l2] +
+                                                               sh[3][slot][l2];
+  }
+}
+
+// adds the chunk groups of each item in group order, then the item's final step
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void k3_gather_finish(GArgs3<T> a) {
+  __shared__ double sh[kSlots3][64];
+  int start, count;
+  seg_range3(a, start, count);
+  const int lane = threadIdx.x & 63, slot = threadIdx.x >> 6;
+  const int idx = blockIdx.x * 64 + lane;
+  const int groups = (a.chunks + 3) / 4;
+  if (slot < kSlots3) {
+    double s = 0.0;
+    if (idx < count)
+      for (int c = 0; c < groups; ++c) s += a.part[(size_t(c) * kSlots3 + slot) * a.count + idx];
+    sh[slot][lane] = s;
+  }
+  __syncthreads();
+  if (slot != 0 || idx >= count) return;
+  const uint32_t w = item3_word(a.items, start + idx, a.g.n);
+  Sums3<double> r;
+#pragma unroll
+  for (int q = 0; q < kSlots3; ++q) r.v[q] = sh[q][lane];
+  item_finish3<T, MODE>(a, w, r);
+}
+
+// ------------------------------------------------------------------ Z0 and W (eq. 1.61)
+
+// Per ray in FP64: walk the octree leaves; every leaf chord adds sign_d(octant) * chord to
+// the seven detail accumulators of each split ancestor, and chord to its root's
+// approximation accumulator; when the ray leaves a node, 2^(-3m/2) |acc| of its details go
+// into the ray's sum and the non-zero ones are counted. Z0 = max over rays, W = total count.
+template <int LT>
+struct Z0Vis3 {
+  double tol, sum, cnt, accLL;
+  double acc[LT + 1][7];
+  int64_t cur[LT + 1];
+  int64_t curLL;
+  __device__ void flush(int m) {
+    const double sc = scale3(m);
+#pragma unroll
+    for (int d = 0; d < 7; ++d) {
+      const double a = fabs(acc[m][d]) * sc;
+      sum += a;
+      cnt += a > tol ? 1.0 : 0.0;
+      acc[m][d] = 0.0;
+    }
+  }
+  __device__ void flushLL() {
+    const double a = fabs(accLL) * scale3(LT);
+    sum += a;
+    cnt += a > tol ? 1.0 : 0.0;
+    accLL = 0.0;
+  }
+  __device__ void visit(int ix, int iy, int iz, int l, double chord) {
+#pragma unroll
+    for (int m = 1; m <= LT; ++m) {
+      const int64_t node = (int64_t(iz >> m) << 40) | (int64_t(iy >> m) << 20) | int64_t(ix >> m);
+      if (node != cur[m]) {
+        if (cur[m] >= 0) flush(m);
+        cur[m] = node;
+      }
+      if (m > l) {
+        const int oct = (((iz >> (m - 1)) & 1) << 2) | (((iy >> (m - 1)) & 1) << 1) | ((ix >> (m - 1)) & 1);
+#pragma unroll
+        for (int d = 0; d < 7; ++d) acc[m][d] += (__popc(uint32_t((d + 1) & oct)) & 1) ? -chord : chord;
+      }
+    }
+    const int64_t root = (int64_t(iz >> LT) << 40) | (int64_t(iy >> LT) << 20) | int64_t(ix >> LT);
+    if (root != curLL) {
+      if (curLL >= 0) flushLL();
+      curLL = root;
+    }
+    accLL += chord;
+  }
+};
+
+template <int LT>
+__global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, const double4* __restrict__ A, const double4* __restrict__ B,
+                                            const double* __restrict__ C, const uint8_t* __restrict__ lev,
+                                            double* __restrict__ part_max, double* __restrict__ part_cnt) {
+  const int64_t r = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int64_t M = int64_t(g.nv) * g.nr * g.nc;
+  double sum = 0.0, cnt = 0.0;
+  if (r < M) {
+    const double4 a = A[r], b = B[r];
+    const double ox = a.x, oy = a.y, oz = a.z, iex = a.w, iey = b.x, iez = b.y, ex = b.z, ey = b.w, ez = C[r];
+    const int n = g.n, nz = g.nz;
+    const double pix = g.pixel, ipix = 1.0 / g.pixel, hn = 0.5 * n, hz = 0.5 * nz;
+    const double tx0 = (-hn * pix - ox) * iex, tx1 = (hn * pix - ox) * iex;
+    const double ty0 = (-hn * pix - oy) * iey, ty1 = (hn * pix - oy) * iey;
+    const double tz0 = (-hz * pix - oz) * iez, tz1 = (hz * pix - oz) * iez;
+    const double t_in = fmax(fmax(fmin(tx0, tx1), fmin(ty0, ty1)), fmin(tz0, tz1));
+    const double t_out = fmin(fmin(fmax(tx0, tx1), fmax(ty0, ty1)), fmax(tz0, tz1));
+    Z0Vis3<LT> z;
+    z.tol = 1e-9 * g.pixel; z.sum = 0.0; z.cnt = 0.0; z.accLL = 0.0; z.curLL = -1;
+#pragma unroll
+    for (int m = 0; m <= LT; ++m) {
+      z.cur[m] = -1;
+#pragma unroll
+      for (int d = 0; d < 7; ++d) z.acc[m][d] = 0.0;
+    }
+    if (t_out > t_in) {
+      int ix = (int)floor(fmin(fmax((ox + t_in * ex) * ipix + hn, -1.0), double(n)));
+      int iy = (int)floor(fmin(fmax((oy + t_in * ey) * ipix + hn, -1.0), double(n)));
+      int iz = (int)floor(fmin(fmax((oz + t_in * ez) * ipix + hz, -1.0), double(nz)));
+      ix = imin3(imax3(ix, 0), n - 1);
+      iy = imin3(imax3(iy, 0), n - 1);
+      iz = imin3(imax3(iz, 0), nz - 1);
+      const bool px = ex > 0, py = ey > 0, pz = ez > 0;
+      double t = t_in;
+      for (int step = 0; step < 4 * (2 * n + nz) + 8; ++step) {
+        const int l = LT > 0 ? int(lev[(int64_t(iz) * n + iy) * n + ix]) : 0;
+        const int s = 1 << l;
+        const int bx0 = ix & -s, by0 = iy & -s, bz0 = iz & -s;
+        const double tX = ((double(px ? bx0 + s : bx0) - hn) * pix - ox) * iex;
+        const double tY = ((double(py ? by0 + s : by0) - hn) * pix - oy) * iey;
+        const double tZ = ((double(pz ? bz0 + s : bz0) - hz) * pix - oz) * iez;
+        const int ax = (tX <= tY && tX <= tZ) ? 0 : (tY <= tZ ? 1 : 2);
+        const double te = fmax(fmin(ax == 0 ? tX : (ax == 1 ? tY : tZ), t_out), t);
+        z.visit(ix, iy, iz, l, te - t);
+        if (te >= t_out) break;
+        const int cx = (int)floor(fmin(fmax((ox + te * ex) * ipix + hn, -1.0), double(n)));
+        const int cy = (int)floor(fmin(fmax((oy + te * ey) * ipix + hn, -1.0), double(n)));
+        const int cz = (int)floor(fmin(fmax((oz + te * ez) * ipix + hz, -1.0), double(nz)));
+        int nx = px ? imin3(imax3(cx, ix), bx0 + s - 1) : imax3(imin3(cx, ix), bx0);
+        int ny = py ? imin3(imax3(cy, iy), by0 + s - 1) : imax3(imin3(cy, iy), by0);
+        int nzi = pz ? imin3(imax3(cz, iz), bz0 + s - 1) : imax3(imin3(cz, iz), bz0);
+        if (ax == 0) nx = px ? bx0 + s : bx0 - 1;
+        else if (ax == 1) ny = py ? by0 + s : by0 - 1;
+        else nzi = pz ? bz0 + s : bz0 - 1;
+        if ((unsigned)nx >= (unsigned)n || (unsigned)ny >= (unsigned)n || (unsigned)nzi >= (unsigned)nz) break;
+        ix = nx; iy = ny; iz = nzi; t = te;
+      }
+#pragma unroll
+      for (int m = 1; m <= LT; ++m)
+        if (z.cur[m] >= 0) z.flush(m);
+      if (z.curLL >= 0) z.flushLL();
+    }
+    sum = z.sum; cnt = z.cnt;
+  }
+  const double mx = breduce<true>(sum);
+  __syncthreads();
+  const double ct = breduce<false>(cnt);
+  if (threadIdx.x == 0) { part_max[blockIdx.x] = mx; part_cnt[blockIdx.x] = ct; }
+}
+
+// ------------------------------------------------------------------ tree rule and work lists
+
+__global__ __launch_bounds__(kB) void k3_expand(DevGeom3 g, const uint8_t* __restrict__ old,
+                                                uint8_t* __restrict__ mask, const double* __restrict__ mu64,
+                                                const double* __restrict__ maxv, double frac,
+                                                int* __restrict__ n_split) {
+  int64_t k = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int n = g.n, nz = g.nz;
+  int l = 1;
+  for (; l <= g.L; ++l) {
+    const int64_t cntl = int64_t(nz >> l) * (n >> l) * (n >> l);
+    if (k < cntl) break;
+    k -= cntl;
+  }
+  if (l > g.L) return;
+  const double top = *maxv;
+  if (!(top > 0.0)) return;
+  const int m = n >> l;
+  const int kz = int(k / (int64_t(m) * m)), i = int((k / m) % m), j = int(k % m);
+  if (split3(old, n, l, kz, i, j)) return;
+  if (l < g.L && !split3(old, n, l + 1, kz >> 1, i >> 1, j >> 1)) return;
+  const int s = 1 << l;
+  const double val = mu64[(int64_t(kz * s) * n + i * s) * n + j * s];   // leaf-constant
+  if (val > frac * top) {
+    for (int d = 0; d < 7; ++d) mask[detail_pos(n, nz, l, d, kz, i, j)] = 1;
+    atomicAdd(n_split, 1);
+  }
+}
+
+// Single work-group compaction of the work list (as in 2-D): levels from L down to 1 (L = 0:
+// voxels), 3-D Morton order within a level, wave ballots + LDS prefix, order deterministic.
+__global__ __launch_bounds__(1024) void k3_items(DevGeom3 g, const uint8_t* __restrict__ mask,
+                                                 uint32_t* __restrict__ items, int* __restrict__ counts) {
+  __shared__ int wave_tot[16];
+  __shared__ int base_sh;
+  const int n = g.n, nz = g.nz, L = g.L;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) base_sh = 0;
+  __syncthreads();
+  const int lmin = L == 0 ? 0 : 1;
+  for (int l = L; l >= lmin; --l) {
+    const int level_start = base_sh;
+    const int m = n >> l, mz = nz >> l;
+    int pw = 1;
+    while (pw < m || pw < mz) pw <<= 1;
+    const int64_t total = int64_t(pw) * pw * pw;
+    for (int64_t base = 0; base < total; base += 1024) {
+      const int64_t code = base + threadIdx.x;
+      bool inc = false;
+      uint32_t word = 0;
+      if (code < total) {
+        const int j = int(morton3_compact(uint32_t(code)));
+        const int i = int(morton3_compact(uint32_t(code >> 1)));
+        const int k = int(morton3_compact(uint32_t(code >> 2)));
+        if (i < m && j < m && k < mz) {
+          if (l == L) {
+            inc = true;
+            word = item3_pack((L > 0 && split3(mask, n, L, k, i, j)) ? 1 : 0, l, k, i, j);
+          } else if (split3(mask, n, l, k, i, j)) {
+            inc = true;
+            word = item3_pack(1, l, k, i, j);
+          }
+        }
+      }
+      const uint64_t bal = __ballot(inc);
+      const int before = __popcll(bal & ((uint64_t(1) << lane) - 1));
+      if (lane == 0) wave_tot[wv] = __popcll(bal);
+      __syncthreads();
+      int off = base_sh;
+      for (int w2 = 0; w2 < wv; ++w2) off += wave_tot[w2];
+      if (inc) items[off + before] = word;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w2 = 0; w2 < 16; ++w2) t += wave_tot[w2];
+        base_sh += t;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[1 + (L - l)] = base_sh - level_start;
+  }
+  if (threadIdx.x == 0) counts[0] = base_sh;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+template <typename T>
+void Geo3<T>::ray_table(const DevGeom3& g, const double2* views, void* A, void* B, double* C, hipStream_t s) {
+  const int64_t M = int64_t(g.nv) * g.nr * g.nc;
+  hipLaunchKernelGGL(k3_ray_table, dim3(blocks3(M)), dim3(kB), 0, s, g, views, (double4*)A, (double4*)B, C);
+}
+template <typename T>
+int Geo3<T>::forward(const DevGeom3& g, const void* A, const void* B, const double* C, const void* recR,
+                     const void* recC, const T* d, const T* i0v, const double* i0s, T* q, T* p, double* part,
+                     hipStream_t s) {
+  const int nb = blocks3(int64_t(g.nv) * g.nr * g.nc);
+  hipLaunchKernelGGL(k3_forward<T>, dim3(nb), dim3(kB), 0, s, g, (const double4*)A, (const double4*)B, C,
+                     (const Rec3<T>*)recR, (const Rec3<T>*)recC, d, i0v, i0s, q, p, part);
+  return nb;
+}
+template <typename T>
+void Geo3<T>::gather(const DevGeom3& g, int mode, const double2* views, const void* A, const void* B, const T* y,
+                     const uint32_t* items, const int* counts, const Segment* segs, int n_segs, void* part,
+                     T* beta, const T* b, const double* z0, int* held, T* bp, T* bm, T* out, hipStream_t s) {
+  GArgs3<T> a;
+  a.g = g; a.views = views; a.A = (const double4*)A; a.B = (const double4*)B; a.y = y;
+  a.items = items; a.counts = counts; a.part = (double*)part;
+  a.beta = beta; a.b = b; a.z0 = z0; a.held = held; a.bp = bp; a.bm = bm; a.out = out;
+  for (int k = 0; k < n_segs; ++k) {
+    const Segment& sg = segs[k];
+    if (sg.count <= 0) continue;
+    a.kseg = sg.kseg; a.start = sg.start; a.count = sg.count; a.chunks = sg.chunks; a.vpc = sg.vpc;
+    if (sg.chunks <= 1) {
+      const dim3 grid(blocks3(sg.count));
+      if (mode == kPlain) hipLaunchKernelGGL((k3_gather<T, kPlain>), grid, dim3(kB), 0, s, a);
+      else if (mode == kSplit) hipLaunchKernelGGL((k3_gather<T, kSplit>), grid, dim3(kB), 0, s, a);
+      else hipLaunchKernelGGL((k3_gather<T, kUpdate>), grid, dim3(kB), 0, s, a);
+      continue;
+    }
+    const int groups = (sg.chunks + 3) / 4;
+    hipLaunchKernelGGL(k3_gather_part<T>, dim3(((sg.count + 63) / 64) * groups), dim3(256), 0, s, a);
+    const dim3 grid((sg.count + 63) / 64);
+    if (mode == kPlain) hipLaunchKernelGGL((k3_gather_finish<T, kPlain>), grid, dim3(1024), 0, s, a);
+    else if (mode == kSplit) hipLaunchKernelGGL((k3_gather_finish<T, kSplit>), grid, dim3(1024), 0, s, a);
+    else hipLaunchKernelGGL((k3_gather_finish<T, kUpdate>), grid, dim3(1024), 0, s, a);
+  }
+}
+template <typename T>
+void Geo3<T>::synth_records(const DevGeom3& g, const T* beta, const uint8_t* lev, void* recR, void* recC,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k3_synth_records<T>, dim3(blocks3(int64_t(g.n) * g.n * g.nz)), dim3(kB), 0, s, g, beta, lev,
+                     (Rec3<T>*)recR, (Rec3<T>*)recC);
+}
+template <typename T>
+void Geo3<T>::synth(const DevGeom3& g, const T* beta, T* mu, hipStream_t s) {
+  hipLaunchKernelGGL(k3_synth<T>, dim3(blocks3(int64_t(g.n) * g.n * g.nz)), dim3(kB), 0, s, g, beta, mu);
+}
+template <typename T>
+int Geo3<T>::mu64(const DevGeom3& g, const T* beta, double* mu64, double* part, hipStream_t s) {
+  const int nb = blocks3(int64_t(g.n) * g.n * g.nz);
+  hipLaunchKernelGGL(k3_mu64<T>, dim3(nb), dim3(kB), 0, s, g, beta, mu64, part);
+  return nb;
+}
+template <typename T>
+void Geo3<T>::analysis(const DevGeom3& g, const T* vol, T* coef, hipStream_t s) {
+  hipLaunchKernelGGL(k3_analysis<T>, dim3(blocks3(int64_t(g.n) * g.n * g.nz)), dim3(kB), 0, s, g, vol, coef);
+}
+template <typename T>
+void Geo3<T>::apply_mask(const DevGeom3& g, T* beta, const uint8_t* mask, hipStream_t s) {
+  const int64_t len = int64_t(g.n) * g.n * g.nz;
+  hipLaunchKernelGGL(k3_apply_mask<T>, dim3(blocks3(len)), dim3(kB), 0, s, len, beta, mask);
+}
+template struct Geo3<float>;
+template struct Geo3<double>;
+
+int z0_partials3(const DevGeom3& g, const void* A, const void* B, const double* C, const uint8_t* lev,
+                 double* part_max, double* part_cnt, hipStream_t s) {
+  const int nb = blocks3(int64_t(g.nv) * g.nr * g.nc);
+  auto a = (const double4*)A;
+  auto b = (const double4*)B;
+  switch (g.L) {
+#define Z3_CASE(K) \
+    case K: hipLaunchKernelGGL(k3_z0<K>, dim3(nb), dim3(kB), 0, s, g, a, b, C, lev, part_max, part_cnt); break;
+    Z3_CASE(0) Z3_CASE(1) Z3_CASE(2) Z3_CASE(3) Z3_CASE(4)
+#undef Z3_CASE
+  }
+  return nb;
+}
+void levmap3(const DevGeom3& g, const uint8_t* mask, uint8_t* lev, hipStream_t s) {
+  hipLaunchKernelGGL(k3_levmap, dim3(blocks3(int64_t(g.n) * g.n * g.nz)), dim3(kB), 0, s, g, mask, lev);
+}
+void build_items3(const DevGeom3& g, const uint8_t* mask, uint32_t* items, int* counts, hipStream_t s) {
+  hipLaunchKernelGGL(k3_items, dim3(1), dim3(1024), 0, s, g, mask, items, counts);
+}
+void expand3(const DevGeom3& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64, const double* maxv,
+             double frac, int* n_split, hipStream_t s) {
+  int64_t nodes = 0;
+  for (int l = 1; l <= g.L; ++l) nodes += int64_t(g.nz >> l) * (g.n >> l) * (g.n >> l);
+  if (nodes == 0) return;
+  hipLaunchKernelGGL(k3_expand, dim3(blocks3(nodes)), dim3(kB), 0, s, g, mask_old, mask, mu64, maxv, frac, n_split);
+}
+void check_mask3(const DevGeom3& g, const uint8_t* mask, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k3_check_mask, dim3(blocks3(int64_t(g.n) * g.n * g.nz)), dim3(kB), 0, s, g, mask, bad);
+}
+void approx_mask3(const DevGeom3& g, uint8_t* mask, hipStream_t s) {
+  hipLaunchKernelGGL(k3_approx_mask, dim3(blocks3(int64_t(g.n) * g.n * g.nz)), dim3(kB), 0, s, g, mask);
+}
+
+}  // namespace wamct

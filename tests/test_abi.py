@@ -81,3 +81,31 @@ def test_create_rejects_invalid_geometry_before_touching_the_gpu(lib):
     assert b"circumradius" in lib.lib.wamct_last_error(None)
     assert lib.lib.wamct_create(ctypes.byref(g), ctypes.byref(opt), None, None) == lib.E_INVALID
     assert lib.lib.wamct_iterate(None, 1, None) == lib.E_INVALID
+
+
+@pytest.mark.parametrize("change,levels,dtype,batch,needle", [
+    (dict(n=1024), 2, "f32", 1, "outside [2, 512]"),
+    (dict(nz=0), 2, "f32", 1, "nz"),
+    (dict(nz=12), 3, "f32", 1, "divisible"),
+    (dict(n_rows=0), 2, "f32", 1, "n_rows"),
+    (dict(row_pitch=0.0), 2, "f32", 1, "pitch"),
+    (dict(sod=20.0), 2, "f32", 1, "circumradius"),
+    (dict(sdd=50.0), 2, "f32", 1, "sdd"),
+    ({}, 5, "f32", 1, "levels"),
+    ({}, 2, "f32/f32", 1, "FP64 only"),
+    ({}, 2, "f32", 2, "one scan"),
+])
+def test_cone_validation_rejects(lib, change, levels, dtype, batch, needle):
+    import dataclasses
+    from paper_1508_04458_amd import api
+    g = dataclasses.replace(synth.CONE_CONFIGS["cone32"]["geom"](), **change)
+    dtype, _, geometry = dtype.partition("/")
+    msg = api.validate(g, levels, dtype, geometry or "f64", batch)
+    assert msg is not None and needle in msg, msg
+
+
+def test_cone_validation_accepts_configs(lib):
+    from paper_1508_04458_amd import api
+    for name, cfg in synth.CONE_CONFIGS.items():
+        assert api.validate(cfg["geom"](), cfg["levels"], "f32") is None, name
+        assert api.validate(cfg["geom"](), 0, "f64") is None, name
