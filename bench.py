@@ -15,7 +15,8 @@ Extra fields:
   cpu_baseline      the FP64 CPU oracle on a bounded sample of the same workload
 
 Other workloads: --config uneven (256 independent problems of uneven size solved as one
-batch, graph-replayed) and --config loss16 (differentiable loss + adjoint, 16 slices).
+batch, graph-replayed), --config loss16 (differentiable loss + adjoint, 16 slices) and
+--config cone512 (3-D cone beam, 512x512x256 volume, 3-D Haar octree, 50 iterations).
 """
 import argparse
 import hashlib
@@ -51,6 +52,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="uneven: launch directly instead of graph replay")
     ap.add_argument("--autotune", action="store_true", help="uneven: tune the backprojection tiling first")
     ap.add_argument("--no-sequential", action="store_true", help="uneven: skip the one-context-at-a-time run")
+    ap.add_argument("--cone-iters", type=int, default=0, help="cone: iterations per solve (0 = the config's)")
     return ap.parse_args()
 
 
@@ -289,17 +291,169 @@ def bench_loss(args):
     print(json.dumps(out), flush=True)
 
 
+def cone_cpu_baseline(name, n_full_rays, n_full_side):
+    """The FP64 3-D oracle (never tuned) on the downscaled cone-beam case in full (its
+    synthesis matrix at full size would not fit a CPU run): Algorithm 1 with the octree rule
+    and its schedule; solve time (trees, Phi builds, iterations; not H or b) scaled to the
+    full workload by the ratio of rays x volume side (the number of ray-voxel crossings)."""
+    from oracle import vol3d
+    from paper_1508_04458_amd import synth
+    P = synth.make_cone_problem(name)
+    g = P.geom
+    H = vol3d.system_matrix3(g)
+    t0 = time.perf_counter()
+    vol3d.wam_solve3(H, g.n, g.nz, P.levels, P.d, P.i0, P.n_iters, g.pixel, schedule=P.schedule)
+    dt = time.perf_counter() - t0
+    scale = (n_full_rays * n_full_side) / (g.n_rays * g.n)
+    per_iter = dt * scale / P.n_iters
+    return {"value": 1.0 / per_iter, "unit": "AM iter/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 NumPy/SciPy 3-D oracle, octree AM, {P.n_iters} iterations (expansions "
+                       f"{P.schedule}) on the downscaled case {name} ({g.n}^2 x {g.nz}, {g.n_views} views of "
+                       f"{g.n_rows} x {g.n_cols}); solve time {dt:.1f} s scaled by rays x side = {scale:.0f}; "
+                       f"setup (H, b) excluded; single thread")}
+
+
+def bench_cone(args):
+    """3-D circular cone beam: 512x512x256 volume (1 mm voxels), 720 views of a 256x1024
+    flat detector, 200 random ellipsoids + 10 metal cylinders, I0 = 1e5, 3-level 3-D Haar
+    octree AM in FP32, 50 iterations with expansions at 11, 21 and 43. A step is one
+    complete reconstruction from beta = 0."""
+    if not args.no_cpu_baseline:
+        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            os.environ[k] = "1"
+    import numpy as np
+    import torch
+    from paper_1508_04458_amd import api, synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t_gen = time.perf_counter()
+    log(f"{args.config}: drawing the phantom (line integrals on the GPU) and the counts")
+    P = synth.make_cone_problem(args.config, device=dev)
+    g = P.geom
+    log(f"phantom and counts ready in {time.perf_counter() - t_gen:.1f} s; {g.n_rays} rays")
+    J = args.cone_iters or P.n_iters
+    sched = [int(s) for s in synth.scaled_schedule(J, P.levels)]
+    d = torch.as_tensor(P.d, dtype=torch.float32, device=dev)
+    P = dataclasses_replace(P, d=None, line_integrals=None)
+    ctx = api.Context(g, P.levels, "f32", device=dev)
+    t1 = time.perf_counter()
+    ctx.set_data(d, P.i0)
+    torch.cuda.synchronize()
+    log(f"context and b = Omega^T H^T d ready in {time.perf_counter() - t1:.1f} s")
+    idiv = torch.empty(J + 1, dtype=torch.float64, device=dev)
+
+    # ---- warmup 1 doubles as the per-tree statistics run (W_j, |Z_s|, Z0)
+    ctx.reset()
+    marks = [0] + sched + [J]
+    seg = []
+    for k, (a, b) in enumerate(zip(marks[:-1], marks[1:])):
+        if k > 0:
+            ctx.expand(0.1)
+        st = ctx.tree_stats()
+        seg.append(dict(start=a, iters=b - a, w=st["w"], n_active=st["n_active"], z0=st["z0"]))
+        ctx.iterate(b - a)
+        torch.cuda.synchronize()
+        log(f"tree {k}: {st['n_active']} active, W = {st['w']:.3e}, iterations {a}..{b}")
+    pairs = sum(2 * s["w"] * s["iters"] for s in seg)
+    w_avg = sum(s["w"] * s["iters"] for s in seg) / J
+    active_avg = sum(s["n_active"] * s["iters"] for s in seg) / J
+
+    def step():
+        ctx.reset()
+        ctx.solve(J, sched, 0.1, idiv)
+
+    for _ in range(max(0, args.warmup - 1)):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        log(f"step {k + 1}/{args.steps} done")
+    dt = time.perf_counter() - t0
+    tim = ctx.get_timing()
+    ctx.timing(False)
+    tr = idiv.cpu().numpy()
+    it_s = J * args.steps / dt
+    M, N = g.n_rays, g.n_voxels
+
+    def roof(ms, alg, **kw):
+        a = alg / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None, **kw}
+
+    # algorithmic bytes of the same passes with Phi stored: 8 B per (ray, active coefficient)
+    # pair, 4 B per active coefficient read (forward) or 12 B (b, beta read, beta written),
+    # 8 B per ray (d read and q-hat written; q-hat read by the update: 4 B)
+    fw, up = tim["forward"], tim["update"]
+    fw_ms = fw["ms"] / max(1, fw["launches"])
+    up_ms = up["ms"] / max(1, J * args.steps)
+    alg_fw = 8.0 * w_avg + 4.0 * active_avg + 8.0 * M
+    alg_up = 8.0 * w_avg + 4.0 * M + 12.0 * active_avg
+    r_fw = roof(fw_ms, alg_fw, kernel="k3_forward<float>", avg_launch_ms=round(fw_ms, 4),
+                launches=fw["launches"], alg_bytes_per_launch=int(alg_fw))
+    r_up = roof(up_ms, alg_up, kernels="k3_gather_part + k3_gather_finish per octree level",
+                avg_pass_ms=round(up_ms, 4), passes=J * args.steps, alg_bytes_per_pass=int(alg_up))
+    dominant = "update" if up["ms"] >= fw["ms"] else "forward"
+    out = {"metric": METRIC, "value": round(it_s, 3), "unit": "AM iter/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 1),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 data, f64 ray geometry", "data": "synthetic",
+           "config": {"workload": f"{args.config}: 3-D cone beam {g.n}x{g.n}x{g.nz}, {g.n_views} views x "
+                                  f"{g.n_rows}x{g.n_cols} detector, {P.levels}-level 3-D Haar octree AM, {J} "
+                                  f"iterations, expansions at {sched}",
+                      "levels": P.levels, "iterations": J, "schedule": sched, "rays": M, "voxels": N},
+           "gray_voxel_per_s": round(pairs * args.steps / dt / 1e9, 3),
+           "final_idiv": float(tr[-1]), "idiv_decreasing": bool(np.all(np.diff(tr) <= 1e-6 * np.abs(tr[:-1]))),
+           "trees": seg,
+           "time_ms_per_step_by_kernel": {k: round(v["ms"] / args.steps, 2) for k, v in tim.items()},
+           "roofline": r_up if dominant == "update" else r_fw,
+           "roofline_other": r_fw if dominant == "update" else r_up}
+    if not args.no_full_am:
+        full = api.Context(g, 0, "f32", device=dev)
+        full.set_data(d, P.i0)
+        full.reset()
+        full.iterate(1)
+        torch.cuda.synchronize()
+        K = 2
+        t2 = time.perf_counter()
+        full.iterate(K)
+        torch.cuda.synchronize()
+        f_it_s = K / (time.perf_counter() - t2)
+        w_pix = full.tree_stats()["w"]
+        out["full_am"] = {"iter_per_s": round(f_it_s, 3), "iterations_timed": K, "w_per_pass": int(w_pix),
+                          "gray_voxel_per_s": round(2 * w_pix * f_it_s / 1e9, 3)}
+        out["pixel_equiv_gray_voxel_per_s"] = round(2 * w_pix * it_s / 1e9, 3)
+        full.close()
+        log(f"voxel AM: {f_it_s:.3f} it/s")
+    if not args.no_cpu_baseline:
+        log("CPU oracle on the downscaled case")
+        out["cpu_baseline"] = cone_cpu_baseline("cone64", M, g.n)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def dataclasses_replace(obj, **kw):
+    import dataclasses
+    return dataclasses.replace(obj, **kw)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the view-sharded "
-              "multi-GPU design is described in DESIGN.md and not built.", file=sys.stderr)
+              "multi-GPU design is not built.", file=sys.stderr)
         sys.exit(2)
     if args.config == "uneven":
         bench_uneven(args)
         return
     if args.config == "loss16":
         bench_loss(args)
+        return
+    if args.config.startswith("cone"):
+        bench_cone(args)
         return
     if args.no_cpu_baseline is False:
         # the CPU baseline is a single-threaded oracle
