@@ -53,6 +53,9 @@ struct Ctx3 final : wamct_ctx {
   void *A = nullptr, *B = nullptr;
   double* C = nullptr;
   T *d = nullptr, *i0v = nullptr, *q = nullptr, *beta = nullptr, *b = nullptr, *img = nullptr;
+  T* yn = nullptr;                 // ray values scaled by |D| for the gather
+  double2* colt = nullptr;         // [nv][nc] (1/Dx, 1/Dy)
+  double *rowt = nullptr, *nrm = nullptr;  // [nr] 1/Dz, [nr][nc] |D|
   void *recR = nullptr, *recC = nullptr;
   uint8_t *mask = nullptr, *mask_old = nullptr, *lev = nullptr;
   uint32_t* items = nullptr;
@@ -165,12 +168,13 @@ struct Ctx3 final : wamct_ctx {
     part_cap = need;
     return WAMCT_OK;
   }
+  // work-list segments: 0 split roots, 1 roots not split, 2 + m split nodes of level L - 1 - m
   void build_segs() {
     segs.clear();
-    const int n_levels = g.L == 0 ? 1 : g.L;
-    for (int k = 0; k < n_levels; ++k) {
+    const int n_seg = g.L >= 1 ? g.L + 1 : 2;
+    for (int k = 0; k < n_seg; ++k) {
       const int c = h_ints[9 + k];
-      if (c > 0) segs.push_back(make_segment(k, 0, c, g.L - k));
+      if (c > 0) segs.push_back(make_segment(k, 0, c, k <= 1 ? g.L : g.L - (k - 1)));
     }
     vox_segs = {make_segment(-1, 0, int(N), 0)};
   }
@@ -180,7 +184,8 @@ struct Ctx3 final : wamct_ctx {
       if (x.chunks > 1 && int64_t(kSlots3) * ((x.chunks + 3) / 4) * x.count > part_cap)
         return fail(WAMCT_E_HIP, "internal: gather partial buffer too small for its tiling");
     const bool tree = &sg == &segs;
-    Geo3<T>::gather(g, mode, views, A, B, y, tree ? items : nullptr, tree ? ints + 9 : nullptr, sg.data(),
+    Geo3<T>::scale_rays(g, y, nrm, yn, s);
+    Geo3<T>::gather(g, mode, views, colt, rowt, yn, tree ? items : nullptr, tree ? ints + 9 : nullptr, sg.data(),
                     int(sg.size()), part, bt, b, scal + 0, held, bp, bm, out, s);
     return WAMCT_OK;
   }
@@ -204,7 +209,8 @@ struct Ctx3 final : wamct_ctx {
     double4 *a4 = nullptr, *b4 = nullptr;
     CHECKED(alloc(a4, M)); CHECKED(alloc(b4, M)); CHECKED(alloc(C, M));
     A = a4; B = b4;
-    CHECKED(alloc(d, M)); CHECKED(alloc(i0v, M)); CHECKED(alloc(q, M));
+    CHECKED(alloc(d, M)); CHECKED(alloc(i0v, M)); CHECKED(alloc(q, M)); CHECKED(alloc(yn, M));
+    CHECKED(alloc(colt, int64_t(g.nv) * g.nc)); CHECKED(alloc(rowt, g.nr)); CHECKED(alloc(nrm, int64_t(g.nr) * g.nc));
     CHECKED(alloc(beta, N)); CHECKED(alloc(b, N)); CHECKED(alloc(img, N)); CHECKED(alloc(mu64, N));
     T *rr = nullptr, *rc = nullptr;
     CHECKED(alloc(rr, N)); CHECKED(alloc(rc, N));
@@ -220,6 +226,7 @@ struct Ctx3 final : wamct_ctx {
     }
     HIPCHK(hipMemcpyAsync(views, hv.data(), sizeof(double2) * g.nv, hipMemcpyHostToDevice, st));
     Geo3<T>::ray_table(g, views, A, B, C, st);
+    Geo3<T>::ray_factors(g, views, colt, rowt, nrm, st);
     fill_i32(ints, kInts, 0, st);
     Launch<double>::fill(scal, kScal, 0.0, st);
     Launch<T>::fill(q, M, T(0), st);

@@ -25,7 +25,7 @@ __host__ __device__ inline uint32_t item3_pack(int split, int l, int k, int i, i
   return (uint32_t(split) << 31) | (uint32_t(l) << 27) | (uint32_t(k) << 18) | (uint32_t(i) << 9) | uint32_t(j);
 }
 
-// Sums of one 3-D item: the plain sum and, per detail, the positive and negative parts.
+// Sums of one 3-D item: the plain sum and, per detail, the signed sum and the sum of magnitudes.
 constexpr int kSlots3 = 15;
 
 template <typename T>
@@ -40,11 +40,18 @@ struct Geo3 {
   static int forward(const DevGeom3& g, const void* A, const void* B, const double* C, const void* recR,
                      const void* recC, const T* d, const T* i0v, const double* i0s, T* q, T* p, double* part,
                      hipStream_t s);
-  // Node-driven backprojection of y over item segments (items null: every voxel as a
-  // level-0 box); part holds 15 partial sums per (chunk group, item).
-  static void gather(const DevGeom3& g, int mode, const double2* views, const void* A, const void* B, const T* y,
-                     const uint32_t* items, const int* counts, const Segment* segs, int n_segs, void* part,
-                     T* beta, const T* b, const double* z0, int* held, T* bp, T* bm, T* out, hipStream_t s);
+  // Per-view ray factors of the gather: colt [nv][nc] = (1/Dx, 1/Dy), rowt [nr] = 1/Dz,
+  // nrm [nr][nc] = |D| for D = detector element - source.
+  static void ray_factors(const DevGeom3& g, const double2* views, double2* colt, double* rowt, double* nrm,
+                          hipStream_t s);
+  // out = y |D| per ray (the ray values the gather takes)
+  static void scale_rays(const DevGeom3& g, const T* y, const double* nrm, T* out, hipStream_t s);
+  // Node-driven backprojection of the scaled ray values y over item segments (items null:
+  // every voxel as a level-0 box); part holds 15 partial sums per (chunk group, item).
+  static void gather(const DevGeom3& g, int mode, const double2* views, const double2* colt, const double* rowt,
+                     const T* y, const uint32_t* items, const int* counts, const Segment* segs, int n_segs,
+                     void* part, T* beta, const T* b, const double* z0, int* held, T* bp, T* bm, T* out,
+                     hipStream_t s);
   // leaf records of mu = Omega beta (both layouts); with L = 0 in g and lev null, records of
   // the volume `beta` itself at level 0
   static void synth_records(const DevGeom3& g, const T* beta, const uint8_t* lev, void* recR, void* recC,
@@ -60,8 +67,9 @@ struct Geo3 {
 int z0_partials3(const DevGeom3& g, const void* A, const void* B, const double* C, const uint8_t* lev,
                  double* part_max, double* part_cnt, hipStream_t s);
 void levmap3(const DevGeom3& g, const uint8_t* mask, uint8_t* lev, hipStream_t s);
-// Work list: roots, then split nodes level by level, 3-D Morton order within a level;
-// counts[0] = items, counts[1 + k] = items of level L - k (level 0 when L = 0).
+// Work list in segments: split roots, roots not split (every voxel when L = 0), then split
+// nodes level by level (L - 1 down to 1), 3-D Morton order within a segment; counts[0] =
+// items, counts[1 + k] = items of segment k.
 void build_items3(const DevGeom3& g, const uint8_t* mask, uint32_t* items, int* counts, hipStream_t s);
 void expand3(const DevGeom3& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64, const double* maxv,
              double frac, int* n_split, hipStream_t s);

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "wamct_internal3.h"
 
 namespace wamct {
@@ -355,19 +357,59 @@ __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, const double4* __re
 
 template <typename R>
 struct Sums3 {
-  R v[kSlots3];   // [0] plain sum, [1 + d] positive part of detail d, [8 + d] negative part
+  R v[kSlots3];   // [0] plain sum, [1 + d] signed sum of detail d, [8 + d] sum of its magnitudes
 };
+
+// Rays of one view, factorised: every ray of view v leaves the source S = sod (c, s, 0)
+// along D = (-sdd c - u s, -sdd s + u c, w) (u: column offset, w: row offset on the
+// detector), so the parameter of the plane x = X is (X - Sx) / Dx with 1/Dx, 1/Dy per
+// (view, column) and 1/Dz per row. Parameter differences are lengths / |D|, and
+// |D| = sqrt(sdd^2 + u^2 + w^2) depends on (row, column) only; the ray values are scaled by
+// |D| before the gather. A component within 1e-12 sdd of 0 gets the reciprocal +-1e300 (a
+// line parallel to that axis: inside a slab or not, as decided by the source's coordinate).
+__device__ inline double inv_or_big(double x, double scale) {
+  return fabs(x) < 1e-12 * scale ? (x < 0.0 ? -1e300 : 1e300) : 1.0 / x;
+}
+
+__global__ __launch_bounds__(kB) void k3_ray_factors(DevGeom3 g, const double2* __restrict__ views,
+                                                     double2* __restrict__ colt, double* __restrict__ rowt,
+                                                     double* __restrict__ nrm) {
+  const int64_t t = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int64_t nvc = int64_t(g.nv) * g.nc, nrc = int64_t(g.nr) * g.nc;
+  if (t < nvc) {
+    const int v = int(t / g.nc), col = int(t - int64_t(v) * g.nc);
+    const double c = views[v].x, s = views[v].y, u = (col - 0.5 * (g.nc - 1)) * g.cpitch;
+    colt[t] = make_double2(inv_or_big(-g.sdd * c - u * s, g.sdd), inv_or_big(-g.sdd * s + u * c, g.sdd));
+  }
+  if (t < nrc) {
+    const int row = int(t / g.nc), col = int(t - int64_t(row) * g.nc);
+    const double u = (col - 0.5 * (g.nc - 1)) * g.cpitch, w = (row - 0.5 * (g.nr - 1)) * g.rpitch;
+    nrm[t] = sqrt(g.sdd * g.sdd + u * u + w * w);
+    if (col == 0) rowt[row] = inv_or_big(w, g.sdd);
+  }
+}
+
+// out[ray] = y[ray] |D| (the ray values of the factorised gather)
+template <typename T>
+__global__ __launch_bounds__(kB) void k3_scale_rays(DevGeom3 g, const T* __restrict__ y,
+                                                    const double* __restrict__ nrm, T* __restrict__ out) {
+  const int64_t r = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int64_t nrc = int64_t(g.nr) * g.nc;
+  if (r >= nrc * g.nv) return;
+  out[r] = T(double(y[r]) * nrm[r % nrc]);
+}
 
 // Sums of one item over views [v0, v1). Per view the item box's eight corners are projected
 // onto the detector (FP32 with the hardware reciprocal, widened by 1e-3 element) to bound the
-// rows and columns whose rays can cross it; per such ray the chords through the box, or
-// through its eight octants, come from slab clipping in FP64, and the seven detail values
-// from a 2x2x2 Haar butterfly of the octant chords (per (ray, coefficient) sign split).
-template <typename T>
+// rows and columns whose rays can cross it; per such ray the parameter intervals of the box,
+// or of its eight octants, come from slab clipping in FP64 (z slabs once per row), and the
+// seven detail values from a 2x2x2 Haar butterfly of the octant chords. Per detail the signed
+// sum S and the sum of magnitudes A are kept: the positive part is (A + S) / 2 and the
+// negative part (S - A) / 2 (per (ray, coefficient) sign split, eq. 1.10).
+template <typename T, bool SPLIT>
 __device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __restrict__ views,
-                                           const double4* __restrict__ A, const double4* __restrict__ B,
-                                           const T* __restrict__ y, bool split, int l, int k, int i, int j, int v0,
-                                           int v1) {
+                                           const double2* __restrict__ colt, const double* __restrict__ rowt,
+                                           const T* __restrict__ y, int l, int k, int i, int j, int v0, int v1) {
   const int n = g.n, nz = g.nz, s = 1 << l;
   const double pix = g.pixel, hn = 0.5 * n, hz = 0.5 * nz;
   const double X0 = (double(j * s) - hn) * pix, X2 = (double((j + 1) * s) - hn) * pix;
@@ -381,7 +423,8 @@ __device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __r
 #pragma unroll
   for (int q = 0; q < kSlots3; ++q) r.v[q] = 0.0;
   for (int v = v0; v < v1; ++v) {
-    const float c = float(views[v].x), sn = float(views[v].y);
+    const double2 cs = views[v];
+    const float c = float(cs.x), sn = float(cs.y);
     float umin = 1e30f, umax = -1e30f, wmin = 1e30f, wmax = -1e30f;
 #pragma unroll
     for (int corner = 0; corner < 8; ++corner) {
@@ -398,32 +441,43 @@ __device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __r
     const float fr1 = fminf(fmaxf(wmax * irp + rc0 + 1e-3f, -1.f), float(g.nr));
     const int clo = max(int(ceilf(fc0)), 0), chi = min(int(floorf(fc1)), g.nc - 1);
     const int rlo = max(int(ceilf(fr0)), 0), rhi = min(int(floorf(fr1)), g.nr - 1);
+    const double Sx = g.sod * cs.x, Sy = g.sod * cs.y;
+    const double ax0 = X0 - Sx, ax1 = X1 - Sx, ax2 = X2 - Sx;
+    const double ay0 = Y0 - Sy, ay1 = Y1 - Sy, ay2 = Y2 - Sy;
+    const double2* __restrict__ cv = colt + int64_t(v) * g.nc;
     for (int row = rlo; row <= rhi; ++row) {
-      const int64_t rowbase = (int64_t(v) * g.nr + row) * g.nc;
-      for (int col = clo; col <= chi; ++col) {
-        const double4 a = A[rowbase + col];
-        const double4 bb = B[rowbase + col];
-        const double yv = double(y[rowbase + col]);
-        const double tx0 = (X0 - a.x) * a.w, tx2 = (X2 - a.x) * a.w;
-        const double ty0 = (Y0 - a.y) * bb.x, ty2 = (Y2 - a.y) * bb.x;
-        const double tz0 = (Z0 - a.z) * bb.y, tz2 = (Z2 - a.z) * bb.y;
-        if (!split) {
-          const double lo = fmax(fmax(fmin(tx0, tx2), fmin(ty0, ty2)), fmin(tz0, tz2));
-          const double hi = fmin(fmin(fmax(tx0, tx2), fmax(ty0, ty2)), fmax(tz0, tz2));
-          r.v[0] += yv * fmax(hi - lo, 0.0);
-          continue;
+      const double iz = rowt[row];
+      const double tz0 = Z0 * iz, tz2 = Z2 * iz;
+      const T* __restrict__ yr = y + (int64_t(v) * g.nr + row) * g.nc;
+      if (!SPLIT) {
+        const double zlo = fmin(tz0, tz2), zhi = fmax(tz0, tz2);
+        for (int col = clo; col <= chi; ++col) {
+          const double2 cd = cv[col];
+          const double tx0 = ax0 * cd.x, tx2 = ax2 * cd.x, ty0 = ay0 * cd.y, ty2 = ay2 * cd.y;
+          const double lo = fmax(fmax(fmin(tx0, tx2), fmin(ty0, ty2)), zlo);
+          const double hi = fmin(fmin(fmax(tx0, tx2), fmax(ty0, ty2)), zhi);
+          r.v[0] += double(yr[col]) * fmax(hi - lo, 0.0);
         }
-        const double tx1 = (X1 - a.x) * a.w, ty1 = (Y1 - a.y) * bb.x, tz1 = (Z1 - a.z) * bb.y;
-        // per axis the parameter interval of the lower [.0] and upper [.1] half
+        continue;
+      }
+      const double tz1 = Z1 * iz;
+      const double zl[2] = {fmin(tz0, tz1), fmin(tz1, tz2)}, zh[2] = {fmax(tz0, tz1), fmax(tz1, tz2)};
+      for (int col = clo; col <= chi; ++col) {
+        const double2 cd = cv[col];
+        const double yv = double(yr[col]);
+        const double tx0 = ax0 * cd.x, tx1 = ax1 * cd.x, tx2 = ax2 * cd.x;
+        const double ty0 = ay0 * cd.y, ty1 = ay1 * cd.y, ty2 = ay2 * cd.y;
         const double xl[2] = {fmin(tx0, tx1), fmin(tx1, tx2)}, xh[2] = {fmax(tx0, tx1), fmax(tx1, tx2)};
         const double yl[2] = {fmin(ty0, ty1), fmin(ty1, ty2)}, yh[2] = {fmax(ty0, ty1), fmax(ty1, ty2)};
-        const double zl[2] = {fmin(tz0, tz1), fmin(tz1, tz2)}, zh[2] = {fmax(tz0, tz1), fmax(tz1, tz2)};
+        double lq[4], hq[4];   // xy quarter (by, bx) intervals
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          lq[q] = fmax(xl[q & 1], yl[q >> 1]);
+          hq[q] = fmin(xh[q & 1], yh[q >> 1]);
+        }
         double ch[8];
 #pragma unroll
-        for (int o = 0; o < 8; ++o) {
-          const int bx = o & 1, by = (o >> 1) & 1, bz = (o >> 2) & 1;
-          ch[o] = fmax(fmin(fmin(xh[bx], yh[by]), zh[bz]) - fmax(fmax(xl[bx], yl[by]), zl[bz]), 0.0);
-        }
+        for (int o = 0; o < 8; ++o) ch[o] = fmax(fmin(hq[o & 3], zh[o >> 2]) - fmax(lq[o & 3], zl[o >> 2]), 0.0);
         // 2x2x2 butterfly: x, then y, then z (lower half +, upper half -)
         double s1[4], d1[4];
 #pragma unroll
@@ -435,8 +489,8 @@ __device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __r
 #pragma unroll
         for (int d = 0; d < 7; ++d) {
           const double wv = yv * det[d];
-          r.v[1 + d] += fmax(wv, 0.0);
-          r.v[8 + d] += fmin(wv, 0.0);
+          r.v[1 + d] += wv;
+          r.v[8 + d] += fabs(wv);
         }
       }
     }
@@ -464,8 +518,8 @@ template <typename T>
 struct GArgs3 {
   DevGeom3 g;
   const double2* views;
-  const double4* A;
-  const double4* B;
+  const double2* colt;
+  const double* rowt;
   const T* y;
   const uint32_t* items;
   const int* counts;
@@ -514,8 +568,8 @@ __device__ inline void item_finish3(const GArgs3<T>& a, uint32_t w, const Sums3<
     if (split)
       for (int d = 0; d < 7; ++d) {
         const int64_t z = detail_pos(n, nz, l, d, k, i, j);
-        a.bp[z] = T(r.v[1 + d] * sc);
-        a.bm[z] = T(r.v[8 + d] * sc);
+        a.bp[z] = T(0.5 * (r.v[8 + d] + r.v[1 + d]) * sc);
+        a.bm[z] = T(0.5 * (r.v[1 + d] - r.v[8 + d]) * sc);
       }
     return;
   }
@@ -524,25 +578,27 @@ __device__ inline void item_finish3(const GArgs3<T>& a, uint32_t w, const Sums3<
   if (split)
     for (int d = 0; d < 7; ++d) {
       const int64_t z = detail_pos(n, nz, l, d, k, i, j);
-      a.beta[z] = T(double(a.beta[z]) + am_delta3(double(a.b[z]), r.v[1 + d] * sc, r.v[8 + d] * sc, z0, a.held));
+      const double bp = 0.5 * (r.v[8 + d] + r.v[1 + d]) * sc, bm = 0.5 * (r.v[1 + d] - r.v[8 + d]) * sc;
+      a.beta[z] = T(double(a.beta[z]) + am_delta3(double(a.b[z]), bp, bm, z0, a.held));
     }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool SPLIT>
 __global__ __launch_bounds__(kB) void k3_gather(GArgs3<T> a) {
   int start, count;
   seg_range3(a, start, count);
   const int it = blockIdx.x * kB + threadIdx.x;
   if (it >= count) return;
   const uint32_t w = item3_word(a.items, start + it, a.g.n);
-  const Sums3<double> r = item_sums3<T>(a.g, a.views, a.A, a.B, a.y, (w >> 31) != 0, int((w >> 27) & 15u),
-                                        int((w >> 18) & 0x1ffu), int((w >> 9) & 0x1ffu), int(w & 0x1ffu), 0, a.g.nv);
+  const Sums3<double> r = item_sums3<T, SPLIT>(a.g, a.views, a.colt, a.rowt, a.y, int((w >> 27) & 15u),
+                                               int((w >> 18) & 0x1ffu), int((w >> 9) & 0x1ffu), int(w & 0x1ffu), 0,
+                                               a.g.nv);
   item_finish3<T, MODE>(a, w, r);
 }
 
 // (item, view chunk) tasks: a block of 4 waves takes 64 items; wave w handles view chunk
 // 4 group + w; the four chunk sums are added in LDS in wave order and stored per group.
-template <typename T>
+template <typename T, bool SPLIT>
 __global__ __launch_bounds__(256) void k3_gather_part(GArgs3<T> a) {
   __shared__ double sh[4][kSlots3][64];
   int start, count;
@@ -557,8 +613,8 @@ __global__ __launch_bounds__(256) void k3_gather_part(GArgs3<T> a) {
   if (idx < count && chunk < a.chunks) {
     const uint32_t w = item3_word(a.items, start + idx, a.g.n);
     const int v0 = chunk * a.vpc, v1 = min(a.g.nv, v0 + a.vpc);
-    r = item_sums3<T>(a.g, a.views, a.A, a.B, a.y, (w >> 31) != 0, int((w >> 27) & 15u), int((w >> 18) & 0x1ffu),
-                      int((w >> 9) & 0x1ffu), int(w & 0x1ffu), v0, v1);
+    r = item_sums3<T, SPLIT>(a.g, a.views, a.colt, a.rowt, a.y, int((w >> 27) & 15u), int((w >> 18) & 0x1ffu),
+                             int((w >> 9) & 0x1ffu), int(w & 0x1ffu), v0, v1);
   }
 #pragma unroll
   for (int q = 0; q < kSlots3; ++q) sh[wv][q][lane] = r.v[q];
@@ -746,8 +802,9 @@ __global__ __launch_bounds__(kB) void k3_expand(DevGeom3 g, const uint8_t* __res
   }
 }
 
-// Single work-group compaction of the work list (as in 2-D): levels from L down to 1 (L = 0:
-// voxels), 3-D Morton order within a level, wave ballots + LDS prefix, order deterministic.
+// Single work-group compaction of the work list in segments: 0 = split roots, 1 = roots not
+// split (with L = 0: every voxel), 2 + m = split nodes of level L - 1 - m; 3-D Morton order
+// within a segment, wave ballots + LDS prefix, order deterministic.
 __global__ __launch_bounds__(1024) void k3_items(DevGeom3 g, const uint8_t* __restrict__ mask,
                                                  uint32_t* __restrict__ items, int* __restrict__ counts) {
   __shared__ int wave_tot[16];
@@ -756,8 +813,9 @@ __global__ __launch_bounds__(1024) void k3_items(DevGeom3 g, const uint8_t* __re
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (threadIdx.x == 0) base_sh = 0;
   __syncthreads();
-  const int lmin = L == 0 ? 0 : 1;
-  for (int l = L; l >= lmin; --l) {
+  const int n_seg = L >= 1 ? L + 1 : 2;
+  for (int sgi = 0; sgi < n_seg; ++sgi) {
+    const int l = sgi <= 1 ? L : L - (sgi - 1);
     const int level_start = base_sh;
     const int m = n >> l, mz = nz >> l;
     int pw = 1;
@@ -772,13 +830,9 @@ __global__ __launch_bounds__(1024) void k3_items(DevGeom3 g, const uint8_t* __re
         const int i = int(morton3_compact(uint32_t(code >> 1)));
         const int k = int(morton3_compact(uint32_t(code >> 2)));
         if (i < m && j < m && k < mz) {
-          if (l == L) {
-            inc = true;
-            word = item3_pack((L > 0 && split3(mask, n, L, k, i, j)) ? 1 : 0, l, k, i, j);
-          } else if (split3(mask, n, l, k, i, j)) {
-            inc = true;
-            word = item3_pack(1, l, k, i, j);
-          }
+          const bool sp = l > 0 && split3(mask, n, l, k, i, j);
+          inc = sgi == 1 ? !sp : sp;
+          word = item3_pack(sp ? 1 : 0, l, k, i, j);
         }
       }
       const uint64_t bal = __ballot(inc);
@@ -796,7 +850,7 @@ __global__ __launch_bounds__(1024) void k3_items(DevGeom3 g, const uint8_t* __re
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0) counts[1 + (L - l)] = base_sh - level_start;
+    if (threadIdx.x == 0) counts[1 + sgi] = base_sh - level_start;
   }
   if (threadIdx.x == 0) counts[0] = base_sh;
 }
@@ -820,30 +874,48 @@ int Geo3<T>::forward(const DevGeom3& g, const void* A, const void* B, const doub
   return nb;
 }
 template <typename T>
-void Geo3<T>::gather(const DevGeom3& g, int mode, const double2* views, const void* A, const void* B, const T* y,
-                     const uint32_t* items, const int* counts, const Segment* segs, int n_segs, void* part,
+void Geo3<T>::ray_factors(const DevGeom3& g, const double2* views, double2* colt, double* rowt, double* nrm,
+                          hipStream_t s) {
+  const int64_t t = std::max(int64_t(g.nv) * g.nc, int64_t(g.nr) * g.nc);
+  hipLaunchKernelGGL(k3_ray_factors, dim3(blocks3(t)), dim3(kB), 0, s, g, views, colt, rowt, nrm);
+}
+template <typename T>
+void Geo3<T>::scale_rays(const DevGeom3& g, const T* y, const double* nrm, T* out, hipStream_t s) {
+  hipLaunchKernelGGL(k3_scale_rays<T>, dim3(blocks3(int64_t(g.nv) * g.nr * g.nc)), dim3(kB), 0, s, g, y, nrm, out);
+}
+template <typename T, int MODE, bool SPLIT>
+static void gather_seg3(const GArgs3<T>& a, const Segment& sg, hipStream_t s) {
+  if (sg.chunks <= 1) {
+    hipLaunchKernelGGL((k3_gather<T, MODE, SPLIT>), dim3(blocks3(sg.count)), dim3(kB), 0, s, a);
+    return;
+  }
+  const int groups = (sg.chunks + 3) / 4;
+  hipLaunchKernelGGL((k3_gather_part<T, SPLIT>), dim3(((sg.count + 63) / 64) * groups), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k3_gather_finish<T, MODE>), dim3((sg.count + 63) / 64), dim3(1024), 0, s, a);
+}
+template <typename T, int MODE>
+static void gather_mode3(const GArgs3<T>& a, const Segment& sg, bool split, hipStream_t s) {
+  if (split) gather_seg3<T, MODE, true>(a, sg, s);
+  else gather_seg3<T, MODE, false>(a, sg, s);
+}
+template <typename T>
+void Geo3<T>::gather(const DevGeom3& g, int mode, const double2* views, const double2* colt, const double* rowt,
+                     const T* y, const uint32_t* items, const int* counts, const Segment* segs, int n_segs, void* part,
                      T* beta, const T* b, const double* z0, int* held, T* bp, T* bm, T* out, hipStream_t s) {
   GArgs3<T> a;
-  a.g = g; a.views = views; a.A = (const double4*)A; a.B = (const double4*)B; a.y = y;
+  a.g = g; a.views = views; a.colt = colt; a.rowt = rowt; a.y = y;
   a.items = items; a.counts = counts; a.part = (double*)part;
   a.beta = beta; a.b = b; a.z0 = z0; a.held = held; a.bp = bp; a.bm = bm; a.out = out;
   for (int k = 0; k < n_segs; ++k) {
     const Segment& sg = segs[k];
     if (sg.count <= 0) continue;
     a.kseg = sg.kseg; a.start = sg.start; a.count = sg.count; a.chunks = sg.chunks; a.vpc = sg.vpc;
-    if (sg.chunks <= 1) {
-      const dim3 grid(blocks3(sg.count));
-      if (mode == kPlain) hipLaunchKernelGGL((k3_gather<T, kPlain>), grid, dim3(kB), 0, s, a);
-      else if (mode == kSplit) hipLaunchKernelGGL((k3_gather<T, kSplit>), grid, dim3(kB), 0, s, a);
-      else hipLaunchKernelGGL((k3_gather<T, kUpdate>), grid, dim3(kB), 0, s, a);
-      continue;
-    }
-    const int groups = (sg.chunks + 3) / 4;
-    hipLaunchKernelGGL(k3_gather_part<T>, dim3(((sg.count + 63) / 64) * groups), dim3(256), 0, s, a);
-    const dim3 grid((sg.count + 63) / 64);
-    if (mode == kPlain) hipLaunchKernelGGL((k3_gather_finish<T, kPlain>), grid, dim3(1024), 0, s, a);
-    else if (mode == kSplit) hipLaunchKernelGGL((k3_gather_finish<T, kSplit>), grid, dim3(1024), 0, s, a);
-    else hipLaunchKernelGGL((k3_gather_finish<T, kUpdate>), grid, dim3(1024), 0, s, a);
+    // work-list segment 1 holds the roots that are not split; every other segment of a
+    // work list holds nodes with octant chords; no work list: voxels as plain boxes
+    const bool split = items != nullptr && sg.kseg != 1;
+    if (mode == kPlain) gather_mode3<T, kPlain>(a, sg, split, s);
+    else if (mode == kSplit) gather_mode3<T, kSplit>(a, sg, split, s);
+    else gather_mode3<T, kUpdate>(a, sg, split, s);
   }
 }
 template <typename T>
