@@ -266,12 +266,71 @@ __global__ void k3_approx_mask(DevGeom3 g, uint8_t* __restrict__ mask) {
 
 // ------------------------------------------------------------------ forward (leaf walk)
 
-// Per ray: walk the octree leaves (cubes of side 2^l voxels) from the entry point; each leaf
-// is left through the nearest of its three exit planes; the crossed axis steps to the
-// neighbouring leaf, the two others take the exit point's voxel, clamped into the old
-// leaf's range and never moving backwards. p = sum of chord * leaf value; then Beer's law
-// and the FP64 I-divergence term. x-major rays read the [z][x][y] records (neighbouring
-// lanes, neighbouring rays of a detector row, then touch neighbouring addresses).
+// Octree leaf walk of one ray (cubes of side 2^l voxels, l from the voxel's record). The walk
+// runs in a frame mirrored per axis so that every direction component is >= 0 (leaf
+// boundaries stay aligned since 2^l divides n and nz): a leaf is left through the nearest of
+// its three upper faces; the crossed axis steps to the neighbouring leaf, the two others take
+// the exit point's voxel, clamped into the old leaf's range and never moving backwards.
+// Voxel indices fit in 32 bits (n, nz <= 512).
+struct Walker3 {
+  double x0, y0, z0;   // mirrored voxel coordinates of the ray at t = 0
+  double ux, uy, uz;   // voxels per unit t along each axis
+  double kx, ky, kz;   // t per voxel along each axis
+  double t, t_out;
+  int x, y, z;         // current voxel, mirrored frame
+  int mx, my, mz;      // real index = m + s * mirrored index
+  int sx, sy, sz;
+  int n, nz;
+
+  __device__ bool init(const DevGeom3& g, double ox, double oy, double oz, double iex, double iey, double iez,
+                       double ex, double ey, double ez) {
+    n = g.n; nz = g.nz;
+    const double ipix = 1.0 / g.pixel;
+    const double X = ox * ipix + 0.5 * n, Y = oy * ipix + 0.5 * n, Z = oz * ipix + 0.5 * nz;
+    x0 = ex < 0.0 ? double(n) - X : X;
+    y0 = ey < 0.0 ? double(n) - Y : Y;
+    z0 = ez < 0.0 ? double(nz) - Z : Z;
+    ux = fabs(ex) * ipix; uy = fabs(ey) * ipix; uz = fabs(ez) * ipix;
+    kx = fabs(iex) * g.pixel; ky = fabs(iey) * g.pixel; kz = fabs(iez) * g.pixel;
+    mx = ex < 0.0 ? n - 1 : 0;  sx = ex < 0.0 ? -1 : 1;
+    my = ey < 0.0 ? n - 1 : 0;  sy = ey < 0.0 ? -1 : 1;
+    mz = ez < 0.0 ? nz - 1 : 0; sz = ez < 0.0 ? -1 : 1;
+    const double t_in = fmax(fmax(-x0 * kx, -y0 * ky), -z0 * kz);
+    t_out = fmin(fmin((double(n) - x0) * kx, (double(n) - y0) * ky), (double(nz) - z0) * kz);
+    if (!(t_out > t_in)) return false;
+    t = t_in;
+    x = min(max(int(fma(t_in, ux, x0)), 0), n - 1);
+    y = min(max(int(fma(t_in, uy, y0)), 0), n - 1);
+    z = min(max(int(fma(t_in, uz, z0)), 0), nz - 1);
+    return true;
+  }
+  __device__ int rx() const { return mx + sx * x; }
+  __device__ int ry() const { return my + sy * y; }
+  __device__ int rz() const { return mz + sz * z; }
+  // Leaves the current leaf (level l): chord = parameter length inside it; returns whether the
+  // walk goes on (then x, y, z is a voxel of the next leaf; else possibly out of range).
+  __device__ bool step(int l, double& chord) {
+    const int s = 1 << l;
+    const int ex_ = (x & -s) + s, ey_ = (y & -s) + s, ez_ = (z & -s) + s;
+    const double tX = (double(ex_) - x0) * kx, tY = (double(ey_) - y0) * ky, tZ = (double(ez_) - z0) * kz;
+    const bool ax0 = tX <= tY && tX <= tZ;
+    const bool ax1 = !ax0 && tY <= tZ;
+    const double te = fmax(fmin(fmin(tX, fmin(tY, tZ)), t_out), t);
+    chord = te - t;
+    int nx = min(max(int(fma(te, ux, x0)), x), ex_ - 1);
+    int ny = min(max(int(fma(te, uy, y0)), y), ey_ - 1);
+    int nzv = min(max(int(fma(te, uz, z0)), z), ez_ - 1);
+    nx = ax0 ? ex_ : nx;
+    ny = ax1 ? ey_ : ny;
+    nzv = (!ax0 && !ax1) ? ez_ : nzv;
+    t = te; x = nx; y = ny; z = nzv;
+    return te < t_out && nx < n && ny < n && nzv < nz;
+  }
+};
+
+// Per ray: p = sum over the leaves crossed of chord * leaf value; then Beer's law and the FP64
+// I-divergence term. x-major rays read the [z][x][y] records (neighbouring lanes,
+// neighbouring rays of a detector row, then touch neighbouring addresses).
 template <typename T>
 __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, const double4* __restrict__ A,
                                                  const double4* __restrict__ B, const double* __restrict__ C,
@@ -284,57 +343,27 @@ __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, const double4* __re
   double term = 0.0;
   if (r < M) {
     const double4 a = A[r], b = B[r];
-    const double ox = a.x, oy = a.y, oz = a.z, iex = a.w, iey = b.x, iez = b.y, ex = b.z, ey = b.w, ez = C[r];
-    const int n = g.n, nz = g.nz;
-    const double pix = g.pixel, ipix = 1.0 / g.pixel, hn = 0.5 * n, hz = 0.5 * nz;
-    const double tx0 = (-hn * pix - ox) * iex, tx1 = (hn * pix - ox) * iex;
-    const double ty0 = (-hn * pix - oy) * iey, ty1 = (hn * pix - oy) * iey;
-    const double tz0 = (-hz * pix - oz) * iez, tz1 = (hz * pix - oz) * iez;
-    const double t_in = fmax(fmax(fmin(tx0, tx1), fmin(ty0, ty1)), fmin(tz0, tz1));
-    const double t_out = fmin(fmin(fmax(tx0, tx1), fmax(ty0, ty1)), fmax(tz0, tz1));
+    const double ex = b.z, ey = b.w;
+    Walker3 w;
     double acc = 0.0;
-    if (t_out > t_in) {
-      int ix = (int)floor(fmin(fmax((ox + t_in * ex) * ipix + hn, -1.0), double(n)));
-      int iy = (int)floor(fmin(fmax((oy + t_in * ey) * ipix + hn, -1.0), double(n)));
-      int iz = (int)floor(fmin(fmax((oz + t_in * ez) * ipix + hz, -1.0), double(nz)));
-      ix = imin3(imax3(ix, 0), n - 1);
-      iy = imin3(imax3(iy, 0), n - 1);
-      iz = imin3(imax3(iz, 0), nz - 1);
-      const bool px = ex > 0, py = ey > 0, pz = ez > 0;
+    if (w.init(g, a.x, a.y, a.z, a.w, b.x, b.y, ex, ey, C[r])) {
+      const int n = g.n;
       const bool xmaj = fabs(ex) >= fabs(ey);
       const Rec3<T>* __restrict__ base = xmaj ? recC : recR;
+      // [z][x][y] or [z][y][x] address of the mirrored voxel (x, y, z), clamped into range
       auto addr = [&](int x, int y, int z) {
-        return xmaj ? (int64_t(z) * n + x) * n + y : (int64_t(z) * n + y) * n + x;
+        const int rx = w.mx + w.sx * min(x, n - 1), ry = w.my + w.sy * min(y, n - 1);
+        const int rz = w.mz + w.sz * min(z, g.nz - 1);
+        return xmaj ? (rz * n + rx) * n + ry : (rz * n + ry) * n + rx;
       };
-      Rec3<T> rec = base[addr(ix, iy, iz)];
-      double t = t_in;
-      for (int step = 0; step < 4 * (2 * n + nz) + 8; ++step) {
-        const int l = int(rec.lev());
-        const int s = 1 << l;
-        const int bx0 = ix & -s, by0 = iy & -s, bz0 = iz & -s;
-        const double tX = ((double(px ? bx0 + s : bx0) - hn) * pix - ox) * iex;
-        const double tY = ((double(py ? by0 + s : by0) - hn) * pix - oy) * iey;
-        const double tZ = ((double(pz ? bz0 + s : bz0) - hz) * pix - oz) * iez;
-        const int ax = (tX <= tY && tX <= tZ) ? 0 : (tY <= tZ ? 1 : 2);
-        const double tmin = ax == 0 ? tX : (ax == 1 ? tY : tZ);
-        const double te = fmax(fmin(tmin, t_out), t);
-        // exit point's voxel along every axis, clamped into the old leaf, never backwards
-        const int cx = (int)floorf(fminf(fmaxf(float((ox + te * ex) * ipix + hn), -1.f), float(n)));
-        const int cy = (int)floorf(fminf(fmaxf(float((oy + te * ey) * ipix + hn), -1.f), float(n)));
-        const int cz = (int)floorf(fminf(fmaxf(float((oz + te * ez) * ipix + hz), -1.f), float(nz)));
-        int nx = px ? imin3(imax3(cx, ix), bx0 + s - 1) : imax3(imin3(cx, ix), bx0);
-        int ny = py ? imin3(imax3(cy, iy), by0 + s - 1) : imax3(imin3(cy, iy), by0);
-        int nzi = pz ? imin3(imax3(cz, iz), bz0 + s - 1) : imax3(imin3(cz, iz), bz0);
-        if (ax == 0) nx = px ? bx0 + s : bx0 - 1;
-        else if (ax == 1) ny = py ? by0 + s : by0 - 1;
-        else nzi = pz ? bz0 + s : bz0 - 1;
-        const bool go = te < t_out && (unsigned)nx < (unsigned)n && (unsigned)ny < (unsigned)n &&
-                        (unsigned)nzi < (unsigned)nz;
-        Rec3<T> nrec = rec;
-        if (go) nrec = base[addr(nx, ny, nzi)];
-        acc += (te - t) * double(rec.mu());
+      Rec3<T> rec = base[addr(w.x, w.y, w.z)];
+      for (int step = 0; step < 4 * (2 * n + g.nz) + 8; ++step) {
+        double chord;
+        const bool go = w.step(int(rec.lev()), chord);
+        const Rec3<T> nrec = base[addr(w.x, w.y, w.z)];
+        acc += chord * double(rec.mu());
         if (!go) break;
-        t = te; ix = nx; iy = ny; iz = nzi; rec = nrec;
+        rec = nrec;
       }
     }
     if (pout) pout[r] = T(acc);
@@ -654,47 +683,59 @@ __global__ __launch_bounds__(1024) void k3_gather_finish(GArgs3<T> a) {
 
 // ------------------------------------------------------------------ Z0 and W (eq. 1.61)
 
+__device__ inline double flip_sign(double v, int neg) {
+  return __longlong_as_double(__double_as_longlong(v) ^ (static_cast<long long>(neg) << 63));
+}
+
 // Per ray in FP64: walk the octree leaves; every leaf chord adds sign_d(octant) * chord to
-// the seven detail accumulators of each split ancestor, and chord to its root's
-// approximation accumulator; when the ray leaves a node, 2^(-3m/2) |acc| of its details go
-// into the ray's sum and the non-zero ones are counted. Z0 = max over rays, W = total count.
+// the seven signed detail sums of each split ancestor, and chord to its root's approximation
+// sum; when the ray leaves a node, |sum| of its details enter the ray's level total and the
+// non-zero ones are counted (threshold 1e-9 pixel on the scaled value). The ray's value is
+// sum over levels of 2^(-3m/2) x its level total; Z0 = max over rays, W = total count.
 template <int LT>
 struct Z0Vis3 {
-  double tol, sum, cnt, accLL;
+  double tolm[LT + 1];     // count threshold per level, unscaled
+  double tot[LT + 1];      // per level: sum of |detail sums| (index 0: root approximations)
+  double cnt;
   double acc[LT + 1][7];
-  int64_t cur[LT + 1];
-  int64_t curLL;
+  double accLL;
+  int cur[LT + 1];
+  int curLL;
   __device__ void flush(int m) {
-    const double sc = scale3(m);
 #pragma unroll
     for (int d = 0; d < 7; ++d) {
-      const double a = fabs(acc[m][d]) * sc;
-      sum += a;
-      cnt += a > tol ? 1.0 : 0.0;
+      const double a = fabs(acc[m][d]);
+      tot[m] += a;
+      cnt += a > tolm[m] ? 1.0 : 0.0;
       acc[m][d] = 0.0;
     }
   }
   __device__ void flushLL() {
-    const double a = fabs(accLL) * scale3(LT);
-    sum += a;
-    cnt += a > tol ? 1.0 : 0.0;
+    tot[0] += accLL;
+    cnt += accLL > tolm[0] ? 1.0 : 0.0;
     accLL = 0.0;
   }
   __device__ void visit(int ix, int iy, int iz, int l, double chord) {
 #pragma unroll
     for (int m = 1; m <= LT; ++m) {
-      const int64_t node = (int64_t(iz >> m) << 40) | (int64_t(iy >> m) << 20) | int64_t(ix >> m);
+      const int node = ((iz >> m) << 18) | ((iy >> m) << 9) | (ix >> m);
       if (node != cur[m]) {
         if (cur[m] >= 0) flush(m);
         cur[m] = node;
       }
       if (m > l) {
-        const int oct = (((iz >> (m - 1)) & 1) << 2) | (((iy >> (m - 1)) & 1) << 1) | ((ix >> (m - 1)) & 1);
-#pragma unroll
-        for (int d = 0; d < 7; ++d) acc[m][d] += (__popc(uint32_t((d + 1) & oct)) & 1) ? -chord : chord;
+        const int bx = (ix >> (m - 1)) & 1, by = (iy >> (m - 1)) & 1, bz = (iz >> (m - 1)) & 1;
+        const double cx = flip_sign(chord, bx), cy = flip_sign(chord, by), cxy = flip_sign(cx, by);
+        acc[m][0] += cx;                    // types (tz, ty, tx) = 001 .. 111
+        acc[m][1] += cy;
+        acc[m][2] += cxy;
+        acc[m][3] += flip_sign(chord, bz);
+        acc[m][4] += flip_sign(cx, bz);
+        acc[m][5] += flip_sign(cy, bz);
+        acc[m][6] += flip_sign(cxy, bz);
       }
     }
-    const int64_t root = (int64_t(iz >> LT) << 40) | (int64_t(iy >> LT) << 20) | int64_t(ix >> LT);
+    const int root = ((iz >> LT) << 18) | ((iy >> LT) << 9) | (ix >> LT);
     if (root != curLL) {
       if (curLL >= 0) flushLL();
       curLL = root;
@@ -712,60 +753,39 @@ __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, const double4* __restric
   double sum = 0.0, cnt = 0.0;
   if (r < M) {
     const double4 a = A[r], b = B[r];
-    const double ox = a.x, oy = a.y, oz = a.z, iex = a.w, iey = b.x, iez = b.y, ex = b.z, ey = b.w, ez = C[r];
-    const int n = g.n, nz = g.nz;
-    const double pix = g.pixel, ipix = 1.0 / g.pixel, hn = 0.5 * n, hz = 0.5 * nz;
-    const double tx0 = (-hn * pix - ox) * iex, tx1 = (hn * pix - ox) * iex;
-    const double ty0 = (-hn * pix - oy) * iey, ty1 = (hn * pix - oy) * iey;
-    const double tz0 = (-hz * pix - oz) * iez, tz1 = (hz * pix - oz) * iez;
-    const double t_in = fmax(fmax(fmin(tx0, tx1), fmin(ty0, ty1)), fmin(tz0, tz1));
-    const double t_out = fmin(fmin(fmax(tx0, tx1), fmax(ty0, ty1)), fmax(tz0, tz1));
     Z0Vis3<LT> z;
-    z.tol = 1e-9 * g.pixel; z.sum = 0.0; z.cnt = 0.0; z.accLL = 0.0; z.curLL = -1;
+    const double tol = 1e-9 * g.pixel;
+    z.cnt = 0.0; z.accLL = 0.0; z.curLL = -1;
+    z.tolm[0] = tol / scale3(LT);
+    z.tot[0] = 0.0;
 #pragma unroll
-    for (int m = 0; m <= LT; ++m) {
+    for (int m = 1; m <= LT; ++m) {
+      z.tolm[m] = tol / scale3(m);
+      z.tot[m] = 0.0;
       z.cur[m] = -1;
 #pragma unroll
       for (int d = 0; d < 7; ++d) z.acc[m][d] = 0.0;
     }
-    if (t_out > t_in) {
-      int ix = (int)floor(fmin(fmax((ox + t_in * ex) * ipix + hn, -1.0), double(n)));
-      int iy = (int)floor(fmin(fmax((oy + t_in * ey) * ipix + hn, -1.0), double(n)));
-      int iz = (int)floor(fmin(fmax((oz + t_in * ez) * ipix + hz, -1.0), double(nz)));
-      ix = imin3(imax3(ix, 0), n - 1);
-      iy = imin3(imax3(iy, 0), n - 1);
-      iz = imin3(imax3(iz, 0), nz - 1);
-      const bool px = ex > 0, py = ey > 0, pz = ez > 0;
-      double t = t_in;
-      for (int step = 0; step < 4 * (2 * n + nz) + 8; ++step) {
-        const int l = LT > 0 ? int(lev[(int64_t(iz) * n + iy) * n + ix]) : 0;
-        const int s = 1 << l;
-        const int bx0 = ix & -s, by0 = iy & -s, bz0 = iz & -s;
-        const double tX = ((double(px ? bx0 + s : bx0) - hn) * pix - ox) * iex;
-        const double tY = ((double(py ? by0 + s : by0) - hn) * pix - oy) * iey;
-        const double tZ = ((double(pz ? bz0 + s : bz0) - hz) * pix - oz) * iez;
-        const int ax = (tX <= tY && tX <= tZ) ? 0 : (tY <= tZ ? 1 : 2);
-        const double te = fmax(fmin(ax == 0 ? tX : (ax == 1 ? tY : tZ), t_out), t);
-        z.visit(ix, iy, iz, l, te - t);
-        if (te >= t_out) break;
-        const int cx = (int)floor(fmin(fmax((ox + te * ex) * ipix + hn, -1.0), double(n)));
-        const int cy = (int)floor(fmin(fmax((oy + te * ey) * ipix + hn, -1.0), double(n)));
-        const int cz = (int)floor(fmin(fmax((oz + te * ez) * ipix + hz, -1.0), double(nz)));
-        int nx = px ? imin3(imax3(cx, ix), bx0 + s - 1) : imax3(imin3(cx, ix), bx0);
-        int ny = py ? imin3(imax3(cy, iy), by0 + s - 1) : imax3(imin3(cy, iy), by0);
-        int nzi = pz ? imin3(imax3(cz, iz), bz0 + s - 1) : imax3(imin3(cz, iz), bz0);
-        if (ax == 0) nx = px ? bx0 + s : bx0 - 1;
-        else if (ax == 1) ny = py ? by0 + s : by0 - 1;
-        else nzi = pz ? bz0 + s : bz0 - 1;
-        if ((unsigned)nx >= (unsigned)n || (unsigned)ny >= (unsigned)n || (unsigned)nzi >= (unsigned)nz) break;
-        ix = nx; iy = ny; iz = nzi; t = te;
+    Walker3 w;
+    if (w.init(g, a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, C[r])) {
+      const int n = g.n;
+      for (int step = 0; step < 4 * (2 * n + g.nz) + 8; ++step) {
+        const int ix = w.rx(), iy = w.ry(), iz = w.rz();
+        const int l = LT > 0 ? int(lev[(iz * n + iy) * n + ix]) : 0;
+        double chord;
+        const bool go = w.step(l, chord);
+        z.visit(ix, iy, iz, l, chord);
+        if (!go) break;
       }
 #pragma unroll
       for (int m = 1; m <= LT; ++m)
         if (z.cur[m] >= 0) z.flush(m);
       if (z.curLL >= 0) z.flushLL();
     }
-    sum = z.sum; cnt = z.cnt;
+    sum = z.tot[0] * scale3(LT);
+#pragma unroll
+    for (int m = 1; m <= LT; ++m) sum += z.tot[m] * scale3(m);
+    cnt = z.cnt;
   }
   const double mx = breduce<true>(sum);
   __syncthreads();
