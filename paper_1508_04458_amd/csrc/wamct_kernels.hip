@@ -439,44 +439,40 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
       // this lane's piece [t_s, t_out) of the path
       const R t_s = piece == 0 ? t_in : t_in + (t_end - t_in) * (R(piece) / R(K));
       const R t_out = piece == K - 1 ? t_end : t_in + (t_end - t_in) * (R(piece + 1) / R(K));
-      int ix = (int)floor(fmin(fmax((ox + t_s * ex) * ipix + hn, R(-1)), R(n)));
-      int iy = (int)floor(fmin(fmax((oy + t_s * ey) * ipix + hn, R(-1)), R(n)));
-      ix = imin(imax(ix, 0), n - 1);
-      iy = imin(imax(iy, 0), n - 1);
       // major axis u (the one the ray travels along more; its records are contiguous in
-      // the minor axis w) and minor axis w: the record of pixel (u, w) is base[u n + w]
+      // the minor axis w) and minor axis w: the record of pixel (u, w) is base[u n + w].
+      // The walk runs in a frame mirrored per axis so that both coordinates grow along the
+      // ray (leaf boundaries stay aligned since 2^l divides n): pixel coordinate c0 + t ce,
+      // plane k crossed at t = t0 + k dt, real index = m + sg * mirrored index.
       const bool xmaj = fabs(ex) >= fabs(ey);
       const Leaf<T>* __restrict__ base = xmaj ? leafC : leafR;
-      const bool pu = (xmaj ? ex : ey) > R(0), pw = (xmaj ? ey : ex) > R(0);
-      // plane k of an axis (at -half + k pix) is crossed at t = t0 + k dt; the pixel
-      // coordinate along an axis at parameter t is c0 + t ce
-      const R tu0 = xmaj ? tx0 : ty0, tw0 = xmaj ? ty0 : tx0;
-      const R dtu = pix * (xmaj ? iex : iey), dtw = pix * (xmaj ? iey : iex);
-      const R cu0 = (xmaj ? ox : oy) * ipix + hn, cue = (xmaj ? ex : ey) * ipix;
-      const R cw0 = (xmaj ? oy : ox) * ipix + hn, cwe = (xmaj ? ey : ex) * ipix;
-      int iu = xmaj ? ix : iy, iw = xmaj ? iy : ix;
-      Leaf<T> rec = base[iu * n + iw];
+      const R eu = xmaj ? ex : ey, ew = xmaj ? ey : ex;
+      const R ieu = xmaj ? iex : iey, iew = xmaj ? iey : iex;
+      const R Ou = (xmaj ? ox : oy) * ipix + hn, Ow = (xmaj ? oy : ox) * ipix + hn;
+      const R cu0 = eu < R(0) ? R(n) - Ou : Ou, cw0 = ew < R(0) ? R(n) - Ow : Ow;
+      const R cue = fabs(eu) * ipix, cwe = fabs(ew) * ipix;
+      const R dtu = fabs(ieu) * pix, dtw = fabs(iew) * pix;
+      const R tu0 = -cu0 * dtu, tw0 = -cw0 * dtw;
+      const int mu = eu < R(0) ? n - 1 : 0, su = eu < R(0) ? -1 : 1;
+      const int mw = ew < R(0) ? n - 1 : 0, sw = ew < R(0) ? -1 : 1;
+      auto idx = [&](int u, int w) { return (mu + su * imin(u, n - 1)) * n + (mw + sw * imin(w, n - 1)); };
+      int iu = imin(imax(int(fma(t_s, cue, cu0)), 0), n - 1);
+      int iw = imin(imax(int(fma(t_s, cwe, cw0)), 0), n - 1);
+      Leaf<T> rec = base[idx(iu, iw)];
       R t = t_s;
       for (int step = 0; step < 4 * n + 8; ++step) {
-        const int l = int(rec.lev());
-        const int s = 1 << l;
-        const int bu0 = iu & -s, bw0 = iw & -s;
-        const R tU = fma(R(pu ? bu0 + s : bu0), dtu, tu0);
-        const R tW = fma(R(pw ? bw0 + s : bw0), dtw, tw0);
+        const int s = 1 << int(rec.lev());
+        const int eu_ = (iu & -s) + s, ew_ = (iw & -s) + s;   // upper planes of the leaf
+        const R tU = fma(R(eu_), dtu, tu0), tW = fma(R(ew_), dtw, tw0);
         const bool cu = tU <= tW;   // the leaf is left through a u plane
-        const R te = fmax(fmin(cu ? tU : tW, t_out), t);
+        const R te = fmax(fmin(fmin(tU, tW), t_out), t);
         // the axis not crossed takes the exit point's pixel, clamped into the old leaf's
         // range and never moving backwards; the crossed axis steps to the neighbour leaf
-        const int o = (int)floorf(fminf(fmaxf(float(fma(te, cu ? cwe : cue, cu ? cw0 : cu0)), -1.f), float(n)));
-        const int cur = cu ? iw : iu, b0 = cu ? bw0 : bu0;
-        const bool pos = cu ? pw : pu;
-        const int lo = pos ? cur : b0, hi = pos ? b0 + s - 1 : cur;
-        const int oth = imin(imax(o, lo), hi);
-        const int nu = pu ? bu0 + s : bu0 - 1, nw = pw ? bw0 + s : bw0 - 1;
-        const int niu = cu ? nu : oth, niw = cu ? oth : nw;
-        const bool go = te < t_out && (unsigned)niu < (unsigned)n && (unsigned)niw < (unsigned)n;
-        Leaf<T> nrec = rec;
-        if (go) nrec = base[niu * n + niw];
+        const int ou = imin(imax(int(fma(te, cue, cu0)), iu), eu_ - 1);
+        const int ow = imin(imax(int(fma(te, cwe, cw0)), iw), ew_ - 1);
+        const int niu = cu ? eu_ : ou, niw = cu ? ow : ew_;
+        const bool go = te < t_out && niu < n && niw < n;
+        const Leaf<T> nrec = base[idx(niu, niw)];
         acc += (te - t) * R(rec.mu());
         if (!go) break;
         t = te; iu = niu; iw = niw; rec = nrec;
