@@ -443,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
       // the minor axis w) and minor axis w: the record of pixel (u, w) is base[u n + w].
       // The walk runs in a frame mirrored per axis so that both coordinates grow along the
       // ray (leaf boundaries stay aligned since 2^l divides n): pixel coordinate c0 + t ce,
-      // plane k crossed at t = t0 + k dt, real index = m + sg * mirrored index.
+      // plane k crossed at t = t0 + k dt.
       const bool xmaj = fabs(ex) >= fabs(ey);
       const Leaf<T>* __restrict__ base = xmaj ? leafC : leafR;
       const R eu = xmaj ? ex : ey, ew = xmaj ? ey : ex;
@@ -453,9 +453,12 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
       const R cue = fabs(eu) * ipix, cwe = fabs(ew) * ipix;
       const R dtu = fabs(ieu) * pix, dtw = fabs(iew) * pix;
       const R tu0 = -cu0 * dtu, tw0 = -cw0 * dtw;
-      const int mu = eu < R(0) ? n - 1 : 0, su = eu < R(0) ? -1 : 1;
-      const int mw = ew < R(0) ? n - 1 : 0, sw = ew < R(0) ? -1 : 1;
-      auto idx = [&](int u, int w) { return (mu + su * imin(u, n - 1)) * n + (mw + sw * imin(w, n - 1)); };
+      // real index = (mirrored ^ x) + a: (x, a) = (0, 0), or (-1, n) for n - 1 - mirrored
+      const int xu = eu < R(0) ? -1 : 0, au = eu < R(0) ? n : 0;
+      const int xw = ew < R(0) ? -1 : 0, aw = ew < R(0) ? n : 0;
+      auto idx = [&](int u, int w) {
+        return __umul24(unsigned((imin(u, n - 1) ^ xu) + au), unsigned(n)) + unsigned((imin(w, n - 1) ^ xw) + aw);
+      };
       int iu = imin(imax(int(fma(t_s, cue, cu0)), 0), n - 1);
       int iw = imin(imax(int(fma(t_s, cwe, cw0)), 0), n - 1);
       Leaf<T> rec = base[idx(iu, iw)];

@@ -276,10 +276,11 @@ struct Walker3 {
   double x0, y0, z0;   // mirrored voxel coordinates of the ray at t = 0
   double ux, uy, uz;   // voxels per unit t along each axis
   double kx, ky, kz;   // t per voxel along each axis
+  double cx, cy, cz;   // t at mirrored coordinate 0
   double t, t_out;
   int x, y, z;         // current voxel, mirrored frame
-  int mx, my, mz;      // real index = m + s * mirrored index
-  int sx, sy, sz;
+  int xx, xy, xz;      // real index = (mirrored ^ x) + a: (0, 0), or (-1, size) for size - 1 - mirrored
+  int ax, ay, az;
   int n, nz;
 
   __device__ bool init(const DevGeom3& g, double ox, double oy, double oz, double iex, double iey, double iez,
@@ -292,10 +293,11 @@ struct Walker3 {
     z0 = ez < 0.0 ? double(nz) - Z : Z;
     ux = fabs(ex) * ipix; uy = fabs(ey) * ipix; uz = fabs(ez) * ipix;
     kx = fabs(iex) * g.pixel; ky = fabs(iey) * g.pixel; kz = fabs(iez) * g.pixel;
-    mx = ex < 0.0 ? n - 1 : 0;  sx = ex < 0.0 ? -1 : 1;
-    my = ey < 0.0 ? n - 1 : 0;  sy = ey < 0.0 ? -1 : 1;
-    mz = ez < 0.0 ? nz - 1 : 0; sz = ez < 0.0 ? -1 : 1;
-    const double t_in = fmax(fmax(-x0 * kx, -y0 * ky), -z0 * kz);
+    xx = ex < 0.0 ? -1 : 0; ax = ex < 0.0 ? n : 0;
+    xy = ey < 0.0 ? -1 : 0; ay = ey < 0.0 ? n : 0;
+    xz = ez < 0.0 ? -1 : 0; az = ez < 0.0 ? nz : 0;
+    cx = -x0 * kx; cy = -y0 * ky; cz = -z0 * kz;
+    const double t_in = fmax(fmax(cx, cy), cz);
     t_out = fmin(fmin((double(n) - x0) * kx, (double(n) - y0) * ky), (double(nz) - z0) * kz);
     if (!(t_out > t_in)) return false;
     t = t_in;
@@ -304,15 +306,18 @@ struct Walker3 {
     z = min(max(int(fma(t_in, uz, z0)), 0), nz - 1);
     return true;
   }
-  __device__ int rx() const { return mx + sx * x; }
-  __device__ int ry() const { return my + sy * y; }
-  __device__ int rz() const { return mz + sz * z; }
+  __device__ int real_x(int m) const { return (m ^ xx) + ax; }
+  __device__ int real_y(int m) const { return (m ^ xy) + ay; }
+  __device__ int real_z(int m) const { return (m ^ xz) + az; }
+  __device__ int rx() const { return real_x(x); }
+  __device__ int ry() const { return real_y(y); }
+  __device__ int rz() const { return real_z(z); }
   // Leaves the current leaf (level l): chord = parameter length inside it; returns whether the
   // walk goes on (then x, y, z is a voxel of the next leaf; else possibly out of range).
   __device__ bool step(int l, double& chord) {
     const int s = 1 << l;
     const int ex_ = (x & -s) + s, ey_ = (y & -s) + s, ez_ = (z & -s) + s;
-    const double tX = (double(ex_) - x0) * kx, tY = (double(ey_) - y0) * ky, tZ = (double(ez_) - z0) * kz;
+    const double tX = fma(double(ex_), kx, cx), tY = fma(double(ey_), ky, cy), tZ = fma(double(ez_), kz, cz);
     const bool ax0 = tX <= tY && tX <= tZ;
     const bool ax1 = !ax0 && tY <= tZ;
     const double te = fmax(fmin(fmin(tX, fmin(tY, tZ)), t_out), t);
@@ -352,9 +357,9 @@ __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, const double4* __re
       const Rec3<T>* __restrict__ base = xmaj ? recC : recR;
       // [z][x][y] or [z][y][x] address of the mirrored voxel (x, y, z), clamped into range
       auto addr = [&](int x, int y, int z) {
-        const int rx = w.mx + w.sx * min(x, n - 1), ry = w.my + w.sy * min(y, n - 1);
-        const int rz = w.mz + w.sz * min(z, g.nz - 1);
-        return xmaj ? (rz * n + rx) * n + ry : (rz * n + ry) * n + rx;
+        const unsigned rx = w.real_x(min(x, n - 1)), ry = w.real_y(min(y, n - 1)), rz = w.real_z(min(z, g.nz - 1));
+        const unsigned nn = unsigned(n);
+        return xmaj ? __umul24(__umul24(rz, nn) + rx, nn) + ry : __umul24(__umul24(rz, nn) + ry, nn) + rx;
       };
       Rec3<T> rec = base[addr(w.x, w.y, w.z)];
       for (int step = 0; step < 4 * (2 * n + g.nz) + 8; ++step) {
@@ -771,7 +776,7 @@ __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, const double4* __restric
       const int n = g.n;
       for (int step = 0; step < 4 * (2 * n + g.nz) + 8; ++step) {
         const int ix = w.rx(), iy = w.ry(), iz = w.rz();
-        const int l = LT > 0 ? int(lev[(iz * n + iy) * n + ix]) : 0;
+        const int l = LT > 0 ? int(lev[__umul24(__umul24(unsigned(iz), unsigned(n)) + iy, unsigned(n)) + ix]) : 0;
         double chord;
         const bool go = w.step(l, chord);
         z.visit(ix, iy, iz, l, chord);
