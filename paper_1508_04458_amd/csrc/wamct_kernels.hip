@@ -1220,10 +1220,12 @@ template <typename T, typename R>
 int Geo<T, R>::forward_records(const DevGeom& g, const void* A, const void* B, const void* leafR, const void* leafC,
                                const T* d, const T* i0v, const double* i0s, T* q, T* p, double* part, int S,
                                hipStream_t s) {
-  // rays per lane group: a launch with fewer rays than ~2^19 (the GPU holds 2^19 lanes at
-  // 8 waves per SIMD) splits each ray over 2 or 4 lanes
+  // rays per lane group: a launch with fewer than 2^21 rays splits each ray over 2 lanes,
+  // one with fewer than 2^17 over 4 (the GPU holds 2^19 lanes at 8 waves per SIMD; two
+  // half-length walks per ray also hide more of the record-load latency, measured faster
+  // for the 737K rays of a 720 x 1024 scan)
   const int64_t rays = int64_t(g.nvs) * g.nb * S;
-  const int k = rays >= (int64_t(1) << 19) ? 1 : (rays >= (int64_t(1) << 17) ? 2 : 4);
+  const int k = rays >= (int64_t(1) << 21) ? 1 : (rays >= (int64_t(1) << 17) ? 2 : 4);
   const int nb = blocks_for(int64_t(g.nvs) * g.nb * k);
   auto a = (const typename V4<R>::t*)A;
   auto b = (const typename V4<R>::t*)B;
