@@ -224,7 +224,8 @@ wamct_status wamct_get_timing(wamct_ctx* ctx, double* ms, int64_t* launches);
 
 /* Tiling of the node-driven backprojection: a level segment whose items (over the whole
  * stack) number fewer than `lanes` has its views split into chunks so that about `lanes`
- * (item, view chunk) tasks run; 2^12 <= lanes <= 2^24, default 2^20. A larger value may
+ * (item, view chunk) tasks run; 2^12 <= lanes <= 2^24, default 2^20 (2^23 for the cone beam,
+ * whose 3-D update measured faster with more view chunks). A larger value may
  * reallocate the context's partial-sum buffer (synchronizes). Results do not depend on the
  * tiling beyond floating-point summation order. */
 wamct_status wamct_set_tiling(wamct_ctx* ctx, int32_t lanes);

@@ -18,6 +18,16 @@ namespace {
 constexpr int kB = 256;
 inline int blocks3(int64_t n, int b = kB) { return int((n + b - 1) / b); }
 
+// Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b mod 8), each XCD with
+// its own L2. The one-lane-per-item gather maps block b of a padded grid to the work unit
+// (b mod 8) (grid / 8) + b / 8, so every XCD takes one contiguous range of items (a compact
+// region of the volume, whose rays it then finds in its L2). The leaf walks and the
+// view-chunked gather keep the round-robin order: there every XCD works on the same views at
+// the same time, which shares the last-level cache and balances the load.
+constexpr int kXcd3 = 8;
+__device__ inline int xcd_unit3(int b, int grid) { return (b % kXcd3) * (grid / kXcd3) + b / kXcd3; }
+inline int xcd_pad3(int units) { return (units + kXcd3 - 1) / kXcd3 * kXcd3; }
+
 __device__ inline int imin3(int a, int b) { return a < b ? a : b; }
 __device__ inline int imax3(int a, int b) { return a > b ? a : b; }
 
@@ -343,7 +353,8 @@ __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, const double4* __re
                                                  const T* __restrict__ d, const T* __restrict__ i0v,
                                                  const double* __restrict__ i0s, T* __restrict__ q,
                                                  T* __restrict__ pout, double* __restrict__ part) {
-  const int64_t r = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int blk = blockIdx.x;
+  const int64_t r = int64_t(blk) * kB + threadIdx.x;
   const int64_t M = int64_t(g.nv) * g.nr * g.nc;
   double term = 0.0;
   if (r < M) {
@@ -383,7 +394,7 @@ __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, const double4* __re
   }
   if (part) {
     term = breduce<false>(term);
-    if (threadIdx.x == 0) part[blockIdx.x] = term;
+    if (threadIdx.x == 0 && int64_t(blk) * kB < M) part[blk] = term;
   }
 }
 
@@ -621,7 +632,7 @@ template <typename T, int MODE, bool SPLIT>
 __global__ __launch_bounds__(kB) void k3_gather(GArgs3<T> a) {
   int start, count;
   seg_range3(a, start, count);
-  const int it = blockIdx.x * kB + threadIdx.x;
+  const int it = xcd_unit3(blockIdx.x, gridDim.x) * kB + threadIdx.x;
   if (it >= count) return;
   const uint32_t w = item3_word(a.items, start + it, a.g.n);
   const Sums3<double> r = item_sums3<T, SPLIT>(a.g, a.views, a.colt, a.rowt, a.y, int((w >> 27) & 15u),
@@ -753,7 +764,8 @@ template <int LT>
 __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, const double4* __restrict__ A, const double4* __restrict__ B,
                                             const double* __restrict__ C, const uint8_t* __restrict__ lev,
                                             double* __restrict__ part_max, double* __restrict__ part_cnt) {
-  const int64_t r = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int blk = blockIdx.x;
+  const int64_t r = int64_t(blk) * kB + threadIdx.x;
   const int64_t M = int64_t(g.nv) * g.nr * g.nc;
   double sum = 0.0, cnt = 0.0;
   if (r < M) {
@@ -795,7 +807,7 @@ __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, const double4* __restric
   const double mx = breduce<true>(sum);
   __syncthreads();
   const double ct = breduce<false>(cnt);
-  if (threadIdx.x == 0) { part_max[blockIdx.x] = mx; part_cnt[blockIdx.x] = ct; }
+  if (threadIdx.x == 0 && int64_t(blk) * kB < M) { part_max[blk] = mx; part_cnt[blk] = ct; }
 }
 
 // ------------------------------------------------------------------ tree rule and work lists
@@ -911,7 +923,7 @@ void Geo3<T>::scale_rays(const DevGeom3& g, const T* y, const double* nrm, T* ou
 template <typename T, int MODE, bool SPLIT>
 static void gather_seg3(const GArgs3<T>& a, const Segment& sg, hipStream_t s) {
   if (sg.chunks <= 1) {
-    hipLaunchKernelGGL((k3_gather<T, MODE, SPLIT>), dim3(blocks3(sg.count)), dim3(kB), 0, s, a);
+    hipLaunchKernelGGL((k3_gather<T, MODE, SPLIT>), dim3(xcd_pad3(blocks3(sg.count))), dim3(kB), 0, s, a);
     return;
   }
   const int groups = (sg.chunks + 3) / 4;
