@@ -338,7 +338,7 @@ struct Ctx final : wamct_ctx {
       if (segment_part_elems(x, S) > part_cap)
         return fail(WAMCT_E_HIP, "internal: gather partial buffer too small for its tiling");
     const bool tree = &sg == &segs || &sg == &segs_sub;
-    Geo<T, R>::gather(v.g, mode, vT, A, y, tree ? items : nullptr, tree ? ints + 9 : nullptr, sg.data(),
+    Geo<T, R>::gather(v.g, mode, vT, views, A, y, tree ? items : nullptr, tree ? ints + 9 : nullptr, sg.data(),
                       int(sg.size()), part, bt, v.b, v.z0, v.z0stride, held, bp, bm, out, S, s);
     return WAMCT_OK;
   }

@@ -107,8 +107,8 @@ struct Geo {
   // node-driven backprojection of y over the segments of `items` (items null: every pixel
   // as a level-0 box), over the views of g's subset. counts: per-scan level counts (stride
   // kInts; null for fixed ranges); z0 per scan at stride z0stride, held at stride kInts;
-  // `part` holds segment_part_elems.
-  static void gather(const DevGeom& g, int mode, const void* vF, const void* A, const T* y,
+  // `part` holds segment_part_elems. views: (cos, sin) per view in FP64 (fan-beam source).
+  static void gather(const DevGeom& g, int mode, const void* vF, const double2* views, const void* A, const T* y,
                      const uint32_t* items, const int* counts, const Segment* segs, int n_segs, void* part,
                      T* beta, const T* b, const double* z0, int z0stride, int* held, T* bp, T* bm, T* out,
                      int S, hipStream_t s);

@@ -550,13 +550,15 @@ __device__ inline R am_delta(R b, R bp, R bm, R z0, int* held) {
 // (ray, coefficient), so b-hat+ and b-hat- need no atomics.
 template <typename R>
 struct ItemSums {
-  R acc, pos0, pos1, pos2, neg0, neg1, neg2;
+  R acc;             // plain sum (box chord)
+  R s0, s1, s2;      // per detail: signed sum
+  R a0, a1, a2;      // per detail: sum of magnitudes (positive part (a + s) / 2, negative (s - a) / 2)
 };
 
-template <typename T, typename R>
-__device__ inline ItemSums<R> item_sums(const DevGeom& g, const float2* __restrict__ vf,
-                                        const typename V4<R>::t* __restrict__ A, const T* __restrict__ y,
-                                        bool quad, int l, int i, int j, int v0, int v1) {
+template <typename T, typename R, bool FAN>
+__device__ inline ItemSums<R> item_sums_k(const DevGeom& g, const float2* __restrict__ vf,
+                                        const double2* __restrict__ views, const typename V4<R>::t* __restrict__ A,
+                                        const T* __restrict__ y, bool quad, int l, int i, int j, int v0, int v1) {
   const int n = g.n, s = 1 << l, nb = g.nb;
   const R pix = R(g.pixel), hn = R(0.5 * n);
   const R X0 = (R(j * s) - hn) * pix, X2 = (R((j + 1) * s) - hn) * pix;
@@ -571,7 +573,7 @@ __device__ inline ItemSums<R> item_sums(const DevGeom& g, const float2* __restri
     const float2 cs = vf[v];
     const float c = cs.x, sn = cs.y;
     float u00, u01, u10, u11;
-    if (g.kind == 0) {
+    if (!FAN) {
       u00 = fx0 * c + fy0 * sn; u01 = fx2 * c + fy0 * sn; u10 = fx0 * c + fy2 * sn; u11 = fx2 * c + fy2 * sn;
     } else {
       // hardware reciprocal (1 ulp): the bound is widened by 1e-3 bin anyway
@@ -589,17 +591,29 @@ __device__ inline ItemSums<R> item_sums(const DevGeom& g, const float2* __restri
     const int blo = max(int(ceilf(flo)), 0);
     const int bhi = min(int(floorf(fhi)), nb - 1);
     const int base = v * nb;
+    // Fan beam: every ray of the view passes through the source S = sod (c, s), so the
+    // parameters are measured from S (a plane x = X at (X - Sx) / ex) and the differences
+    // X - S are computed once per view; parallel beam: from each ray's own origin.
+    R sx = R(0), sy = R(0);
+    if (FAN) {
+      const double2 cv = views[v];
+      sx = R(g.sod * cv.x);
+      sy = R(g.sod * cv.y);
+    }
+    const R dx0 = X0 - sx, dx1 = X1 - sx, dx2 = X2 - sx, dy0 = Y0 - sy, dy1 = Y1 - sy, dy2 = Y2 - sy;
     for (int bb = blo; bb <= bhi; ++bb) {
       const typename V4<R>::t a = A[base + bb];
       const R yv = R(y[base + bb]);
-      const R tx0 = (X0 - a.x) * a.z, tx2 = (X2 - a.x) * a.z;
-      const R ty0 = (Y0 - a.y) * a.w, ty2 = (Y2 - a.y) * a.w;
+      // origin offset: 0 for the fan beam (parameters from S), the ray's origin otherwise
+      const R ox = FAN ? R(0) : a.x, oy = FAN ? R(0) : a.y;
+      const R tx0 = (dx0 - ox) * a.z, tx2 = (dx2 - ox) * a.z;
+      const R ty0 = (dy0 - oy) * a.w, ty2 = (dy2 - oy) * a.w;
       if (!quad) {
         const R lo = fmax(fmin(tx0, tx2), fmin(ty0, ty2));
         const R hi = fmin(fmax(tx0, tx2), fmax(ty0, ty2));
         r.acc += yv * fmax(hi - lo, R(0));
       } else {
-        const R tx1 = (X1 - a.x) * a.z, ty1 = (Y1 - a.y) * a.w;
+        const R tx1 = (dx1 - ox) * a.z, ty1 = (dy1 - oy) * a.w;
         const R xl0 = fmin(tx0, tx1), xh0 = fmax(tx0, tx1), xl1 = fmin(tx1, tx2), xh1 = fmax(tx1, tx2);
         const R yl0 = fmin(ty0, ty1), yh0 = fmax(ty0, ty1), yl1 = fmin(ty1, ty2), yh1 = fmax(ty1, ty2);
         const R cTL = fmax(fmin(xh0, yh0) - fmax(xl0, yl0), R(0));
@@ -609,13 +623,21 @@ __device__ inline ItemSums<R> item_sums(const DevGeom& g, const float2* __restri
         const R u1 = cTL - cTR, u2 = cBL - cBR, w1v = cTL + cTR, w2v = cBL + cBR;
         const R w1 = yv * (u1 + u2), w2 = yv * (w1v - w2v), w3 = yv * (u1 - u2);
         r.acc += yv * (w1v + w2v);
-        r.pos0 += fmax(w1, R(0)); r.neg0 += fmin(w1, R(0));
-        r.pos1 += fmax(w2, R(0)); r.neg1 += fmin(w2, R(0));
-        r.pos2 += fmax(w3, R(0)); r.neg2 += fmin(w3, R(0));
+        r.s0 += w1; r.a0 += fabs(w1);
+        r.s1 += w2; r.a1 += fabs(w2);
+        r.s2 += w3; r.a2 += fabs(w3);
       }
     }
   }
   return r;
+}
+
+template <typename T, typename R>
+__device__ inline ItemSums<R> item_sums(const DevGeom& g, const float2* __restrict__ vf,
+                                        const double2* __restrict__ views, const typename V4<R>::t* __restrict__ A,
+                                        const T* __restrict__ y, bool quad, int l, int i, int j, int v0, int v1) {
+  if (g.kind != 0) return item_sums_k<T, R, true>(g, vf, views, A, y, quad, l, i, j, v0, v1);
+  return item_sums_k<T, R, false>(g, vf, views, A, y, quad, l, i, j, v0, v1);
 }
 
 __device__ inline uint32_t item_word(const uint32_t* __restrict__ items, int it, int n) {
@@ -646,12 +668,13 @@ __device__ inline void item_finish(const DevGeom& g, uint32_t w, const ItemSums<
       bm_out[i * n + j] = T(0);
     }
     if (quad) {
-      bp_out[i * n + m + j] = T(r.pos0 * sc);
-      bm_out[i * n + m + j] = T(r.neg0 * sc);
-      bp_out[(m + i) * n + j] = T(r.pos1 * sc);
-      bm_out[(m + i) * n + j] = T(r.neg1 * sc);
-      bp_out[(m + i) * n + m + j] = T(r.pos2 * sc);
-      bm_out[(m + i) * n + m + j] = T(r.neg2 * sc);
+      const R h = R(0.5) * sc;
+      bp_out[i * n + m + j] = T((r.a0 + r.s0) * h);
+      bm_out[i * n + m + j] = T((r.s0 - r.a0) * h);
+      bp_out[(m + i) * n + j] = T((r.a1 + r.s1) * h);
+      bm_out[(m + i) * n + j] = T((r.s1 - r.a1) * h);
+      bp_out[(m + i) * n + m + j] = T((r.a2 + r.s2) * h);
+      bm_out[(m + i) * n + m + j] = T((r.s2 - r.a2) * h);
     }
     return;
   }
@@ -662,9 +685,10 @@ __device__ inline void item_finish(const DevGeom& g, uint32_t w, const ItemSums<
   }
   if (quad) {
     const int z1 = i * n + m + j, z2 = (m + i) * n + j, z3 = (m + i) * n + m + j;
-    beta[z1] = T(R(beta[z1]) + am_delta<R>(R(bvec[z1]), r.pos0 * sc, r.neg0 * sc, z0, held));
-    beta[z2] = T(R(beta[z2]) + am_delta<R>(R(bvec[z2]), r.pos1 * sc, r.neg1 * sc, z0, held));
-    beta[z3] = T(R(beta[z3]) + am_delta<R>(R(bvec[z3]), r.pos2 * sc, r.neg2 * sc, z0, held));
+    const R h = R(0.5) * sc;
+    beta[z1] = T(R(beta[z1]) + am_delta<R>(R(bvec[z1]), (r.a0 + r.s0) * h, (r.s0 - r.a0) * h, z0, held));
+    beta[z2] = T(R(beta[z2]) + am_delta<R>(R(bvec[z2]), (r.a1 + r.s1) * h, (r.s1 - r.a1) * h, z0, held));
+    beta[z3] = T(R(beta[z3]) + am_delta<R>(R(bvec[z3]), (r.a2 + r.s2) * h, (r.s2 - r.a2) * h, z0, held));
   }
 }
 
@@ -678,6 +702,7 @@ template <typename T, typename R>
 struct GatherArgs {
   DevGeom g;
   const float2* vf;
+  const double2* views;
   const typename V4<R>::t* A;
   const T* y;
   const uint32_t* items;
@@ -750,7 +775,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs<T, R> a) {
   const int k = blk * kBlock + threadIdx.x;
   if (k >= v.count) return;
   const uint32_t w = item_word(v.items, v.start + k, a.g.n);
-  const ItemSums<R> r = item_sums<T, R>(a.g, a.vf, a.A, v.y, (w >> 31) != 0, int((w >> 27) & 15u),
+  const ItemSums<R> r = item_sums<T, R>(a.g, a.vf, a.views, a.A, v.y, (w >> 31) != 0, int((w >> 27) & 15u),
                                         int((w >> 13) & 0x1fffu), int(w & 0x1fffu), 0, a.g.nvs);
   item_finish<T, R, MODE>(a.g, w, r, v.beta, v.b, v.z0, v.held, v.bp, v.bm, v.out);
 }
@@ -778,12 +803,12 @@ __global__ __launch_bounds__(64 * kChunkWaves) void k_gather_part(GatherArgs<T, 
   if (idx < v.count && chunk < a.chunks) {
     const uint32_t w = item_word(v.items, v.start + idx, a.g.n);
     const int v0 = chunk * a.vpc, v1 = min(a.g.nvs, v0 + a.vpc);
-    r = item_sums<T, R>(a.g, a.vf, a.A, v.y, (w >> 31) != 0, int((w >> 27) & 15u), int((w >> 13) & 0x1fffu),
+    r = item_sums<T, R>(a.g, a.vf, a.views, a.A, v.y, (w >> 31) != 0, int((w >> 27) & 15u), int((w >> 13) & 0x1fffu),
                         int(w & 0x1fffu), v0, v1);
   }
   sh[wv][0][lane] = r.acc;
-  sh[wv][1][lane] = r.pos0; sh[wv][2][lane] = r.pos1; sh[wv][3][lane] = r.pos2;
-  sh[wv][4][lane] = r.neg0; sh[wv][5][lane] = r.neg1; sh[wv][6][lane] = r.neg2;
+  sh[wv][1][lane] = r.s0; sh[wv][2][lane] = r.s1; sh[wv][3][lane] = r.s2;
+  sh[wv][4][lane] = r.a0; sh[wv][5][lane] = r.a1; sh[wv][6][lane] = r.a2;
   __syncthreads();
   for (int k = threadIdx.x; k < 7 * 64; k += 64 * kChunkWaves) {
     const int slot = k / 64, l2 = k % 64;
@@ -1074,21 +1099,21 @@ __global__ __launch_bounds__(1024) void k_items(DevGeom g, const uint8_t* __rest
     int pw = 1;
     while (pw < m) pw <<= 1;
     const int64_t total = int64_t(pw) * pw;
-    for (int64_t base = 0; base < total; base += 1024) {
-      const int64_t kk = base + threadIdx.x;
+    // the roots' segment lists the split roots first, then the others (waves of one kind)
+    const int passes = (l == L && L > 0) ? 2 : 1;
+    for (int64_t base = 0; base < passes * total; base += 1024) {
+      const int64_t code = base + threadIdx.x;
+      const int pass = int(code / total);
+      const int64_t kk = code - pass * total;
       bool inc = false;
       uint32_t word = 0;
-      if (kk < total) {
+      if (pass < passes) {
         const int j = int(morton_compact(uint32_t(kk)));
         const int i = int(morton_compact(uint32_t(kk >> 1)));
         if (i < m && j < m) {
-          if (l == L) {
-            inc = true;
-            word = item_pack((L > 0 && is_split(mask, n, L, i, j)) ? 1 : 0, l, i, j);
-          } else if (is_split(mask, n, l, i, j)) {
-            inc = true;
-            word = item_pack(1, l, i, j);
-          }
+          const bool sp = l > 0 && is_split(mask, n, l, i, j);
+          inc = l == L ? (passes == 1 || (pass == 0) == sp) : sp;
+          word = item_pack(sp ? 1 : 0, l, i, j);
         }
       }
       const uint64_t bal = __ballot(inc);
@@ -1255,13 +1280,14 @@ void launch_segment(const GatherArgs<T, R>& a, int S, hipStream_t s) {
 }  // namespace
 
 template <typename T, typename R>
-void Geo<T, R>::gather(const DevGeom& g, int mode, const void* vF, const void* A, const T* y,
+void Geo<T, R>::gather(const DevGeom& g, int mode, const void* vF, const double2* views, const void* A, const T* y,
                        const uint32_t* items, const int* counts, const Segment* segs, int n_segs, void* part,
                        T* beta, const T* b, const double* z0, int z0stride, int* held, T* bp, T* bm, T* out,
                        int S, hipStream_t s) {
   GatherArgs<T, R> a;
   a.g = g;
   a.vf = (const float2*)vF;
+  a.views = views;
   a.A = (const typename V4<R>::t*)A;
   a.y = y;
   a.items = items;
