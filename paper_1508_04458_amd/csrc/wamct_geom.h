@@ -46,55 +46,48 @@ __host__ __device__ inline void ray_of(const DevGeom& g, double2 cs, int b, doub
 }
 
 // Walk one ray through the leaves of the tree (or through pixels when !TREE) and call
-// f(ix, iy, level, chord) for every leaf it crosses, in order. The current position is a
-// pixel (ix, iy) inside the current leaf; the exit parameter of the leaf is the nearer of
-// its two exit planes, and the next pixel is the neighbour across that plane (its other
-// coordinate clamped into the leaf's range, which keeps the walk monotone even when
-// rounding puts the exit point on a corner). Every step moves to a new leaf, so at most
-// 2n steps occur; the loop bound 4n + 8 only guards against malformed input.
+// f(ix, iy, level, chord) for every leaf it crosses, in order. The walk runs in a frame
+// mirrored per axis so that both coordinates grow along the ray (leaf boundaries stay aligned
+// because 2^L divides n): the current position is a pixel inside the current leaf; the exit
+// parameter of the leaf is the nearer of its two upper planes, and the next pixel is the
+// neighbour across that plane, its other coordinate taken at the exit point and clamped into
+// the leaf's range (monotone even when rounding puts the exit point on a corner). Every step
+// moves to a new leaf, so at most 2n steps occur; the loop bound 4n + 8 only guards against
+// malformed input.
 template <typename R, bool TREE, typename F>
 __host__ __device__ inline void walk(const DevGeom& g, R ox, R oy, R ex, R ey, R iex, R iey,
                             const uint8_t* lev, F& f) {
   const int n = g.n;
-  const R pix = R(g.pixel), ipix = R(1.0 / g.pixel), hn = R(0.5 * n), half = R(0.5 * n * g.pixel);
-  const R tx0 = (-half - ox) * iex, tx1 = (half - ox) * iex;
-  const R ty0 = (-half - oy) * iey, ty1 = (half - oy) * iey;
-  const R t_in = fmax(fmin(tx0, tx1), fmin(ty0, ty1));
-  const R t_out = fmin(fmax(tx0, tx1), fmax(ty0, ty1));
+  const R ipix = R(1.0 / g.pixel), hn = R(0.5 * n);
+  const R X = ox * ipix + hn, Y = oy * ipix + hn;                 // pixel coordinates at t = 0
+  const R x0 = ex < R(0) ? R(n) - X : X, y0 = ey < R(0) ? R(n) - Y : Y;
+  const R ux = fabs(ex) * ipix, uy = fabs(ey) * ipix;             // pixels per unit t
+  const R kx = fabs(iex) * R(g.pixel), ky = fabs(iey) * R(g.pixel);   // t per pixel
+  const R cx = -x0 * kx, cy = -y0 * ky;                           // t at mirrored coordinate 0
+  // real index = (mirrored ^ m) + a: (m, a) = (0, 0), or (-1, n) for n - 1 - mirrored
+  const int mx = ex < R(0) ? -1 : 0, ax = ex < R(0) ? n : 0;
+  const int my = ey < R(0) ? -1 : 0, ay = ey < R(0) ? n : 0;
+  const R t_in = fmax(cx, cy);
+  const R t_out = fmin(fma(R(n), kx, cx), fma(R(n), ky, cy));
   if (!(t_out > t_in)) return;
-  int ix = (int)floor(fmin(fmax((ox + t_in * ex) * ipix + hn, R(-1)), R(n)));
-  int iy = (int)floor(fmin(fmax((oy + t_in * ey) * ipix + hn, R(-1)), R(n)));
-  ix = imin(imax(ix, 0), n - 1);
-  iy = imin(imax(iy, 0), n - 1);
-  const bool px = ex > R(0), py = ey > R(0);
+  int x = imin(imax(int(fma(t_in, ux, x0)), 0), n - 1);
+  int y = imin(imax(int(fma(t_in, uy, y0)), 0), n - 1);
   R t = t_in;
   for (int step = 0; step < 4 * n + 8; ++step) {
-    const int l = TREE ? int(lev[iy * n + ix]) : 0;
+    const int rx = (x ^ mx) + ax, ry = (y ^ my) + ay;
+    const int l = TREE ? int(lev[ry * n + rx]) : 0;
     const int s = 1 << l;
-    const int bx0 = (ix >> l) << l, by0 = (iy >> l) << l;
-    const int X = px ? bx0 + s : bx0;
-    const int Y = py ? by0 + s : by0;
-    const R tX = ((R(X) - hn) * pix - ox) * iex;
-    const R tY = ((R(Y) - hn) * pix - oy) * iey;
-    R te = fmin(fmin(tX, tY), t_out);
-    te = fmax(te, t);
-    f(ix, iy, l, te - t);
+    const int ex_ = (x & -s) + s, ey_ = (y & -s) + s;
+    const R tX = fma(R(ex_), kx, cx), tY = fma(R(ey_), ky, cy);
+    const bool cross_x = tX <= tY;
+    const R te = fmax(fmin(fmin(tX, tY), t_out), t);
+    f(rx, ry, l, te - t);
     if (te >= t_out) break;
-    // the other coordinate never moves backwards (monotone walk) and stays in the leaf
-    if (tX <= tY) {
-      ix = px ? bx0 + s : bx0 - 1;
-      if (TREE) {
-        const int rr = (int)floor(fmin(fmax((oy + te * ey) * ipix + hn, R(-1)), R(n)));
-        iy = py ? imin(imax(rr, iy), by0 + s - 1) : imax(imin(rr, iy), by0);
-      }
-    } else {
-      iy = py ? by0 + s : by0 - 1;
-      if (TREE) {
-        const int cc = (int)floor(fmin(fmax((ox + te * ex) * ipix + hn, R(-1)), R(n)));
-        ix = px ? imin(imax(cc, ix), bx0 + s - 1) : imax(imin(cc, ix), bx0);
-      }
-    }
-    if ((unsigned)ix >= (unsigned)n || (unsigned)iy >= (unsigned)n) break;
+    const int xo = imin(imax(int(fma(te, ux, x0)), x), ex_ - 1);
+    const int yo = imin(imax(int(fma(te, uy, y0)), y), ey_ - 1);
+    x = cross_x ? ex_ : xo;
+    y = cross_x ? yo : ey_;
+    if (x >= n || y >= n) break;
     t = te;
   }
 }

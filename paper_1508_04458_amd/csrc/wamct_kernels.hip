@@ -919,28 +919,31 @@ __global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ x, int64_t len,
 // the approximation accumulator of its root. When the ray leaves a node, its |phi| =
 // 2^-m |acc_k| are added to the ray's sum and the non-zero ones counted. Z0 is the
 // maximum of the sums over rays; W the total count.
+__device__ inline double flip_sign(double v, int neg) {
+  return __longlong_as_double(__double_as_longlong(v) ^ (static_cast<long long>(neg) << 63));
+}
+
 template <int LT>
 struct Z0Visitor {
-  double tol;
+  double tolm[LT + 1];    // count threshold per level, unscaled (index 0: root approximations)
+  double tot[LT + 1];     // per level: sum of |detail sums| over the nodes left so far
   double acc[LT + 1][3];
   int cur[LT + 1];
   double accLL;
   int curLL;
-  double sum, cnt;
+  double cnt;
   __device__ inline void flush_level(int m) {
-    const double sc = 1.0 / double(1 << m);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double a = fabs(acc[m][k]) * sc;
-      sum += a;
-      cnt += (a > tol) ? 1.0 : 0.0;
+      const double a = fabs(acc[m][k]);
+      tot[m] += a;
+      cnt += (a > tolm[m]) ? 1.0 : 0.0;
       acc[m][k] = 0.0;
     }
   }
   __device__ inline void flush_ll() {
-    const double a = fabs(accLL) / double(1 << LT);
-    sum += a;
-    cnt += (a > tol) ? 1.0 : 0.0;
+    tot[0] += accLL;
+    cnt += (accLL > tolm[0]) ? 1.0 : 0.0;
     accLL = 0.0;
   }
   __device__ inline void operator()(int ix, int iy, int l, double chord) {
@@ -952,10 +955,11 @@ struct Z0Visitor {
         cur[m] = node;
       }
       if (m > l) {
-        const bool right = (ix >> (m - 1)) & 1, bottom = (iy >> (m - 1)) & 1;
-        acc[m][0] += right ? -chord : chord;
-        acc[m][1] += bottom ? -chord : chord;
-        acc[m][2] += (right != bottom) ? -chord : chord;
+        const int right = (ix >> (m - 1)) & 1, bottom = (iy >> (m - 1)) & 1;
+        const double cr = flip_sign(chord, right);
+        acc[m][0] += cr;
+        acc[m][1] += flip_sign(chord, bottom);
+        acc[m][2] += flip_sign(cr, bottom);
       }
     }
     const int root = ((iy >> LT) << 16) | (ix >> LT);
@@ -981,19 +985,27 @@ __global__ __launch_bounds__(kBlock) void k_z0(DevGeom g, const double2* __restr
     double ox, oy, ex, ey;
     ray_of(g, views[v], b, ox, oy, ex, ey);
     Z0Visitor<LT> z;
-    z.tol = 1e-9 * g.pixel;
+    const double tol = 1e-9 * g.pixel;
+    z.tolm[0] = tol * double(1 << LT);
+    z.tot[0] = 0.0;
 #pragma unroll
-    for (int m = 0; m <= LT; ++m) {
+    for (int m = 1; m <= LT; ++m) {
+      z.tolm[m] = tol * double(1 << m);
+      z.tot[m] = 0.0;
       z.cur[m] = -1;
       z.acc[m][0] = z.acc[m][1] = z.acc[m][2] = 0.0;
     }
-    z.accLL = 0.0; z.curLL = -1; z.sum = 0.0; z.cnt = 0.0;
+    z.accLL = 0.0; z.curLL = -1; z.cnt = 0.0;
     walk<double, (LT > 0)>(g, ox, oy, ex, ey, 1.0 / ex, 1.0 / ey, lev, z);
 #pragma unroll
     for (int m = 1; m <= LT; ++m)
       if (z.cur[m] >= 0) z.flush_level(m);
     if (z.curLL >= 0) z.flush_ll();
-    sum = z.sum; cnt = z.cnt;
+    // phi of a level-m detail is 2^-m x its signed chord sum, of a root 2^-L x its chord
+    sum = z.tot[0] / double(1 << LT);
+#pragma unroll
+    for (int m = 1; m <= LT; ++m) sum += z.tot[m] / double(1 << m);
+    cnt = z.cnt;
   }
   const double mx = block_reduce<true>(sum);
   __syncthreads();
