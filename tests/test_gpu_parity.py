@@ -362,3 +362,30 @@ def test_forward_tree_large_non_power_of_two_image():
     p = -np.log(host(q) / 100.0)
     # q is stored in FP32: compare p through q with the FP32 storage error of q added
     assert np.all(np.abs(p - p_ref) <= proj_tol(p_ref, "f32") + 2e-7), np.abs(p - p_ref).max()
+
+
+def test_fp32_ray_geometry_matches_oracle():
+    """The FP32 ray-geometry build (wamct_options.geometry = F32). Ray parameters reach the
+    image half-diagonal (~90 mm for fan128), so FP32 rounding puts ~5e-6 mm on every plane
+    parameter: an absolute error per chord, at most ~2n crossings x 5e-6 mm x max mu (0.2)
+    ~ 2.6e-4 per ray, so projections are held to 5e-5 x max p (~3e-4) in absolute terms;
+    after 8 iterations beta and the I-divergence meet the FP32-data bars (relative L2 1e-4,
+    rtol 2e-5): the chord errors are far below the FP32 storage of q-hat and beta."""
+    from paper_1508_04458_amd import api
+    P, H = problem("fan128")
+    g = P.geom
+    print(f"\n[case] fan128 FP32 ray geometry", flush=True)
+    c = api.Context(g, 0, "f32", geometry="f32")
+    img = synth.rasterize(P.ellipses, g.n, g.pixel)
+    p = host(c.project(dev(img.ravel(), "f32")))
+    ref = H @ img.ravel()
+    assert np.abs(p - ref).max() <= 5e-5 * np.abs(ref).max()
+    c2 = api.Context(g, P.levels, "f32", geometry="f32")
+    c2.set_data(dev(P.d, "f32"), P.i0)
+    J = 8
+    idv = host(c2.solve(J))
+    ref = wam.wam_solve(H, g.n, P.levels, P.d, P.i0, J, g.pixel)
+    err = rel_l2(host(c2.get_state()[0]), ref["beta"])
+    print(f"beta rel L2 {err:.2e}, idiv max rel {np.max(np.abs(idv / ref['idiv'] - 1)):.2e}", flush=True)
+    assert err <= 1e-4
+    np.testing.assert_allclose(idv, ref["idiv"], rtol=2e-5)
