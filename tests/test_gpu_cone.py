@@ -105,6 +105,26 @@ def test_cone64_project_sampled_views():
     assert np.all(np.abs(p - ref) <= proj_tol(ref, "f32")), np.abs(p - ref).max()
 
 
+def test_cone_ragged_detector():
+    """A 6 x 70 detector (neither a multiple of a wave nor of a block of rays): projection,
+    Z0 and W against the oracle."""
+    g = synth.cone_geometry(16, 8, 7, 6, 70, sod=60.0, sdd=100.0)
+    H = vol3d.system_matrix3(g)
+    c = make_ctx(g, 0, "f64")
+    vol = random_volume(g, 6)
+    p = host(c.project(dev(vol.ravel(), "f64")))
+    ref = H @ vol.ravel()
+    assert np.all(np.abs(p - ref) <= proj_tol(ref, "f64")), np.abs(p - ref).max()
+    L = 2
+    c2 = make_ctx(g, L, "f64")
+    mask = random_octree_mask(g.n, g.nz, L, 12, 0.6)
+    c2.set_state(dev(np.zeros(g.n_voxels), "f64"), dev(mask.ravel(), torch.uint8))
+    st = c2.tree_stats()
+    Phi, act = wam.phi_matrix(H, vol3d.synthesis_matrix3(g.n, g.nz, L), mask, g.pixel)
+    assert abs(st["z0"] - wam.z0_of(Phi)) <= 1e-11 * st["z0"]
+    assert abs(st["w"] - Phi.nnz) <= 1e-4 * Phi.nnz
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_cone_backproject_matches_oracle(dtype):
     P, H = problem("cone32")
