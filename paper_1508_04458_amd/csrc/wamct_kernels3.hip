@@ -25,6 +25,17 @@ inline int blocks3(int64_t n, int b = kB) { return int((n + b - 1) / b); }
 // view-chunked gather keep the round-robin order: there every XCD works on the same views at
 // the same time, which shares the last-level cache and balances the load.
 constexpr int kXcd3 = 8;
+
+// Ray of launch index k in the walks: k runs over (detector row, view, column), so the rays
+// in flight at any time belong to one detector row of many views and traverse one band of
+// z-slabs (a fraction of the volume) rather than the whole volume of one view.
+__device__ inline int64_t row_major_ray(const DevGeom3& g, int64_t k) {
+  const int64_t per_row = int64_t(g.nv) * g.nc;
+  const int row = int(k / per_row);
+  const int64_t rem = k - row * per_row;
+  const int v = int(rem / g.nc), col = int(rem - int64_t(v) * g.nc);
+  return (int64_t(v) * g.nr + row) * g.nc + col;
+}
 __device__ inline int xcd_unit3(int b, int grid) { return (b % kXcd3) * (grid / kXcd3) + b / kXcd3; }
 inline int xcd_pad3(int units) { return (units + kXcd3 - 1) / kXcd3 * kXcd3; }
 
@@ -354,10 +365,11 @@ __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, const double4* __re
                                                  const double* __restrict__ i0s, T* __restrict__ q,
                                                  T* __restrict__ pout, double* __restrict__ part) {
   const int blk = blockIdx.x;
-  const int64_t r = int64_t(blk) * kB + threadIdx.x;
+  const int64_t k = int64_t(blk) * kB + threadIdx.x;
   const int64_t M = int64_t(g.nv) * g.nr * g.nc;
   double term = 0.0;
-  if (r < M) {
+  if (k < M) {
+    const int64_t r = row_major_ray(g, k);
     const double4 a = A[r], b = B[r];
     const double ex = b.z, ey = b.w;
     Walker3 w;
@@ -394,7 +406,7 @@ __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, const double4* __re
   }
   if (part) {
     term = breduce<false>(term);
-    if (threadIdx.x == 0 && int64_t(blk) * kB < M) part[blk] = term;
+    if (threadIdx.x == 0) part[blk] = term;
   }
 }
 
@@ -765,10 +777,11 @@ __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, const double4* __restric
                                             const double* __restrict__ C, const uint8_t* __restrict__ lev,
                                             double* __restrict__ part_max, double* __restrict__ part_cnt) {
   const int blk = blockIdx.x;
-  const int64_t r = int64_t(blk) * kB + threadIdx.x;
+  const int64_t k = int64_t(blk) * kB + threadIdx.x;
   const int64_t M = int64_t(g.nv) * g.nr * g.nc;
   double sum = 0.0, cnt = 0.0;
-  if (r < M) {
+  if (k < M) {
+    const int64_t r = row_major_ray(g, k);
     const double4 a = A[r], b = B[r];
     Z0Vis3<LT> z;
     const double tol = 1e-9 * g.pixel;
@@ -807,7 +820,7 @@ __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, const double4* __restric
   const double mx = breduce<true>(sum);
   __syncthreads();
   const double ct = breduce<false>(cnt);
-  if (threadIdx.x == 0 && int64_t(blk) * kB < M) { part_max[blk] = mx; part_cnt[blk] = ct; }
+  if (threadIdx.x == 0) { part_max[blk] = mx; part_cnt[blk] = ct; }
 }
 
 // ------------------------------------------------------------------ tree rule and work lists
