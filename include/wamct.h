@@ -256,6 +256,20 @@ wamct_status wamct_get_subsets(wamct_ctx* ctx, int32_t* n_subsets);
 wamct_status wamct_set_tree_sharing(wamct_ctx* ctx, int32_t shared);
 wamct_status wamct_get_tree_sharing(wamct_ctx* ctx, int32_t* shared);
 
+/* Tree rule used by wamct_expand, wamct_solve and batches.
+ * WAMCT_RULE_VALUE (default; Results): every leaf containing a pixel of mu = Omega beta above
+ * frac x max(mu) splits one level.
+ * WAMCT_RULE_GRADIENT (an other expansion rule, as the Conclusion invites): with q-hat the
+ * mean counts of the current beta, c = Omega^T H^T (d - q-hat) is the gradient of the
+ * I-divergence with respect to every coefficient (eq. 1.6 applied to the residual); a leaf's
+ * score is the largest |c| of its would-be details (the three details of its node), and
+ * every leaf scoring above frac x the largest score splits one level (nothing if all scores
+ * are 0). Costs one forward pass, one pixel backprojection and one Haar analysis per scan and
+ * expansion. 2-D scans only, not with tree sharing (E_UNSUPPORTED). Synchronizes. */
+enum { WAMCT_RULE_VALUE = 0, WAMCT_RULE_GRADIENT = 1 };
+wamct_status wamct_set_tree_rule(wamct_ctx* ctx, int32_t rule);
+wamct_status wamct_get_tree_rule(wamct_ctx* ctx, int32_t* rule);
+
 /* ---------------------------------------------------------------- batches
  * Uneven batches: several contexts (different geometries, image sizes and view counts,
  * each a stack of scans) solved together. Each context is bound to one of n_streams

@@ -145,12 +145,49 @@ def expand_tree(beta, mask, levels, frac, Omega):
     return new, count
 
 
+def expand_tree_gradient(beta, mask, levels, frac, Omega, H, d, i0):
+    """Residual-gradient tree rule (an "other expansion rule" in the sense of the Conclusion)
+    -> (new mask, number of nodes split).
+
+    q-hat = I0 exp(-H Omega beta) (Beer's law), c = Omega^T H^T (d - q-hat): the derivative
+    of I(d || q-hat) with respect to every coefficient (from eq. 1.6's form, dI/dbeta_z =
+    sum_y phi(y|z) (d(y) - q-hat(y))). A leaf (as in expand_tree) scores max |c| over its
+    node's three details; every leaf scoring above frac x the largest leaf score (strict >)
+    splits once; nothing splits if every score is 0. Decisions on the old tree."""
+    n = mask.shape[0]
+    q = beer_mean(i0, H @ (Omega @ np.asarray(beta, np.float64).ravel()))
+    c = (Omega.T @ (H.T @ (np.asarray(d, np.float64) - q))).reshape(n, n)
+    scores, leaves = {}, {}
+    for lev in range(1, levels + 1):
+        m = n >> lev
+        split = haar.split_flags(mask, lev)
+        if lev == levels:
+            parent = np.ones((m, m), bool)
+        else:
+            parent = np.repeat(np.repeat(haar.split_flags(mask, lev + 1), 2, 0), 2, 1)
+        leaves[lev] = ~split & parent
+        det = np.stack([c[:m, m:2 * m], c[m:2 * m, :m], c[m:2 * m, m:2 * m]])
+        scores[lev] = np.where(leaves[lev], np.abs(det).max(axis=0), 0.0)
+    top = max((s.max() for s in scores.values()), default=0.0)
+    new = mask.copy()
+    if not top > 0:
+        return new, 0
+    thr = frac * top
+    count = 0
+    for lev in range(1, levels + 1):
+        grow = leaves[lev] & (scores[lev] > thr)
+        count += int(grow.sum())
+        haar.set_split(new, lev, haar.split_flags(mask, lev) | grow)
+    return new, count
+
+
 def wam_solve(H, n, levels, d, i0, n_iters, pixel, schedule=(), frac=0.1, masks=None,
-              beta0=None, mask0=None, Omega=None, record_beta=False):
+              beta0=None, mask0=None, Omega=None, record_beta=False, rule="value"):
     """Algorithm 1 with the tree rule of the Results section.
 
     H: CSR system matrix (M x n*n); d: counts; i0: scalar or per-ray incident counts.
-    schedule: iterations j before whose update the tree is expanded by `expand_tree`.
+    schedule: iterations j before whose update the tree is expanded by `expand_tree`
+    (rule "value", the Results section) or `expand_tree_gradient` (rule "gradient").
     masks: optional {j: mask} giving Z_s^(j) explicitly (Algorithm 1 takes the sequence
     of active sets as an input); it overrides the rule at those j.
     Returns a dict with beta (Mallat, n x n), mu, idiv (n_iters + 1 values: I(d||q-hat^(j))
@@ -171,7 +208,10 @@ def wam_solve(H, n, levels, d, i0, n_iters, pixel, schedule=(), frac=0.1, masks=
             mask = np.array(masks[j], np.uint8)
             changed = True
         elif j in schedule:
-            mask, _ = expand_tree(beta, mask, levels, frac, Omega)
+            if rule == "gradient":
+                mask, _ = expand_tree_gradient(beta, mask, levels, frac, Omega, H, d, i0)
+            else:
+                mask, _ = expand_tree(beta, mask, levels, frac, Omega)
             changed = True
         if Phi is None or changed:
             Phi, act = phi_matrix(H, Omega, mask, pixel)

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libwamct.so")
 
 OK, E_INVALID, E_UNSUPPORTED, E_OOM, E_HIP, E_NUMERIC, E_STATE = range(7)
 PARALLEL, FAN, CONE = 0, 1, 2
+RULE_VALUE, RULE_GRADIENT = 0, 1
 F32, F64 = 0, 1
 K_SYNTH, K_FORWARD, K_UPDATE, K_TREE, K_OTHER, NK = range(6)
 KERNEL_CLASSES = ("synth", "forward", "update", "tree", "other")
@@ -27,7 +28,7 @@ SYMBOLS = (
     "wamct_set_tiling", "wamct_get_tiling", "wamct_batch_create", "wamct_batch_destroy",
     "wamct_batch_last_error", "wamct_batch_reset", "wamct_batch_solve", "wamct_batch_autotune",
     "wamct_batch_stats", "wamct_set_subsets", "wamct_get_subsets", "wamct_set_tree_sharing",
-    "wamct_get_tree_sharing",
+    "wamct_get_tree_sharing", "wamct_set_tree_rule", "wamct_get_tree_rule",
 )
 
 
@@ -88,6 +89,8 @@ def _load():
         "wamct_set_subsets": (vp, i32),
         "wamct_set_tree_sharing": (vp, i32),
         "wamct_get_tree_sharing": (vp, P(i32)),
+        "wamct_set_tree_rule": (vp, i32),
+        "wamct_get_tree_rule": (vp, P(i32)),
         "wamct_get_subsets": (vp, P(i32)),
         "wamct_batch_create": (i32, P(vp), i32, i32, vp, P(vp)),
         "wamct_batch_destroy": (vp,),

@@ -173,6 +173,21 @@ class Context:
         self._call(lib.wamct_get_tree_sharing, ctypes.byref(v))
         return bool(v.value)
 
+    _RULES = {"value": _lib.RULE_VALUE, "gradient": _lib.RULE_GRADIENT}
+
+    def set_tree_rule(self, rule: str) -> None:
+        """"value" (the paper's rule: leaves holding a pixel above frac x max(mu) split) or
+        "gradient" (leaves whose would-be details have the largest I-divergence gradient
+        |Omega^T H^T (d - q-hat)| above frac x its maximum split)."""
+        if rule not in self._RULES:
+            raise ValueError("rule must be 'value' or 'gradient'")
+        self._call(lib.wamct_set_tree_rule, self._RULES[rule])
+
+    def tree_rule(self) -> str:
+        v = ctypes.c_int32()
+        self._call(lib.wamct_get_tree_rule, ctypes.byref(v))
+        return {b: a for a, b in self._RULES.items()}[v.value]
+
     def set_subsets(self, n_subsets: int) -> None:
         """Ordered subsets of views: every iteration becomes a pass of n_subsets updates."""
         self._call(lib.wamct_set_subsets, int(n_subsets))

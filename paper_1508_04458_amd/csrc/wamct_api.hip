@@ -95,6 +95,7 @@ struct Ctx final : wamct_ctx {
   double* h_scal = nullptr;
   // one tree for the whole stack, grown on the slice-summed image
   bool shared_tree = false;
+  int rule = WAMCT_RULE_VALUE;   // tree rule of the expansions
   // ordered subsets of views (n_sub > 1): b and Z0 of every subset, [n_sub][P][...]
   int n_sub = 1;
   T* bsub = nullptr;
@@ -317,8 +318,19 @@ struct Ctx final : wamct_ctx {
   }
   int32_t subsets() const override { return n_sub; }
 
+  wamct_status set_tree_rule(int32_t r) override {
+    if (r != WAMCT_RULE_VALUE && r != WAMCT_RULE_GRADIENT) return fail(WAMCT_E_INVALID, fmt("unknown tree rule %d", r));
+    if (r == WAMCT_RULE_GRADIENT && shared_tree)
+      return fail(WAMCT_E_UNSUPPORTED, "the residual-gradient rule is not implemented for slices sharing one tree");
+    HIPCHK(hipStreamSynchronize(st));
+    rule = r;
+    return WAMCT_OK;
+  }
+  int32_t tree_rule() const override { return rule; }
   wamct_status set_tree_sharing(int32_t on) override {
     if (on != 0 && on != 1) return fail(WAMCT_E_INVALID, "shared must be 0 or 1");
+    if (on == 1 && rule == WAMCT_RULE_GRADIENT)
+      return fail(WAMCT_E_UNSUPPORTED, "the residual-gradient rule is not implemented for slices sharing one tree");
     shared_tree = on == 1;
     if (shared_tree && P > 1) {
       // every slice takes slice 0's tree; coefficients outside it become 0
@@ -631,6 +643,27 @@ struct Ctx final : wamct_ctx {
         expand(g, mask_old, mask, mu64, scal + 2, frac, ints + 2, 1, s);
         for (int p = 1; p < P; ++p)
           HIPCHK(hipMemcpyAsync(mask + p * NN, mask, NN, hipMemcpyDeviceToDevice, s));
+      }
+      LAUNCHED();
+      return enq_tree(s);
+    }
+    if (g.L > 0 && rule == WAMCT_RULE_GRADIENT) {
+      // q-hat of the current beta over all views, residual d - q-hat (in q), then per scan
+      // c = Omega^T H^T (d - q-hat) (in mu, free in tree runs) and the leaf scores (in mu64)
+      forward_pass(s, g, nullptr);
+      {
+        Scope sc(this, WAMCT_K_TREE, s);
+        Launch<T>::residual_inplace(d, q, M * P, s);
+        for (int p = 0; p < P; ++p) {
+          CHECKED(gather(kPlain, q + p * M, pix_segs, 1, nullptr, nullptr, nullptr, nullptr, img, s));
+          Launch<T>::analysis(g, img, mu + p * NN, s);
+        }
+        Launch<double>::fill(mu64, NN * P, 0.0, s);
+        HIPCHK(hipMemcpyAsync(mask_old, mask, NN * P, hipMemcpyDeviceToDevice, s));
+        Launch<T>::grad_scores(g, mask_old, mu, mu64, P, s);
+        reduce_stack(true, mu64, int(NN), int(NN), scal + 2, kScal, nullptr, P, s);
+        fill_i32_strided(ints + 2, P, kInts, 0, s);
+        expand(g, mask_old, mask, mu64, scal + 2, frac, ints + 2, P, s, WAMCT_RULE_GRADIENT);
       }
       LAUNCHED();
       return enq_tree(s);
@@ -1194,6 +1227,13 @@ wamct_status wamct_get_timing(wamct_ctx* ctx, double* ms, int64_t* n) { CTX_CALL
 wamct_status wamct_set_tiling(wamct_ctx* ctx, int32_t lanes) { CTX_CALL(set_tiling(lanes)); }
 wamct_status wamct_set_subsets(wamct_ctx* ctx, int32_t n_subsets) { CTX_CALL(set_subsets(n_subsets)); }
 wamct_status wamct_set_tree_sharing(wamct_ctx* ctx, int32_t shared) { CTX_CALL(set_tree_sharing(shared)); }
+wamct_status wamct_set_tree_rule(wamct_ctx* ctx, int32_t rule) { CTX_CALL(set_tree_rule(rule)); }
+wamct_status wamct_get_tree_rule(wamct_ctx* ctx, int32_t* rule) {
+  if (!ctx) { g_last_error = "ctx is NULL"; return WAMCT_E_INVALID; }
+  if (!rule) return ctx->fail(WAMCT_E_INVALID, "rule must not be NULL");
+  *rule = ctx->tree_rule();
+  return WAMCT_OK;
+}
 wamct_status wamct_get_tree_sharing(wamct_ctx* ctx, int32_t* shared) {
   if (!ctx) { g_last_error = "ctx is NULL"; return WAMCT_E_INVALID; }
   if (!shared) return ctx->fail(WAMCT_E_INVALID, "shared must not be NULL");

@@ -562,6 +562,12 @@ struct Ctx3 final : wamct_ctx {
     return fail(WAMCT_E_UNSUPPORTED, "tree sharing applies to stacks of 2-D slices");
   }
   int32_t tree_sharing() const override { return 0; }
+  wamct_status set_tree_rule(int32_t r) override {
+    if (r == WAMCT_RULE_VALUE) return WAMCT_OK;
+    if (r == WAMCT_RULE_GRADIENT) return fail(WAMCT_E_UNSUPPORTED, "the residual-gradient rule is implemented for 2-D scans");
+    return fail(WAMCT_E_INVALID, fmt("unknown tree rule %d", r));
+  }
+  int32_t tree_rule() const override { return WAMCT_RULE_VALUE; }
   int n_scans() const override { return 1; }
   hipStream_t stream() const override { return st; }
   double work() const override { return double(M) * double(g.n); }

@@ -75,6 +75,12 @@ struct Launch {
   static int idiv_terms(const DevGeom& g, const T* q, const T* d, double* part, int S, hipStream_t s);
   // b = Omega^T g for every coefficient (FP64 accumulation), one scan
   static void analysis(const DevGeom& g, const T* img, T* coef, hipStream_t s);
+  // residual-gradient rule: per-leaf score max |coef| of its would-be details -> score
+  // [S][n][n] at the node's first detail position (other entries untouched)
+  static void grad_scores(const DevGeom& g, const uint8_t* mask, const T* coef, double* score, int S,
+                          hipStream_t s);
+  // q <- d - q over len values
+  static void residual_inplace(const T* d, T* q, int64_t len, hipStream_t s);
   // FP64 synthesis of the current beta and per-block maxima. Returns the blocks per scan.
   static int mu64(const DevGeom& g, const T* beta, double* mu64, double* part, int S, hipStream_t s);
   // zero beta outside the mask
@@ -131,10 +137,11 @@ void reduce_stack(bool max, const double* part, int n, int64_t pstride, double* 
 // of items, counts[1 + k] = items of level L - k (k = 0..L; level 0 only when L = 0);
 // counts at stride kInts, items at stride n*n.
 void build_items(const DevGeom& g, const uint8_t* mask, uint32_t* items, int* counts, int S, hipStream_t s);
-// Tree rule: split every leaf (level >= 1) of mask_old whose FP64 value exceeds frac * max
-// (maxv at stride kScal, n_split at stride kInts).
+// Tree rule: split every leaf of mask_old whose value exceeds frac * max (maxv at stride
+// kScal, n_split at stride kInts). rule 0: the FP64 image mu64 (leaf-constant); rule 1: the
+// leaf scores of grad_scores held in mu64 at each node's first detail position.
 void expand(const DevGeom& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64,
-            const double* maxv, double frac, int* n_split, int S, hipStream_t s);
+            const double* maxv, double frac, int* n_split, int S, hipStream_t s, int rule = 0);
 // Sum of the FP64 images of S slices into slice 0 (slice order) and per-block maxima of the
 // sum. Returns the number of blocks.
 int sum_slices(const DevGeom& g, double* mu64, double* part, int S, hipStream_t s);

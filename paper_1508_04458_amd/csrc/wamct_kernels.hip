@@ -1019,10 +1019,48 @@ __global__ __launch_bounds__(kBlock) void k_z0(DevGeom g, const double2* __restr
 
 // ------------------------------------------------------------------ tree rule (Results)
 
+// Leaf scores of the residual-gradient rule: for every leaf node (a node at level >= 1 not
+// split whose parent is split, or a root) the largest |c| of its three would-be details, c =
+// Omega^T H^T (d - q-hat) (the gradient of the I-divergence with respect to the detail
+// coefficients), stored at the node's first detail position [i][m + j]; other positions
+// keep their value (the caller fills zeros). Per scan: blockIdx.y.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_grad_scores(DevGeom g, const uint8_t* __restrict__ mask,
+                                                        const T* __restrict__ coef, double* __restrict__ score) {
+  const int n = g.n;
+  {
+    const int64_t off = int64_t(blockIdx.y) * n * n;
+    mask += off; coef += off; score += off;
+  }
+  int k = blockIdx.x * kBlock + threadIdx.x;
+  int l = 1;
+  for (; l <= g.L; ++l) {
+    const int m = n >> l;
+    if (k < m * m) break;
+    k -= m * m;
+  }
+  if (l > g.L) return;
+  const int m = n >> l, i = k / m, j = k % m;
+  if (is_split(mask, n, l, i, j)) return;
+  if (l < g.L && !is_split(mask, n, l + 1, i >> 1, j >> 1)) return;
+  const double c1 = fabs(double(coef[i * n + m + j])), c2 = fabs(double(coef[(m + i) * n + j]));
+  const double c3 = fabs(double(coef[(m + i) * n + m + j]));
+  score[i * n + m + j] = fmax(c1, fmax(c2, c3));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual_inplace(int64_t len, const T* __restrict__ d, T* __restrict__ q) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k < len) q[k] = T(double(d[k]) - double(q[k]));
+}
+
+// Tree rule: rule 0 (Results) splits leaves whose leaf-constant value mu64 exceeds frac x max;
+// rule 1 (residual gradient) splits leaves whose score (k_grad_scores, in `val`) exceeds
+// frac x max score.
 __global__ __launch_bounds__(kBlock) void k_expand(DevGeom g, const uint8_t* __restrict__ old,
                                                    uint8_t* __restrict__ mask, const double* __restrict__ mu64,
                                                    const double* __restrict__ maxv, double frac,
-                                                   int* __restrict__ n_split) {
+                                                   int* __restrict__ n_split, int rule) {
   const int n = g.n;
   {
     const int p = blockIdx.y;
@@ -1046,7 +1084,8 @@ __global__ __launch_bounds__(kBlock) void k_expand(DevGeom g, const uint8_t* __r
   if (is_split(old, n, l, i, j)) return;
   if (l < g.L && !is_split(old, n, l + 1, i >> 1, j >> 1)) return;
   const int s = 1 << l;
-  const double val = mu64[(i * s) * n + j * s];   // leaf-constant: any pixel of the block
+  // rule 0: leaf-constant value (any pixel of the block); rule 1: the node's score
+  const double val = rule == 0 ? mu64[(i * s) * n + j * s] : mu64[i * n + m + j];
   if (val > frac * top) {
     mask[i * n + m + j] = 1;
     mask[(m + i) * n + j] = 1;
@@ -1232,6 +1271,18 @@ void Launch<T>::fill(T* x, int64_t len, T v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(len)), dim3(kBlock), 0, s, x, len, v);
 }
 
+template <typename T>
+void Launch<T>::grad_scores(const DevGeom& g, const uint8_t* mask, const T* coef, double* score, int S,
+                            hipStream_t s) {
+  int64_t nodes = 0;
+  for (int l = 1; l <= g.L; ++l) nodes += int64_t(g.n >> l) * (g.n >> l);
+  if (nodes == 0) return;
+  hipLaunchKernelGGL(k_grad_scores<T>, dim3(blocks_for(nodes), S), dim3(kBlock), 0, s, g, mask, coef, score);
+}
+template <typename T>
+void Launch<T>::residual_inplace(const T* d, T* q, int64_t len, hipStream_t s) {
+  if (len > 0) hipLaunchKernelGGL(k_residual_inplace<T>, dim3(blocks_for(len)), dim3(kBlock), 0, s, len, d, q);
+}
 template struct Launch<float>;
 template struct Launch<double>;
 
@@ -1362,12 +1413,12 @@ void build_items(const DevGeom& g, const uint8_t* mask, uint32_t* items, int* co
   hipLaunchKernelGGL(k_items, dim3(S), dim3(1024), 0, s, g, mask, items, counts);
 }
 void expand(const DevGeom& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64,
-            const double* maxv, double frac, int* n_split, int S, hipStream_t s) {
+            const double* maxv, double frac, int* n_split, int S, hipStream_t s, int rule) {
   int64_t nodes = 0;
   for (int l = 1; l <= g.L; ++l) nodes += int64_t(g.n >> l) * (g.n >> l);
   if (nodes == 0) return;
   hipLaunchKernelGGL(k_expand, dim3(blocks_for(nodes), S), dim3(kBlock), 0, s, g, mask_old, mask, mu64, maxv,
-                     frac, n_split);
+                     frac, n_split, rule);
 }
 void check_mask(const DevGeom& g, const uint8_t* mask, int* bad, int S, hipStream_t s) {
   hipLaunchKernelGGL(k_check_mask, dim3(blocks_for(int64_t(g.n) * g.n), S), dim3(kBlock), 0, s, g, mask, bad);
