@@ -9,6 +9,8 @@ Extra fields:
   gray_voxel_per_s  sum_j 2 W_j / time, W_j = (ray, active coefficient) pairs with phi != 0
   full_am           image-domain AM (levels = 0) on the same GPU: it/s, and the time it
                     needs to reach the tree run's final I-divergence (equal-objective)
+  gradient_rule     the same solve with the residual-gradient tree rule instead of the
+                    paper's value rule (final I-divergence, time to the value rule's final)
   roofline          the tree walk (forward projection over the leaves, Beer's law, I-div
                     term), timed with HIP events on the library's stream over the timed steps;
                     roofline_update: the update pass, likewise
@@ -47,6 +49,7 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized buffer 3 times (reference kernel for PMC byte counters)")
     ap.add_argument("--os-subsets", type=int, default=8, help="fan512: ordered-subsets comparison (0 = skip)")
+    ap.add_argument("--no-gradient-rule", action="store_true", help="fan512: skip the residual-gradient rule leg")
     ap.add_argument("--problems", type=int, default=256, help="uneven: number of problems")
     ap.add_argument("--streams", type=int, default=4, help="uneven: streams of the batch")
     ap.add_argument("--no-graph", action="store_true", help="uneven: launch directly instead of graph replay")
@@ -551,6 +554,7 @@ def main():
            "roofline_update": roof_up}
 
     # ---- full-image AM (levels = 0) on the same GPU: equal-I-div comparison
+    full_trace = None
     if not args.no_full_am:
         full = api.Context(g, 0, "f32", device=dev, geometry=args.geometry)
         full.set_data(d, P.i0)
@@ -563,6 +567,7 @@ def main():
         torch.cuda.synchronize()
         t_full = time.perf_counter() - t1
         ft = fidiv.cpu().numpy()
+        full_trace = (ft, cap / t_full)
         w_pix = full.tree_stats()["w"]
         target = tr[-1]
         hit = np.nonzero(ft <= target)[0]
@@ -579,6 +584,39 @@ def main():
         out["pixel_equiv_gray_voxel_per_s"] = round(2 * w_pix * it_s / 1e9, 3)
         out["equal_idiv"] = eq
         full.close()
+
+    # ---- the same solve with the residual-gradient tree rule (same schedule and fraction)
+    if not args.no_gradient_rule:
+        grc = api.Context(g, P.levels, "f32", device=dev, geometry=args.geometry)
+        grc.set_tree_rule("gradient")
+        grc.set_data(d, P.i0)
+        grc.reset()
+        gtr = grc.solve(J, sched, 0.1).cpu().numpy()          # traced run (untimed)
+        g_active = grc.tree_stats()["n_active"]
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for _ in range(2):
+            grc.reset()
+            grc.solve(J, sched, 0.1, trace=False)
+        torch.cuda.synchronize()
+        t_gr = (time.perf_counter() - t3) / 2
+        target = tr[-1]
+        hit = np.nonzero(gtr <= target)[0]
+        k_gr = int(hit[0]) if hit.size else None
+        out["gradient_rule"] = {
+            "iter_per_s": round(J / t_gr, 2), "ms_per_solve": round(t_gr * 1e3, 3), "final_idiv": float(gtr[-1]),
+            "final_active": int(g_active), "iters_to_value_rule_final_idiv": k_gr,
+            "time_to_value_rule_final_idiv_ms": None if k_gr is None else round(k_gr * t_gr / J * 1e3, 3)}
+        if full_trace is not None:
+            # image-domain AM to the gradient-rule run's final I-divergence
+            ft, f_it_s = full_trace
+            hit = np.nonzero(ft <= gtr[-1])[0]
+            k_f = int(hit[0]) if hit.size else None
+            out["gradient_rule"].update(
+                full_am_iters_to_its_final_idiv=k_f,
+                full_am_time_to_its_final_idiv_ms=None if k_f is None else round(k_f / f_it_s * 1e3, 3),
+                speedup_vs_full_am=None if k_f is None else round(k_f / f_it_s / t_gr, 3))
+        grc.close()
 
     # ---- wavelet AM with ordered subsets of views (same tree schedule, passes of S updates)
     if args.os_subsets > 1:
