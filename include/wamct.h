@@ -264,8 +264,10 @@ wamct_status wamct_get_tree_sharing(wamct_ctx* ctx, int32_t* shared);
  * I-divergence with respect to every coefficient (eq. 1.6 applied to the residual); a leaf's
  * score is the largest |c| of its would-be details (the three details of its node), and
  * every leaf scoring above frac x the largest score splits one level (nothing if all scores
- * are 0). Costs one forward pass, one pixel backprojection and one Haar analysis per scan and
- * expansion. 2-D scans only, not with tree sharing (E_UNSUPPORTED). Synchronizes. */
+ * are 0); for the cone beam the same with the seven details of an octree node. Costs one
+ * forward pass, one pixel (voxel) backprojection and one Haar analysis per scan and
+ * expansion. Not with tree sharing (E_UNSUPPORTED). Synchronizes; a cone-beam context
+ * allocates one coefficient volume when the rule is first selected. */
 enum { WAMCT_RULE_VALUE = 0, WAMCT_RULE_GRADIENT = 1 };
 wamct_status wamct_set_tree_rule(wamct_ctx* ctx, int32_t rule);
 wamct_status wamct_get_tree_rule(wamct_ctx* ctx, int32_t* rule);

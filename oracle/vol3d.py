@@ -247,10 +247,43 @@ def expand_tree3(beta, mask, levels, frac, Omega):
     return new, count
 
 
+def expand_tree3_gradient(beta, mask, levels, frac, Omega, H, d, i0):
+    """Residual-gradient rule on the octree (oracle.wam.expand_tree_gradient in 3-D): c =
+    Omega^T H^T (d - q-hat) at the current beta; a leaf scores max |c| over its node's seven
+    details; leaves scoring above frac x the largest score split once (nothing if all are 0).
+    Returns (new mask, number of nodes split)."""
+    nz, n = mask.shape[0], mask.shape[1]
+    q = wam.beer_mean(i0, H @ (Omega @ np.asarray(beta, np.float64).ravel()))
+    c = (Omega.T @ (H.T @ (np.asarray(d, np.float64) - q))).reshape(nz, n, n)
+    scores, leaves = {}, {}
+    for lev in range(1, levels + 1):
+        m, mz = n >> lev, nz >> lev
+        split = split_flags3(mask, lev)
+        if lev == levels:
+            parent = np.ones((mz, m, m), bool)
+        else:
+            parent = split_flags3(mask, lev + 1).repeat(2, 0).repeat(2, 1).repeat(2, 2)
+        leaves[lev] = ~split & parent
+        det = np.stack([np.abs(c[tz * mz:tz * mz + mz, ty * m:ty * m + m, tx * m:tx * m + m])
+                        for tz, ty, tx in DETAILS])
+        scores[lev] = np.where(leaves[lev], det.max(axis=0), 0.0)
+    top = max((s_.max() for s_ in scores.values()), default=0.0)
+    new = mask.copy()
+    if not top > 0:
+        return new, 0
+    thr = frac * top
+    count = 0
+    for lev in range(1, levels + 1):
+        grow = leaves[lev] & (scores[lev] > thr)
+        count += int(grow.sum())
+        set_split3(new, lev, split_flags3(mask, lev) | grow)
+    return new, count
+
+
 # ------------------------------------------------------------------ Algorithm 1 in 3-D
 
 def wam_solve3(H, n, nz, levels, d, i0, n_iters, pixel, schedule=(), frac=0.1, Omega=None, beta0=None,
-               mask0=None):
+               mask0=None, rule="value"):
     """Algorithm 1 with the octree rule on a 3-D volume (same steps as wam.wam_solve: eq. 1.6
     b for every coefficient, eq. 1.61 Z0 per tree, eq. 1.10 sign split, eq. 1.9 zero)."""
     if Omega is None:
@@ -265,7 +298,10 @@ def wam_solve3(H, n, nz, levels, d, i0, n_iters, pixel, schedule=(), frac=0.1, O
     for j in range(n_iters):
         changed = False
         if j in schedule:
-            mask, _ = expand_tree3(beta, mask, levels, frac, Omega)
+            if rule == "gradient":
+                mask, _ = expand_tree3_gradient(beta, mask, levels, frac, Omega, H, d, i0)
+            else:
+                mask, _ = expand_tree3(beta, mask, levels, frac, Omega)
             changed = True
         if Phi is None or changed:
             Phi, act = wam.phi_matrix(H, Omega, mask, pixel)

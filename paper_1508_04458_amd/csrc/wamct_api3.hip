@@ -54,6 +54,8 @@ struct Ctx3 final : wamct_ctx {
   double* C = nullptr;
   T *d = nullptr, *i0v = nullptr, *q = nullptr, *beta = nullptr, *b = nullptr, *img = nullptr;
   T* yn = nullptr;                 // ray values scaled by |D| for the gather
+  T* coefg = nullptr;              // Omega^T H^T (d - q-hat) of the residual-gradient rule
+  int rule = WAMCT_RULE_VALUE;     // tree rule of the expansions
   double2* colt = nullptr;         // [nv][nc] (1/Dx, 1/Dy)
   double *rowt = nullptr, *nrm = nullptr;  // [nr] 1/Dz, [nr][nc] |D|
   void *recR = nullptr, *recC = nullptr;
@@ -383,6 +385,25 @@ struct Ctx3 final : wamct_ctx {
     return WAMCT_OK;
   }
   wamct_status enq_expand(hipStream_t s, double frac) override {
+    if (g.L > 0 && rule == WAMCT_RULE_GRADIENT) {
+      // q-hat of the current beta, residual d - q-hat (in q), c = Omega^T H^T (d - q-hat),
+      // leaf scores (in mu64) and the split of every leaf above frac x the largest score
+      forward_pass(s);
+      {
+        Scope sc(this, WAMCT_K_TREE, s);
+        Launch<T>::residual_inplace(d, q, M, s);
+        CHECKED(gather(kPlain, q, vox_segs, nullptr, nullptr, nullptr, nullptr, img, s));
+        Geo3<T>::analysis(g, img, coefg, s);
+        Launch<double>::fill(mu64, N, 0.0, s);
+        HIPCHK(hipMemcpyAsync(mask_old, mask, N, hipMemcpyDeviceToDevice, s));
+        Geo3<T>::grad_scores(g, mask_old, coefg, mu64, s);
+        reduce_max(mu64, int(N), scal + 2, s);
+        fill_i32(ints + 2, 1, 0, s);
+        expand3(g, mask_old, mask, mu64, scal + 2, frac, ints + 2, s, WAMCT_RULE_GRADIENT);
+      }
+      LAUNCHED();
+      return enq_tree(s);
+    }
     if (g.L > 0) {
       {
         Scope sc(this, WAMCT_K_TREE, s);
@@ -563,11 +584,13 @@ struct Ctx3 final : wamct_ctx {
   }
   int32_t tree_sharing() const override { return 0; }
   wamct_status set_tree_rule(int32_t r) override {
-    if (r == WAMCT_RULE_VALUE) return WAMCT_OK;
-    if (r == WAMCT_RULE_GRADIENT) return fail(WAMCT_E_UNSUPPORTED, "the residual-gradient rule is implemented for 2-D scans");
-    return fail(WAMCT_E_INVALID, fmt("unknown tree rule %d", r));
+    if (r != WAMCT_RULE_VALUE && r != WAMCT_RULE_GRADIENT) return fail(WAMCT_E_INVALID, fmt("unknown tree rule %d", r));
+    HIPCHK(hipStreamSynchronize(st));
+    if (r == WAMCT_RULE_GRADIENT && !coefg) CHECKED(alloc(coefg, N));   // gradient coefficients
+    rule = r;
+    return WAMCT_OK;
   }
-  int32_t tree_rule() const override { return WAMCT_RULE_VALUE; }
+  int32_t tree_rule() const override { return rule; }
   int n_scans() const override { return 1; }
   hipStream_t stream() const override { return st; }
   double work() const override { return double(M) * double(g.n); }

@@ -61,6 +61,9 @@ struct Geo3 {
   static int mu64(const DevGeom3& g, const T* beta, double* mu64, double* part, hipStream_t s);
   static void analysis(const DevGeom3& g, const T* vol, T* coef, hipStream_t s);
   static void apply_mask(const DevGeom3& g, T* beta, const uint8_t* mask, hipStream_t s);
+  // residual-gradient rule: per-leaf score max |coef| over its seven would-be details, at the
+  // node's first detail position of score (other entries untouched)
+  static void grad_scores(const DevGeom3& g, const uint8_t* mask, const T* coef, double* score, hipStream_t s);
 };
 
 // Z0 and W of the current octree (per ray FP64 walk); returns the number of blocks.
@@ -71,8 +74,9 @@ void levmap3(const DevGeom3& g, const uint8_t* mask, uint8_t* lev, hipStream_t s
 // nodes level by level (L - 1 down to 1), 3-D Morton order within a segment; counts[0] =
 // items, counts[1 + k] = items of segment k.
 void build_items3(const DevGeom3& g, const uint8_t* mask, uint32_t* items, int* counts, hipStream_t s);
+// rule 0: leaf-constant values of mu64; rule 1: leaf scores of grad_scores held in mu64
 void expand3(const DevGeom3& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64, const double* maxv,
-             double frac, int* n_split, hipStream_t s);
+             double frac, int* n_split, hipStream_t s, int rule = 0);
 void approx_mask3(const DevGeom3& g, uint8_t* mask, hipStream_t s);
 // *bad += number of violated octree constraints of the mask
 void check_mask3(const DevGeom3& g, const uint8_t* mask, int* bad, hipStream_t s);

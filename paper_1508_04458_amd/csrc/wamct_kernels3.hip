@@ -827,10 +827,36 @@ __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, const double4* __restric
 
 // ------------------------------------------------------------------ tree rule and work lists
 
+// Leaf scores of the residual-gradient rule: for every leaf node the largest |c| of its seven
+// would-be details (c = Omega^T H^T (d - q-hat)), stored at its first detail position.
+template <typename T>
+__global__ __launch_bounds__(kB) void k3_grad_scores(DevGeom3 g, const uint8_t* __restrict__ mask,
+                                                     const T* __restrict__ coef, double* __restrict__ score) {
+  int64_t k = int64_t(blockIdx.x) * kB + threadIdx.x;
+  const int n = g.n, nz = g.nz;
+  int l = 1;
+  for (; l <= g.L; ++l) {
+    const int64_t cntl = int64_t(nz >> l) * (n >> l) * (n >> l);
+    if (k < cntl) break;
+    k -= cntl;
+  }
+  if (l > g.L) return;
+  const int m = n >> l;
+  const int kz = int(k / (int64_t(m) * m)), i = int((k / m) % m), j = int(k % m);
+  if (split3(mask, n, l, kz, i, j)) return;
+  if (l < g.L && !split3(mask, n, l + 1, kz >> 1, i >> 1, j >> 1)) return;
+  double sc = 0.0;
+#pragma unroll
+  for (int d = 0; d < 7; ++d) sc = fmax(sc, fabs(double(coef[detail_pos(n, nz, l, d, kz, i, j)])));
+  score[detail_pos(n, nz, l, 0, kz, i, j)] = sc;
+}
+
+// Tree rule: rule 0 (Results) on the leaf-constant FP64 image mu64, rule 1 (residual
+// gradient) on the leaf scores held in mu64 at each node's first detail position.
 __global__ __launch_bounds__(kB) void k3_expand(DevGeom3 g, const uint8_t* __restrict__ old,
                                                 uint8_t* __restrict__ mask, const double* __restrict__ mu64,
                                                 const double* __restrict__ maxv, double frac,
-                                                int* __restrict__ n_split) {
+                                                int* __restrict__ n_split, int rule) {
   int64_t k = int64_t(blockIdx.x) * kB + threadIdx.x;
   const int n = g.n, nz = g.nz;
   int l = 1;
@@ -847,7 +873,8 @@ __global__ __launch_bounds__(kB) void k3_expand(DevGeom3 g, const uint8_t* __res
   if (split3(old, n, l, kz, i, j)) return;
   if (l < g.L && !split3(old, n, l + 1, kz >> 1, i >> 1, j >> 1)) return;
   const int s = 1 << l;
-  const double val = mu64[(int64_t(kz * s) * n + i * s) * n + j * s];   // leaf-constant
+  const double val = rule == 0 ? mu64[(int64_t(kz * s) * n + i * s) * n + j * s]   // leaf-constant
+                               : mu64[detail_pos(n, nz, l, 0, kz, i, j)];
   if (val > frac * top) {
     for (int d = 0; d < 7; ++d) mask[detail_pos(n, nz, l, d, kz, i, j)] = 1;
     atomicAdd(n_split, 1);
@@ -995,6 +1022,13 @@ void Geo3<T>::apply_mask(const DevGeom3& g, T* beta, const uint8_t* mask, hipStr
   const int64_t len = int64_t(g.n) * g.n * g.nz;
   hipLaunchKernelGGL(k3_apply_mask<T>, dim3(blocks3(len)), dim3(kB), 0, s, len, beta, mask);
 }
+template <typename T>
+void Geo3<T>::grad_scores(const DevGeom3& g, const uint8_t* mask, const T* coef, double* score, hipStream_t s) {
+  int64_t nodes = 0;
+  for (int l = 1; l <= g.L; ++l) nodes += int64_t(g.nz >> l) * (g.n >> l) * (g.n >> l);
+  if (nodes == 0) return;
+  hipLaunchKernelGGL(k3_grad_scores<T>, dim3(blocks3(nodes)), dim3(kB), 0, s, g, mask, coef, score);
+}
 template struct Geo3<float>;
 template struct Geo3<double>;
 
@@ -1018,11 +1052,12 @@ void build_items3(const DevGeom3& g, const uint8_t* mask, uint32_t* items, int* 
   hipLaunchKernelGGL(k3_items, dim3(1), dim3(1024), 0, s, g, mask, items, counts);
 }
 void expand3(const DevGeom3& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64, const double* maxv,
-             double frac, int* n_split, hipStream_t s) {
+             double frac, int* n_split, hipStream_t s, int rule) {
   int64_t nodes = 0;
   for (int l = 1; l <= g.L; ++l) nodes += int64_t(g.nz >> l) * (g.n >> l) * (g.n >> l);
   if (nodes == 0) return;
-  hipLaunchKernelGGL(k3_expand, dim3(blocks3(nodes)), dim3(kB), 0, s, g, mask_old, mask, mu64, maxv, frac, n_split);
+  hipLaunchKernelGGL(k3_expand, dim3(blocks3(nodes)), dim3(kB), 0, s, g, mask_old, mask, mu64, maxv, frac, n_split,
+                     rule);
 }
 void check_mask3(const DevGeom3& g, const uint8_t* mask, int* bad, hipStream_t s) {
   hipLaunchKernelGGL(k3_check_mask, dim3(blocks3(int64_t(g.n) * g.n * g.nz)), dim3(kB), 0, s, g, mask, bad);

@@ -6,7 +6,8 @@
   * FP32: the I-divergence falls at every iteration (factor 1 + 1e-6) and ends within 1e-3
     of the oracle's (leaf decisions near the threshold may differ in FP32);
   * a batch holding a gradient-rule context gives bitwise that context's own solve;
-  * errors: unknown rule, the rule with tree sharing, a cone-beam context.
+  * cone beam (3-D octree, seven details per node): FP64 against the 3-D oracle as above;
+  * errors: unknown rule, the rule with tree sharing.
 """
 import numpy as np
 import pytest
@@ -104,9 +105,24 @@ def test_tree_rule_errors():
     with pytest.raises(_lib.WamctError) as e:
         c.set_tree_rule("gradient")
     assert e.value.status == _lib.E_UNSUPPORTED
-    g3 = synth.CONE_CONFIGS["cone32"]["geom"]()
+
+
+def test_gradient_rule_cone_fp64():
+    """Cone beam, 3-D octree: the rule with the seven details of each node."""
+    from oracle import vol3d
     from paper_1508_04458_amd import api
-    c3 = api.Context(g3, 2, "f32")
-    with pytest.raises(_lib.WamctError) as e:
-        c3.set_tree_rule("gradient")
-    assert e.value.status == _lib.E_UNSUPPORTED
+    P = synth.make_cone_problem("cone32")
+    g = P.geom
+    H = vol3d.system_matrix3(g)
+    ref = vol3d.wam_solve3(H, g.n, g.nz, P.levels, P.d, P.i0, P.n_iters, g.pixel, schedule=P.schedule,
+                           rule="gradient")
+    print("\n[case] cone32 gradient rule f64", flush=True)
+    c = api.Context(g, P.levels, "f64")
+    c.set_tree_rule("gradient")
+    c.set_data(dev(P.d, "f64"), P.i0)
+    idv = host(c.solve(P.n_iters, P.schedule, 0.1))
+    beta, mask, _ = c.get_state()
+    np.testing.assert_array_equal(host(mask), ref["mask"])
+    assert rel_l2(host(beta), ref["beta"]) <= 1e-9
+    np.testing.assert_allclose(idv, ref["idiv"], rtol=1e-10)
+    assert c.tree_stats()["n_held"] == ref["held"]
