@@ -414,6 +414,25 @@ def bench_cone(args):
            "time_ms_per_step_by_kernel": {k: round(v["ms"] / args.steps, 2) for k, v in tim.items()},
            "roofline": r_up if dominant == "update" else r_fw,
            "roofline_other": r_fw if dominant == "update" else r_up}
+    if not args.no_gradient_rule:
+        # the same solve with the residual-gradient tree rule
+        grc = api.Context(g, P.levels, "f32", device=dev)
+        grc.set_tree_rule("gradient")
+        grc.set_data(d, P.i0)
+        grc.reset()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        gtr = grc.solve(J, sched, 0.1).cpu().numpy()
+        t_gr = time.perf_counter() - t3
+        hit = np.nonzero(gtr <= tr[-1])[0]
+        k_gr = int(hit[0]) if hit.size else None
+        out["gradient_rule"] = {
+            "iter_per_s": round(J / t_gr, 3), "ms_per_solve": round(t_gr * 1e3, 1),
+            "final_idiv": float(gtr[-1]), "final_active": int(grc.tree_stats()["n_active"]),
+            "iters_to_value_rule_final_idiv": k_gr,
+            "time_to_value_rule_final_idiv_ms": None if k_gr is None else round(k_gr * t_gr / J * 1e3, 1)}
+        grc.close()
+        log(f"gradient rule: {J / t_gr:.3f} it/s, final I-div {gtr[-1]:.4e} (value rule {tr[-1]:.4e})")
     if not args.no_full_am:
         full = api.Context(g, 0, "f32", device=dev)
         full.set_data(d, P.i0)
