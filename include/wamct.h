@@ -272,6 +272,20 @@ enum { WAMCT_RULE_VALUE = 0, WAMCT_RULE_GRADIENT = 1 };
 wamct_status wamct_set_tree_rule(wamct_ctx* ctx, int32_t rule);
 wamct_status wamct_get_tree_rule(wamct_ctx* ctx, int32_t* rule);
 
+/* Roughness penalty (the Introduction's penalized objective I(d || q) + lambda R(mu), whose R the
+ * paper does not spell out). Here R(mu) = 1/2 sum over horizontally and vertically adjacent
+ * pixel pairs of (mu_x - mu_x')^2. With lambda > 0 every update minimizes eq. 1.8's surrogate
+ * plus lambda times the separable quadratic surrogate R + g (beta - beta-hat) + 4 |beta -
+ * beta-hat|^2 of R(Omega beta) (g = Omega^T grad R(mu-hat); 8 bounds the Hessian of R and Omega
+ * is orthonormal), so I + lambda R cannot increase; per coefficient the minimizer is the root
+ * of b - b-hat+ exp(-Z0 delta) - b-hat- exp(Z0 delta) + lambda (g + 8 delta), found in FP64 by
+ * safeguarded Newton (no coefficient is held). lambda = 0 (default) is Algorithm 1. The
+ * idiv traces still report I(d || q-hat). E_INVALID for lambda < 0 or not finite;
+ * E_UNSUPPORTED with ordered subsets and for the cone beam. Synchronizes; the first lambda
+ * > 0 allocates one coefficient image per scan. */
+wamct_status wamct_set_penalty(wamct_ctx* ctx, double lambda);
+wamct_status wamct_get_penalty(wamct_ctx* ctx, double* lambda);
+
 /* ---------------------------------------------------------------- batches
  * Uneven batches: several contexts (different geometries, image sizes and view counts,
  * each a stack of scans) solved together. Each context is bound to one of n_streams

@@ -105,6 +105,60 @@ def closed_form_update(b, bp, bm, z0):
     return delta, held
 
 
+# ------------------------------------------------------------------ roughness penalty (NEXT-3)
+# The Introduction's objective adds lambda R(mu) with a roughness penalty whose form it does not
+# give. Reading: R(mu) = 1/2 sum over horizontally and vertically adjacent pixel pairs of
+# (mu_x - mu_x')^2. Its Hessian (a graph Laplacian) is below 8 I (Gershgorin: degree <= 4), and
+# Omega is orthonormal, so at beta-hat R(Omega beta) <= R + g^T delta + (8 / 2) |delta|^2 with
+# g = Omega^T grad R(mu-hat): a separable quadratic surrogate added to eq. 1.8's.
+PENALTY_CURVATURE = 8.0
+
+
+def roughness(mu):
+    mu = np.asarray(mu, np.float64)
+    dh = mu[:, 1:] - mu[:, :-1]
+    dv = mu[1:, :] - mu[:-1, :]
+    return 0.5 * float((dh * dh).sum() + (dv * dv).sum())
+
+
+def roughness_grad(mu):
+    """dR/dmu_x = sum over the 4-neighbours x' of x of (mu_x - mu_x')."""
+    mu = np.asarray(mu, np.float64)
+    g = np.zeros_like(mu)
+    dh = mu[:, 1:] - mu[:, :-1]
+    g[:, 1:] += dh
+    g[:, :-1] -= dh
+    dv = mu[1:, :] - mu[:-1, :]
+    g[1:, :] += dv
+    g[:-1, :] -= dv
+    return g
+
+
+def penalized_update(b, bp, bm, z0, lam, g, iters=200):
+    """Minimizer of eq. 1.8's surrogate plus lam (g delta + 4 delta^2) for each coefficient:
+    the root of G(delta) = b - bp exp(-Z0 delta) - bm exp(Z0 delta) + lam (g + 8 delta), an
+    increasing function (bp >= 0 >= bm, lam > 0). G(0) fixes the side of the root and
+    |delta| <= |G(0)| / (8 lam) bounds it; plain bisection on that bracket."""
+    b, bp, bm, g = (np.asarray(x, np.float64) for x in (b, bp, bm, g))
+
+    def G(dl):
+        with np.errstate(over="ignore", invalid="ignore"):
+            ep = np.where(bp != 0, bp * np.exp(-z0 * dl), 0.0)
+            em = np.where(bm != 0, bm * np.exp(z0 * dl), 0.0)
+        return b - ep - em + lam * (g + PENALTY_CURVATURE * dl)
+
+    g0 = G(np.zeros_like(b))
+    width = np.abs(g0) / (PENALTY_CURVATURE * lam)
+    lo = np.where(g0 > 0, -width, 0.0)
+    hi = np.where(g0 > 0, 0.0, width)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        neg = G(mid) < 0
+        lo = np.where(neg, mid, lo)
+        hi = np.where(neg, hi, mid)
+    return 0.5 * (lo + hi)
+
+
 def surrogate_increment(b, q_hat, Phi, z0, delta):
     """Surrogate of eq. 1.8 minus its value at delta = 0, for a step `delta` over Z_s:
     sum_z b(z) delta(z) + sum_y sum_z q(y) |phi|/Z0 (exp(-Z0 sign(phi) delta(z)) - 1)."""
@@ -182,7 +236,7 @@ def expand_tree_gradient(beta, mask, levels, frac, Omega, H, d, i0):
 
 
 def wam_solve(H, n, levels, d, i0, n_iters, pixel, schedule=(), frac=0.1, masks=None,
-              beta0=None, mask0=None, Omega=None, record_beta=False, rule="value"):
+              beta0=None, mask0=None, Omega=None, record_beta=False, rule="value", penalty=0.0):
     """Algorithm 1 with the tree rule of the Results section.
 
     H: CSR system matrix (M x n*n); d: counts; i0: scalar or per-ray incident counts.
@@ -192,7 +246,9 @@ def wam_solve(H, n, levels, d, i0, n_iters, pixel, schedule=(), frac=0.1, masks=
     of active sets as an input); it overrides the rule at those j.
     Returns a dict with beta (Mallat, n x n), mu, idiv (n_iters + 1 values: I(d||q-hat^(j))
     before each update and after the last), the trees, Z0 and W = nnz(Phi_s) per tree, and
-    the number of held coefficients."""
+    the number of held coefficients. penalty = lambda > 0 minimizes I + lambda R(Omega beta)
+    instead (roughness penalty above; `penalized_update` replaces the eq. 1.9 root; the result
+    also holds the penalized objective before each update and after the last, `objective`)."""
     if Omega is None:
         Omega = haar.synthesis_matrix(n, levels)
     d = np.asarray(d, np.float64)
@@ -200,7 +256,7 @@ def wam_solve(H, n, levels, d, i0, n_iters, pixel, schedule=(), frac=0.1, masks=
     mask = haar.approx_mask(n, levels) if mask0 is None else np.array(mask0, np.uint8)
     masks = masks or {}
     b_all = Omega.T @ (H.T @ d)                       # eq. 1.6, for every coefficient
-    trace, trees, z0s, ws, held_total, betas = [], [], [], [], 0, []
+    trace, trees, z0s, ws, held_total, betas, objective = [], [], [], [], 0, [], []
     Phi = None
     for j in range(n_iters):
         changed = False
@@ -224,8 +280,14 @@ def wam_solve(H, n, levels, d, i0, n_iters, pixel, schedule=(), frac=0.1, masks=
         trace.append(idiv(d, q_hat))
         bp = Php.T @ q_hat
         bm = Phm.T @ q_hat
-        delta, held = closed_form_update(b_all[act], bp, bm, z0)
-        held_total += int(held.sum())
+        if penalty > 0:
+            mu_hat = (Omega @ beta).reshape(n, n)
+            objective.append(trace[-1] + penalty * roughness(mu_hat))
+            g = (Omega.T @ roughness_grad(mu_hat).ravel())[act]
+            delta = penalized_update(b_all[act], bp, bm, z0, penalty, g)
+        else:
+            delta, held = closed_form_update(b_all[act], bp, bm, z0)
+            held_total += int(held.sum())
         beta[act] += delta
         if record_beta:
             betas.append(beta.copy())
@@ -235,6 +297,9 @@ def wam_solve(H, n, levels, d, i0, n_iters, pixel, schedule=(), frac=0.1, masks=
                trees=trees, z0=z0s, w=ws, held=held_total, mask=mask, b=b_all.reshape(n, n))
     if record_beta:
         out["betas"] = betas
+    if penalty > 0:
+        objective.append(trace[-1] + penalty * roughness(out["mu"]))
+        out["objective"] = np.array(objective)
     return out
 
 

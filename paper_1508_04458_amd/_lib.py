@@ -28,7 +28,8 @@ SYMBOLS = (
     "wamct_set_tiling", "wamct_get_tiling", "wamct_batch_create", "wamct_batch_destroy",
     "wamct_batch_last_error", "wamct_batch_reset", "wamct_batch_solve", "wamct_batch_autotune",
     "wamct_batch_stats", "wamct_set_subsets", "wamct_get_subsets", "wamct_set_tree_sharing",
-    "wamct_get_tree_sharing", "wamct_set_tree_rule", "wamct_get_tree_rule",
+    "wamct_get_tree_sharing", "wamct_set_tree_rule", "wamct_get_tree_rule", "wamct_set_penalty",
+    "wamct_get_penalty",
 )
 
 
@@ -91,6 +92,8 @@ def _load():
         "wamct_get_tree_sharing": (vp, P(i32)),
         "wamct_set_tree_rule": (vp, i32),
         "wamct_get_tree_rule": (vp, P(i32)),
+        "wamct_set_penalty": (vp, ctypes.c_double),
+        "wamct_get_penalty": (vp, P(ctypes.c_double)),
         "wamct_get_subsets": (vp, P(i32)),
         "wamct_batch_create": (i32, P(vp), i32, i32, vp, P(vp)),
         "wamct_batch_destroy": (vp,),

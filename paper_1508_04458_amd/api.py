@@ -188,6 +188,15 @@ class Context:
         self._call(lib.wamct_get_tree_rule, ctypes.byref(v))
         return {b: a for a, b in self._RULES.items()}[v.value]
 
+    def set_penalty(self, lam: float) -> None:
+        """Weight of the roughness penalty lambda R(mu) (0 = Algorithm 1 without penalty)."""
+        self._call(lib.wamct_set_penalty, float(lam))
+
+    def penalty(self) -> float:
+        v = ctypes.c_double()
+        self._call(lib.wamct_get_penalty, ctypes.byref(v))
+        return v.value
+
     def set_subsets(self, n_subsets: int) -> None:
         """Ordered subsets of views: every iteration becomes a pass of n_subsets updates."""
         self._call(lib.wamct_set_subsets, int(n_subsets))

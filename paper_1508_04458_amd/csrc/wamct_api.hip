@@ -96,6 +96,8 @@ struct Ctx final : wamct_ctx {
   // one tree for the whole stack, grown on the slice-summed image
   bool shared_tree = false;
   int rule = WAMCT_RULE_VALUE;   // tree rule of the expansions
+  double lam = 0.0;              // roughness-penalty weight (0: Algorithm 1 as in the paper)
+  T* gpen = nullptr;             // [P][n][n] Omega^T grad R(mu-hat) of the current iteration
   // ordered subsets of views (n_sub > 1): b and Z0 of every subset, [n_sub][P][...]
   int n_sub = 1;
   T* bsub = nullptr;
@@ -289,6 +291,8 @@ struct Ctx final : wamct_ctx {
     return WAMCT_OK;
   }
   wamct_status set_subsets(int32_t ns) override {
+    if (ns > 1 && lam > 0.0)
+      return fail(WAMCT_E_UNSUPPORTED, "ordered subsets are not implemented with the roughness penalty");
     if (ns < 1 || ns > g.nv) return fail(WAMCT_E_INVALID, fmt("n_subsets = %d outside [1, n_views = %d]", ns, g.nv));
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipDeviceSynchronize());
@@ -327,6 +331,16 @@ struct Ctx final : wamct_ctx {
     return WAMCT_OK;
   }
   int32_t tree_rule() const override { return rule; }
+  wamct_status set_penalty(double l) override {
+    if (!(l >= 0.0) || !std::isfinite(l)) return fail(WAMCT_E_INVALID, "the penalty weight must be finite and >= 0");
+    if (l > 0.0 && n_sub > 1)
+      return fail(WAMCT_E_UNSUPPORTED, "the roughness penalty is not implemented with ordered subsets");
+    HIPCHK(hipStreamSynchronize(st));
+    if (l > 0.0 && !gpen) CHECKED(alloc(gpen, NN * P));
+    lam = l;
+    return WAMCT_OK;
+  }
+  double penalty() const override { return lam; }
   wamct_status set_tree_sharing(int32_t on) override {
     if (on != 0 && on != 1) return fail(WAMCT_E_INVALID, "shared must be 0 or 1");
     if (on == 1 && rule == WAMCT_RULE_GRADIENT)
@@ -350,8 +364,10 @@ struct Ctx final : wamct_ctx {
       if (segment_part_elems(x, S) > part_cap)
         return fail(WAMCT_E_HIP, "internal: gather partial buffer too small for its tiling");
     const bool tree = &sg == &segs || &sg == &segs_sub;
+    const bool pen = mode == kUpdate && lam > 0.0;
     Geo<T, R>::gather(v.g, mode, vT, views, A, y, tree ? items : nullptr, tree ? ints + 9 : nullptr, sg.data(),
-                      int(sg.size()), part, bt, v.b, v.z0, v.z0stride, held, bp, bm, out, S, s);
+                      int(sg.size()), part, bt, v.b, v.z0, v.z0stride, held, bp, bm, out, S, s,
+                      pen ? gpen : nullptr, lam);
     return WAMCT_OK;
   }
   wamct_status gather(int mode, const T* y, const std::vector<Segment>& sg, int S, T* bt, int* held, T* bp, T* bm,
@@ -600,6 +616,14 @@ struct Ctx final : wamct_ctx {
     }
     const int nbk = forward_pass(s);
     store_idiv(nbk, out, ostride, counted, s);
+    if (lam > 0.0) {
+      // gradient of the roughness penalty at beta-hat for every coefficient:
+      // Omega^T grad R(Omega beta-hat) (mu and part2 are free at this point of an iteration)
+      Scope sc(this, WAMCT_K_OTHER, s);
+      Launch<T>::mu64(g, beta, mu64, part2, P, s);
+      Launch<T>::rough_grad(g, mu64, mu, P, s);
+      for (int p = 0; p < P; ++p) Launch<T>::analysis(g, mu + p * NN, gpen + p * NN, s);
+    }
     {
       Scope sc(this, WAMCT_K_UPDATE, s);
       CHECKED(gather(kUpdate, q, segs, P, beta, ints + 0, nullptr, nullptr, nullptr, s));
@@ -1228,6 +1252,13 @@ wamct_status wamct_set_tiling(wamct_ctx* ctx, int32_t lanes) { CTX_CALL(set_tili
 wamct_status wamct_set_subsets(wamct_ctx* ctx, int32_t n_subsets) { CTX_CALL(set_subsets(n_subsets)); }
 wamct_status wamct_set_tree_sharing(wamct_ctx* ctx, int32_t shared) { CTX_CALL(set_tree_sharing(shared)); }
 wamct_status wamct_set_tree_rule(wamct_ctx* ctx, int32_t rule) { CTX_CALL(set_tree_rule(rule)); }
+wamct_status wamct_set_penalty(wamct_ctx* ctx, double lambda) { CTX_CALL(set_penalty(lambda)); }
+wamct_status wamct_get_penalty(wamct_ctx* ctx, double* lambda) {
+  if (!ctx) { g_last_error = "ctx is NULL"; return WAMCT_E_INVALID; }
+  if (!lambda) return ctx->fail(WAMCT_E_INVALID, "lambda must not be NULL");
+  *lambda = ctx->penalty();
+  return WAMCT_OK;
+}
 wamct_status wamct_get_tree_rule(wamct_ctx* ctx, int32_t* rule) {
   if (!ctx) { g_last_error = "ctx is NULL"; return WAMCT_E_INVALID; }
   if (!rule) return ctx->fail(WAMCT_E_INVALID, "rule must not be NULL");

@@ -591,6 +591,12 @@ struct Ctx3 final : wamct_ctx {
     return WAMCT_OK;
   }
   int32_t tree_rule() const override { return rule; }
+  wamct_status set_penalty(double l) override {
+    if (!(l >= 0.0) || !std::isfinite(l)) return fail(WAMCT_E_INVALID, "the penalty weight must be finite and >= 0");
+    if (l > 0.0) return fail(WAMCT_E_UNSUPPORTED, "the roughness penalty is implemented for 2-D scans");
+    return WAMCT_OK;
+  }
+  double penalty() const override { return 0.0; }
   int n_scans() const override { return 1; }
   hipStream_t stream() const override { return st; }
   double work() const override { return double(M) * double(g.n); }

@@ -45,6 +45,8 @@ struct wamct_ctx {
   virtual int32_t tree_sharing() const = 0;
   virtual wamct_status set_tree_rule(int32_t) = 0;
   virtual int32_t tree_rule() const = 0;
+  virtual wamct_status set_penalty(double) = 0;
+  virtual double penalty() const = 0;
   // stream-ordered pieces used by batches (no host synchronization inside)
   virtual int n_scans() const = 0;
   virtual hipStream_t stream() const = 0;

@@ -81,6 +81,8 @@ struct Launch {
                           hipStream_t s);
   // q <- d - q over len values
   static void residual_inplace(const T* d, T* q, int64_t len, hipStream_t s);
+  // gradient of the roughness penalty of the FP64 images mu64 [S][n][n] -> out [S][n][n]
+  static void rough_grad(const DevGeom& g, const double* mu64, T* out, int S, hipStream_t s);
   // FP64 synthesis of the current beta and per-block maxima. Returns the blocks per scan.
   static int mu64(const DevGeom& g, const T* beta, double* mu64, double* part, int S, hipStream_t s);
   // zero beta outside the mask
@@ -117,7 +119,7 @@ struct Geo {
   static void gather(const DevGeom& g, int mode, const void* vF, const double2* views, const void* A, const T* y,
                      const uint32_t* items, const int* counts, const Segment* segs, int n_segs, void* part,
                      T* beta, const T* b, const double* z0, int z0stride, int* held, T* bp, T* bm, T* out,
-                     int S, hipStream_t s);
+                     int S, hipStream_t s, const T* gpen = nullptr, double lam = 0.0);
 };
 
 // Z0 and W of the current tree: per-ray FP64 sums of |phi| over active coefficients and

@@ -644,12 +644,48 @@ __device__ inline uint32_t item_word(const uint32_t* __restrict__ items, int it,
   return items ? items[it] : item_pack(0, 0, it / n, it % n);
 }
 
+// Roughness-penalized update of one coefficient (FP64): the root of
+//   G(delta) = b - bp exp(-Z0 delta) - bm exp(Z0 delta) + lam (g + 8 delta),
+// the derivative of eq. 1.8's surrogate plus lam times the separable quadratic surrogate of the
+// penalty (curvature 8 bounds the penalty's Hessian). G increases (bp >= 0 >= bm, lam > 0);
+// G(0) fixes the side of the root and |delta| <= |G(0)| / (8 lam). Newton steps that leave the
+// current bracket are replaced by bisection; at most 100 steps, stopping when a Newton step is
+// below 1e-15 of the iterate (converged), the bracket shrinks to 1e-15 of its size or G is 0.
+__device__ inline double pen_G(double dl, double b, double bp, double bm, double z0, double lam, double g,
+                               double* dG) {
+  const double ep = bp != 0.0 ? bp * exp(-z0 * dl) : 0.0;
+  const double em = bm != 0.0 ? bm * exp(z0 * dl) : 0.0;
+  *dG = z0 * (ep - em) + 8.0 * lam;
+  return b - ep - em + lam * (g + 8.0 * dl);
+}
+__device__ inline double pen_delta(double b, double bp, double bm, double z0, double lam, double g) {
+  double dG;
+  const double g0 = pen_G(0.0, b, bp, bm, z0, lam, g, &dG);
+  if (g0 == 0.0) return 0.0;
+  const double w = fabs(g0) / (8.0 * lam);
+  double lo = g0 > 0.0 ? -w : 0.0, hi = g0 > 0.0 ? 0.0 : w;
+  double x = 0.0, gx = g0;
+  const double tol = 1e-15 * w;
+  for (int it = 0; it < 100 && hi - lo > tol; ++it) {
+    const double step = gx / dG;
+    if (fabs(step) <= 1e-15 * fabs(x)) return x;       // Newton has converged
+    double nx = x - step;                              // Newton step from x
+    if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);   // outside the bracket: bisect
+    x = nx;
+    gx = pen_G(x, b, bp, bm, z0, lam, g, &dG);
+    if (gx == 0.0) return x;
+    if (gx < 0.0) lo = x; else hi = x;
+  }
+  return x;
+}
+
 // Final write of one item's sums (scaled by 2^-l): H^T y (plain), b-hat+/- (split), or the
 // closed-form zero of eq. 1.9 applied to beta (update).
 template <typename T, typename R, int MODE>
 __device__ inline void item_finish(const DevGeom& g, uint32_t w, const ItemSums<R>& r, T* __restrict__ beta,
                                    const T* __restrict__ bvec, const double* __restrict__ z0p, int* held,
-                                   T* __restrict__ bp_out, T* __restrict__ bm_out, T* __restrict__ out) {
+                                   T* __restrict__ bp_out, T* __restrict__ bm_out, T* __restrict__ out,
+                                   const T* __restrict__ gpen = nullptr, double lam = 0.0) {
   const int n = g.n;
   const bool quad = (w >> 31) != 0;
   const int l = int((w >> 27) & 15u);
@@ -679,6 +715,24 @@ __device__ inline void item_finish(const DevGeom& g, uint32_t w, const ItemSums<
     return;
   }
   const R z0 = R(*z0p);
+  if (gpen) {   // roughness penalty: root of eq. 1.9's left side plus lam (g + 8 delta)
+    const double z0d = *z0p;
+    if (root) {
+      const int z = i * n + j;
+      beta[z] = T(double(beta[z]) + pen_delta(double(bvec[z]), double(r.acc * sc), 0.0, z0d, lam, double(gpen[z])));
+    }
+    if (quad) {
+      const int z1 = i * n + m + j, z2 = (m + i) * n + j, z3 = (m + i) * n + m + j;
+      const double h = 0.5 * double(sc);
+      beta[z1] = T(double(beta[z1]) + pen_delta(double(bvec[z1]), double(r.a0 + r.s0) * h, double(r.s0 - r.a0) * h,
+                                                z0d, lam, double(gpen[z1])));
+      beta[z2] = T(double(beta[z2]) + pen_delta(double(bvec[z2]), double(r.a1 + r.s1) * h, double(r.s1 - r.a1) * h,
+                                                z0d, lam, double(gpen[z2])));
+      beta[z3] = T(double(beta[z3]) + pen_delta(double(bvec[z3]), double(r.a2 + r.s2) * h, double(r.s2 - r.a2) * h,
+                                                z0d, lam, double(gpen[z3])));
+    }
+    return;
+  }
   if (root) {
     const int z = i * n + j;
     beta[z] = T(R(beta[z]) + am_delta<R>(R(bvec[z]), r.acc * sc, R(0), z0, held));
@@ -716,6 +770,8 @@ struct GatherArgs {
   int z0stride;
   int* held;
   T *bp, *bm, *out;
+  const T* gpen;   // roughness-penalty gradient Omega^T grad R per coefficient (null: no penalty)
+  double lam;      // penalty weight lambda
 };
 
 template <typename T, typename R>
@@ -727,6 +783,7 @@ struct ScanView {
   const double* z0;
   int* held;
   T *bp, *bm, *out;
+  const T* gpen;
   R* part;
   int start, count;
 };
@@ -745,6 +802,7 @@ __device__ inline ScanView<T, R> scan_view(const GatherArgs<T, R>& a) {
   v.bp = at(a.bp, p * NN);
   v.bm = at(a.bm, p * NN);
   v.out = at(a.out, p * NN);
+  v.gpen = at(a.gpen, p * NN);
   v.part = at(a.part, p * a.pstride);
   v.start = a.start;
   v.count = a.count;
@@ -777,7 +835,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs<T, R> a) {
   const uint32_t w = item_word(v.items, v.start + k, a.g.n);
   const ItemSums<R> r = item_sums<T, R>(a.g, a.vf, a.views, a.A, v.y, (w >> 31) != 0, int((w >> 27) & 15u),
                                         int((w >> 13) & 0x1fffu), int(w & 0x1fffu), 0, a.g.nvs);
-  item_finish<T, R, MODE>(a.g, w, r, v.beta, v.b, v.z0, v.held, v.bp, v.bm, v.out);
+  item_finish<T, R, MODE>(a.g, w, r, v.beta, v.b, v.z0, v.held, v.bp, v.bm, v.out, v.gpen, a.lam);
 }
 
 // (item, view chunk) tasks for a level segment whose items alone would leave the GPU idle.
@@ -840,7 +898,7 @@ __global__ __launch_bounds__(512) void k_gather_finish(GatherArgs<T, R> a) {
   if (slot != 0 || idx >= v.count) return;
   const uint32_t w = item_word(v.items, v.start + idx, a.g.n);
   ItemSums<R> r{sh[0][lane], sh[1][lane], sh[2][lane], sh[3][lane], sh[4][lane], sh[5][lane], sh[6][lane]};
-  item_finish<T, R, MODE>(a.g, w, r, v.beta, v.b, v.z0, v.held, v.bp, v.bm, v.out);
+  item_finish<T, R, MODE>(a.g, w, r, v.beta, v.b, v.z0, v.held, v.bp, v.bm, v.out, v.gpen, a.lam);
 }
 
 // ------------------------------------------------------------------ Haar analysis
@@ -1046,6 +1104,26 @@ __global__ __launch_bounds__(kBlock) void k_grad_scores(DevGeom g, const uint8_t
   const double c1 = fabs(double(coef[i * n + m + j])), c2 = fabs(double(coef[(m + i) * n + j]));
   const double c3 = fabs(double(coef[(m + i) * n + m + j]));
   score[i * n + m + j] = fmax(c1, fmax(c2, c3));
+}
+
+// Gradient of the roughness penalty R(mu) = 1/2 sum over 4-neighbour pixel pairs (mu_x -
+// mu_x')^2: out_x = sum over the neighbours x' of x of (mu_x - mu_x'), from the FP64 image
+// (per scan: blockIdx.y).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rough_grad(int n, const double* __restrict__ mu, T* __restrict__ out) {
+  const int64_t off = int64_t(blockIdx.y) * n * n;
+  mu += off;
+  out += off;
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  if (x >= n * n) return;
+  const int i = x / n, j = x - i * n;
+  const double c = mu[x];
+  double gsum = 0.0;
+  if (j > 0) gsum += c - mu[x - 1];
+  if (j < n - 1) gsum += c - mu[x + 1];
+  if (i > 0) gsum += c - mu[x - n];
+  if (i < n - 1) gsum += c - mu[x + n];
+  out[x] = T(gsum);
 }
 
 template <typename T>
@@ -1283,6 +1361,10 @@ template <typename T>
 void Launch<T>::residual_inplace(const T* d, T* q, int64_t len, hipStream_t s) {
   if (len > 0) hipLaunchKernelGGL(k_residual_inplace<T>, dim3(blocks_for(len)), dim3(kBlock), 0, s, len, d, q);
 }
+template <typename T>
+void Launch<T>::rough_grad(const DevGeom& g, const double* mu64, T* out, int S, hipStream_t s) {
+  hipLaunchKernelGGL(k_rough_grad<T>, dim3(blocks_for(int64_t(g.n) * g.n), S), dim3(kBlock), 0, s, g.n, mu64, out);
+}
 template struct Launch<float>;
 template struct Launch<double>;
 
@@ -1346,8 +1428,10 @@ template <typename T, typename R>
 void Geo<T, R>::gather(const DevGeom& g, int mode, const void* vF, const double2* views, const void* A, const T* y,
                        const uint32_t* items, const int* counts, const Segment* segs, int n_segs, void* part,
                        T* beta, const T* b, const double* z0, int z0stride, int* held, T* bp, T* bm, T* out,
-                       int S, hipStream_t s) {
+                       int S, hipStream_t s, const T* gpen, double lam) {
   GatherArgs<T, R> a;
+  a.gpen = gpen;
+  a.lam = lam;
   a.g = g;
   a.vf = (const float2*)vF;
   a.views = views;
