@@ -30,15 +30,23 @@ DETAILS = [(tz, ty, tx) for tz in (0, 1) for ty in (0, 1) for tx in (0, 1) if (t
 
 # ------------------------------------------------------------------ geometry
 
-def rays3(g, views=None):
-    """(origin [M,3], unit direction [M,3]) of the cone-beam rays of the selected views."""
-    ang = g.angle0 + np.arange(g.n_views, dtype=np.float64) * (g.angle_span / g.n_views)
-    if views is not None:
-        ang = ang[np.asarray(views)]
-    u = (np.arange(g.n_cols) - (g.n_cols - 1) / 2.0) * g.col_pitch
-    w = (np.arange(g.n_rows) - (g.n_rows - 1) / 2.0) * g.row_pitch
-    A, W, U = np.meshgrid(ang, w, u, indexing="ij")
-    A, W, U = A.ravel(), W.ravel(), U.ravel()
+def rays3(g, views=None, ids=None):
+    """(origin [M,3], unit direction [M,3]) of the cone-beam rays of the selected views, or
+    of the rays with the given indices y = (v n_rows + rr) n_cols + cc."""
+    if ids is not None:
+        ids = np.asarray(ids, np.int64)
+        v, rr, cc = ids // (g.n_rows * g.n_cols), (ids // g.n_cols) % g.n_rows, ids % g.n_cols
+        A = g.angle0 + v * (g.angle_span / g.n_views)
+        W = (rr - (g.n_rows - 1) / 2.0) * g.row_pitch
+        U = (cc - (g.n_cols - 1) / 2.0) * g.col_pitch
+    else:
+        ang = g.angle0 + np.arange(g.n_views, dtype=np.float64) * (g.angle_span / g.n_views)
+        if views is not None:
+            ang = ang[np.asarray(views)]
+        u = (np.arange(g.n_cols) - (g.n_cols - 1) / 2.0) * g.col_pitch
+        w = (np.arange(g.n_rows) - (g.n_rows - 1) / 2.0) * g.row_pitch
+        A, W, U = np.meshgrid(ang, w, u, indexing="ij")
+        A, W, U = A.ravel(), W.ravel(), U.ravel()
     ca, sa = np.cos(A), np.sin(A)
     src = np.stack([g.sod * ca, g.sod * sa, np.zeros_like(A)], axis=1)
     det = np.stack([-(g.sdd - g.sod) * ca - U * sa, -(g.sdd - g.sod) * sa + U * ca, W], axis=1)
@@ -110,6 +118,88 @@ def trace3(g, o, e):
     return ray_idx, ((s * n + r) * n + c)[keep], seg[keep]
 
 
+def project_rays3(g, vol, ids, rays_per_batch=256):
+    """Line integrals of the volume `vol` [nz, n, n] along the rays with the given indices
+    (one row of H each, traced as in `trace3`)."""
+    o, e = rays3(g, ids=ids)
+    flat = np.asarray(vol, np.float64).ravel()
+    out = np.zeros(o.shape[0])
+    for s0 in range(0, o.shape[0], rays_per_batch):
+        ri, vi, li = trace3(g, o[s0:s0 + rays_per_batch], e[s0:s0 + rays_per_batch])
+        out[s0:s0 + rays_per_batch] = np.bincount(ri, weights=flat[vi] * li, minlength=min(rays_per_batch, o.shape[0] - s0))
+    return out
+
+
+def project_coef_rays3(g, coef, levels, ids, rays_per_batch=256):
+    """Line integrals of the volume Omega coef along the rays with the given indices, with the
+    volume synthesised only at the voxels those rays cross (rows of Omega)."""
+    o, e = rays3(g, ids=ids)
+    flat = np.asarray(coef, np.float64).ravel()
+    out = np.zeros(o.shape[0])
+    for s0 in range(0, o.shape[0], rays_per_batch):
+        ri, vi, li = trace3(g, o[s0:s0 + rays_per_batch], e[s0:s0 + rays_per_batch])
+        uv, inv = np.unique(vi, return_inverse=True)
+        mu = synthesis_matrix3(g.n, g.nz, levels, voxels=uv) @ flat
+        out[s0:s0 + rays_per_batch] = np.bincount(ri, weights=mu[inv] * li, minlength=min(rays_per_batch, o.shape[0] - s0))
+    return out
+
+
+def box_shadow3(g, lo, hi, margin=1):
+    """Indices of the rays that can meet the box [lo, hi): in each view, the detector
+    elements inside the bounding rectangle of the central projections of the box's eight
+    corners, widened by `margin` elements (a superset: a ray through the box meets the
+    detector inside the convex hull of those projections). The box must lie on the
+    detector's side of the source plane."""
+    ang = g.angle0 + np.arange(g.n_views, dtype=np.float64) * (g.angle_span / g.n_views)
+    ca, sa = np.cos(ang)[:, None], np.sin(ang)[:, None]
+    cx = np.array([lo[0], hi[0]])[[0, 1, 0, 1, 0, 1, 0, 1]][None, :]
+    cy = np.array([lo[1], hi[1]])[[0, 0, 1, 1, 0, 0, 1, 1]][None, :]
+    cz = np.array([lo[2], hi[2]])[[0, 0, 0, 0, 1, 1, 1, 1]][None, :]
+    depth = g.sod - (cx * ca + cy * sa)             # distance from the source plane
+    if np.any(depth <= 0):
+        raise ValueError("box reaches behind the source")
+    t = g.sdd / depth
+    u = t * (-cx * sa + cy * ca)
+    w = t * cz
+    c0 = np.floor(u.min(1) / g.col_pitch + (g.n_cols - 1) / 2.0).astype(np.int64) - margin
+    c1 = np.ceil(u.max(1) / g.col_pitch + (g.n_cols - 1) / 2.0).astype(np.int64) + margin
+    r0 = np.floor(w.min(1) / g.row_pitch + (g.n_rows - 1) / 2.0).astype(np.int64) - margin
+    r1 = np.ceil(w.max(1) / g.row_pitch + (g.n_rows - 1) / 2.0).astype(np.int64) + margin
+    out = []
+    for v in range(g.n_views):
+        cols = np.arange(max(c0[v], 0), min(c1[v], g.n_cols - 1) + 1)
+        rows = np.arange(max(r0[v], 0), min(r1[v], g.n_rows - 1) + 1)
+        if cols.size and rows.size:
+            out.append(((v * g.n_rows + rows[:, None]) * g.n_cols + cols[None, :]).ravel())
+    return np.concatenate(out) if out else np.zeros(0, np.int64)
+
+
+def node_phi3(g, o, e, lev, k, i, j):
+    """Projections along the rays (o, e) of the basis functions of node (lev, k, i, j), from
+    the chords of the node's eight octant boxes by direct clipping: a dict from each detail's
+    position (z, y, x) in the Mallat layout to its phi, plus the key 'approx' for the
+    2^(-3 lev / 2)-scaled block sum (a coefficient of the basis when lev is the coarsest level)."""
+    exy, ez = edges3(g)
+    s, h = 1 << lev, 1 << (lev - 1)
+    ch = {}
+    for bz in (0, 1):
+        for by in (0, 1):
+            for bx in (0, 1):
+                lo = np.array([exy[j * s + bx * h], exy[i * s + by * h], ez[k * s + bz * h]])
+                hi = np.array([exy[j * s + (bx + 1) * h], exy[i * s + (by + 1) * h], ez[k * s + (bz + 1) * h]])
+                ch[bz, by, bx] = box_chord3(o, e, lo, hi)
+    sc = 2.0 ** (-1.5 * lev)
+    m, mz = g.n >> lev, g.nz >> lev
+    out = {"approx": sum(ch.values()) * sc}
+    for tz, ty, tx in DETAILS:
+        acc = 0.0
+        for (bz, by, bx), c in ch.items():
+            sgn = (-1.0 if (tz and bz) else 1.0) * (-1.0 if (ty and by) else 1.0) * (-1.0 if (tx and bx) else 1.0)
+            acc = acc + sgn * c
+        out[k + tz * mz, i + ty * m, j + tx * m] = acc * sc
+    return out
+
+
 def system_matrix3(g, views=None, rays_per_batch=2048):
     """H (rays x voxels, CSR) of the cone-beam scan."""
     o, e = rays3(g, views)
@@ -127,15 +217,20 @@ def system_matrix3(g, views=None, rays_per_batch=2048):
 
 # ------------------------------------------------------------------ 3-D Haar
 
-def synthesis_matrix3(n, nz, levels):
+def synthesis_matrix3(n, nz, levels, voxels=None):
     """Omega (voxels x coefficients, CSR), built voxel by voxel: voxel (s, r, c) receives
     2^(-3L/2) from its root's approximation and 2^(-3l/2) sign_t from detail t of the level-l
-    node containing it."""
+    node containing it. With `voxels` (flat indices (s n + r) n + c), only those rows, in
+    that order."""
     if n % (1 << levels) or nz % (1 << levels):
         raise ValueError("volume sides must be divisible by 2^levels")
-    s, r, c = np.meshgrid(np.arange(nz), np.arange(n), np.arange(n), indexing="ij")
-    s, r, c = s.ravel(), r.ravel(), c.ravel()
-    vox = (s * n + r) * n + c
+    if voxels is None:
+        s, r, c = np.meshgrid(np.arange(nz), np.arange(n), np.arange(n), indexing="ij")
+        s, r, c = s.ravel(), r.ravel(), c.ravel()
+    else:
+        flat = np.asarray(voxels, np.int64)
+        s, r, c = flat // (n * n), (flat // n) % n, flat % n
+    vox = np.arange(s.size)
     L = levels
 
     def at(z, y, x):
@@ -157,7 +252,7 @@ def synthesis_matrix3(n, nz, levels):
             cols.append(at(k + tz * mz, i + ty * m, j + tx * m))
             vals.append(sign * 2.0 ** (-1.5 * lev))
     N = n * n * nz
-    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(s.size, N))
 
 
 def cascade_analysis3(vol, levels):
@@ -177,6 +272,29 @@ def cascade_analysis3(vol, levels):
         a = sum(sub.values()) / (2.0 * np.sqrt(2.0))
     out[:a.shape[0], :a.shape[1], :a.shape[2]] = a
     return out
+
+
+def cascade_synthesis3(coef, levels):
+    """Textbook recursive 2x2x2 Haar synthesis, the inverse of `cascade_analysis3`: from the
+    coarsest level down, each approximation and its seven details give the eight children
+    v(bz, by, bx) = sum over t of sign_t(b) c_t / (2 sqrt 2)."""
+    c = np.array(coef, np.float64)
+    nz, n = c.shape[0], c.shape[1]
+    a = c[:nz >> levels, :n >> levels, :n >> levels].copy()
+    for lev in range(levels, 0, -1):
+        m, mz = n >> lev, nz >> lev
+        det = {t: c[t[0] * mz:t[0] * mz + mz, t[1] * m:t[1] * m + m, t[2] * m:t[2] * m + m] for t in DETAILS}
+        out = np.empty((2 * mz, 2 * m, 2 * m))
+        for bz in (0, 1):
+            for by in (0, 1):
+                for bx in (0, 1):
+                    acc = a.copy()
+                    for (tz, ty, tx), dv in det.items():
+                        sgn = (-1.0 if (tz and bz) else 1.0) * (-1.0 if (ty and by) else 1.0) * (-1.0 if (tx and bx) else 1.0)
+                        acc += sgn * dv
+                    out[bz::2, by::2, bx::2] = acc / (2.0 * np.sqrt(2.0))
+        a = out
+    return a
 
 
 # ------------------------------------------------------------------ octree masks

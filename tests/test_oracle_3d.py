@@ -10,6 +10,8 @@
   * noise-free data are a fixed point; the octree rule splits exactly the leaves holding
     a voxel above the threshold (hand-made case).
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -163,3 +165,106 @@ def test_gradient_rule_scores_are_derivatives_and_solve_is_monotone():
     r = vol3d.wam_solve3(H, g.n, g.nz, L, d, i0, 8, g.pixel, schedule=[2, 5], rule="gradient")
     assert np.all(np.diff(r["idiv"]) <= 1e-12 * np.abs(r["idiv"][:-1]))
     assert vol3d.valid_mask3(r["mask"], L) and len(r["trees"]) == 3
+
+
+# ------------------------------------------------------------------ sampled-ray helpers
+
+def test_rays_by_index_and_sampled_projection():
+    g = tiny_geom(8, 4, 5, 6, 12)
+    o, e = vol3d.rays3(g)
+    ids = np.array([0, 5, 71, 72, 200, g.n_rays - 1])
+    o2, e2 = vol3d.rays3(g, ids=ids)
+    np.testing.assert_allclose(o2, o[ids], atol=1e-13)
+    np.testing.assert_allclose(e2, e[ids], atol=1e-15)
+    vol = np.random.default_rng(2).uniform(0, 1, (g.nz, g.n, g.n))
+    H = vol3d.system_matrix3(g)
+    np.testing.assert_allclose(vol3d.project_rays3(g, vol, ids, rays_per_batch=4), (H @ vol.ravel())[ids],
+                               rtol=1e-12, atol=1e-12)
+
+
+def test_cascade_synthesis3_inverts_analysis_and_equals_omega():
+    n, nz, L = 8, 8, 3
+    coef = np.random.default_rng(3).normal(size=(nz, n, n))
+    O = vol3d.synthesis_matrix3(n, nz, L)
+    np.testing.assert_allclose(vol3d.cascade_synthesis3(coef, L).ravel(), O @ coef.ravel(), atol=1e-12)
+    vol = np.random.default_rng(4).normal(size=(4, 8, 8))
+    np.testing.assert_allclose(vol3d.cascade_synthesis3(vol3d.cascade_analysis3(vol, 2), 2), vol, atol=1e-12)
+    rows = np.array([7, 0, 300, 511, 7])
+    np.testing.assert_allclose(vol3d.synthesis_matrix3(n, nz, L, voxels=rows).toarray(), O[rows].toarray(), atol=0)
+
+
+def test_sampled_projection_of_coefficients():
+    g = tiny_geom(8, 8, 5, 6, 12)
+    L = 2
+    coef = np.random.default_rng(7).normal(size=(g.nz, g.n, g.n))
+    ids = np.array([3, 40, 41, 170, 359])
+    ref = (vol3d.system_matrix3(g) @ (vol3d.synthesis_matrix3(g.n, g.nz, L) @ coef.ravel()))[ids]
+    np.testing.assert_allclose(vol3d.project_coef_rays3(g, coef, L, ids, rays_per_batch=2), ref, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(vol3d.project_rays3(g, vol3d.cascade_synthesis3(coef, L), ids), ref,
+                               rtol=1e-12, atol=1e-12)
+
+
+def test_box_shadow_holds_every_ray_through_the_box():
+    g = tiny_geom(8, 4, 7, 9, 15)
+    o, e = vol3d.rays3(g)
+    exy, ez = vol3d.edges3(g)
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        x0, x1 = np.sort(rng.choice(g.n + 1, 2, replace=False))
+        y0, y1 = np.sort(rng.choice(g.n + 1, 2, replace=False))
+        z0, z1 = np.sort(rng.choice(g.nz + 1, 2, replace=False))
+        lo, hi = np.array([exy[x0], exy[y0], ez[z0]]), np.array([exy[x1], exy[y1], ez[z1]])
+        hit = np.flatnonzero(vol3d.box_chord3(o, e, lo, hi) > 0)
+        sh = vol3d.box_shadow3(g, lo, hi)
+        assert np.isin(hit, sh).all()
+        assert np.unique(sh).size == sh.size
+    one = vol3d.box_shadow3(g, np.array([exy[3], exy[3], ez[1]]), np.array([exy[4], exy[4], ez[2]]))
+    assert one.size < g.n_rays // 4
+
+
+def test_node_phi_from_octant_clipping_equals_h_omega():
+    g = tiny_geom(8, 8, 4, 7, 11)
+    L = 2
+    o, e = vol3d.rays3(g)
+    Phi = (vol3d.system_matrix3(g) @ vol3d.synthesis_matrix3(g.n, g.nz, L)).tocsc()
+    n = g.n
+    rng = np.random.default_rng(6)
+    for _ in range(8):
+        lev = int(rng.integers(1, L + 1))
+        k, i, j = (int(x) for x in rng.integers(0, n >> lev, 3))
+        phis = vol3d.node_phi3(g, o, e, lev, k, i, j)
+        keys = [key for key in phis if key != "approx"] + ([(k, i, j)] if lev == L else [])
+        assert len(keys) == 7 + (lev == L)
+        for key in keys:
+            ref = phis["approx"] if key == (k, i, j) and lev == L else phis[key]
+            col = Phi[:, (key[0] * n + key[1]) * n + key[2]].toarray().ravel()
+            assert np.abs(col - ref).max() < 1e-12
+
+
+def longest_chord(g):
+    """Longest chord through the volume over every ray of the scan. The volume is invariant
+    under 90-degree rotations about z and under the mirrors y -> -y and z -> -z; with the
+    orbit starting at angle 0 in 720 equal steps and a detector centred on the central ray,
+    these map the rays of view v onto those of views v + 180 and 720 - v, and row rr onto
+    row n_rows - 1 - rr. Views 0..90 and the lower half of the rows therefore hold every
+    chord length of the scan."""
+    assert g.n_views % 4 == 0 and g.angle0 == 0.0 and abs(g.angle_span - 2 * math.pi) < 1e-15
+    exy, ez = vol3d.edges3(g)
+    lo, hi = np.array([exy[0], exy[0], ez[0]]), np.array([exy[-1], exy[-1], ez[-1]])
+    rows = np.arange((g.n_rows + 1) // 2)
+    cols = np.arange(g.n_cols)
+    best = 0.0
+    for v in range(g.n_views // 8 + 1):
+        ids = ((v * g.n_rows + rows[:, None]) * g.n_cols + cols[None, :]).ravel()
+        o, e = vol3d.rays3(g, ids=ids)
+        best = max(best, float(vol3d.box_chord3(o, e, lo, hi).max()))
+    return best
+
+
+def test_longest_chord_symmetry_reduction():
+    """The reduced scan of `longest_chord` finds the maximum of a full scan."""
+    for g in (synth.cone_geometry(16, 8, 24, 10, 40, sod=40.0, sdd=80.0),
+              synth.cone_geometry(16, 16, 16, 9, 33, sod=30.0, sdd=60.0)):
+        o, e = vol3d.rays3(g)
+        lo = np.array([-g.n / 2, -g.n / 2, -g.nz / 2]) * g.pixel
+        assert abs(longest_chord(g) - vol3d.box_chord3(o, e, lo, -lo).max()) <= 1e-12 * g.n
