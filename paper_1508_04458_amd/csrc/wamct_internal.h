@@ -35,6 +35,24 @@ __host__ __device__ inline uint32_t item_pack(int quad, int l, int i, int j) {
 
 enum GatherMode { kPlain = 0, kSplit = 1, kUpdate = 2 };
 
+// x[0] + x[stride] + ... + x[(n - 1) stride], added strictly in index order (the same
+// rounding as a plain loop), with the loads issued eight at a time so that eight are in
+// flight instead of one.
+template <typename R>
+__device__ inline R ordered_sum(const R* __restrict__ x, int n, size_t stride) {
+  R s = R(0);
+  int c = 0;
+  for (; c + 8 <= n; c += 8) {
+    R v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = x[size_t(c + k) * stride];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += v[k];
+  }
+  for (; c < n; ++c) s += x[size_t(c) * stride];
+  return s;
+}
+
 // A run of work items of one level, processed with its views split into `chunks` ranges
 // of `vpc` views (chunks = 1: one lane per item over all views). For a stack of scans the
 // run of scan p is level index kseg of its per-scan counts (start and length read on the

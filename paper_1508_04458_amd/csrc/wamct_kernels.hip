@@ -70,8 +70,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ pa
                                                    int* __restrict__ ctr) {
   const int p = blockIdx.x;
   part += p * pstride;
-  double v = MAX ? -INFINITY : 0.0;
-  for (int k = threadIdx.x; k < n; k += kBlock) v = MAX ? fmax(v, part[k]) : v + part[k];
+  double v;
+  if (MAX) {
+    v = -INFINITY;
+    for (int k = threadIdx.x; k < n; k += kBlock) v = fmax(v, part[k]);
+  } else {
+    const int cnt = int(threadIdx.x) < n ? (n - 1 - int(threadIdx.x)) / kBlock + 1 : 0;
+    v = ordered_sum(part + threadIdx.x, cnt, size_t(kBlock));
+  }
   v = block_reduce<MAX>(v);
   if (threadIdx.x == 0) {
     int64_t o = p * ostride;
@@ -889,10 +895,8 @@ __global__ __launch_bounds__(512) void k_gather_finish(GatherArgs<T, R> a) {
   const int idx = blockIdx.x * 64 + lane;
   const int groups = (a.chunks + kChunkWaves - 1) / kChunkWaves;
   if (slot < 7) {
-    R s = R(0);
-    if (idx < v.count)
-      for (int c = 0; c < groups; ++c) s += v.part[(size_t(c) * 7 + slot) * a.count + idx];
-    sh[slot][lane] = s;
+    sh[slot][lane] = idx < v.count ? ordered_sum(v.part + size_t(slot) * a.count + idx, groups, size_t(7) * a.count)
+                                   : R(0);
   }
   __syncthreads();
   if (slot != 0 || idx >= v.count) return;

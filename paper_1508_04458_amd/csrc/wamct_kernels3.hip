@@ -697,10 +697,9 @@ __global__ __launch_bounds__(1024) void k3_gather_finish(GArgs3<T> a) {
   const int idx = blockIdx.x * 64 + lane;
   const int groups = (a.chunks + 3) / 4;
   if (slot < kSlots3) {
-    double s = 0.0;
-    if (idx < count)
-      for (int c = 0; c < groups; ++c) s += a.part[(size_t(c) * kSlots3 + slot) * a.count + idx];
-    sh[slot][lane] = s;
+    sh[slot][lane] = idx < count ? ordered_sum(a.part + size_t(slot) * a.count + idx, groups,
+                                               size_t(kSlots3) * a.count)
+                                 : 0.0;
   }
   __syncthreads();
   if (slot != 0 || idx >= count) return;
