@@ -389,3 +389,36 @@ def test_fp32_ray_geometry_matches_oracle():
     print(f"beta rel L2 {err:.2e}, idiv max rel {np.max(np.abs(idv / ref['idiv'] - 1)):.2e}", flush=True)
     assert err <= 1e-4
     np.testing.assert_allclose(idv, ref["idiv"], rtol=2e-5)
+
+
+def test_golden_hand_example_on_the_gpu():
+    """The smallest problem (2x2 image, 4 views x 2 bins, one Haar level), against the values
+    derived by hand in tests/golden/tiny2x2_parallel.txt: H column by column, Phi row by row
+    (split backprojection of unit ray vectors on the full tree), Z0 of the approximation-only
+    tree, the full tree and pixel AM, and one update of each kind. FP64 at 1e-12."""
+    from golden_io import load
+    gold = load("tiny2x2_parallel.txt")
+    g = synth.parallel_geometry(2, 4, 2, 1.0)
+    c0 = make_ctx(g, 0, "f64")
+    for x in range(4):
+        e = np.zeros(4)
+        e[x] = 1.0
+        col = host(c0.project(dev(e, "f64")))
+        np.testing.assert_allclose(col, [gold[f"H_row {r}"][x] for r in range(8)], atol=1e-12)
+    c = make_ctx(g, 1, "f64", np.full(8, 50.0), 100.0)
+    assert abs(c.tree_stats()["z0"] - gold["Z0_approx"][0]) <= 1e-12
+    c.set_state(dev(np.zeros(4), "f64"), dev(haar.full_mask(2).ravel(), torch.uint8))
+    assert abs(c.tree_stats()["z0"] - gold["Z0_full"][0]) <= 1e-12
+    for r in range(8):
+        y = np.zeros(8)
+        y[r] = 1.0
+        bp, bm = (host(t).ravel() for t in c.backproject_split(dev(y, "f64")))
+        np.testing.assert_allclose(bp + bm, gold[f"Phi_row {r}"], atol=1e-12)
+        np.testing.assert_allclose(bp, np.maximum(gold[f"Phi_row {r}"], 0), atol=1e-12)
+    c1 = make_ctx(g, 1, "f64", np.full(8, 50.0), 100.0)
+    c1.iterate(1)
+    np.testing.assert_allclose(host(c1.synthesize()).ravel(), gold["step_approx_mu"][0], rtol=1e-12)
+    cp = make_ctx(g, 0, "f64", np.asarray(gold["step_pixel_d"]), 100.0)
+    assert abs(cp.tree_stats()["z0"] - gold["Z0_pixel"][0]) <= 1e-12
+    cp.iterate(1)
+    np.testing.assert_allclose(host(cp.synthesize()).ravel(), gold["step_pixel_mu"], rtol=1e-12)
