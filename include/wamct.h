@@ -124,7 +124,9 @@ typedef struct wamct_ctx wamct_ctx;   /* opaque; owns every device work buffer *
  * the iteration needs (iterating allocates nothing), builds the ray table and the
  * approximation-only tree (Results: the initial tree) with beta = 0 (beta^(0) is an input
  * of Algorithm 1 whose value the paper does not give). `stream` is a hipStream_t
- * (NULL = default stream). On success *out owns the context (free with wamct_destroy). */
+ * (NULL = default stream). On success *out owns the context (free with wamct_destroy).
+ * A scan none of whose rays crosses the image has Z0 = 0 (eq. 1.61), for which the update
+ * is undefined: creation then fails with WAMCT_E_INVALID. */
 wamct_status wamct_create(const wamct_geometry* geom, const wamct_options* opt,
                           void* stream, wamct_ctx** out);
 wamct_status wamct_destroy(wamct_ctx* ctx);

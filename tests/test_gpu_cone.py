@@ -280,3 +280,15 @@ def test_cone_errors():
     with pytest.raises(_lib.WamctError) as e:
         c.set_subsets(3)
     assert e.value.status == _lib.E_UNSUPPORTED
+
+
+def test_cone_scan_that_misses_the_volume_is_rejected():
+    """Every detector element far outside the volume's shadow: Z0 = 0, and creating the
+    context fails with WAMCT_E_INVALID (octree and voxel AM alike)."""
+    from paper_1508_04458_amd import _lib
+    base = synth.cone_geometry(8, 4, 3, 2, 2, sod=40.0, sdd=70.0)
+    g = synth.Geometry3(**{**base.__dict__, "col_pitch": 200.0, "row_pitch": 200.0})
+    for levels in (0, 1):
+        with pytest.raises(_lib.WamctError) as e:
+            make_ctx(g, levels, "f64")
+        assert e.value.status == _lib.E_INVALID and "Z0 = 0" in str(e.value)

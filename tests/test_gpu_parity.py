@@ -422,3 +422,14 @@ def test_golden_hand_example_on_the_gpu():
     assert abs(cp.tree_stats()["z0"] - gold["Z0_pixel"][0]) <= 1e-12
     cp.iterate(1)
     np.testing.assert_allclose(host(cp.synthesize()).ravel(), gold["step_pixel_mu"], rtol=1e-12)
+
+
+def test_scan_that_misses_the_image_is_rejected():
+    """No ray crosses the image (every bin outside it): Z0 = 0, the update is undefined, and
+    creating the context fails with WAMCT_E_INVALID (tree and pixel AM alike)."""
+    from paper_1508_04458_amd import _lib
+    g = synth.parallel_geometry(8, 3, 2, 100.0)        # bins at u = -50 and +50 mm
+    for levels in (0, 1):
+        with pytest.raises(_lib.WamctError) as e:
+            make_ctx(g, levels, "f64")
+        assert e.value.status == _lib.E_INVALID and "Z0 = 0" in str(e.value)
