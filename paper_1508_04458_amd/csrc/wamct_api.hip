@@ -82,6 +82,7 @@ struct Ctx final : wamct_ctx {
   void *leafR = nullptr, *leafC = nullptr;  // leaf records (value | level) for the tree walk
   uint8_t *mask = nullptr, *mask_old = nullptr, *lev = nullptr;
   uint32_t* items = nullptr;
+  int* list_tmp = nullptr;      // block counts and offsets of the work-list builder
   double *partd = nullptr, *part2 = nullptr, *mu64 = nullptr;
   double* scal = nullptr;     // [P][kScal]
   int* ints = nullptr;        // [P][kInts]
@@ -407,6 +408,7 @@ struct Ctx final : wamct_ctx {
     }
     CHECKED(alloc(mask, NN * P)); CHECKED(alloc(mask_old, NN * P)); CHECKED(alloc(lev, NN * P));
     CHECKED(alloc(items, NN * P)); CHECKED(alloc(mu64, NN * P));
+    CHECKED(alloc(list_tmp, list_scratch_ints(g, P)));
     CHECKED(alloc(partd, int64_t(np) * P)); CHECKED(alloc(part2, int64_t(np) * P));
     CHECKED(alloc(scal, int64_t(kScal) * P)); CHECKED(alloc(ints, int64_t(kInts) * P));
     CHECKED(alloc(i0one, 1));
@@ -486,7 +488,7 @@ struct Ctx final : wamct_ctx {
   wamct_status enq_tree(hipStream_t s) override {
     {
       Scope sc(this, WAMCT_K_TREE, s);
-      build_items(g, mask, items, ints + 8, P, s);
+      build_items(g, mask, items, ints + 8, P, list_tmp, s);
       Launch<T>::levmap(g, mask, lev, P, s);
       const int nbk = z0_partials(g, views, lev, partd, part2, P, s);
       reduce_stack(true, partd, nbk, nbk, scal + 0, kScal, nullptr, P, s);

@@ -61,6 +61,7 @@ struct Ctx3 final : wamct_ctx {
   void *recR = nullptr, *recC = nullptr;
   uint8_t *mask = nullptr, *mask_old = nullptr, *lev = nullptr;
   uint32_t* items = nullptr;
+  int* list_tmp = nullptr;      // block counts and offsets of the work-list builder
   double *partd = nullptr, *part2 = nullptr, *mu64 = nullptr, *scal = nullptr;  // [0] Z0 [1] W [2] max [3] tmp [4] I0
   int* ints = nullptr;  // [0] held [1] bad [2] n_split [3] iteration counter [8] items [9 + k] level counts
   T* beta_save = nullptr;
@@ -223,6 +224,7 @@ struct Ctx3 final : wamct_ctx {
     CHECKED(alloc(rr, N)); CHECKED(alloc(rc, N));
     recR = rr; recC = rc;
     CHECKED(alloc(mask, N)); CHECKED(alloc(mask_old, N)); CHECKED(alloc(lev, N)); CHECKED(alloc(items, N));
+    CHECKED(alloc(list_tmp, list_scratch_ints3(g)));
     CHECKED(alloc(partd, np)); CHECKED(alloc(part2, np)); CHECKED(alloc(scal, kScal)); CHECKED(alloc(ints, kInts));
     CHECKED(ensure_part(target_lanes));
     vox_segs = {make_segment(-1, 0, int(N), 0)};
@@ -281,7 +283,7 @@ struct Ctx3 final : wamct_ctx {
   wamct_status enq_tree(hipStream_t s) override {
     {
       Scope sc(this, WAMCT_K_TREE, s);
-      build_items3(g, mask, items, ints + 8, s);
+      build_items3(g, mask, items, ints + 8, list_tmp, s);
       levmap3(g, mask, lev, s);
       const int nbk = z0_partials3(g, A, B, C, lev, partd, part2, s);
       reduce_max(partd, nbk, scal + 0, s);

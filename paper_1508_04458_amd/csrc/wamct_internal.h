@@ -156,7 +156,11 @@ void reduce_stack(bool max, const double* part, int n, int64_t pstride, double* 
 // Morton order within a level), compacted with wave ballots; per scan counts[0] = number
 // of items, counts[1 + k] = items of level L - k (k = 0..L; level 0 only when L = 0);
 // counts at stride kInts, items at stride n*n.
-void build_items(const DevGeom& g, const uint8_t* mask, uint32_t* items, int* counts, int S, hipStream_t s);
+// work lists of the active trees (items, per-scan counts at stride kInts); `scratch` holds
+// list_scratch_ints(g, S) ints
+int64_t list_scratch_ints(const DevGeom& g, int S);
+void build_items(const DevGeom& g, const uint8_t* mask, uint32_t* items, int* counts, int S, int* scratch,
+                 hipStream_t s);
 // Tree rule: split every leaf of mask_old whose value exceeds frac * max (maxv at stride
 // kScal, n_split at stride kInts). rule 0: the FP64 image mu64 (leaf-constant); rule 1: the
 // leaf scores of grad_scores held in mu64 at each node's first detail position.

@@ -73,7 +73,10 @@ void levmap3(const DevGeom3& g, const uint8_t* mask, uint8_t* lev, hipStream_t s
 // Work list in segments: split roots, roots not split (every voxel when L = 0), then split
 // nodes level by level (L - 1 down to 1), 3-D Morton order within a segment; counts[0] =
 // items, counts[1 + k] = items of segment k.
-void build_items3(const DevGeom3& g, const uint8_t* mask, uint32_t* items, int* counts, hipStream_t s);
+// octree work list (items, counts); `scratch` holds list_scratch_ints3(g) ints
+int64_t list_scratch_ints3(const DevGeom3& g);
+void build_items3(const DevGeom3& g, const uint8_t* mask, uint32_t* items, int* counts, int* scratch,
+                  hipStream_t s);
 // rule 0: leaf-constant values of mu64; rule 1: leaf scores of grad_scores held in mu64
 void expand3(const DevGeom3& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64, const double* maxv,
              double frac, int* n_split, hipStream_t s, int rule = 0);

@@ -9,6 +9,7 @@
 
 #include "wamct_internal.h"
 #include "wamct_geom.h"
+#include "wamct_worklist.h"
 
 namespace wamct {
 namespace {
@@ -1207,68 +1208,6 @@ __global__ void k_approx_mask(int n, int L, uint8_t* __restrict__ mask) {
   mask[z] = (L == 0 || ((z / n) < nL && (z % n) < nL)) ? 1 : 0;
 }
 
-// Single work-group compaction of the work list. Levels from L down to 1 (L = 0: pixels);
-// within a level the nodes are visited in Morton order (spatially compact waves). Each
-// wave forms its inclusion mask with a ballot, each lane its offset with mbcnt, and the
-// wave totals are prefix-summed in LDS; order is deterministic.
-__global__ __launch_bounds__(1024) void k_items(DevGeom g, const uint8_t* __restrict__ mask,
-                                                uint32_t* __restrict__ items, int* __restrict__ counts) {
-  __shared__ int wave_tot[16];
-  __shared__ int base_sh;
-  const int n = g.n, L = g.L;
-  {
-    const int64_t off = int64_t(blockIdx.x) * n * n;
-    mask += off;
-    items += off;
-    counts += blockIdx.x * kInts;
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (threadIdx.x == 0) base_sh = 0;
-  __syncthreads();
-  const int lmin = (L == 0) ? 0 : 1;
-  for (int l = L; l >= lmin; --l) {
-    const int level_start = base_sh;
-    const int m = n >> l;
-    int pw = 1;
-    while (pw < m) pw <<= 1;
-    const int64_t total = int64_t(pw) * pw;
-    // the roots' segment lists the split roots first, then the others (waves of one kind)
-    const int passes = (l == L && L > 0) ? 2 : 1;
-    for (int64_t base = 0; base < passes * total; base += 1024) {
-      const int64_t code = base + threadIdx.x;
-      const int pass = int(code / total);
-      const int64_t kk = code - pass * total;
-      bool inc = false;
-      uint32_t word = 0;
-      if (pass < passes) {
-        const int j = int(morton_compact(uint32_t(kk)));
-        const int i = int(morton_compact(uint32_t(kk >> 1)));
-        if (i < m && j < m) {
-          const bool sp = l > 0 && is_split(mask, n, l, i, j);
-          inc = l == L ? (passes == 1 || (pass == 0) == sp) : sp;
-          word = item_pack(sp ? 1 : 0, l, i, j);
-        }
-      }
-      const uint64_t bal = __ballot(inc);
-      const int before = __popcll(bal & ((uint64_t(1) << lane) - 1));
-      if (lane == 0) wave_tot[wv] = __popcll(bal);
-      __syncthreads();
-      int off = base_sh;
-      for (int w2 = 0; w2 < wv; ++w2) off += wave_tot[w2];
-      if (inc) items[off + before] = word;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w2 = 0; w2 < 16; ++w2) t += wave_tot[w2];
-        base_sh += t;
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) counts[1 + (L - l)] = base_sh - level_start;
-  }
-  if (threadIdx.x == 0) counts[0] = base_sh;
-}
-
 __global__ void k_fill_u8(uint8_t* x, int64_t len, uint8_t v) {
   const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (p < len) x[p] = v;
@@ -1497,8 +1436,59 @@ void reduce_stack(bool max, const double* part, int n, int64_t pstride, double* 
   else
     hipLaunchKernelGGL(k_reduce<false>, dim3(S), dim3(kBlock), 0, s, part, n, pstride, out, ostride, ctr);
 }
-void build_items(const DevGeom& g, const uint8_t* mask, uint32_t* items, int* counts, int S, hipStream_t s) {
-  hipLaunchKernelGGL(k_items, dim3(S), dim3(1024), 0, s, g, mask, items, counts);
+namespace {
+// Node of Morton code `code` on level l of scan `scan`: kept by the filter of its pass.
+struct ListSpec2 {
+  const uint8_t* mask;
+  int n;
+  __device__ bool keep(int scan, int l, int filter, int64_t code, uint32_t& word) const {
+    const int j = int(morton_compact(uint32_t(code))), i = int(morton_compact(uint32_t(code >> 1)));
+    const int m = n >> l;
+    if (i >= m || j >= m) return false;
+    const bool sp = l > 0 && is_split(mask + int64_t(scan) * n * n, n, l, i, j);
+    word = item_pack(sp ? 1 : 0, l, i, j);
+    return filter == 2 || (filter == 0) == sp;
+  }
+};
+
+// Levels coarse to fine; the roots' level lists its split roots first, then the others
+// (waves of one kind). Count slot 1 + (L - l) per level; every pixel when L = 0.
+PassTable list_passes(const DevGeom& g) {
+  PassTable pt{};
+  const int L = g.L;
+  for (int l = L; l >= (L == 0 ? 0 : 1); --l) {
+    const int m = g.n >> l;
+    int pw = 1;
+    while (pw < m) pw <<= 1;
+    const int64_t codes = int64_t(pw) * pw;
+    if (L == 0) {
+      add_pass(pt, 0, 2, 1, codes);
+    } else if (l == L) {
+      add_pass(pt, l, 0, 1, codes);
+      add_pass(pt, l, 1, 1, codes);
+    } else {
+      add_pass(pt, l, 0, 1 + (L - l), codes);
+    }
+  }
+  return pt;
+}
+}  // namespace
+
+int64_t list_scratch_ints(const DevGeom& g, int S) {
+  const PassTable pt = list_passes(g);
+  return 2 * int64_t(S) * pt.blk_start[pt.n_pass];
+}
+void build_items(const DevGeom& g, const uint8_t* mask, uint32_t* items, int* counts, int S, int* scratch,
+                 hipStream_t s) {
+  const PassTable pt = list_passes(g);
+  const int nblk = pt.blk_start[pt.n_pass];
+  int* bcount = scratch;
+  int* boff = scratch + int64_t(S) * nblk;
+  const ListSpec2 sp{mask, g.n};
+  hipLaunchKernelGGL(k_list_count<ListSpec2>, dim3(nblk, S), dim3(kListThreads), 0, s, sp, pt, bcount);
+  hipLaunchKernelGGL(k_list_scan, dim3(S), dim3(kListThreads), 0, s, pt, bcount, boff, counts, kInts);
+  hipLaunchKernelGGL(k_list_write<ListSpec2>, dim3(nblk, S), dim3(kListThreads), 0, s, sp, pt, boff, items,
+                     int64_t(g.n) * g.n);
 }
 void expand(const DevGeom& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64,
             const double* maxv, double frac, int* n_split, int S, hipStream_t s, int rule) {

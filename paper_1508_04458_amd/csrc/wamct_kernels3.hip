@@ -11,6 +11,7 @@
 #include <algorithm>
 
 #include "wamct_internal3.h"
+#include "wamct_worklist.h"
 
 namespace wamct {
 namespace {
@@ -880,59 +881,6 @@ __global__ __launch_bounds__(kB) void k3_expand(DevGeom3 g, const uint8_t* __res
   }
 }
 
-// Single work-group compaction of the work list in segments: 0 = split roots, 1 = roots not
-// split (with L = 0: every voxel), 2 + m = split nodes of level L - 1 - m; 3-D Morton order
-// within a segment, wave ballots + LDS prefix, order deterministic.
-__global__ __launch_bounds__(1024) void k3_items(DevGeom3 g, const uint8_t* __restrict__ mask,
-                                                 uint32_t* __restrict__ items, int* __restrict__ counts) {
-  __shared__ int wave_tot[16];
-  __shared__ int base_sh;
-  const int n = g.n, nz = g.nz, L = g.L;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (threadIdx.x == 0) base_sh = 0;
-  __syncthreads();
-  const int n_seg = L >= 1 ? L + 1 : 2;
-  for (int sgi = 0; sgi < n_seg; ++sgi) {
-    const int l = sgi <= 1 ? L : L - (sgi - 1);
-    const int level_start = base_sh;
-    const int m = n >> l, mz = nz >> l;
-    int pw = 1;
-    while (pw < m || pw < mz) pw <<= 1;
-    const int64_t total = int64_t(pw) * pw * pw;
-    for (int64_t base = 0; base < total; base += 1024) {
-      const int64_t code = base + threadIdx.x;
-      bool inc = false;
-      uint32_t word = 0;
-      if (code < total) {
-        const int j = int(morton3_compact(uint32_t(code)));
-        const int i = int(morton3_compact(uint32_t(code >> 1)));
-        const int k = int(morton3_compact(uint32_t(code >> 2)));
-        if (i < m && j < m && k < mz) {
-          const bool sp = l > 0 && split3(mask, n, l, k, i, j);
-          inc = sgi == 1 ? !sp : sp;
-          word = item3_pack(sp ? 1 : 0, l, k, i, j);
-        }
-      }
-      const uint64_t bal = __ballot(inc);
-      const int before = __popcll(bal & ((uint64_t(1) << lane) - 1));
-      if (lane == 0) wave_tot[wv] = __popcll(bal);
-      __syncthreads();
-      int off = base_sh;
-      for (int w2 = 0; w2 < wv; ++w2) off += wave_tot[w2];
-      if (inc) items[off + before] = word;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w2 = 0; w2 < 16; ++w2) t += wave_tot[w2];
-        base_sh += t;
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) counts[1 + sgi] = base_sh - level_start;
-  }
-  if (threadIdx.x == 0) counts[0] = base_sh;
-}
-
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -1047,8 +995,56 @@ int z0_partials3(const DevGeom3& g, const void* A, const void* B, const double* 
 void levmap3(const DevGeom3& g, const uint8_t* mask, uint8_t* lev, hipStream_t s) {
   hipLaunchKernelGGL(k3_levmap, dim3(blocks3(int64_t(g.n) * g.n * g.nz)), dim3(kB), 0, s, g, mask, lev);
 }
-void build_items3(const DevGeom3& g, const uint8_t* mask, uint32_t* items, int* counts, hipStream_t s) {
-  hipLaunchKernelGGL(k3_items, dim3(1), dim3(1024), 0, s, g, mask, items, counts);
+namespace {
+struct ListSpec3 {
+  const uint8_t* mask;
+  int n, nz;
+  __device__ bool keep(int, int l, int filter, int64_t code, uint32_t& word) const {
+    const int j = int(morton3_compact(uint32_t(code)));
+    const int i = int(morton3_compact(uint32_t(code >> 1)));
+    const int k = int(morton3_compact(uint32_t(code >> 2)));
+    const int m = n >> l, mz = nz >> l;
+    if (i >= m || j >= m || k >= mz) return false;
+    const bool sp = l > 0 && split3(mask, n, l, k, i, j);
+    word = item3_pack(sp ? 1 : 0, l, k, i, j);
+    return filter == 2 || (filter == 0) == sp;
+  }
+};
+
+// Segments (count slot 1 + segment): split roots, unsplit roots, then the split nodes of
+// levels L - 1 .. 1; with L = 0 the first is empty and the second holds every voxel.
+PassTable list_passes3(const DevGeom3& g) {
+  PassTable pt{};
+  const int L = g.L;
+  const int n_seg = L >= 1 ? L + 1 : 2;
+  for (int sgi = 0; sgi < n_seg; ++sgi) {
+    const int l = sgi <= 1 ? L : L - (sgi - 1);
+    const int m = g.n >> l, mz = g.nz >> l;
+    int pw = 1;
+    while (pw < m || pw < mz) pw <<= 1;
+    const int filter = sgi == 1 ? 1 : 0;
+    const int64_t codes = (l == 0 && filter == 0) ? 0 : int64_t(pw) * pw * pw;
+    add_pass(pt, l, filter, 1 + sgi, codes);
+  }
+  return pt;
+}
+}  // namespace
+
+int64_t list_scratch_ints3(const DevGeom3& g) {
+  const PassTable pt = list_passes3(g);
+  return 2 * int64_t(pt.blk_start[pt.n_pass]);
+}
+void build_items3(const DevGeom3& g, const uint8_t* mask, uint32_t* items, int* counts, int* scratch,
+                  hipStream_t s) {
+  const PassTable pt = list_passes3(g);
+  const int nblk = pt.blk_start[pt.n_pass];
+  int* bcount = scratch;
+  int* boff = scratch + nblk;
+  const ListSpec3 sp{mask, g.n, g.nz};
+  hipLaunchKernelGGL(k_list_count<ListSpec3>, dim3(nblk, 1), dim3(kListThreads), 0, s, sp, pt, bcount);
+  hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(kListThreads), 0, s, pt, bcount, boff, counts, kInts);
+  hipLaunchKernelGGL(k_list_write<ListSpec3>, dim3(nblk, 1), dim3(kListThreads), 0, s, sp, pt, boff, items,
+                     int64_t(0));
 }
 void expand3(const DevGeom3& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64, const double* maxv,
              double frac, int* n_split, hipStream_t s, int rule) {
