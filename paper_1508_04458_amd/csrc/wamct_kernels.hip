@@ -979,9 +979,10 @@ __global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ x, int64_t len,
 
 // Per ray in FP64: walk the leaves; every leaf chord adds s_k(quadrant) * chord to the
 // three detail accumulators of each split ancestor (levels above the leaf), and chord to
-// the approximation accumulator of its root. When the ray leaves a node, its |phi| =
-// 2^-m |acc_k| are added to the ray's sum and the non-zero ones counted. Z0 is the
-// maximum of the sums over rays; W the total count.
+// the approximation accumulator of its root. When the ray leaves a node (a bit at or above
+// the node's level differs between the pixels of consecutive leaves), its |phi| =
+// 2^-m |acc_k| are added to the ray's sum and the non-zero ones counted. Z0 is the maximum
+// of the sums over rays; W the total count.
 __device__ inline double flip_sign(double v, int neg) {
   return __longlong_as_double(__double_as_longlong(v) ^ (static_cast<long long>(neg) << 63));
 }
@@ -989,34 +990,32 @@ __device__ inline double flip_sign(double v, int neg) {
 template <int LT>
 struct Z0Visitor {
   double tolm[LT + 1];    // count threshold per level, unscaled (index 0: root approximations)
-  double tot[LT + 1];     // per level: sum of |detail sums| over the nodes left so far
+  double sc[LT + 1];      // 2^-m per level (index 0: 2^-LT, the roots)
   double acc[LT + 1][3];
-  int cur[LT + 1];
   double accLL;
-  int curLL;
-  double cnt;
+  double sum;
+  int cnt;
+  int px, py;             // pixel of the previous leaf (all bits set before the first)
   __device__ inline void flush_level(int m) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double a = fabs(acc[m][k]);
-      tot[m] += a;
-      cnt += (a > tolm[m]) ? 1.0 : 0.0;
+      sum = fma(a, sc[m], sum);
+      cnt += (a > tolm[m]) ? 1 : 0;
       acc[m][k] = 0.0;
     }
   }
   __device__ inline void flush_ll() {
-    tot[0] += accLL;
-    cnt += (accLL > tolm[0]) ? 1.0 : 0.0;
+    sum = fma(accLL, sc[0], sum);
+    cnt += (accLL > tolm[0]) ? 1 : 0;
     accLL = 0.0;
   }
   __device__ inline void operator()(int ix, int iy, int l, double chord) {
+    const int dif = (ix ^ px) | (iy ^ py);
+    px = ix; py = iy;
 #pragma unroll
     for (int m = 1; m <= LT; ++m) {
-      const int node = ((iy >> m) << 16) | (ix >> m);
-      if (node != cur[m]) {
-        if (cur[m] >= 0) flush_level(m);
-        cur[m] = node;
-      }
+      if (dif >> m) flush_level(m);   // a new node at level m (empty sums before the first leaf)
       if (m > l) {
         const int right = (ix >> (m - 1)) & 1, bottom = (iy >> (m - 1)) & 1;
         const double cr = flip_sign(chord, right);
@@ -1025,11 +1024,7 @@ struct Z0Visitor {
         acc[m][2] += flip_sign(cr, bottom);
       }
     }
-    const int root = ((iy >> LT) << 16) | (ix >> LT);
-    if (root != curLL) {
-      if (curLL >= 0) flush_ll();
-      curLL = root;
-    }
+    if (dif >> LT) flush_ll();
     accLL += chord;
   }
 };
@@ -1049,26 +1044,21 @@ __global__ __launch_bounds__(kBlock) void k_z0(DevGeom g, const double2* __restr
     ray_of(g, views[v], b, ox, oy, ex, ey);
     Z0Visitor<LT> z;
     const double tol = 1e-9 * g.pixel;
+    z.sc[0] = 1.0 / double(1 << LT);
     z.tolm[0] = tol * double(1 << LT);
-    z.tot[0] = 0.0;
 #pragma unroll
     for (int m = 1; m <= LT; ++m) {
+      z.sc[m] = 1.0 / double(1 << m);
       z.tolm[m] = tol * double(1 << m);
-      z.tot[m] = 0.0;
-      z.cur[m] = -1;
       z.acc[m][0] = z.acc[m][1] = z.acc[m][2] = 0.0;
     }
-    z.accLL = 0.0; z.curLL = -1; z.cnt = 0.0;
+    z.accLL = 0.0; z.sum = 0.0; z.cnt = 0; z.px = z.py = -1;
     walk<double, (LT > 0)>(g, ox, oy, ex, ey, 1.0 / ex, 1.0 / ey, lev, z);
 #pragma unroll
-    for (int m = 1; m <= LT; ++m)
-      if (z.cur[m] >= 0) z.flush_level(m);
-    if (z.curLL >= 0) z.flush_ll();
-    // phi of a level-m detail is 2^-m x its signed chord sum, of a root 2^-L x its chord
-    sum = z.tot[0] / double(1 << LT);
-#pragma unroll
-    for (int m = 1; m <= LT; ++m) sum += z.tot[m] / double(1 << m);
-    cnt = z.cnt;
+    for (int m = 1; m <= LT; ++m) z.flush_level(m);
+    z.flush_ll();
+    sum = z.sum;
+    cnt = double(z.cnt);
   }
   const double mx = block_reduce<true>(sum);
   __syncthreads();

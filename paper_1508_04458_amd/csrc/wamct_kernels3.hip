@@ -719,40 +719,39 @@ __device__ inline double flip_sign(double v, int neg) {
 
 // Per ray in FP64: walk the octree leaves; every leaf chord adds sign_d(octant) * chord to
 // the seven signed detail sums of each split ancestor, and chord to its root's approximation
-// sum; when the ray leaves a node, |sum| of its details enter the ray's level total and the
-// non-zero ones are counted (threshold 1e-9 pixel on the scaled value). The ray's value is
-// sum over levels of 2^(-3m/2) x its level total; Z0 = max over rays, W = total count.
+// sum; when the ray leaves a node (a bit at or above the node's level differs between the
+// voxels of consecutive leaves), 2^(-3m/2) |sum| of its details enter the ray's total and
+// the non-zero ones are counted (threshold 1e-9 pixel on the scaled value). Z0 = max over
+// rays of the totals, W = total count.
 template <int LT>
 struct Z0Vis3 {
-  double tolm[LT + 1];     // count threshold per level, unscaled
-  double tot[LT + 1];      // per level: sum of |detail sums| (index 0: root approximations)
-  double cnt;
+  double tolm[LT + 1];     // count threshold per level, unscaled (index 0: root approximations)
+  double sc[LT + 1];       // 2^(-3m/2) per level (index 0: 2^(-3 LT / 2), the roots)
   double acc[LT + 1][7];
   double accLL;
-  int cur[LT + 1];
-  int curLL;
+  double sum;
+  int cnt;
+  int px, py, pz;          // voxel of the previous leaf (all bits set before the first)
   __device__ void flush(int m) {
 #pragma unroll
     for (int d = 0; d < 7; ++d) {
       const double a = fabs(acc[m][d]);
-      tot[m] += a;
-      cnt += a > tolm[m] ? 1.0 : 0.0;
+      sum = fma(a, sc[m], sum);
+      cnt += a > tolm[m] ? 1 : 0;
       acc[m][d] = 0.0;
     }
   }
   __device__ void flushLL() {
-    tot[0] += accLL;
-    cnt += accLL > tolm[0] ? 1.0 : 0.0;
+    sum = fma(accLL, sc[0], sum);
+    cnt += accLL > tolm[0] ? 1 : 0;
     accLL = 0.0;
   }
   __device__ void visit(int ix, int iy, int iz, int l, double chord) {
+    const int dif = (ix ^ px) | (iy ^ py) | (iz ^ pz);
+    px = ix; py = iy; pz = iz;
 #pragma unroll
     for (int m = 1; m <= LT; ++m) {
-      const int node = ((iz >> m) << 18) | ((iy >> m) << 9) | (ix >> m);
-      if (node != cur[m]) {
-        if (cur[m] >= 0) flush(m);
-        cur[m] = node;
-      }
+      if (dif >> m) flush(m);    // a new node at level m (empty sums before the first leaf)
       if (m > l) {
         const int bx = (ix >> (m - 1)) & 1, by = (iy >> (m - 1)) & 1, bz = (iz >> (m - 1)) & 1;
         const double cx = flip_sign(chord, bx), cy = flip_sign(chord, by), cxy = flip_sign(cx, by);
@@ -765,11 +764,7 @@ struct Z0Vis3 {
         acc[m][6] += flip_sign(cxy, bz);
       }
     }
-    const int root = ((iz >> LT) << 18) | ((iy >> LT) << 9) | (ix >> LT);
-    if (root != curLL) {
-      if (curLL >= 0) flushLL();
-      curLL = root;
-    }
+    if (dif >> LT) flushLL();
     accLL += chord;
   }
 };
@@ -787,14 +782,14 @@ __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, const double4* __restric
     const double4 a = A[r], b = B[r];
     Z0Vis3<LT> z;
     const double tol = 1e-9 * g.pixel;
-    z.cnt = 0.0; z.accLL = 0.0; z.curLL = -1;
-    z.tolm[0] = tol / scale3(LT);
-    z.tot[0] = 0.0;
+    z.sum = 0.0; z.cnt = 0; z.accLL = 0.0;
+    z.px = z.py = z.pz = -1;
+    z.sc[0] = scale3(LT);
+    z.tolm[0] = tol / z.sc[0];
 #pragma unroll
     for (int m = 1; m <= LT; ++m) {
-      z.tolm[m] = tol / scale3(m);
-      z.tot[m] = 0.0;
-      z.cur[m] = -1;
+      z.sc[m] = scale3(m);
+      z.tolm[m] = tol / z.sc[m];
 #pragma unroll
       for (int d = 0; d < 7; ++d) z.acc[m][d] = 0.0;
     }
@@ -810,14 +805,11 @@ __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, const double4* __restric
         if (!go) break;
       }
 #pragma unroll
-      for (int m = 1; m <= LT; ++m)
-        if (z.cur[m] >= 0) z.flush(m);
-      if (z.curLL >= 0) z.flushLL();
+      for (int m = 1; m <= LT; ++m) z.flush(m);
+      z.flushLL();
     }
-    sum = z.tot[0] * scale3(LT);
-#pragma unroll
-    for (int m = 1; m <= LT; ++m) sum += z.tot[m] * scale3(m);
-    cnt = z.cnt;
+    sum = z.sum;
+    cnt = double(z.cnt);
   }
   const double mx = breduce<true>(sum);
   __syncthreads();
