@@ -9,7 +9,9 @@ Geometry (the paper gives none; this project's reading, stated for every impleme
     sod (cos a, sin a, 0); flat detector centred at -(sdd - sod)(cos a, sin a, 0) with
     column axis (-sin a, cos a, 0) and row axis (0, 0, 1); detector element (row rr, col cc)
     at offsets u = (cc - (n_cols - 1)/2) col_pitch, w = (rr - (n_rows - 1)/2) row_pitch;
-  * one ray per element, source to element centre; ray index y = (v n_rows + rr) n_cols + cc.
+  * one ray per element, source to element centre; ray index y = (v n_rows + rr) n_cols + cc;
+  * a direction component within 1e-12 of zero is taken as zero, the line moving to the
+    centre of the voxel slab holding its point closest to the volume centre (as in 2-D).
 
 3-D Haar (config 5 names a "3-level 3D Haar" transform): orthonormal and separable, in a
 3-D Mallat layout. At level l (1..L), with m = n >> l and mz = nz >> l, node (l, k, i, j)
@@ -24,6 +26,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import wam
+from .geometry import snap_axis_parallel
 
 DETAILS = [(tz, ty, tx) for tz in (0, 1) for ty in (0, 1) for tx in (0, 1) if (tz, ty, tx) != (0, 0, 0)]
 
@@ -51,7 +54,7 @@ def rays3(g, views=None, ids=None):
     src = np.stack([g.sod * ca, g.sod * sa, np.zeros_like(A)], axis=1)
     det = np.stack([-(g.sdd - g.sod) * ca - U * sa, -(g.sdd - g.sod) * sa + U * ca, W], axis=1)
     d = det - src
-    return src, d / np.linalg.norm(d, axis=1, keepdims=True)
+    return snap_axis_parallel(src, d / np.linalg.norm(d, axis=1, keepdims=True), [g.n, g.n, g.nz], g.pixel)
 
 
 def edges3(g):

@@ -137,12 +137,39 @@ def test_project_rays_matches_matrix():
 
 
 def test_geometry_matches_generator_rays():
-    """The reference's rays and the input generator's rays follow one convention."""
+    """The reference's rays and the input generator's rays follow one convention; the
+    reference's axis-parallel rays (a direction component below 1e-12) are the generator's
+    lines made exactly parallel and moved by at most half a pixel, to a pixel-row centre."""
     for name in ("parallel64", "fan96"):
         g = synth.CONFIGS[name]["geom"]()
         o1, e1 = geometry.rays(g)
         o2, e2 = synth.ray_lines(g)
         np.testing.assert_allclose(e1, e2, atol=1e-14)
+        snapped = (e1 == 0).any(axis=1)
+        assert snapped.sum() > 0 and np.all(np.abs(e2[snapped]).min(axis=1) < 1e-12)
         # same lines: origin difference is along the direction
         dd = o1 - o2
-        assert np.abs(dd[:, 0] * e1[:, 1] - dd[:, 1] * e1[:, 0]).max() < 1e-9
+        cross = np.abs(dd[:, 0] * e1[:, 1] - dd[:, 1] * e1[:, 0])
+        assert cross[~snapped].max() < 1e-9
+        assert cross[snapped].max() <= 0.5 * g.pixel + 1e-12
+        a = np.where(e1[snapped, 1] == 0, 1, 0)          # the snapped axis
+        pos = o1[snapped][np.arange(a.size), a] / g.pixel + 0.5 * g.n
+        np.testing.assert_allclose(pos - np.floor(pos), 0.5, atol=1e-12)
+
+
+def test_axis_parallel_rays_on_pixel_boundaries_go_to_the_plus_side():
+    """Views at 0 and 90 degrees with bin centres on pixel boundaries (cos and sin of pi/2 are
+    not 0 in floating point, so these lines carry a 1e-16 tilt): every such line lies
+    entirely in the pixel column (row) on the + side of its boundary, chord 1 per pixel, and
+    the line on the image's upper edge misses the image (half-open pixels)."""
+    n = 8
+    g = synth.parallel_geometry(n, 4, n + 1, 1.0)          # views 0, 45, 90, 135 deg; u = -4 .. 4
+    H = siddon.system_matrix(g).toarray().reshape(4, n + 1, n, n)
+    for b in range(n + 1):
+        col = np.zeros((n, n))
+        row = np.zeros((n, n))
+        if b < n:
+            col[:, b] = 1.0       # view 0: the line x = b - 4 in column b
+            row[b, :] = 1.0       # view 90: the line y = b - 4 in row b
+        np.testing.assert_allclose(H[0, b], col, atol=1e-12)
+        np.testing.assert_allclose(H[2, b], row, atol=1e-12)
