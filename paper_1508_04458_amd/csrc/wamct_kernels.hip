@@ -102,8 +102,15 @@ __global__ __launch_bounds__(kBlock) void k_ray_table(DevGeom g, const double2* 
   const int v = r / g.nb, b = r - v * g.nb;
   double ox, oy, ex, ey;
   ray_of(g, views[v], b, ox, oy, ex, ey);
+  // an axis-parallel component (set to +-1e-12 by ray_of) gets an inverse that acts as
+  // infinite: slab parameters (X - x) / e are then beyond any chord for every X off the
+  // line's position, also when measured from the fan-beam source instead of the moved
+  // origin, so the gather and the walks place the line in the same pixel row
+  const double big = sizeof(T) == 8 ? 1e300 : 1e30;
+  const double iex = fabs(ex) <= 1e-12 ? (ex < 0 ? -big : big) : 1.0 / ex;
+  const double iey = fabs(ey) <= 1e-12 ? (ey < 0 ? -big : big) : 1.0 / ey;
   typename V4<T>::t a, bb;
-  a.x = T(ox); a.y = T(oy); a.z = T(1.0 / ex); a.w = T(1.0 / ey);
+  a.x = T(ox); a.y = T(oy); a.z = T(iex); a.w = T(iey);
   bb.x = T(ex); bb.y = T(ey); bb.z = T(0); bb.w = T(0);
   A[r] = a;
   B[r] = bb;
