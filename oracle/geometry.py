@@ -11,8 +11,9 @@ is not given), so the conventions below are this project's reading:
   * pixels are half-open boxes, and a direction component within 1e-12 of zero is taken
     as exactly zero (cos and sin of a multiple of pi/2 are not exactly 0 in floating point):
     the line is then moved, parallel to the axis, to the centre of the pixel row (column)
-    holding its point closest to the image centre, so a line on a pixel boundary lies in
-    the pixel on the + side and no chord is split by a 1e-16 tilt.
+    holding the ray's origin (the source of a fan-beam ray, the foot point u (cos a, sin a)
+    of a parallel-beam ray), so a line on a pixel boundary lies in the pixel on the + side
+    and no chord is split by a 1e-16 tilt.
 Ray index y = v * n_bins + b. Every geometry attribute is read by name from `g`.
 """
 import numpy as np
@@ -53,19 +54,15 @@ def rays(g, views=None):
 
 def snap_axis_parallel(origin, direction, sizes, pixel, tol=1e-12):
     """Rays with a direction component below `tol` in magnitude: that component set to 0 and
-    the line moved along that axis to the centre of the pixel slab holding its point
-    closest to the image centre (grid of `sizes` pixels per axis, centred at 0)."""
+    the origin moved along that axis to the centre of the pixel slab that holds it (grid of
+    `sizes` pixels per axis, centred at 0)."""
     o = np.array(origin, dtype=np.float64)
     e = np.array(direction, dtype=np.float64)
-    tc = -np.sum(o * e, axis=1)
-    p = o + tc[:, None] * e
     for a, n in enumerate(sizes):
         m = np.abs(e[:, a]) < tol
         if m.any():
-            o[m] = p[m]
-            o[m, a] = (np.floor(p[m, a] / pixel + 0.5 * n) + 0.5 - 0.5 * n) * pixel
+            o[m, a] = (np.floor(o[m, a] / pixel + 0.5 * n) + 0.5 - 0.5 * n) * pixel
             e[m, a] = 0.0
-            p[m] = o[m]
     return o, e
 
 

@@ -11,7 +11,7 @@ Geometry (the paper gives none; this project's reading, stated for every impleme
     at offsets u = (cc - (n_cols - 1)/2) col_pitch, w = (rr - (n_rows - 1)/2) row_pitch;
   * one ray per element, source to element centre; ray index y = (v n_rows + rr) n_cols + cc;
   * a direction component within 1e-12 of zero is taken as zero, the line moving to the
-    centre of the voxel slab holding its point closest to the volume centre (as in 2-D).
+    centre of the voxel slab holding the source (as for the 2-D fan beam).
 
 3-D Haar (config 5 names a "3-level 3D Haar" transform): orthonormal and separable, in a
 3-D Mallat layout. At level l (1..L), with m = n >> l and mz = nz >> l, node (l, k, i, j)

@@ -25,24 +25,24 @@ __host__ __device__ inline void ray_of(const DevGeom& g, double2 cs, int b, doub
     const double inv = 1.0 / sqrt(dx * dx + dy * dy);
     ex = dx * inv; ey = dy * inv; ox = sx; oy = sy;
   }
+  // A direction within 1e-12 of an axis is treated as exactly axis-parallel: the line is
+  // moved to the centre of the pixel row (column) holding the ray's origin (the fan-beam
+  // source, or the parallel-beam foot point u (c, s)), which leaves every chord unchanged
+  // and puts a line lying on a boundary into the pixel on the + side (half-open pixels);
+  // it keeps a 1e-12 tilt so that 1/e is finite for the walks (the ray table stores an
+  // inverse that acts as infinite).
+  const double hn = 0.5 * g.n;
+  const bool snap_y = fabs(ey) < 1e-12, snap_x = fabs(ex) < 1e-12;
+  const double py0 = (floor(oy / g.pixel + hn) + 0.5 - hn) * g.pixel;
+  const double px0 = (floor(ox / g.pixel + hn) + 0.5 - hn) * g.pixel;
+  if (snap_y) ey = ey < 0 ? -1e-12 : 1e-12;
+  if (snap_x) ex = ex < 0 ? -1e-12 : 1e-12;
   // move the origin to the point of the line closest to the image centre (|t| stays
   // below the image half-diagonal inside the image, which keeps FP32 chords accurate)
   const double tc = -(ox * ex + oy * ey);
   ox += tc * ex; oy += tc * ey;
-  // A direction within 1e-12 of an axis is treated as exactly axis-parallel: the line is
-  // moved to the centre of the pixel row (column) that contains it, which leaves every
-  // chord unchanged and puts a line lying on a boundary into the pixel on the + side
-  // (half-open pixels), and it gets a 1e-12 tilt so 1/e stays finite; the tilt moves it by
-  // less than 1e-8 pixel across any image this library accepts.
-  const double hn = 0.5 * g.n;
-  if (fabs(ey) < 1e-12) {
-    oy = (floor(oy / g.pixel + hn) + 0.5 - hn) * g.pixel;
-    ey = ey < 0 ? -1e-12 : 1e-12;
-  }
-  if (fabs(ex) < 1e-12) {
-    ox = (floor(ox / g.pixel + hn) + 0.5 - hn) * g.pixel;
-    ex = ex < 0 ? -1e-12 : 1e-12;
-  }
+  if (snap_y) oy = py0;
+  if (snap_x) ox = px0;
 }
 
 // Walk one ray through the leaves of the tree (or through pixels when !TREE) and call

@@ -581,6 +581,10 @@ __device__ inline ItemSums<R> item_sums_k(const DevGeom& g, const float2* __rest
   const float fx0 = float(X0), fx2 = float(X2), fy0 = float(Y0), fy2 = float(Y2);
   const float ipitch = float(1.0 / g.pitch), ctr = float(0.5 * (nb - 1));
   const float sod = float(g.sod), sdd = float(g.sdd);
+  // |phi| <= 1e-12 pixel is rounding residue of chord differences, taken as 0 (phi is 2^-l
+  // times the quadrant combinations below); otherwise a coefficient whose rays all give
+  // phi <= 0 would get a residue-sized b-hat+ and jump to the other branch of eq. 1.9
+  const R tq = R(1e-12 * g.pixel * double(1 << l));
   ItemSums<R> r{R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
   for (int k = v0; k < v1; ++k) {
     const int v = g.vs0 + g.vss * k;   // k-th view of the launch's subset
@@ -625,7 +629,8 @@ __device__ inline ItemSums<R> item_sums_k(const DevGeom& g, const float2* __rest
       if (!quad) {
         const R lo = fmax(fmin(tx0, tx2), fmin(ty0, ty2));
         const R hi = fmin(fmax(tx0, tx2), fmax(ty0, ty2));
-        r.acc += yv * fmax(hi - lo, R(0));
+        const R ch = hi - lo;
+        r.acc += ch > tq ? yv * ch : R(0);
       } else {
         const R tx1 = (dx1 - ox) * a.z, ty1 = (dy1 - oy) * a.w;
         const R xl0 = fmin(tx0, tx1), xh0 = fmax(tx0, tx1), xl1 = fmin(tx1, tx2), xh1 = fmax(tx1, tx2);
@@ -635,8 +640,10 @@ __device__ inline ItemSums<R> item_sums_k(const DevGeom& g, const float2* __rest
         const R cBL = fmax(fmin(xh0, yh1) - fmax(xl0, yl1), R(0));
         const R cBR = fmax(fmin(xh1, yh1) - fmax(xl1, yl1), R(0));
         const R u1 = cTL - cTR, u2 = cBL - cBR, w1v = cTL + cTR, w2v = cBL + cBR;
-        const R w1 = yv * (u1 + u2), w2 = yv * (w1v - w2v), w3 = yv * (u1 - u2);
-        r.acc += yv * (w1v + w2v);
+        const R p1 = u1 + u2, p2 = w1v - w2v, p3 = u1 - u2, pb = w1v + w2v;
+        const R w1 = fabs(p1) > tq ? yv * p1 : R(0), w2 = fabs(p2) > tq ? yv * p2 : R(0);
+        const R w3 = fabs(p3) > tq ? yv * p3 : R(0);
+        r.acc += pb > tq ? yv * pb : R(0);
         r.s0 += w1; r.a0 += fabs(w1);
         r.s1 += w2; r.a1 += fabs(w2);
         r.s2 += w3; r.a2 += fabs(w3);
