@@ -90,12 +90,19 @@ __global__ __launch_bounds__(kB) void k3_ray_table(DevGeom3 g, const double2* __
   const double dx = -(g.sdd - g.sod) * c - u * s - sx, dy = -(g.sdd - g.sod) * s + u * c - sy, dz = w - sz;
   const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
   double ex = dx * inv, ey = dy * inv, ez = dz * inv;
+  // axis-parallel components (within 1e-12): the line moves to the centre of the voxel slab
+  // holding the source, the position the factorised gather (which measures from the
+  // source) sees, and keeps a 1e-12 tilt for the walks
+  const double hn = 0.5 * g.n, hz = 0.5 * g.nz;
+  const bool snx = fabs(ex) < 1e-12, sny = fabs(ey) < 1e-12, snz = fabs(ez) < 1e-12;
+  if (snx) ex = ex < 0 ? -1e-12 : 1e-12;
+  if (sny) ey = ey < 0 ? -1e-12 : 1e-12;
+  if (snz) ez = ez < 0 ? -1e-12 : 1e-12;
   const double tc = -(sx * ex + sy * ey + sz * ez);
   double ox = sx + tc * ex, oy = sy + tc * ey, oz = sz + tc * ez;
-  const double hn = 0.5 * g.n, hz = 0.5 * g.nz;
-  if (fabs(ex) < 1e-12) { ox = (floor(ox / g.pixel + hn) + 0.5 - hn) * g.pixel; ex = ex < 0 ? -1e-12 : 1e-12; }
-  if (fabs(ey) < 1e-12) { oy = (floor(oy / g.pixel + hn) + 0.5 - hn) * g.pixel; ey = ey < 0 ? -1e-12 : 1e-12; }
-  if (fabs(ez) < 1e-12) { oz = (floor(oz / g.pixel + hz) + 0.5 - hz) * g.pixel; ez = ez < 0 ? -1e-12 : 1e-12; }
+  if (snx) ox = (floor(sx / g.pixel + hn) + 0.5 - hn) * g.pixel;
+  if (sny) oy = (floor(sy / g.pixel + hn) + 0.5 - hn) * g.pixel;
+  if (snz) oz = (floor(sz / g.pixel + hz) + 0.5 - hz) * g.pixel;
   A[r] = make_double4(ox, oy, oz, 1.0 / ex);
   B[r] = make_double4(1.0 / ey, 1.0 / ez, ex, ey);
   C[r] = ez;
@@ -477,6 +484,10 @@ __device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __r
   const float sod = float(g.sod), sdd = float(g.sdd);
   const float icp = float(1.0 / g.cpitch), irp = float(1.0 / g.rpitch);
   const float cc0 = float(0.5 * (g.nc - 1)), rc0 = float(0.5 * (g.nr - 1));
+  // |phi| <= 1e-12 pixel is rounding residue of chord differences, taken as 0 (phi is
+  // 2^(-3l/2) times the butterfly outputs, in parameter units of the unnormalised ray
+  // direction: chords there are mm / |D|, and |D| >= sdd)
+  const double tq = 1e-12 * g.pixel * exp2(1.5 * double(l)) / g.sdd;
   Sums3<double> r;
 #pragma unroll
   for (int q = 0; q < kSlots3; ++q) r.v[q] = 0.0;
@@ -514,7 +525,8 @@ __device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __r
           const double tx0 = ax0 * cd.x, tx2 = ax2 * cd.x, ty0 = ay0 * cd.y, ty2 = ay2 * cd.y;
           const double lo = fmax(fmax(fmin(tx0, tx2), fmin(ty0, ty2)), zlo);
           const double hi = fmin(fmin(fmax(tx0, tx2), fmax(ty0, ty2)), zhi);
-          r.v[0] += double(yr[col]) * fmax(hi - lo, 0.0);
+          const double chd = hi - lo;
+          r.v[0] += chd > tq ? double(yr[col]) * chd : 0.0;
         }
         continue;
       }
@@ -543,10 +555,11 @@ __device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __r
         const double ss0 = s1[0] + s1[1], sd0 = s1[0] - s1[1], ds0 = d1[0] + d1[1], dd0 = d1[0] - d1[1];
         const double ss1 = s1[2] + s1[3], sd1 = s1[2] - s1[3], ds1 = d1[2] + d1[3], dd1 = d1[2] - d1[3];
         const double det[7] = {ds0 + ds1, sd0 + sd1, dd0 + dd1, ss0 - ss1, ds0 - ds1, sd0 - sd1, dd0 - dd1};
-        r.v[0] += yv * (ss0 + ss1);
+        const double box = ss0 + ss1;
+        r.v[0] += box > tq ? yv * box : 0.0;
 #pragma unroll
         for (int d = 0; d < 7; ++d) {
-          const double wv = yv * det[d];
+          const double wv = fabs(det[d]) > tq ? yv * det[d] : 0.0;
           r.v[1 + d] += wv;
           r.v[8 + d] += fabs(wv);
         }
