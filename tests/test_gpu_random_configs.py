@@ -74,7 +74,7 @@ def draw_3d(seed):
     return g, L, d, i0, n_it, sched
 
 
-@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4, 18, 24])
 def test_random_cone_solve_fp64(seed):
     from paper_1508_04458_amd import api
     g, L, d, i0, n_it, sched = draw_3d(seed)
@@ -83,6 +83,29 @@ def test_random_cone_solve_fp64(seed):
     H = vol3d.system_matrix3(g)
     ref = vol3d.wam_solve3(H, g.n, g.nz, L, d, i0, n_it, g.pixel, schedule=sched)
     c = api.Context(g, L, "f64")
+    c.set_data(dev(d, "f64"), i0)
+    idv = host(c.solve(n_it, sched, 0.1))
+    beta, mask, _ = c.get_state()
+    np.testing.assert_array_equal(host(mask), ref["mask"])
+    assert rel_l2(host(beta), ref["beta"]) <= 1e-9
+    np.testing.assert_allclose(idv, ref["idiv"], rtol=1e-10)
+    assert c.tree_stats()["n_held"] == ref["held"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_2d_ordered_subsets_fp64(seed):
+    """Ordered subsets on random draws, down to one or two views per subset (where a
+    detail's phi over a subset's rays is often of one sign, so residue-level phi must
+    count as 0)."""
+    from paper_1508_04458_amd import api
+    g, L, d, i0, n_it, sched = draw_2d(100 + seed)
+    ns = min(g.n_views, [2, 4, 9, g.n_views // 2, g.n_views, 3][seed])
+    print(f"\n[case] OS seed {seed}: kind {g.kind} n={g.n} L={L} views={g.n_views} subsets {ns} schedule {sched}",
+          flush=True)
+    H = siddon.system_matrix(g)
+    ref = wam.os_wam_solve(H, g.n, L, d, i0, n_it, g.pixel, g.n_views, ns, schedule=sched)
+    c = api.Context(g, L, "f64")
+    c.set_subsets(ns)
     c.set_data(dev(d, "f64"), i0)
     idv = host(c.solve(n_it, sched, 0.1))
     beta, mask, _ = c.get_state()
