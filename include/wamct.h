@@ -67,7 +67,7 @@ extern "C" {
 typedef enum {
   WAMCT_OK = 0,
   WAMCT_E_INVALID = 1,     /* bad argument, geometry or data */
-  WAMCT_E_UNSUPPORTED = 2, /* valid request this build does not implement */
+  WAMCT_E_UNSUPPORTED = 2, /* valid request the library does not implement */
   WAMCT_E_OOM = 3,         /* device allocation failed */
   WAMCT_E_HIP = 4,         /* HIP runtime error (message carries hipGetErrorString) */
   WAMCT_E_NUMERIC = 5,     /* non-finite values where finite ones are required */
