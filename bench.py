@@ -552,7 +552,7 @@ def main():
     roof_up = {"bound": "hbm", "achieved": round(alg_up / (upd_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                "unit": "GB/s", "frac": round(alg_up / (upd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                "traffic": measured_traffic(khash, args.config, "update"),
-               "kernels": "k_gather_part + k_gather_finish (+ k_gather) per tree level",
+               "kernels": "k_gather_part + k_gather_finish over the chunked tree levels (+ k_gather per level that fills the GPU alone)",
                "avg_pass_ms": round(upd_ms, 5), "passes": up["launches"], "alg_bytes_per_pass": int(alg_up)}
     timing_ms = {k: round(v["ms"] / args.steps, 4) for k, v in tim.items() if k in ("forward", "update")}
 

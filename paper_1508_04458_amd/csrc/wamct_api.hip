@@ -203,10 +203,11 @@ struct Ctx final : wamct_ctx {
     }
     return sg;
   }
-  // Partial sums any segment can need at a given target: 7 (target / 4 + lanes) with
-  // lanes = count * S < target (chunk groups of four waves, rounded up).
+  // Partial sums a gather can need at a given target: per chunked segment 7 (target / 4 +
+  // lanes) with lanes = count * S < target (chunk groups of four waves, rounded up), one
+  // segment per tree level side by side.
   int64_t part_need(int target) const {
-    return 7 * (int64_t(target) / 4 + 1 + std::min<int64_t>(int64_t(P) * NN, target));
+    return int64_t(std::max(1, g.L)) * 7 * (int64_t(target) / 4 + 1 + std::min<int64_t>(int64_t(P) * NN, target));
   }
   wamct_status ensure_part(int target) {
     const int64_t need = part_need(target);
@@ -361,9 +362,10 @@ struct Ctx final : wamct_ctx {
   // partial sums fit; views, b and Z0 of the selection
   wamct_status gather(int mode, const T* y, const std::vector<Segment>& sg, int S, T* bt, int* held, T* bp, T* bm,
                       T* out, hipStream_t s, const Sel& v) {
-    for (const Segment& x : sg)
-      if (segment_part_elems(x, S) > part_cap)
-        return fail(WAMCT_E_HIP, "internal: gather partial buffer too small for its tiling");
+    int64_t need = 0;
+    for (const Segment& x : sg) need += segment_part_elems(x, S);
+    if (need > part_cap || sg.size() > size_t(kMaxGatherSegs))
+      return fail(WAMCT_E_HIP, "internal: gather partial buffer too small for its tiling");
     const bool tree = &sg == &segs || &sg == &segs_sub;
     const bool pen = mode == kUpdate && lam > 0.0;
     Geo<T, R>::gather(v.g, mode, vT, views, A, y, tree ? items : nullptr, tree ? ints + 9 : nullptr, sg.data(),

@@ -61,13 +61,16 @@ __device__ inline R ordered_sum(const R* __restrict__ x, int n, size_t stride) {
 struct Segment {
   int kseg, start, count, level, chunks, vpc;
 };
+// Segments one gather takes (one per tree level, at most kMaxLevels; one for every pixel).
+constexpr int kMaxGatherSegs = 12;
 // Default lanes one level segment should occupy over the whole stack (about 64 wave64 per
 // CU on 256 CUs, several rounds of the resident waves, so short and long tasks even out);
 // tunable per context within [kMinTargetLanes, kMaxTargetLanes].
 constexpr int kTargetLanes = 1 << 20;
 constexpr int kMinTargetLanes = 1 << 12;
 constexpr int kMaxTargetLanes = 1 << 24;
-// Partial sums a chunked segment stores: 7 values of R per (scan, item, chunk group).
+// Partial sums a chunked segment stores: 7 values of R per (scan, item, chunk group). The
+// chunked segments of one gather store theirs side by side (one launch computes them all).
 inline int64_t segment_part_elems(const Segment& sg, int n_scans) {
   if (sg.chunks <= 1) return 0;
   const int64_t groups = (sg.chunks + 3) / 4;

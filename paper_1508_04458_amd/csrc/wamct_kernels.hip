@@ -859,20 +859,51 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs<T, R> a) {
   item_finish<T, R, MODE>(a.g, w, r, v.beta, v.b, v.z0, v.held, v.bp, v.bm, v.out, v.gpen, a.lam);
 }
 
-// (item, view chunk) tasks for a level segment whose items alone would leave the GPU idle.
-// A block of kChunkWaves waves takes 64 consecutive (spatially adjacent) items; wave w
-// handles view chunk kChunkWaves * group + w for all of them (uniform view range per wave).
-// The chunk sums are added in LDS in wave order (deterministic) and written to
+// (item, view chunk) tasks of the level segments whose items alone would leave the GPU idle,
+// all chunked segments of a gather in one launch. A block of kChunkWaves waves takes 64
+// consecutive (spatially adjacent) items of one segment; wave w handles view chunk
+// kChunkWaves * group + w for all of them (uniform view range per wave). The chunk sums are
+// added in LDS in wave order (deterministic) and written to the segment's
 // part[group][slot][count] (count = the stack's largest segment length).
 constexpr int kChunkWaves = 4;
+constexpr int kMaxSegs = kMaxGatherSegs;
+
+// The chunked segments of one launch, coarse levels first. Each segment owns a range of
+// part-kernel blocks starting at a multiple of the XCD count (so a segment's blocks are
+// dealt to the XCDs as in a launch of its own) and a range of finish blocks (64 items each).
+struct SegTable {
+  int n;
+  int kseg[kMaxSegs], start[kMaxSegs], count[kMaxSegs], chunks[kMaxSegs], vpc[kMaxSegs];
+  int64_t part_off[kMaxSegs];   // the segment's partial sums within a scan's block of part
+  int blk0[kMaxSegs + 1];       // first part-kernel block; blk0[n] = blocks of the launch
+  int fin0[kMaxSegs + 1];       // first finish block; fin0[n] = blocks of the launch
+};
+
+__device__ inline int seg_of(const int* first, int n, int b) {
+  int k = 0;
+  while (k + 1 < n && first[k + 1] <= b) ++k;
+  return k;
+}
 
 template <typename T, typename R>
-__global__ __launch_bounds__(64 * kChunkWaves) void k_gather_part(GatherArgs<T, R> a) {
+__device__ inline void select_segment(GatherArgs<T, R>& a, const SegTable& t, int k) {
+  a.kseg = t.kseg[k];
+  a.start = t.start[k];
+  a.count = t.count[k];
+  a.chunks = t.chunks[k];
+  a.vpc = t.vpc[k];
+  a.part = at(a.part, t.part_off[k]);
+}
+
+template <typename T, typename R>
+__global__ __launch_bounds__(64 * kChunkWaves) void k_gather_part(GatherArgs<T, R> a, SegTable t) {
   __shared__ R sh[kChunkWaves][7][64];
+  const int sg = seg_of(t.blk0, t.n, blockIdx.x);
+  select_segment(a, t, sg);
   const ScanView<T, R> v = scan_view(a);
   const int n_item_groups = (a.count + 63) / 64;
   const int groups = (a.chunks + kChunkWaves - 1) / kChunkWaves;
-  const int unit = xcd_unit(blockIdx.x, gridDim.x);   // unit = group * n_item_groups + ig
+  const int unit = xcd_unit(blockIdx.x - t.blk0[sg], t.blk0[sg + 1] - t.blk0[sg]);   // group * n_item_groups + ig
   if (unit >= groups * n_item_groups) return;
   const int ig = unit % n_item_groups, group = unit / n_item_groups;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -901,13 +932,16 @@ __global__ __launch_bounds__(64 * kChunkWaves) void k_gather_part(GatherArgs<T, 
 }
 
 // Sum the chunk groups of each item in group order (deterministic): 7 waves of a block each
-// add one slot for 64 consecutive items (coalesced), then one wave finishes the items.
+// add one slot for 64 consecutive items of one segment (coalesced), then one wave finishes
+// the items. Every chunked segment of the gather in one launch.
 template <typename T, typename R, int MODE>
-__global__ __launch_bounds__(512) void k_gather_finish(GatherArgs<T, R> a) {
+__global__ __launch_bounds__(512) void k_gather_finish(GatherArgs<T, R> a, SegTable t) {
   __shared__ R sh[7][64];
+  const int sg = seg_of(t.fin0, t.n, blockIdx.x);
+  select_segment(a, t, sg);
   const ScanView<T, R> v = scan_view(a);
   const int lane = threadIdx.x & 63, slot = threadIdx.x >> 6;
-  const int idx = blockIdx.x * 64 + lane;
+  const int idx = (blockIdx.x - t.fin0[sg]) * 64 + lane;
   const int groups = (a.chunks + kChunkWaves - 1) / kChunkWaves;
   if (slot < 7) {
     sh[slot][lane] = idx < v.count ? ordered_sum(v.part + size_t(slot) * a.count + idx, groups, size_t(7) * a.count)
@@ -1358,16 +1392,40 @@ int Geo<T, R>::forward_records(const DevGeom& g, const void* A, const void* B, c
 }
 
 namespace {
+// Segments that fill the GPU with one lane per item run k_gather, one launch each; the
+// chunked ones share one part launch and one finish launch.
 template <typename T, typename R, int MODE>
-void launch_segment(const GatherArgs<T, R>& a, int S, hipStream_t s) {
-  if (a.chunks <= 1) {
-    hipLaunchKernelGGL((k_gather<T, R, MODE>), dim3(xcd_pad(blocks_for(a.count)), S), dim3(kBlock), 0, s, a);
-    return;
+void launch_segments(GatherArgs<T, R> a, const Segment* segs, int n_segs, int S, hipStream_t s) {
+  SegTable t{};
+  int64_t off = 0;
+  for (int k = 0; k < n_segs; ++k) {
+    const Segment& sg = segs[k];
+    if (sg.count <= 0) continue;
+    if (sg.chunks <= 1) {
+      a.kseg = sg.kseg;
+      a.start = sg.start;
+      a.count = sg.count;
+      a.chunks = sg.chunks;
+      a.vpc = sg.vpc;
+      hipLaunchKernelGGL((k_gather<T, R, MODE>), dim3(xcd_pad(blocks_for(a.count)), S), dim3(kBlock), 0, s, a);
+      continue;
+    }
+    const int i = t.n++;
+    const int groups = (sg.chunks + kChunkWaves - 1) / kChunkWaves;
+    t.kseg[i] = sg.kseg;
+    t.start[i] = sg.start;
+    t.count[i] = sg.count;
+    t.chunks[i] = sg.chunks;
+    t.vpc[i] = sg.vpc;
+    t.part_off[i] = off;
+    off += segment_part_elems(sg, 1);
+    t.blk0[i + 1] = t.blk0[i] + xcd_pad(((sg.count + 63) / 64) * groups);
+    t.fin0[i + 1] = t.fin0[i] + (sg.count + 63) / 64;
   }
-  const int groups = (a.chunks + kChunkWaves - 1) / kChunkWaves;
-  hipLaunchKernelGGL((k_gather_part<T, R>), dim3(xcd_pad(((a.count + 63) / 64) * groups), S),
-                     dim3(64 * kChunkWaves), 0, s, a);
-  hipLaunchKernelGGL((k_gather_finish<T, R, MODE>), dim3((a.count + 63) / 64, S), dim3(512), 0, s, a);
+  if (t.n == 0) return;
+  a.pstride = off;
+  hipLaunchKernelGGL((k_gather_part<T, R>), dim3(t.blk0[t.n], S), dim3(64 * kChunkWaves), 0, s, a, t);
+  hipLaunchKernelGGL((k_gather_finish<T, R, MODE>), dim3(t.fin0[t.n], S), dim3(512), 0, s, a, t);
 }
 }  // namespace
 
@@ -1395,19 +1453,10 @@ void Geo<T, R>::gather(const DevGeom& g, int mode, const void* vF, const double2
   a.bp = bp;
   a.bm = bm;
   a.out = out;
-  for (int k = 0; k < n_segs; ++k) {
-    const Segment& sg = segs[k];
-    if (sg.count <= 0) continue;
-    a.kseg = sg.kseg;
-    a.start = sg.start;
-    a.count = sg.count;
-    a.chunks = sg.chunks;
-    a.vpc = sg.vpc;
-    a.pstride = segment_part_elems(sg, 1);
-    if (mode == kPlain) launch_segment<T, R, kPlain>(a, S, s);
-    else if (mode == kSplit) launch_segment<T, R, kSplit>(a, S, s);
-    else launch_segment<T, R, kUpdate>(a, S, s);
-  }
+  if (n_segs > kMaxSegs) return;   // refused by the host
+  if (mode == kPlain) launch_segments<T, R, kPlain>(a, segs, n_segs, S, s);
+  else if (mode == kSplit) launch_segments<T, R, kSplit>(a, segs, n_segs, S, s);
+  else launch_segments<T, R, kUpdate>(a, segs, n_segs, S, s);
 }
 
 template struct Geo<float, float>;
