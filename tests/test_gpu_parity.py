@@ -101,8 +101,10 @@ def test_backproject_matches_oracle(name, dtype):
 
 @pytest.mark.parametrize("name,levels,dtype,seed", [("parallel64", 1, "f64", 0), ("parallel64", 3, "f64", 1),
                                                     ("fan96", 2, "f32", 2), ("fan128", 3, "f32", 3),
-                                                    ("fan128", 3, "f64", 4)])
+                                                    ("fan128", 3, "f64", 4), ("parallel64", 6, "f64", 20),
+                                                    ("fan128", 7, "f64", 15), ("fan128", 5, "f32", 15)])
 def test_split_backprojection_matches_oracle(name, levels, dtype, seed):
+    """Random trees of 1 to 7 levels: up to 7 level segments, gathered in one launch."""
     P, H = problem(name)
     g = P.geom
     mask = synth.random_tree_mask(g.n, levels, seed, p_split=0.6)
@@ -139,7 +141,8 @@ def test_b_precompute_matches_oracle(name, dtype):
 
 
 @pytest.mark.parametrize("name,levels,dtype,seed", [("parallel64", 1, "f64", 5), ("fan96", 2, "f32", 6),
-                                                    ("fan128", 3, "f32", 7)])
+                                                    ("fan128", 3, "f32", 7), ("parallel64", 6, "f64", 20),
+                                                    ("fan128", 7, "f64", 24)])
 def test_z0_and_w_match_oracle(name, levels, dtype, seed):
     P, H = problem(name)
     g = P.geom
