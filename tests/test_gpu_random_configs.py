@@ -131,3 +131,19 @@ def test_random_2d_solve_fp32(seed):
     idv = host(c.solve(n_it, sched, 0.1))
     assert np.all(idv[1:] <= idv[:-1] * (1 + 1e-6))
     assert abs(idv[-1] - ref["idiv"][-1]) <= 1e-3 * ref["idiv"][-1]
+
+
+@pytest.mark.parametrize("seed", range(200, 204))
+def test_random_cone_solve_fp32(seed):
+    """FP32 data on random cone-beam draws, at the same bar as the 2-D FP32 draws."""
+    from paper_1508_04458_amd import api
+    g, L, d, i0, n_it, sched = draw_3d(seed)
+    print(f"\n[case] cone fp32 seed {seed}: n={g.n} nz={g.nz} L={L} views={g.n_views} det={g.n_rows}x{g.n_cols} "
+          f"iters {n_it} schedule {sched}", flush=True)
+    H = vol3d.system_matrix3(g)
+    ref = vol3d.wam_solve3(H, g.n, g.nz, L, d, i0, n_it, g.pixel, schedule=sched)
+    c = api.Context(g, L, "f32")
+    c.set_data(dev(d, "f32"), i0)
+    idv = host(c.solve(n_it, sched, 0.1))
+    assert np.all(idv[1:] <= idv[:-1] * (1 + 1e-6))
+    assert abs(idv[-1] - ref["idiv"][-1]) <= 1e-3 * ref["idiv"][-1]
