@@ -147,3 +147,23 @@ def test_random_cone_solve_fp32(seed):
     idv = host(c.solve(n_it, sched, 0.1))
     assert np.all(idv[1:] <= idv[:-1] * (1 + 1e-6))
     assert abs(idv[-1] - ref["idiv"][-1]) <= 1e-3 * ref["idiv"][-1]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_2d_gradient_rule_fp64(seed):
+    """The residual-gradient tree rule on random draws, FP64, at the bar of the value rule."""
+    from paper_1508_04458_amd import api
+    g, L, d, i0, n_it, sched = draw_2d(300 + seed)
+    print(f"\n[case] gradient-rule seed {seed}: kind {g.kind} n={g.n} L={L} views={g.n_views} bins={g.n_bins} "
+          f"iters {n_it} schedule {sched}", flush=True)
+    H = siddon.system_matrix(g)
+    ref = wam.wam_solve(H, g.n, L, d, i0, n_it, g.pixel, schedule=sched, rule="gradient")
+    c = api.Context(g, L, "f64")
+    c.set_tree_rule("gradient")
+    c.set_data(dev(d, "f64"), i0)
+    idv = host(c.solve(n_it, sched, 0.1))
+    beta, mask, _ = c.get_state()
+    np.testing.assert_array_equal(host(mask), ref["mask"])
+    assert rel_l2(host(beta), ref["beta"]) <= 1e-9
+    np.testing.assert_allclose(idv, ref["idiv"], rtol=1e-10)
+    assert c.tree_stats()["n_held"] == ref["held"]
