@@ -2,7 +2,9 @@
 level count, beam kind, view and bin counts (odd and even, not multiples of a wave), I0 and
 expansion schedule drawn from seeded generators, phantom and Poisson counts as for the named
 workloads. FP64 with the GPU's own tree expansions: masks exact, beta relative L2 <= 1e-9,
-I-divergence rtol 1e-10, held counts equal; cone beam likewise with the 3-D oracle."""
+I-divergence rtol 1e-10, held counts equal; cone beam likewise with the 3-D oracle; the same
+for ordered subsets, the residual-gradient rule and the roughness penalty. FP32: I-divergence
+non-increasing and final value within 1e-3 of the oracle's."""
 import math
 
 import numpy as np
@@ -167,3 +169,23 @@ def test_random_2d_gradient_rule_fp64(seed):
     assert rel_l2(host(beta), ref["beta"]) <= 1e-9
     np.testing.assert_allclose(idv, ref["idiv"], rtol=1e-10)
     assert c.tree_stats()["n_held"] == ref["held"]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_random_2d_penalty_fp64(seed):
+    """The roughness penalty (lambda = 1e6) on random draws, FP64: the GPU's Newton roots
+    against the oracle's bisection roots, at the bar of the plain iteration."""
+    from paper_1508_04458_amd import api
+    g, L, d, i0, n_it, sched = draw_2d(400 + seed)
+    print(f"\n[case] penalty seed {seed}: kind {g.kind} n={g.n} L={L} views={g.n_views} bins={g.n_bins} "
+          f"iters {n_it} schedule {sched}", flush=True)
+    H = siddon.system_matrix(g)
+    ref = wam.wam_solve(H, g.n, L, d, i0, n_it, g.pixel, schedule=sched, penalty=1e6)
+    c = api.Context(g, L, "f64")
+    c.set_penalty(1e6)
+    c.set_data(dev(d, "f64"), i0)
+    idv = host(c.solve(n_it, sched, 0.1))
+    beta, mask, _ = c.get_state()
+    np.testing.assert_array_equal(host(mask), ref["mask"])
+    assert rel_l2(host(beta), ref["beta"]) <= 1e-9
+    np.testing.assert_allclose(idv, ref["idiv"], rtol=1e-10)
