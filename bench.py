@@ -59,9 +59,13 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_hash():
+KERNEL_SOURCES_2D = ("wamct_kernels.hip", "wamct_geom.h", "wamct_internal.h")
+KERNEL_SOURCES_3D = ("wamct_kernels3.hip", "wamct_internal3.h", "wamct_internal.h", "wamct_worklist.h")
+
+
+def kernel_source_hash(files=KERNEL_SOURCES_2D):
     h = hashlib.sha256()
-    for f in ("wamct_kernels.hip", "wamct_geom.h", "wamct_internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1508_04458_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -382,10 +386,13 @@ def bench_cone(args):
     it_s = J * args.steps / dt
     M, N = g.n_rays, g.n_voxels
 
-    def roof(ms, alg, **kw):
+    khash = kernel_source_hash(KERNEL_SOURCES_3D)
+
+    def roof(ms, alg, phase, **kw):
         a = alg / (ms * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None, **kw}
+                "frac": round(a / HBM_PEAK_GBS, 4), "traffic": measured_traffic(khash, args.config, phase),
+                **kw, "kernel_hash": khash}
 
     # algorithmic bytes of the same passes with Phi stored: 8 B per (ray, active coefficient)
     # pair, 4 B per active coefficient read (forward) or 12 B (b, beta read, beta written),
@@ -395,9 +402,9 @@ def bench_cone(args):
     up_ms = up["ms"] / max(1, J * args.steps)
     alg_fw = 8.0 * w_avg + 4.0 * active_avg + 8.0 * M
     alg_up = 8.0 * w_avg + 4.0 * M + 12.0 * active_avg
-    r_fw = roof(fw_ms, alg_fw, kernel="k3_forward<float>", avg_launch_ms=round(fw_ms, 4),
+    r_fw = roof(fw_ms, alg_fw, "forward", kernel="k3_forward<float>", avg_launch_ms=round(fw_ms, 4),
                 launches=fw["launches"], alg_bytes_per_launch=int(alg_fw))
-    r_up = roof(up_ms, alg_up, kernels="k3_gather_part + k3_gather_finish per octree level",
+    r_up = roof(up_ms, alg_up, "update", kernels="k3_gather_part + k3_gather_finish per octree level",
                 avg_pass_ms=round(up_ms, 4), passes=J * args.steps, alg_bytes_per_pass=int(alg_up))
     dominant = "update" if up["ms"] >= fw["ms"] else "forward"
     out = {"metric": METRIC, "value": round(it_s, 3), "unit": "AM iter/s", "n_gpus": 1,
@@ -453,8 +460,23 @@ def bench_cone(args):
     if not args.no_cpu_baseline:
         log("CPU oracle on the downscaled case")
         out["cpu_baseline"] = cone_cpu_baseline("cone64", M, g.n)
+    copy_calibration(args, dev, out)
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration(args, dev, out):
+    """Three device copies of a buffer of known size at the end of the run: the reference
+    that scales the byte counters of a profiling run (FETCH_SIZE, WRITE_SIZE per copy)."""
+    if args.copy_calibration <= 0:
+        return
+    import torch
+    src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    out["copy_calibration_bytes"] = int(src.numel() * 4)
 
 
 def dataclasses_replace(obj, **kw):
@@ -664,13 +686,7 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_views)
-    if args.copy_calibration > 0:
-        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = int(src.numel() * 4)
+    copy_calibration(args, dev, out)
     ctx.close()
     print(json.dumps(out), flush=True)
 
