@@ -10,8 +10,11 @@ Geometry (the paper gives none; this project's reading, stated for every impleme
     column axis (-sin a, cos a, 0) and row axis (0, 0, 1); detector element (row rr, col cc)
     at offsets u = (cc - (n_cols - 1)/2) col_pitch, w = (rr - (n_rows - 1)/2) row_pitch;
   * one ray per element, source to element centre; ray index y = (v n_rows + rr) n_cols + cc;
-  * a direction component within 1e-12 of zero is taken as zero, the line moving to the
-    centre of the voxel slab holding the source (as for the 2-D fan beam).
+  * voxels are half-open boxes and a line lying on a voxel boundary belongs to the voxel on
+    the + side, placed as exact arithmetic places it (as for the 2-D fan beam): a view cosine
+    or sine within 1e-12 of zero is exactly zero, a direction component within 1e-12 of zero
+    is zero and the line moves to the centre of the voxel slab holding the source (an origin
+    within 1e-9 voxel of a slab boundary lies on it).
 
 3-D Haar (config 5 names a "3-level 3D Haar" transform): orthonormal and separable, in a
 3-D Mallat layout. At level l (1..L), with m = n >> l and mz = nz >> l, node (l, k, i, j)
@@ -26,7 +29,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import wam
-from .geometry import snap_axis_parallel
+from .geometry import axis_cos_sin, snap_axis_parallel
 
 DETAILS = [(tz, ty, tx) for tz in (0, 1) for ty in (0, 1) for tx in (0, 1) if (tz, ty, tx) != (0, 0, 0)]
 
@@ -50,7 +53,7 @@ def rays3(g, views=None, ids=None):
         w = (np.arange(g.n_rows) - (g.n_rows - 1) / 2.0) * g.row_pitch
         A, W, U = np.meshgrid(ang, w, u, indexing="ij")
         A, W, U = A.ravel(), W.ravel(), U.ravel()
-    ca, sa = np.cos(A), np.sin(A)
+    ca, sa = axis_cos_sin(A)
     src = np.stack([g.sod * ca, g.sod * sa, np.zeros_like(A)], axis=1)
     det = np.stack([-(g.sdd - g.sod) * ca - U * sa, -(g.sdd - g.sod) * sa + U * ca, W], axis=1)
     d = det - src

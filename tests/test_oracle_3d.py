@@ -268,3 +268,29 @@ def test_longest_chord_symmetry_reduction():
         o, e = vol3d.rays3(g)
         lo = np.array([-g.n / 2, -g.n / 2, -g.nz / 2]) * g.pixel
         assert abs(longest_chord(g) - vol3d.box_chord3(o, e, lo, -lo).max()) <= 1e-12 * g.n
+
+
+def test_cone_central_column_at_quarter_turns_takes_the_plus_side():
+    """Hand-derived: a 4x4x4 volume of 1 mm voxels, views at 0, 90, 180 and 270 degrees, 3
+    detector columns (the central column's rays lie in the plane x = 0 at 90 and 270 degrees
+    and y = 0 at 0 and 180, a voxel boundary) and 4 rows (no ray in the plane z = 0). Every
+    voxel such a ray crosses is in voxel column (row) 2, the + side, and the chords of one ray
+    add up to its path length through the volume."""
+    g = synth.cone_geometry(4, 4, 4, 4, 3, sod=10.0, sdd=20.0)
+    H = vol3d.system_matrix3(g).toarray().reshape(4, 4, 3, 4, 4, 4)   # [v][row][col][z][y][x]
+    o, e = vol3d.rays3(g)
+    for v in range(4):
+        for rr in range(4):
+            h = H[v, rr, 1]
+            z, y, x = np.nonzero(h)
+            assert z.size > 0
+            if v % 2:
+                assert np.all(x == 2), (v, rr, x)
+            else:
+                assert np.all(y == 2), (v, rr, y)
+            ray = (v * 4 + rr) * 3 + 1
+            exy, ez = vol3d.edges3(g)
+            want = vol3d.box_chord3(o[ray:ray + 1], e[ray:ray + 1], np.array([[exy[2], -2.0, ez[0]]]) if v % 2
+                                    else np.array([[-2.0, exy[2], ez[0]]]),
+                                    np.array([[exy[3], 2.0, ez[-1]]]) if v % 2 else np.array([[2.0, exy[3], ez[-1]]]))
+            np.testing.assert_allclose(h.sum(), want[0], atol=1e-12)

@@ -173,3 +173,39 @@ def test_axis_parallel_rays_on_pixel_boundaries_go_to_the_plus_side():
             row[b, :] = 1.0       # view 90: the line y = b - 4 in row b
         np.testing.assert_allclose(H[0, b], col, atol=1e-12)
         np.testing.assert_allclose(H[2, b], row, atol=1e-12)
+
+
+def test_fan_central_rays_at_quarter_turns_take_the_plus_side():
+    """Hand-derived: fan beam on a 4x4 image of 1 mm pixels, views at 0, 90, 180 and 270
+    degrees, 5 bins (odd: the central bin's ray passes through the isocentre). In exact
+    arithmetic each central ray lies on the line x = 0 (views 90 and 270) or y = 0 (views 0
+    and 180), the boundary between pixel columns (rows) 1 and 2, so with half-open pixels it
+    runs through column (row) 2 only: chord 1 in each of its four pixels. The sources at 90
+    and 270 degrees have x = 600 cos(a), about +-1e-13 in floating point; the reading places
+    both lines alike, on the + side, whichever way that rounding falls."""
+    n = 4
+    g = synth.fan_geometry(n, 4, 5, sod=10.0, sdd=20.0, pixel=1.0)
+    H = siddon.system_matrix(g).toarray().reshape(4, 5, n, n)
+    col2 = np.zeros((n, n))
+    col2[:, 2] = 1.0
+    row2 = np.zeros((n, n))
+    row2[2, :] = 1.0
+    for v, want in ((0, row2), (1, col2), (2, row2), (3, col2)):
+        np.testing.assert_allclose(H[v, 2], want, atol=1e-12)
+    o, e = geometry.rays(g)
+    np.testing.assert_array_equal(o[[5 + 2, 15 + 2], 0], [0.5, 0.5])   # snapped to column 2's centre
+    # the same with the source coordinates as rounded by cos/sin of the float angle
+    c270 = math.cos(1.5 * math.pi)
+    assert c270 != 0.0 and abs(c270) < 1e-12
+    cs = geometry.axis_cos_sin(np.array([0.5 * math.pi, math.pi, 1.5 * math.pi]))
+    np.testing.assert_array_equal(cs[0], [0.0, -1.0, 0.0])
+    np.testing.assert_array_equal(cs[1], [1.0, 0.0, -1.0])
+
+
+def test_boundary_snap_of_axis_parallel_origins():
+    """An axis-parallel line whose offset is within 1e-9 pixel of a pixel boundary lies on
+    that boundary (+ side); one a millionth of a pixel off it stays where it is."""
+    o = np.array([[1.0 - 3e-13, -50.0], [1.0 + 3e-13, -50.0], [-1.0 - 1e-6, -50.0], [0.25, -50.0]])
+    e = np.tile([0.0, 1.0], (4, 1))
+    o2, _ = geometry.snap_axis_parallel(o, e, [4, 4], 1.0)
+    np.testing.assert_array_equal(o2[:, 0], [1.5, 1.5, -1.5, 0.5])
