@@ -14,6 +14,10 @@
  *            u = (b - (n_bins - 1) / 2) * bin_pitch on the detector axis (-sin a, cos a).
  *            Parallel beam: the line x cos a + y sin a = u. Fan beam (flat detector): from
  *            the source sod (cos a, sin a) to the point -(sdd - sod)(cos a, sin a) + u (-sin a, cos a).
+ *            A line on a pixel boundary belongs to the pixel on the + side, placed as exact
+ *            arithmetic places it: cos a or sin a within 1e-12 of 0 is 0 (the angle is a
+ *            multiple of pi/2), a direction component within 1e-12 of 0 is 0 (axis-parallel
+ *            line), and such a line's offset within 1e-9 pixel of a boundary is on it.
  *   wavelets orthonormal 2-D Haar with `levels` levels in Mallat layout (an n x n array):
  *            at level l (1..L), with m = n >> l, node (l, i, j) covers pixel rows
  *            [i 2^l, (i+1) 2^l) and columns [j 2^l, (j+1) 2^l); its details sit at
@@ -288,6 +292,25 @@ wamct_status wamct_get_tree_rule(wamct_ctx* ctx, int32_t* rule);
 wamct_status wamct_set_penalty(wamct_ctx* ctx, double lambda);
 wamct_status wamct_get_penalty(wamct_ctx* ctx, double* lambda);
 
+/* Explicit tree sequence Z_s^(j): Algorithm 1 takes the sequence of active sets as an input
+ * (the Results section grows it by the tree rule; wamct_solve does that when no schedule is
+ * set). n_trees trees: before update j = at[k] of wamct_solve or wamct_batch_solve, tree k
+ * becomes the active set of every scan. at: HOST int32[n_trees], >= 0 and strictly
+ * ascending, counted from the first update of that solve. masks: DEVICE uint8
+ * [n_trees][S][n*n] (cone beam: [n_trees][nz*n*n]), each a valid tree (E_INVALID
+ * otherwise); they are copied into the context (allocates n_trees x S x n*n bytes) so the
+ * solve needs no host round trip of the state: per tree change it enqueues the mask copy,
+ * zeroes the coefficients outside the new tree (those it adds start at 0, as the tree rule's
+ * do) and rebuilds Z0 (eq. 1.61) and the work lists, with the one host synchronization
+ * every tree change has. With tree sharing, slice 0's tree is used for every slice. While a
+ * schedule is set, wamct_solve needs n_expand = 0 (E_INVALID otherwise) and a batch applies
+ * the context's schedule in place of its expansion list; n_trees = 0 clears the schedule.
+ * wamct_iterate and wamct_expand ignore it. Synchronizes. */
+wamct_status wamct_set_tree_schedule(wamct_ctx* ctx, int32_t n_trees, const int32_t* at, const uint8_t* masks);
+/* Number of scheduled trees into *n_trees and their first min(cap, n) iterations into at
+ * (HOST int32[cap], nullable). */
+wamct_status wamct_get_tree_schedule(wamct_ctx* ctx, int32_t* n_trees, int32_t* at, int32_t cap);
+
 /* ---------------------------------------------------------------- batches
  * Uneven batches: several contexts (different geometries, image sizes and view counts,
  * each a stack of scans) solved together. Each context is bound to one of n_streams
@@ -308,8 +331,9 @@ const char* wamct_batch_last_error(const wamct_batch* batch);
 wamct_status wamct_batch_reset(wamct_batch* batch);
 /* wamct_solve of every context with the same schedule (n_iters, expand_at, frac).
  * idiv: HOST array of n_ctx device pointers (the array or any entry may be NULL); entry i
- * is double[S_i][n_iters + 1] for context i. Results equal those of wamct_solve on each
- * context alone. Synchronizes once per expansion. */
+ * is double[S_i][n_iters + 1] for context i. A context with a tree schedule
+ * (wamct_set_tree_schedule) follows it instead of the expansion list. Results equal those
+ * of wamct_solve on each context alone. Synchronizes once per tree change. */
 wamct_status wamct_batch_solve(wamct_batch* batch, int32_t n_iters, const int32_t* expand_at, int32_t n_expand,
                                double frac, double* const* idiv);
 /* Autotuner of the backprojection tiling: for every context, n_trial iterations (after

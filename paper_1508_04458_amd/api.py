@@ -4,7 +4,7 @@ one GPU) and batches of contexts of different geometries.
 Every method marshals torch tensors (device memory and the current stream) into the
 matching `wamct_*` call; all arithmetic runs in the HIP kernels of libwamct.so."""
 import ctypes
-from typing import Dict, Optional, Sequence
+from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 import torch
@@ -163,6 +163,23 @@ class Context:
         sched = (ctypes.c_int32 * max(1, len(schedule)))(*[int(s) for s in schedule])
         self._call(lib.wamct_solve, int(n_iters), sched, len(schedule), float(frac), _ptr(idiv))
         return idiv
+
+    def set_tree_schedule(self, at: Sequence[int], masks: Optional[torch.Tensor]) -> None:
+        """Explicit tree sequence Z_s^(j): before update at[k] of a solve, masks[k] (uint8,
+        [n_trees, S, *image] contiguous on the device) becomes the active set; solve() then
+        takes no expansion list. An empty `at` clears the schedule."""
+        n = len(at)
+        if n:
+            self._arr(masks, n * self.S * self.npix, "masks", torch.uint8)
+        arr = (ctypes.c_int32 * max(1, n))(*[int(a) for a in at])
+        self._call(lib.wamct_set_tree_schedule, n, arr, _ptr(masks) if n else None)
+
+    def tree_schedule(self) -> List[int]:
+        n = ctypes.c_int32()
+        self._call(lib.wamct_get_tree_schedule, ctypes.byref(n), None, 0)
+        arr = (ctypes.c_int32 * max(1, n.value))()
+        self._call(lib.wamct_get_tree_schedule, ctypes.byref(n), arr, n.value)
+        return [int(arr[k]) for k in range(n.value)]
 
     def set_tree_sharing(self, shared: bool) -> None:
         """Scans as z-slices of one volume sharing one tree grown on the slice-summed image."""

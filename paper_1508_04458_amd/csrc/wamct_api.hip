@@ -99,6 +99,7 @@ struct Ctx final : wamct_ctx {
   int rule = WAMCT_RULE_VALUE;   // tree rule of the expansions
   double lam = 0.0;              // roughness-penalty weight (0: Algorithm 1 as in the paper)
   T* gpen = nullptr;             // [P][n][n] Omega^T grad R(mu-hat) of the current iteration
+  uint8_t* sched = nullptr;       // [n trees][P][n*n] masks of the explicit tree schedule
   // ordered subsets of views (n_sub > 1): b and Z0 of every subset, [n_sub][P][...]
   int n_sub = 1;
   T* bsub = nullptr;
@@ -126,6 +127,7 @@ struct Ctx final : wamct_ctx {
     for (void* p : allocs) hipFree(p);
     if (part) hipFree(part);
     free_subsets();
+    if (sched) hipFree(sched);
     if (h_ints) hipHostFree(h_ints);
     if (h_scal) hipHostFree(h_scal);
   }
@@ -358,6 +360,55 @@ struct Ctx final : wamct_ctx {
     return WAMCT_OK;
   }
   int32_t tree_sharing() const override { return shared_tree ? 1 : 0; }
+
+  // Explicit Z_s^(j): the masks are validated and copied into the context.
+  wamct_status set_tree_schedule(int32_t n, const int32_t* at, const uint8_t* mk) override {
+    const std::string e = check_sched(n, at, mk);
+    if (!e.empty()) return fail(WAMCT_E_INVALID, e);
+    HIPCHK(hipStreamSynchronize(st));
+    sched_at.clear();
+    if (sched) {
+      HIPCHK(hipFree(sched));
+      sched = nullptr;
+    }
+    if (n == 0) return WAMCT_OK;
+    const size_t bytes = size_t(n) * P * NN;
+    hipError_t er = hipMalloc((void**)&sched, bytes);
+    if (er != hipSuccess) {
+      (void)hipGetLastError();
+      sched = nullptr;
+      return fail(WAMCT_E_OOM, fmt("hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(er)));
+    }
+    HIPCHK(hipMemcpyAsync(sched, mk, bytes, hipMemcpyDeviceToDevice, st));
+    fill_i32(ints + 1, 1, 0, st);
+    check_mask(g, sched, ints + 1, n * P, st);
+    LAUNCHED();
+    HIPCHK(hipMemcpyAsync(h_ints + 1, ints + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (h_ints[1]) {
+      HIPCHK(hipFree(sched));
+      sched = nullptr;
+      return fail(WAMCT_E_INVALID, fmt("tree schedule rejected: %d invalid tree entries", h_ints[1]));
+    }
+    sched_at.assign(at, at + n);
+    return WAMCT_OK;
+  }
+  // Tree k becomes the active set: coefficients outside it are zeroed (new ones are zero
+  // already); a shared tree takes slice 0's mask for every slice.
+  wamct_status enq_schedule(hipStream_t s, int k) override {
+    const uint8_t* src = sched + size_t(k) * P * NN;
+    {
+      Scope sc(this, WAMCT_K_TREE, s);
+      if (shared_tree)
+        for (int p = 0; p < P; ++p) HIPCHK(hipMemcpyAsync(mask + p * NN, src, NN, hipMemcpyDeviceToDevice, s));
+      else
+        HIPCHK(hipMemcpyAsync(mask, src, NN * P, hipMemcpyDeviceToDevice, s));
+      Launch<T>::apply_mask(g, beta, mask, P, s);
+      fill_i32_strided(ints + 2, P, kInts, 0, s);
+    }
+    LAUNCHED();
+    return enq_tree(s);
+  }
   // gather over segments (of the tree, or of every pixel) with a host check that their
   // partial sums fit; views, b and Z0 of the selection
   wamct_status gather(int mode, const T* y, const std::vector<Segment>& sg, int S, T* bt, int* held, T* bp, T* bm,
@@ -419,7 +470,9 @@ struct Ctx final : wamct_ctx {
     std::vector<double2> hv(g.nv);
     for (int v = 0; v < g.nv; ++v) {
       const double a = G.angle0 + v * (G.angle_span / G.n_views);
-      hv[v] = make_double2(std::cos(a), std::sin(a));
+      double c, sn;
+      view_cos_sin(a, c, sn);
+      hv[v] = make_double2(c, sn);
     }
     HIPCHK(hipMemcpyAsync(views, hv.data(), sizeof(double2) * g.nv, hipMemcpyHostToDevice, st));
     Geo<T, R>::view_table(g, views, vT, st);
@@ -723,10 +776,18 @@ struct Ctx final : wamct_ctx {
                      double* idv) override {
     if (!has_data) return fail(WAMCT_E_STATE, "solve before set_data");
     if (!(frac >= 0) || !std::isfinite(frac)) return fail(WAMCT_E_INVALID, "frac must be finite and >= 0");
+    if (!sched_at.empty() && n_expand > 0)
+      return fail(WAMCT_E_INVALID, "a tree schedule is set: the expansion list must be empty");
     if (tree_dirty) CHECKED(rebuild_tree());
     const int64_t os = int64_t(n_iters) + 1;
     int e = 0;
     for (int j = 0; j < n_iters; ++j) {
+      const int k = sched_index(j);
+      if (k >= 0) {
+        CHECKED(enq_schedule(st, k));
+        HIPCHK(hipStreamSynchronize(st));
+        CHECKED(finish_tree(nullptr));
+      }
       while (e < n_expand && expand_at[e] < j) ++e;
       if (e < n_expand && expand_at[e] == j) {
         CHECKED(expand_tree(frac, nullptr));
@@ -1108,19 +1169,36 @@ struct wamct_batch {
       if (r) return from(ctx[i], r);
     }
     const int64_t os = int64_t(n_iters) + 1;
-    int e = 0, j = 0;
+    // tree changes: the batch's expansion list (the tree rule, for contexts without a tree
+    // schedule) and every context's own schedule
+    std::vector<int> events(at, at + n_expand);
+    for (wamct_ctx* c : ctx) events.insert(events.end(), c->sched_at.begin(), c->sched_at.end());
+    std::sort(events.begin(), events.end());
+    events.erase(std::unique(events.begin(), events.end()), events.end());
+    size_t e = 0;
+    int j = 0;
     while (j < n_iters) {
-      while (e < n_expand && at[e] < j) ++e;
-      if (e < n_expand && at[e] == j) {
+      while (e < events.size() && events[e] < j) ++e;
+      if (e < events.size() && events[e] == j) {
+        const bool rule_now = std::binary_search(at, at + n_expand, j);
+        bool changed = false;
         for (size_t i = 0; i < ctx.size(); ++i) {
-          wamct_status r = ctx[i]->enq_expand(sof(i), frac);
+          wamct_status r = WAMCT_OK;
+          if (!ctx[i]->sched_at.empty()) {
+            const int k = ctx[i]->sched_index(j);
+            if (k >= 0) r = ctx[i]->enq_schedule(sof(i), k);
+            changed = changed || k >= 0;
+          } else if (rule_now) {
+            r = ctx[i]->enq_expand(sof(i), frac);
+            changed = true;
+          }
           if (r) return from(ctx[i], r);
         }
-        CHECKED(finish_trees());
+        if (changed) CHECKED(finish_trees());
         ++e;
       }
       int stop = n_iters;
-      if (e < n_expand && at[e] < stop) stop = at[e];
+      if (e < events.size() && events[e] < stop) stop = events[e];
       CHECKED(run(stop - j, idiv, os));
       j = stop;
     }
@@ -1257,6 +1335,16 @@ wamct_status wamct_set_subsets(wamct_ctx* ctx, int32_t n_subsets) { CTX_CALL(set
 wamct_status wamct_set_tree_sharing(wamct_ctx* ctx, int32_t shared) { CTX_CALL(set_tree_sharing(shared)); }
 wamct_status wamct_set_tree_rule(wamct_ctx* ctx, int32_t rule) { CTX_CALL(set_tree_rule(rule)); }
 wamct_status wamct_set_penalty(wamct_ctx* ctx, double lambda) { CTX_CALL(set_penalty(lambda)); }
+wamct_status wamct_set_tree_schedule(wamct_ctx* ctx, int32_t n_trees, const int32_t* at, const uint8_t* masks) {
+  CTX_CALL(set_tree_schedule(n_trees, at, masks));
+}
+wamct_status wamct_get_tree_schedule(wamct_ctx* ctx, int32_t* n_trees, int32_t* at, int32_t cap) {
+  if (!ctx) { g_last_error = "ctx is NULL"; return WAMCT_E_INVALID; }
+  if (!n_trees) return ctx->fail(WAMCT_E_INVALID, "n_trees must not be NULL");
+  *n_trees = int32_t(ctx->sched_at.size());
+  for (int k = 0; at && k < cap && k < *n_trees; ++k) at[k] = ctx->sched_at[size_t(k)];
+  return WAMCT_OK;
+}
 wamct_status wamct_get_penalty(wamct_ctx* ctx, double* lambda) {
   if (!ctx) { g_last_error = "ctx is NULL"; return WAMCT_E_INVALID; }
   if (!lambda) return ctx->fail(WAMCT_E_INVALID, "lambda must not be NULL");

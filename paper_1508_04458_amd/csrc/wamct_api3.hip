@@ -56,6 +56,7 @@ struct Ctx3 final : wamct_ctx {
   T* yn = nullptr;                 // ray values scaled by |D| for the gather
   T* coefg = nullptr;              // Omega^T H^T (d - q-hat) of the residual-gradient rule
   int rule = WAMCT_RULE_VALUE;     // tree rule of the expansions
+  uint8_t* sched = nullptr;        // [n trees][N] masks of the explicit tree schedule
   double2* colt = nullptr;         // [nv][nc] (1/Dx, 1/Dy)
   double *rowt = nullptr, *nrm = nullptr;  // [nr] 1/Dz, [nr][nc] |D|
   void *recR = nullptr, *recC = nullptr;
@@ -92,6 +93,7 @@ struct Ctx3 final : wamct_ctx {
     for (auto e : pool) hipEventDestroy(e);
     for (void* p : allocs) hipFree(p);
     if (part) hipFree(part);
+    if (sched) hipFree(sched);
     if (h_ints) hipHostFree(h_ints);
     if (h_scal) hipHostFree(h_scal);
   }
@@ -231,7 +233,9 @@ struct Ctx3 final : wamct_ctx {
     std::vector<double2> hv(g.nv);
     for (int v = 0; v < g.nv; ++v) {
       const double a = G.angle0 + v * (G.angle_span / G.n_views);
-      hv[v] = make_double2(std::cos(a), std::sin(a));
+      double c, sn;
+      view_cos_sin(a, c, sn);
+      hv[v] = make_double2(c, sn);
     }
     HIPCHK(hipMemcpyAsync(views, hv.data(), sizeof(double2) * g.nv, hipMemcpyHostToDevice, st));
     Geo3<T>::ray_table(g, views, A, B, C, st);
@@ -428,12 +432,62 @@ struct Ctx3 final : wamct_ctx {
     HIPCHK(hipStreamSynchronize(st));
     return finish_tree(n_split);
   }
+  // Explicit Z_s^(j): the octree masks are validated and copied into the context.
+  wamct_status set_tree_schedule(int32_t n, const int32_t* at, const uint8_t* mk) override {
+    const std::string e = check_sched(n, at, mk);
+    if (!e.empty()) return fail(WAMCT_E_INVALID, e);
+    HIPCHK(hipStreamSynchronize(st));
+    sched_at.clear();
+    if (sched) {
+      HIPCHK(hipFree(sched));
+      sched = nullptr;
+    }
+    if (n == 0) return WAMCT_OK;
+    const size_t bytes = size_t(n) * N;
+    hipError_t er = hipMalloc((void**)&sched, bytes);
+    if (er != hipSuccess) {
+      (void)hipGetLastError();
+      sched = nullptr;
+      return fail(WAMCT_E_OOM, fmt("hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(er)));
+    }
+    HIPCHK(hipMemcpyAsync(sched, mk, bytes, hipMemcpyDeviceToDevice, st));
+    fill_i32(ints + 1, 1, 0, st);
+    for (int k = 0; k < n; ++k) check_mask3(g, sched + size_t(k) * N, ints + 1, st);
+    LAUNCHED();
+    HIPCHK(hipMemcpyAsync(h_ints + 1, ints + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (h_ints[1]) {
+      HIPCHK(hipFree(sched));
+      sched = nullptr;
+      return fail(WAMCT_E_INVALID, fmt("tree schedule rejected: %d invalid octree entries", h_ints[1]));
+    }
+    sched_at.assign(at, at + n);
+    return WAMCT_OK;
+  }
+  wamct_status enq_schedule(hipStream_t s, int k) override {
+    {
+      Scope sc(this, WAMCT_K_TREE, s);
+      HIPCHK(hipMemcpyAsync(mask, sched + size_t(k) * N, N, hipMemcpyDeviceToDevice, s));
+      Geo3<T>::apply_mask(g, beta, mask, s);
+      fill_i32(ints + 2, 1, 0, s);
+    }
+    LAUNCHED();
+    return enq_tree(s);
+  }
   wamct_status solve(int32_t n_iters, const int32_t* expand_at, int32_t n_expand, double frac,
                      double* idv) override {
     if (!has_data) return fail(WAMCT_E_STATE, "solve before set_data");
+    if (!sched_at.empty() && n_expand > 0)
+      return fail(WAMCT_E_INVALID, "a tree schedule is set: the expansion list must be empty");
     if (tree_dirty) CHECKED(rebuild_tree());
     int e = 0;
     for (int j = 0; j < n_iters; ++j) {
+      const int k = sched_index(j);
+      if (k >= 0) {
+        CHECKED(enq_schedule(st, k));
+        HIPCHK(hipStreamSynchronize(st));
+        CHECKED(finish_tree(nullptr));
+      }
       while (e < n_expand && expand_at[e] < j) ++e;
       if (e < n_expand && expand_at[e] == j) {
         CHECKED(expand_tree(frac, nullptr));

@@ -11,6 +11,12 @@ namespace wamct {
 __host__ __device__ inline int imin(int a, int b) { return a < b ? a : b; }
 __host__ __device__ inline int imax(int a, int b) { return a > b ? a : b; }
 
+// A coordinate in pixel units within 1e-9 of an integer (a pixel boundary) is taken as on it.
+__host__ __device__ inline double edge_snap(double f) {
+  const double r = rint(f);
+  return fabs(f - r) <= 1e-9 ? r : f;
+}
+
 // Ray (origin, unit direction) of view v, bin b in FP64 (conventions in include/wamct.h).
 __host__ __device__ inline void ray_of(const DevGeom& g, double2 cs, int b, double& ox, double& oy,
                               double& ex, double& ey) {
@@ -28,13 +34,14 @@ __host__ __device__ inline void ray_of(const DevGeom& g, double2 cs, int b, doub
   // A direction within 1e-12 of an axis is treated as exactly axis-parallel: the line is
   // moved to the centre of the pixel row (column) holding the ray's origin (the fan-beam
   // source, or the parallel-beam foot point u (c, s)), which leaves every chord unchanged
-  // and puts a line lying on a boundary into the pixel on the + side (half-open pixels);
+  // and puts a line lying on a boundary into the pixel on the + side (half-open pixels; an
+  // origin within 1e-9 pixel of a boundary is on it, as exact arithmetic would place it);
   // it keeps a 1e-12 tilt so that 1/e is finite for the walks (the ray table stores an
   // inverse that acts as infinite).
   const double hn = 0.5 * g.n;
   const bool snap_y = fabs(ey) < 1e-12, snap_x = fabs(ex) < 1e-12;
-  const double py0 = (floor(oy / g.pixel + hn) + 0.5 - hn) * g.pixel;
-  const double px0 = (floor(ox / g.pixel + hn) + 0.5 - hn) * g.pixel;
+  const double py0 = (floor(edge_snap(oy / g.pixel + hn)) + 0.5 - hn) * g.pixel;
+  const double px0 = (floor(edge_snap(ox / g.pixel + hn)) + 0.5 - hn) * g.pixel;
   if (snap_y) ey = ey < 0 ? -1e-12 : 1e-12;
   if (snap_x) ex = ex < 0 ? -1e-12 : 1e-12;
   // move the origin to the point of the line closest to the image centre (|t| stays

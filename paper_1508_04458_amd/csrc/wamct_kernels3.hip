@@ -70,11 +70,18 @@ __device__ inline double breduce(double v) {
 
 // ------------------------------------------------------------------ geometry
 
+// A coordinate in voxel units within 1e-9 of an integer (a voxel boundary) is taken as on it.
+__device__ inline double edge_snap3(double f) {
+  const double r = rint(f);
+  return fabs(f - r) <= 1e-9 ? r : f;
+}
+
 // Ray of detector element (row, col) of a view: from the source sod (c, s, 0) to the element
 // centre on the flat detector; origin moved to the point closest to the volume centre. A
 // direction component within 1e-12 of 0 is treated as exactly 0: the line is moved to the
 // centre of the voxel slab that contains it along that axis (chords unchanged; a line on a
-// boundary goes to the + side, half-open voxels) and tilted by 1e-12 so 1/e stays finite.
+// boundary goes to the + side, half-open voxels, with the source's coordinate taken as on a
+// boundary when within 1e-9 voxel of it) and tilted by 1e-12 so 1/e stays finite.
 __global__ __launch_bounds__(kB) void k3_ray_table(DevGeom3 g, const double2* __restrict__ views,
                                                    double4* __restrict__ A, double4* __restrict__ B,
                                                    double* __restrict__ C) {
@@ -100,9 +107,9 @@ __global__ __launch_bounds__(kB) void k3_ray_table(DevGeom3 g, const double2* __
   if (snz) ez = ez < 0 ? -1e-12 : 1e-12;
   const double tc = -(sx * ex + sy * ey + sz * ez);
   double ox = sx + tc * ex, oy = sy + tc * ey, oz = sz + tc * ez;
-  if (snx) ox = (floor(sx / g.pixel + hn) + 0.5 - hn) * g.pixel;
-  if (sny) oy = (floor(sy / g.pixel + hn) + 0.5 - hn) * g.pixel;
-  if (snz) oz = (floor(sz / g.pixel + hz) + 0.5 - hz) * g.pixel;
+  if (snx) ox = (floor(edge_snap3(sx / g.pixel + hn)) + 0.5 - hn) * g.pixel;
+  if (sny) oy = (floor(edge_snap3(sy / g.pixel + hn)) + 0.5 - hn) * g.pixel;
+  if (snz) oz = (floor(edge_snap3(sz / g.pixel + hz)) + 0.5 - hz) * g.pixel;
   A[r] = make_double4(ox, oy, oz, 1.0 / ex);
   B[r] = make_double4(1.0 / ey, 1.0 / ez, ex, ey);
   C[r] = ez;
