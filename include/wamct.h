@@ -311,6 +311,28 @@ wamct_status wamct_set_tree_schedule(wamct_ctx* ctx, int32_t n_trees, const int3
  * (HOST int32[cap], nullable). */
 wamct_status wamct_get_tree_schedule(wamct_ctx* ctx, int32_t* n_trees, int32_t* at, int32_t cap);
 
+/* ---------------------------------------------------------------- no-allocation call
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc) and hold no context: the I-divergence
+ * of wamct_idiv, out[s] = I(d_s || q_s) = sum_y q_s(y) - d_s(y) + d_s(y) log(d_s(y) / q_s(y))
+ * (0 log 0 = 0) for s < n_scans, from plain device arrays d, q ([n_scans][n_rays], float
+ * for WAMCT_F32, double for WAMCT_F64) into out (device double[n_scans]), enqueued on
+ * `stream` (hipStream_t, NULL = default). It runs the kernels of wamct_idiv (FP64 partial
+ * sums of WAMCT_NOALLOC_RAYS_PER_PARTIAL rays, added in a fixed order), so the result equals
+ * wamct_idiv's bit for bit. It allocates nothing: the partial sums live in a static device
+ * buffer of WAMCT_NOALLOC_MAX_PARTIALS doubles (8 MiB) that every device the call runs on
+ * holds until the process ends; its address is looked up once per device on the first
+ * call there. n_scans x ceil(n_rays / WAMCT_NOALLOC_RAYS_PER_PARTIAL) may not exceed
+ * WAMCT_NOALLOC_MAX_PARTIALS (E_INVALID; so up to 268 M rays in all). Calls on one device
+ * share that buffer: calls that overlap in time on one device (other streams, other host
+ * threads) race and must be ordered by the caller. Errors: E_INVALID for a bad dtype,
+ * n_rays outside [1, 2^31 - 1], n_scans outside [1, 65535], NULL pointers or too many
+ * partial sums; E_HIP for runtime failures. The message is wamct_last_error(NULL). */
+#define WAMCT_NOALLOC_MAX_PARTIALS (1 << 20)
+#define WAMCT_NOALLOC_RAYS_PER_PARTIAL 256
+wamct_status wamct_idiv_noalloc(int32_t dtype, int64_t n_rays, int32_t n_scans, const void* d, const void* q,
+                               double* out, void* stream);
+
 /* ---------------------------------------------------------------- batches
  * Uneven batches: several contexts (different geometries, image sizes and view counts,
  * each a stack of scans) solved together. Each context is bound to one of n_streams

@@ -29,7 +29,7 @@ SYMBOLS = (
     "wamct_batch_last_error", "wamct_batch_reset", "wamct_batch_solve", "wamct_batch_autotune",
     "wamct_batch_stats", "wamct_set_subsets", "wamct_get_subsets", "wamct_set_tree_sharing",
     "wamct_get_tree_sharing", "wamct_set_tree_rule", "wamct_get_tree_rule", "wamct_set_penalty",
-    "wamct_get_penalty", "wamct_set_tree_schedule", "wamct_get_tree_schedule",
+    "wamct_get_penalty", "wamct_set_tree_schedule", "wamct_get_tree_schedule", "wamct_idiv_noalloc",
 )
 
 
@@ -97,6 +97,7 @@ def _load():
         "wamct_get_subsets": (vp, P(i32)),
         "wamct_set_tree_schedule": (vp, i32, P(i32), vp),
         "wamct_get_tree_schedule": (vp, P(i32), P(i32), i32),
+        "wamct_idiv_noalloc": (i32, i64, i32, vp, vp, vp, vp),
         "wamct_batch_create": (i32, P(vp), i32, i32, vp, P(vp)),
         "wamct_batch_destroy": (vp,),
         "wamct_batch_reset": (vp,),

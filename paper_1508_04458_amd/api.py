@@ -390,3 +390,29 @@ class Batch:
         self._call(lib.wamct_batch_stats, lanes, ctypes.byref(gl), ctypes.byref(gn), ctypes.byref(cap))
         return dict(stream_of_context=list(lanes), graph_launches=gl.value, graph_nodes=gn.value,
                     captures=cap.value)
+
+
+NOALLOC_MAX_PARTIALS = 1 << 20
+NOALLOC_RAYS_PER_PARTIAL = 256
+
+
+def idiv_noalloc(d: torch.Tensor, q: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    """I(d_s || q_s) for every row s of d, q ([n_scans, n_rays] or [n_rays], float32 or
+    float64, one dtype, on the current device) into `out` (float64 [n_scans]) through
+    wamct_idiv_noalloc: no context and no device allocation by the library (its partial
+    sums live in a static per-device buffer), enqueued on the current stream. `out` is the
+    caller's, so nothing here allocates either."""
+    if d.dtype != q.dtype or d.dtype not in (torch.float32, torch.float64):
+        raise TypeError("d and q must share a dtype, float32 or float64")
+    if d.shape != q.shape or d.dim() not in (1, 2):
+        raise ValueError(f"d {tuple(d.shape)} and q {tuple(q.shape)} must have one shape [n_scans, n_rays]")
+    if not (d.is_contiguous() and q.is_contiguous() and out.is_contiguous()):
+        raise ValueError("d, q and out must be contiguous")
+    scans = 1 if d.dim() == 1 else d.shape[0]
+    if out.dtype != torch.float64 or out.numel() != scans:
+        raise ValueError(f"out must be float64 with {scans} entries")
+    dt = _lib.F32 if d.dtype == torch.float32 else _lib.F64
+    stream = torch.cuda.current_stream(d.device).cuda_stream
+    check(lib.wamct_idiv_noalloc(dt, int(d.shape[-1]), int(scans), _ptr(d), _ptr(q), _ptr(out),
+                                 ctypes.c_void_p(stream)))
+    return out

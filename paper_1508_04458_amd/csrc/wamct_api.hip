@@ -13,6 +13,7 @@
 #include <cstring>
 #include <string>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/wamct.h"
@@ -1259,6 +1260,41 @@ struct wamct_batch {
   }
 };
 
+// ------------------------------------------------------------------ no-allocation I-divergence
+
+// FP64 partial sums of wamct_idiv_noalloc: one copy per device, held until the process ends.
+// Host code never passes this name to a kernel (on the host it is only a stand-in for the
+// symbol); it passes the device address looked up below.
+static __device__ __align__(256) double scratch[WAMCT_NOALLOC_MAX_PARTIALS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (which must be current), looked up once per device.
+hipError_t scratch_on(int dev, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+template <typename T>
+void idiv_into(const T* d, const T* q, int64_t rays, int scans, double* part, double* out, hipStream_t s) {
+  DevGeom g{};
+  g.nv = 1;
+  g.nb = int(rays);
+  const int nbk = Launch<T>::idiv_terms(g, q, d, part, scans, s);
+  reduce_stack(false, part, nbk, nbk, out, 1, nullptr, scans, s);
+}
+}  // namespace
+
 // ------------------------------------------------------------------ C ABI
 
 extern "C" {
@@ -1458,6 +1494,39 @@ wamct_status wamct_batch_autotune(wamct_batch* batch, int32_t n_trial, const int
   for (wamct_ctx* c : batch->ctx)
     if (!c->has_data_()) return batch->fail(WAMCT_E_STATE, "autotune before set_data on every context");
   return batch->autotune(n_trial, candidates, n_candidates, chosen);
+}
+
+wamct_status wamct_idiv_noalloc(int32_t dtype, int64_t n_rays, int32_t n_scans, const void* d, const void* q,
+                               double* out, void* stream) {
+  auto bad = [](wamct_status st, const std::string& m) {
+    g_last_error = m;
+    return st;
+  };
+  if (dtype != WAMCT_F32 && dtype != WAMCT_F64) return bad(WAMCT_E_INVALID, fmt("unknown dtype %d", dtype));
+  if (n_rays < 1 || n_rays > (int64_t(1) << 31) - 1)
+    return bad(WAMCT_E_INVALID, fmt("n_rays = %lld outside [1, 2^31 - 1]", (long long)n_rays));
+  if (n_scans < 1 || n_scans > 65535) return bad(WAMCT_E_INVALID, fmt("n_scans = %d outside [1, 65535]", n_scans));
+  if (!d || !q || !out) return bad(WAMCT_E_INVALID, "d, q and out must not be NULL");
+  const int64_t need = int64_t(n_scans) * idiv_blocks(n_rays);
+  if (need > WAMCT_NOALLOC_MAX_PARTIALS)
+    return bad(WAMCT_E_INVALID, fmt("n_scans x ceil(n_rays / %d) = %lld partial sums exceed the static buffer "
+                                    "of %lld", WAMCT_NOALLOC_RAYS_PER_PARTIAL, (long long)need,
+                                    (long long)WAMCT_NOALLOC_MAX_PARTIALS));
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return bad(WAMCT_E_HIP, fmt("hipGetDevice: %s", hipGetErrorString(e)));
+  if (dev < 0 || dev >= kMaxDevices) return bad(WAMCT_E_UNSUPPORTED, fmt("device %d >= %d", dev, kMaxDevices));
+  double* part = nullptr;
+  e = scratch_on(dev, &part);
+  if (e != hipSuccess) return bad(WAMCT_E_HIP, fmt("hipGetSymbolAddress(scratch): %s", hipGetErrorString(e)));
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dtype == WAMCT_F32)
+    idiv_into(static_cast<const float*>(d), static_cast<const float*>(q), n_rays, n_scans, part, out, s);
+  else
+    idiv_into(static_cast<const double*>(d), static_cast<const double*>(q), n_rays, n_scans, part, out, s);
+  e = hipGetLastError();
+  if (e != hipSuccess) return bad(WAMCT_E_HIP, fmt("kernel launch: %s", hipGetErrorString(e)));
+  return WAMCT_OK;
 }
 
 wamct_status wamct_batch_stats(wamct_batch* batch, int32_t* stream_of_ctx, int64_t* graph_launches,

@@ -148,6 +148,8 @@ struct Geo {
 int z0_partials(const DevGeom& g, const double2* views, const uint8_t* lev, double* part_max,
                 double* part_cnt, int S, hipStream_t s);
 // Deterministic single-block reductions of per-block partials: out[0] = sum or max.
+// per-block partial sums per scan that Launch<T>::idiv_terms writes for `rays` rays
+int idiv_blocks(int64_t rays);
 void reduce_sum(const double* part, int n, double* out, hipStream_t s);
 void reduce_max(const double* part, int n, double* out, hipStream_t s);
 // The same for a stack of S scans, one block per scan: scan p reduces part[p * pstride ..

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "../../include/wamct.h"
 #include "wamct_internal.h"
 #include "wamct_geom.h"
 #include "wamct_worklist.h"
@@ -22,6 +23,8 @@ template <> struct V2<float> { using t = float2; };
 template <> struct V2<double> { using t = double2; };
 
 constexpr int kBlock = 256;
+// wamct_idiv_noalloc sizes its static buffer by the rays one I-divergence partial covers
+static_assert(kBlock == WAMCT_NOALLOC_RAYS_PER_PARTIAL, "partial-sum size of the I-divergence");
 
 inline int blocks_for(int64_t n, int b = kBlock) { return int((n + b - 1) / b); }
 
@@ -1474,6 +1477,7 @@ int z0_partials(const DevGeom& g, const double2* views, const uint8_t* lev, doub
   }
   return nb;
 }
+int idiv_blocks(int64_t rays) { return blocks_for(rays); }
 void reduce_sum(const double* part, int n, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce<false>, dim3(1), dim3(kBlock), 0, s, part, n, int64_t(0), out, int64_t(0),
                      (int*)nullptr);

@@ -109,3 +109,16 @@ def test_cone_validation_accepts_configs(lib):
     for name, cfg in synth.CONE_CONFIGS.items():
         assert api.validate(cfg["geom"](), cfg["levels"], "f32") is None, name
         assert api.validate(cfg["geom"](), 0, "f64") is None, name
+
+
+def test_idiv_noalloc_rejects_bad_sizes_on_the_host(lib):
+    """Every rejection happens before any HIP call (so it runs without a GPU)."""
+    L = lib.lib
+    x = ctypes.c_void_p(16)    # never dereferenced: the calls fail validation first
+    too_many = (1 << 20) * 256 + 1
+    for args in ((lib.F32, too_many, 1, x, x, x), (lib.F32, 0, 1, x, x, x), (lib.F64, 1 << 31, 1, x, x, x),
+                 (lib.F32, 4, 0, x, x, x), (lib.F32, 4, 65536, x, x, x), (5, 4, 1, x, x, x),
+                 (lib.F32, 4, 1, None, x, x), (lib.F32, 4, 1, x, None, x), (lib.F32, 4, 1, x, x, None),
+                 (lib.F32, 256 * 4096, 257, x, x, x)):
+        assert L.wamct_idiv_noalloc(*args, None) == lib.E_INVALID, args
+    assert b"static buffer" in L.wamct_last_error(None)
