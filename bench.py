@@ -1,24 +1,30 @@
-"""Benchmark: tree-adaptive wavelet AM on one MI355X (fan512 workload by default).
+"""Benchmark: tree-adaptive wavelet AM on one MI355X.
 
-A step is one complete reconstruction of Algorithm 1 with the tree rule: 100 iterations
-from beta = 0 on the approximation-only 3-level tree, expanding at iterations 21, 43 and 85
-(the paper's 64/128/256-of-300 schedule scaled to 100 iterations). Inputs (counts, I0)
-are resident in HBM before timing starts. Prints ONE JSON line.
+Default workload (what `python bench.py` runs): cone512, the 3-D circular cone beam
+(512x512x256 volume, 720 views of a 256x1024 flat detector, 3-level 3-D Haar octree, FP32,
+50 iterations with expansions at 11, 21 and 43). A step is one complete reconstruction of
+Algorithm 1 with the tree rule from beta = 0 (Z0 and work lists rebuilt at every
+expansion). Inputs (counts, I0) are resident in HBM before timing starts. The 2-D fan-beam
+workload fan512 (512x512, 720 views x 1024 bins, 3-level Haar tree, 100 iterations with
+expansions at 21/43/85) runs after it and is reported as the nested object "fan512".
+Prints ONE JSON line.
 
-Extra fields:
+Extra fields (for either workload):
   gray_voxel_per_s  sum_j 2 W_j / time, W_j = (ray, active coefficient) pairs with phi != 0
-  full_am           image-domain AM (levels = 0) on the same GPU: it/s, and the time it
-                    needs to reach the tree run's final I-divergence (equal-objective)
+  full_am           image-domain AM (levels = 0) on the same GPU: it/s
+  equal_idiv        iterations and time image-domain AM needs to reach the tree run's final
+                    I-divergence (the Results section's "same objective function value level")
   gradient_rule     the same solve with the residual-gradient tree rule instead of the
                     paper's value rule (final I-divergence, time to the value rule's final)
-  roofline          the tree walk (forward projection over the leaves, Beer's law, I-div
-                    term), timed with HIP events on the library's stream over the timed steps;
-                    roofline_update: the update pass, likewise
-  cpu_baseline      the FP64 CPU oracle on a bounded sample of the same workload
+  roofline          the dominant kernel class, timed with HIP events on the library's stream
+                    over the timed steps, against stored-Phi-equivalent bytes (achieved, frac)
+                    and, where the committed byte counters match the current sources, against
+                    the measured bytes (measured_gbs, measured_frac)
+  cpu_baseline      the FP64 CPU oracle on a bounded sample of the workload, with the host
 
-Other workloads: --config uneven (256 independent problems of uneven size solved as one
-batch, graph-replayed), --config loss16 (differentiable loss + adjoint, 16 slices) and
---config cone512 (3-D cone beam, 512x512x256 volume, 3-D Haar octree, 50 iterations).
+Other workloads: --config fan512 alone, --config uneven (256 independent problems of uneven
+size solved as one batch, graph-replayed) and --config loss16 (differentiable loss +
+adjoint, 16 slices).
 """
 import argparse
 import hashlib
@@ -38,9 +44,9 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="fan512")
+    ap.add_argument("--config", default="cone512")
     ap.add_argument("--geometry", default="f64", choices=["f32", "f64"])
     ap.add_argument("--full-iters", type=int, default=300, help="cap for the equal-I-div full-AM run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -56,19 +62,61 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="uneven: tune the backprojection tiling first")
     ap.add_argument("--no-sequential", action="store_true", help="uneven: skip the one-context-at-a-time run")
     ap.add_argument("--cone-iters", type=int, default=0, help="cone: iterations per solve (0 = the config's)")
+    ap.add_argument("--cone-full-iters", type=int, default=60,
+                    help="cone: cap for the equal-I-div voxel-AM run")
+    ap.add_argument("--no-fan512", action="store_true", help="cone512: skip the nested fan512 workload")
+    ap.add_argument("--fan-steps", type=int, default=10, help="cone512: timed steps of the nested fan512 run")
+    ap.add_argument("--fan-warmup", type=int, default=2, help="cone512: warm-up steps of the nested fan512 run")
     return ap.parse_args()
 
 
-KERNEL_SOURCES_2D = ("wamct_kernels.hip", "wamct_geom.h", "wamct_internal.h")
-KERNEL_SOURCES_3D = ("wamct_kernels3.hip", "wamct_internal3.h", "wamct_internal.h", "wamct_worklist.h")
+# sources whose change can change a kernel's traffic: kernels, the headers they include,
+# and the host code that sets tilings and launch shapes
+KERNEL_SOURCES_2D = ("wamct_kernels.hip", "wamct_geom.h", "wamct_internal.h", "wamct_worklist.h",
+                     "wamct_api.hip", "wamct_ctx.h")
+KERNEL_SOURCES_3D = ("wamct_kernels3.hip", "wamct_internal3.h", "wamct_internal.h", "wamct_worklist.h",
+                     "wamct_api3.hip", "wamct_ctx.h")
 
 
-def kernel_source_hash(files=KERNEL_SOURCES_2D):
+def kernel_source_hash(files=KERNEL_SOURCES_2D, tiling=None):
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, "paper_1508_04458_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    if tiling is not None:
+        h.update(f"tiling={int(tiling)}".encode())
     return h.hexdigest()[:16]
+
+
+def host_info():
+    """CPU model and logical CPU count of the host the CPU baseline ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def roofline(alg_bytes, ms, traffic, **kw):
+    """Roofline object of one launch (or pass) of `ms` milliseconds: `achieved`/`frac` are the
+    stored-Phi-equivalent (algorithmic) bytes over the time against the 8 TB/s HBM peak;
+    `measured_gbs`/`measured_frac` are the measured memory-side bytes (`traffic`, from the
+    committed byte counters, null when they were taken on other sources) over the same time."""
+    a = alg_bytes / (ms * 1e-3) / 1e9
+    r = {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(a / HBM_PEAK_GBS, 4), "traffic": traffic}
+    if traffic:
+        m = traffic / (ms * 1e-3) / 1e9
+        r.update(measured_gbs=round(m, 1), measured_frac=round(m / HBM_PEAK_GBS, 4))
+    else:
+        r.update(measured_gbs=None, measured_frac=None)
+    r.update(kw)
+    return r
 
 
 def measured_traffic(kernel_hash, config, phase):
@@ -84,28 +132,43 @@ def measured_traffic(kernel_hash, config, phase):
     return rec.get("bytes_per_launch", {}).get(phase)
 
 
+GOLD_FAN512 = os.path.join(ROOT, "tests", "golden", "fan512_solve.npz")
+
+
 def cpu_baseline(P, n_views_sample):
-    """The FP64 oracle (never tuned) on a view subset of the same scan: Algorithm 1 with
-    the same schedule; time of the solve (trees, Phi builds and iterations; not H or b)
-    scaled by n_views / n_views_sample, as AM iterations per second."""
+    """The FP64 oracle (never tuned) on a view subset of the same scan: Algorithm 1 over the
+    rays of `n_views_sample` evenly spaced views, timed (trees, Phi builds and iterations; not
+    H or b) and scaled by n_views / n_views_sample to AM iterations per second. For fan512 the
+    solve follows the oracle's own tree sequence of the whole scan (tests/golden, written by
+    the oracle alone), so every Phi_j holds the whole scan's active set on the sampled rays and
+    the work per iteration is that of the whole scan's, in proportion; otherwise the tree rule
+    runs on the subset."""
     import numpy as np
     from oracle import siddon, wam
-    from paper_1508_04458_amd import synth
     g = P.geom
     step = max(1, g.n_views // n_views_sample)
     views = np.arange(0, g.n_views, step)[:n_views_sample]
     rows = (views[:, None] * g.n_bins + np.arange(g.n_bins)[None, :]).ravel()
+    masks = None
+    if P.name == "fan512" and os.path.exists(GOLD_FAN512):
+        z = np.load(GOLD_FAN512, allow_pickle=False)
+        nn = g.n * g.n
+        mk = np.unpackbits(z["masks"], axis=1)[:, :nn].reshape(-1, g.n, g.n)
+        masks = {int(a): mk[k] for k, a in enumerate(z["tree_at"]) if k > 0}
     H = siddon.system_matrix(g, views=views)
     t0 = time.perf_counter()
-    r = wam.wam_solve(H, g.n, P.levels, P.d[rows], P.i0, P.n_iters, g.pixel, schedule=P.schedule)
+    r = wam.wam_solve(H, g.n, P.levels, P.d[rows], P.i0, P.n_iters, g.pixel,
+                      schedule=() if masks else P.schedule, masks=masks)
     dt = time.perf_counter() - t0
     scale = g.n_views / len(views)
     per_iter = dt * scale / P.n_iters
+    trees = ("the whole scan's tree sequence of the oracle (trees at "
+             f"{sorted(masks)})" if masks else f"its own tree rule (expansions {P.schedule})")
     return {"value": 1.0 / per_iter, "unit": "AM iter/s", "cores": 1, "kind": "oracle",
-            "sample": (f"FP64 NumPy/SciPy oracle, Algorithm 1 with the tree rule, {P.n_iters} iterations "
-                       f"(expansions {P.schedule}) on {len(views)} of {g.n_views} views; solve time "
-                       f"{dt:.1f} s scaled by {scale:.0f}; setup (H, b) excluded; single thread"),
-            "final_idiv_sample": float(r["idiv"][-1])}
+            "sample": (f"FP64 NumPy/SciPy oracle, Algorithm 1, {P.n_iters} iterations on the rays of "
+                       f"{len(views)} of {g.n_views} views following {trees}; solve time {dt:.1f} s "
+                       f"scaled by {scale:.0f}; setup (H, b) excluded; single thread"),
+            "host": host_info(), "final_idiv_sample": float(r["idiv"][-1])}
 
 
 def log(msg):
@@ -317,7 +380,8 @@ def cone_cpu_baseline(name, n_full_rays, n_full_side):
             "sample": (f"FP64 NumPy/SciPy 3-D oracle, octree AM, {P.n_iters} iterations (expansions "
                        f"{P.schedule}) on the downscaled case {name} ({g.n}^2 x {g.nz}, {g.n_views} views of "
                        f"{g.n_rows} x {g.n_cols}); solve time {dt:.1f} s scaled by rays x side = {scale:.0f}; "
-                       f"setup (H, b) excluded; single thread")}
+                       f"setup (H, b) excluded; single thread"),
+            "host": host_info()}
 
 
 def bench_cone(args):
@@ -386,13 +450,7 @@ def bench_cone(args):
     it_s = J * args.steps / dt
     M, N = g.n_rays, g.n_voxels
 
-    khash = kernel_source_hash(KERNEL_SOURCES_3D)
-
-    def roof(ms, alg, phase, **kw):
-        a = alg / (ms * 1e-3) / 1e9
-        return {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(a / HBM_PEAK_GBS, 4), "traffic": measured_traffic(khash, args.config, phase),
-                **kw, "kernel_hash": khash}
+    khash = kernel_source_hash(KERNEL_SOURCES_3D, ctx.tiling())
 
     # algorithmic bytes of the same passes with Phi stored: 8 B per (ray, active coefficient)
     # pair, 4 B per active coefficient read (forward) or 12 B (b, beta read, beta written),
@@ -402,10 +460,12 @@ def bench_cone(args):
     up_ms = up["ms"] / max(1, J * args.steps)
     alg_fw = 8.0 * w_avg + 4.0 * active_avg + 8.0 * M
     alg_up = 8.0 * w_avg + 4.0 * M + 12.0 * active_avg
-    r_fw = roof(fw_ms, alg_fw, "forward", kernel="k3_forward<float>", avg_launch_ms=round(fw_ms, 4),
-                launches=fw["launches"], alg_bytes_per_launch=int(alg_fw))
-    r_up = roof(up_ms, alg_up, "update", kernels="k3_gather_part + k3_gather_finish per octree level",
-                avg_pass_ms=round(up_ms, 4), passes=J * args.steps, alg_bytes_per_pass=int(alg_up))
+    r_fw = roofline(alg_fw, fw_ms, measured_traffic(khash, args.config, "forward"), kernel="k3_forward<float>",
+                    avg_launch_ms=round(fw_ms, 4), launches=fw["launches"], alg_bytes_per_launch=int(alg_fw),
+                    kernel_hash=khash)
+    r_up = roofline(alg_up, up_ms, measured_traffic(khash, args.config, "update"),
+                    kernels="k3_gather_part + k3_gather_finish per octree level", avg_pass_ms=round(up_ms, 4),
+                    passes=J * args.steps, alg_bytes_per_pass=int(alg_up), kernel_hash=khash)
     dominant = "update" if up["ms"] >= fw["ms"] else "forward"
     out = {"metric": METRIC, "value": round(it_s, 3), "unit": "AM iter/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 1),
@@ -421,6 +481,7 @@ def bench_cone(args):
            "time_ms_per_step_by_kernel": {k: round(v["ms"] / args.steps, 2) for k, v in tim.items()},
            "roofline": r_up if dominant == "update" else r_fw,
            "roofline_other": r_fw if dominant == "update" else r_up}
+    ctx.close()
     if not args.no_gradient_rule:
         # the same solve with the residual-gradient tree rule
         grc = api.Context(g, P.levels, "f32", device=dev)
@@ -441,28 +502,59 @@ def bench_cone(args):
         grc.close()
         log(f"gradient rule: {J / t_gr:.3f} it/s, final I-div {gtr[-1]:.4e} (value rule {tr[-1]:.4e})")
     if not args.no_full_am:
+        # voxel AM (levels = 0) from mu = 0 until it reaches the tree run's final I-divergence
+        # (or the cap): the Results section compares the two at the same objective value
         full = api.Context(g, 0, "f32", device=dev)
         full.set_data(d, P.i0)
         full.reset()
-        full.iterate(1)
         torch.cuda.synchronize()
-        K = 2
-        t2 = time.perf_counter()
-        full.iterate(K)
-        torch.cuda.synchronize()
-        f_it_s = K / (time.perf_counter() - t2)
+        target = float(tr[-1])
+        # run until the lower of the value-rule and gradient-rule final I-divergences
+        stop_at = min(target, out.get("gradient_rule", {}).get("final_idiv", target))
+        cap, chunk = args.cone_full_iters, 5
+        buf = torch.empty(chunk, dtype=torch.float64, device=dev)
+        trace, done, t_run = [], 0, 0.0
+        while done < cap:
+            n = min(chunk, cap - done)
+            t2 = time.perf_counter()
+            full.iterate(n, buf[:n])
+            torch.cuda.synchronize()
+            t_run += time.perf_counter() - t2
+            trace += buf[:n].cpu().tolist()      # I-div before each of these updates
+            done += n
+            if min(trace[1:] or [math.inf]) <= stop_at:
+                break
+        last = full.forward()[1]                 # I-div after the last update
+        trace.append(float(last.item() if hasattr(last, "item") else last))
+        f_it_s = done / t_run
         w_pix = full.tree_stats()["w"]
-        out["full_am"] = {"iter_per_s": round(f_it_s, 3), "iterations_timed": K, "w_per_pass": int(w_pix),
+        hit = [k for k, v in enumerate(trace) if v <= target]
+        k_star = hit[0] if hit else None
+        out["full_am"] = {"iter_per_s": round(f_it_s, 3), "iterations_run": done, "w_per_pass": int(w_pix),
                           "gray_voxel_per_s": round(2 * w_pix * f_it_s / 1e9, 3)}
+        eq = {"tree_final_idiv": target, "full_iters_to_reach": k_star, "full_idiv_at_end": trace[-1],
+              "cap": cap}
+        if k_star is not None:
+            t_eq = k_star / f_it_s
+            eq.update(full_time_ms=round(t_eq * 1e3, 1), tree_time_ms=round(dt * 1e3 / args.steps, 1),
+                      tree_speedup=round(t_eq / (dt / args.steps), 3))
+        out["equal_idiv"] = eq
+        if "gradient_rule" in out:
+            gr = out["gradient_rule"]
+            hit = [k for k, v in enumerate(trace) if v <= gr["final_idiv"]]
+            k_f = hit[0] if hit else None
+            gr.update(full_am_iters_to_its_final_idiv=k_f,
+                      full_am_time_to_its_final_idiv_ms=None if k_f is None else round(k_f / f_it_s * 1e3, 1),
+                      speedup_vs_full_am=None if k_f is None else round(k_f / f_it_s / (gr["ms_per_solve"] * 1e-3), 3))
         out["pixel_equiv_gray_voxel_per_s"] = round(2 * w_pix * it_s / 1e9, 3)
         full.close()
-        log(f"voxel AM: {f_it_s:.3f} it/s")
+        log(f"voxel AM: {f_it_s:.3f} it/s, {done} iterations, reaches the tree run's I-div after {k_star}")
     if not args.no_cpu_baseline:
         log("CPU oracle on the downscaled case")
         out["cpu_baseline"] = cone_cpu_baseline("cone64", M, g.n)
-    copy_calibration(args, dev, out)
-    ctx.close()
-    print(json.dumps(out), flush=True)
+    del d
+    torch.cuda.empty_cache()
+    return out
 
 
 def copy_calibration(args, dev, out):
@@ -484,30 +576,15 @@ def dataclasses_replace(obj, **kw):
     return dataclasses.replace(obj, **kw)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the view-sharded "
-              "multi-GPU design is not built.", file=sys.stderr)
-        sys.exit(2)
-    if args.config == "uneven":
-        bench_uneven(args)
-        return
-    if args.config == "loss16":
-        bench_loss(args)
-        return
-    if args.config.startswith("cone"):
-        bench_cone(args)
-        return
-    if args.no_cpu_baseline is False:
-        # the CPU baseline is a single-threaded oracle
-        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-            os.environ[k] = "1"
+def bench_fan(args, config, steps, warmup):
+    """2-D fan beam (fan512: 512x512 image, 720 views x 1024 bins, 40 ellipses + 4 metal disks,
+    I0 = 1e5, 3-level Haar tree AM in FP32, 100 iterations with expansions at 21, 43 and 85).
+    A step is one complete reconstruction from beta = 0. Returns the result object."""
     import numpy as np
     import torch
     from paper_1508_04458_amd import api, synth
 
-    P = synth.make_problem(args.config)
+    P = synth.make_problem(config)
     g = P.geom
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -535,22 +612,22 @@ def main():
         ctx.reset()
         ctx.solve(J, sched, 0.1, idiv)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     # HIP events around the two kernel classes whose rooflines are reported
     ctx.timing(True, ("forward", "update"))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     tim = ctx.get_timing()
     ctx.timing(False)
     tr = idiv.cpu().numpy()
-    ms_step = dt * 1e3 / args.steps
-    it_s = J * args.steps / dt
+    ms_step = dt * 1e3 / steps
+    it_s = J * steps / dt
 
     # ---- roofline of the dominant kernel: the tree walk (forward projection over the leaves
     # of Z_s, Beer's law, I-divergence term). Algorithmic bytes are those of the same pass
@@ -561,32 +638,29 @@ def main():
     fw = tim["forward"]
     fw_ms = fw["ms"] / max(1, fw["launches"])
     alg_fw = 8.0 * w_update_avg + 4.0 * active_avg + 8.0 * M
-    khash = kernel_source_hash()
-    traffic = measured_traffic(khash, args.config, "forward")
-    roof = {"bound": "hbm", "achieved": round(alg_fw / (fw_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(alg_fw / (fw_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_forward_rec<float,double>", "avg_launch_ms": round(fw_ms, 5), "launches": fw["launches"],
-            "alg_bytes_per_launch": int(alg_fw), "kernel_hash": khash}
+    khash = kernel_source_hash(KERNEL_SOURCES_2D, ctx.tiling())
+    roof = roofline(alg_fw, fw_ms, measured_traffic(khash, config, "forward"), kernel="k_forward_rec<float,double>",
+                    avg_launch_ms=round(fw_ms, 5), launches=fw["launches"], alg_bytes_per_launch=int(alg_fw),
+                    kernel_hash=khash)
     # the update pass (sign-split backprojection + eq. 1.9 zero; one or two kernels per level)
     up = tim["update"]
     upd_ms = up["ms"] / max(1, up["launches"])
     alg_up = 8.0 * w_update_avg + 4.0 * M + 12.0 * active_avg
-    roof_up = {"bound": "hbm", "achieved": round(alg_up / (upd_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-               "unit": "GB/s", "frac": round(alg_up / (upd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-               "traffic": measured_traffic(khash, args.config, "update"),
-               "kernels": "k_gather_part + k_gather_finish over the chunked tree levels (+ k_gather per level that fills the GPU alone)",
-               "avg_pass_ms": round(upd_ms, 5), "passes": up["launches"], "alg_bytes_per_pass": int(alg_up)}
-    timing_ms = {k: round(v["ms"] / args.steps, 4) for k, v in tim.items() if k in ("forward", "update")}
+    roof_up = roofline(alg_up, upd_ms, measured_traffic(khash, config, "update"),
+                       kernels="k_gather_part + k_gather_finish over the chunked tree levels (+ k_gather per "
+                               "level that fills the GPU alone)",
+                       avg_pass_ms=round(upd_ms, 5), passes=up["launches"], alg_bytes_per_pass=int(alg_up))
+    timing_ms = {k: round(v["ms"] / steps, 4) for k, v in tim.items() if k in ("forward", "update")}
 
     out = {"metric": METRIC, "value": round(it_s, 2), "unit": "AM iter/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "steps": steps, "warmup": warmup, "ms_per_step": round(ms_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32" if args.geometry == "f32" else "f32 data, f64 ray geometry",
            "data": "synthetic",
-           "config": {"workload": f"{args.config}: 2-D fan beam {g.n}x{g.n}, {g.n_views} views x {g.n_bins} bins, "
+           "config": {"workload": f"{config}: 2-D fan beam {g.n}x{g.n}, {g.n_views} views x {g.n_bins} bins, "
                                   f"{P.levels}-level tree-adaptive wavelet AM, {J} iterations, expansions at {sched}",
                       "levels": P.levels, "iterations": J, "schedule": sched, "rays": M, "pixels": g.n * g.n},
-           "gray_voxel_per_s": round(pairs * args.steps / dt / 1e9, 3),
+           "gray_voxel_per_s": round(pairs * steps / dt / 1e9, 3),
            "pixel_equiv_gray_voxel_per_s": None,
            "final_idiv": float(tr[-1]),
            "trees": seg,
@@ -625,6 +699,7 @@ def main():
         out["pixel_equiv_gray_voxel_per_s"] = round(2 * w_pix * it_s / 1e9, 3)
         out["equal_idiv"] = eq
         full.close()
+        log(f"{config}: image-domain AM reaches the tree run's I-div after {k_star} iterations")
 
     # ---- the same solve with the residual-gradient tree rule (same schedule and fraction)
     if not args.no_gradient_rule:
@@ -685,9 +760,44 @@ def main():
         osc.close()
 
     if not args.no_cpu_baseline:
+        log(f"{config}: CPU oracle on {args.cpu_views} views")
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_views)
-    copy_calibration(args, dev, out)
     ctx.close()
+    del d
+    torch.cuda.empty_cache()
+    return out
+
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the view-sharded "
+              "multi-GPU design is not built.", file=sys.stderr)
+        sys.exit(2)
+    if args.config == "uneven":
+        bench_uneven(args)
+        return
+    if args.config == "loss16":
+        bench_loss(args)
+        return
+    if not args.no_cpu_baseline:
+        # the CPU baseline is a single-threaded oracle
+        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            os.environ[k] = "1"
+    import torch
+    dev = torch.device("cuda", 0)
+    if args.config.startswith("cone"):
+        out = bench_cone(args)
+        if args.config == "cone512" and not args.no_fan512:
+            log("fan512 (nested)")
+            fan = bench_fan(args, "fan512", args.fan_steps, args.fan_warmup)
+            for k in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
+                fan.pop(k, None)
+            out["fan512"] = fan
+    else:
+        out = bench_fan(args, args.config, args.steps, args.warmup)
+    copy_calibration(args, dev, out)
     print(json.dumps(out), flush=True)
 
 
