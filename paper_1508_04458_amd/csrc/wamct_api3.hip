@@ -50,8 +50,6 @@ struct Ctx3 final : wamct_ctx {
   int64_t M = 0, N = 0;
   int np = 0;
   double2* views = nullptr;
-  void *A = nullptr, *B = nullptr;
-  double* C = nullptr;
   T *d = nullptr, *i0v = nullptr, *q = nullptr, *beta = nullptr, *b = nullptr, *img = nullptr;
   T* yn = nullptr;                 // ray values scaled by |D| for the gather
   T* coefg = nullptr;              // Omega^T H^T (d - q-hat) of the residual-gradient rule
@@ -60,7 +58,7 @@ struct Ctx3 final : wamct_ctx {
   double2* colt = nullptr;         // [nv][nc] (1/Dx, 1/Dy)
   double *rowt = nullptr, *nrm = nullptr;  // [nr] 1/Dz, [nr][nc] |D|
   void *recR = nullptr, *recC = nullptr;
-  uint8_t *mask = nullptr, *mask_old = nullptr, *lev = nullptr;
+  uint8_t *mask = nullptr, *mask_old = nullptr, *lev = nullptr, *levC = nullptr;  // levC: [z][x][y]
   uint32_t* items = nullptr;
   int* list_tmp = nullptr;      // block counts and offsets of the work-list builder
   double *partd = nullptr, *part2 = nullptr, *mu64 = nullptr, *scal = nullptr;  // [0] Z0 [1] W [2] max [3] tmp [4] I0
@@ -98,7 +96,8 @@ struct Ctx3 final : wamct_ctx {
     if (h_scal) hipHostFree(h_scal);
   }
 
-  template <typename Q>
+    RayF3 rayf() const { return RayF3{views, colt, rowt, nrm}; }
+template <typename Q>
   wamct_status alloc(Q*& p, int64_t count) {
     void* v = nullptr;
     const size_t bytes = size_t(count > 0 ? count : 1) * sizeof(Q);
@@ -216,16 +215,14 @@ struct Ctx3 final : wamct_ctx {
     std::memset(h_ints, 0, sizeof(int) * kInts);
     std::memset(h_scal, 0, sizeof(double) * kScal);
     CHECKED(alloc(views, g.nv));
-    double4 *a4 = nullptr, *b4 = nullptr;
-    CHECKED(alloc(a4, M)); CHECKED(alloc(b4, M)); CHECKED(alloc(C, M));
-    A = a4; B = b4;
     CHECKED(alloc(d, M)); CHECKED(alloc(i0v, M)); CHECKED(alloc(q, M)); CHECKED(alloc(yn, M));
     CHECKED(alloc(colt, int64_t(g.nv) * g.nc)); CHECKED(alloc(rowt, g.nr)); CHECKED(alloc(nrm, int64_t(g.nr) * g.nc));
     CHECKED(alloc(beta, N)); CHECKED(alloc(b, N)); CHECKED(alloc(img, N)); CHECKED(alloc(mu64, N));
     T *rr = nullptr, *rc = nullptr;
     CHECKED(alloc(rr, N)); CHECKED(alloc(rc, N));
     recR = rr; recC = rc;
-    CHECKED(alloc(mask, N)); CHECKED(alloc(mask_old, N)); CHECKED(alloc(lev, N)); CHECKED(alloc(items, N));
+    CHECKED(alloc(mask, N)); CHECKED(alloc(mask_old, N)); CHECKED(alloc(lev, N)); CHECKED(alloc(levC, N));
+    CHECKED(alloc(items, N));
     CHECKED(alloc(list_tmp, list_scratch_ints3(g)));
     CHECKED(alloc(partd, np)); CHECKED(alloc(part2, np)); CHECKED(alloc(scal, kScal)); CHECKED(alloc(ints, kInts));
     CHECKED(ensure_part(target_lanes));
@@ -238,7 +235,6 @@ struct Ctx3 final : wamct_ctx {
       hv[v] = make_double2(c, sn);
     }
     HIPCHK(hipMemcpyAsync(views, hv.data(), sizeof(double2) * g.nv, hipMemcpyHostToDevice, st));
-    Geo3<T>::ray_table(g, views, A, B, C, st);
     Geo3<T>::ray_factors(g, views, colt, rowt, nrm, st);
     fill_i32(ints, kInts, 0, st);
     Launch<double>::fill(scal, kScal, 0.0, st);
@@ -288,8 +284,8 @@ struct Ctx3 final : wamct_ctx {
     {
       Scope sc(this, WAMCT_K_TREE, s);
       build_items3(g, mask, items, ints + 8, list_tmp, s);
-      levmap3(g, mask, lev, s);
-      const int nbk = z0_partials3(g, A, B, C, lev, partd, part2, s);
+      levmap3(g, mask, lev, levC, s);
+      const int nbk = z0_partials3(g, rayf(), lev, levC, partd, part2, s);
       reduce_max(partd, nbk, scal + 0, s);
       reduce_sum(part2, nbk, scal + 1, s);
     }
@@ -357,7 +353,7 @@ struct Ctx3 final : wamct_ctx {
       Geo3<T>::synth_records(g, beta, lev, recR, recC, s);
     }
     Scope sc(this, WAMCT_K_FORWARD, s);
-    return Geo3<T>::forward(g, A, B, C, recR, recC, d, i0v_used ? i0v : nullptr, scal + 4, q, nullptr, partd, s);
+    return Geo3<T>::forward(g, rayf(), recR, recC, d, i0v_used ? i0v : nullptr, scal + 4, q, nullptr, partd, s);
   }
   void store_idiv(int nbk, double* out, bool counted, hipStream_t s) {
     Scope sc(this, WAMCT_K_OTHER, s);
@@ -527,7 +523,7 @@ struct Ctx3 final : wamct_ctx {
     if (!m || !p) return fail(WAMCT_E_INVALID, "mu and p must not be NULL");
     Scope sc(this, WAMCT_K_OTHER, st);
     Geo3<T>::synth_records(g, (const T*)m, nullptr, recR, recC, st);   // the volume itself, one voxel per leaf
-    Geo3<T>::forward(g, A, B, C, recR, recC, nullptr, nullptr, nullptr, nullptr, (T*)p, nullptr, st);
+    Geo3<T>::forward(g, rayf(), recR, recC, nullptr, nullptr, nullptr, nullptr, (T*)p, nullptr, st);
     LAUNCHED();
     return WAMCT_OK;
   }

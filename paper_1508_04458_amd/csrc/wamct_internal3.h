@@ -28,18 +28,25 @@ __host__ __device__ inline uint32_t item3_pack(int split, int l, int k, int i, i
 // Sums of one 3-D item: the plain sum and, per detail, the signed sum and the sum of magnitudes.
 constexpr int kSlots3 = 15;
 
+// Per-view ray factors of the scan (device arrays): views = (cos a, sin a) per view,
+// colt [nv][nc] = (1/Dx, 1/Dy), rowt [nr] = 1/Dz, nrm [nr][nc] = |D| for D = detector element -
+// source (a component within 1e-12 sdd of 0 has the factor +-1e300). The walks and the gather
+// build every ray from them.
+struct RayF3 {
+  const double2* views;
+  const double2* colt;
+  const double* rowt;
+  const double* nrm;
+};
+
 template <typename T>
 struct Geo3 {
-  // Per ray (double): A = (ox, oy, oz, 1/ex), B = (1/ey, 1/ez, ex, ey), C = ez; the origin is
-  // the point of the ray closest to the volume centre. views = (cos a, sin a) per view.
-  static void ray_table(const DevGeom3& g, const double2* views, void* A, void* B, double* C, hipStream_t s);
   // Leaf walk over (value | level) records (row layout [z][y][x] and [z][x][y]): p = sum of
   // chord * leaf value; if q != null, q = I0 exp(-p) (I0 per ray or the scalar *i0s) and
   // per-block FP64 partials of the I-divergence terms in `part`; if p != null p is stored.
   // Returns the number of blocks.
-  static int forward(const DevGeom3& g, const void* A, const void* B, const double* C, const void* recR,
-                     const void* recC, const T* d, const T* i0v, const double* i0s, T* q, T* p, double* part,
-                     hipStream_t s);
+  static int forward(const DevGeom3& g, const RayF3& f, const void* recR, const void* recC, const T* d,
+                     const T* i0v, const double* i0s, T* q, T* p, double* part, hipStream_t s);
   // Per-view ray factors of the gather: colt [nv][nc] = (1/Dx, 1/Dy), rowt [nr] = 1/Dz,
   // nrm [nr][nc] = |D| for D = detector element - source.
   static void ray_factors(const DevGeom3& g, const double2* views, double2* colt, double* rowt, double* nrm,
@@ -67,9 +74,10 @@ struct Geo3 {
 };
 
 // Z0 and W of the current octree (per ray FP64 walk); returns the number of blocks.
-int z0_partials3(const DevGeom3& g, const void* A, const void* B, const double* C, const uint8_t* lev,
-                 double* part_max, double* part_cnt, hipStream_t s);
-void levmap3(const DevGeom3& g, const uint8_t* mask, uint8_t* lev, hipStream_t s);
+// lev: per-voxel leaf level [z][y][x]; levC the same in [z][x][y] (read by x-major rays)
+int z0_partials3(const DevGeom3& g, const RayF3& f, const uint8_t* lev, const uint8_t* levC, double* part_max,
+                 double* part_cnt, hipStream_t s);
+void levmap3(const DevGeom3& g, const uint8_t* mask, uint8_t* lev, uint8_t* levC, hipStream_t s);
 // Work list in segments: split roots, roots not split (every voxel when L = 0), then split
 // nodes level by level (L - 1 down to 1), 3-D Morton order within a segment; counts[0] =
 // items, counts[1 + k] = items of segment k.

@@ -76,43 +76,48 @@ __device__ inline double edge_snap3(double f) {
   return fabs(f - r) <= 1e-9 ? r : f;
 }
 
-// Ray of detector element (row, col) of a view: from the source sod (c, s, 0) to the element
-// centre on the flat detector; origin moved to the point closest to the volume centre. A
-// direction component within 1e-12 of 0 is treated as exactly 0: the line is moved to the
-// centre of the voxel slab that contains it along that axis (chords unchanged; a line on a
-// boundary goes to the + side, half-open voxels, with the source's coordinate taken as on a
-// boundary when within 1e-9 voxel of it) and tilted by 1e-12 so 1/e stays finite.
-__global__ __launch_bounds__(kB) void k3_ray_table(DevGeom3 g, const double2* __restrict__ views,
-                                                   double4* __restrict__ A, double4* __restrict__ B,
-                                                   double* __restrict__ C) {
-  const int64_t r = int64_t(blockIdx.x) * kB + threadIdx.x;
+// Ray of detector element (row, col) of view v for the leaf walks, from the per-view factors
+// the gather also uses (no per-ray table): the line starts at the source S = sod (c, s, 0)
+// and runs along D = (-sdd c - u s, -sdd s + u c, w) (u, w: column and row offsets on the
+// detector), unit direction e = D / |D|, 1/e from the factors 1/Dx, 1/Dy (per view and column)
+// and 1/Dz (per row) times |D| (per row and column). A component of D within 1e-12 sdd of 0
+// (the factor is then +-1e300) is exactly 0: e is axis-parallel there, with a positive
+// reciprocal (no mirroring), and the source's coordinate on that axis, within 1e-9 voxel of a
+// boundary taken as on it, decides the slab: a line on a boundary lies in the voxel on the +
+// side (half-open voxels), as in the gather, which also measures from the source.
+struct Ray3 {
+  double X, Y, Z;        // source in voxel coordinates (0 .. n, 0 .. nz across the volume)
+  double ex, ey, ez;     // unit direction
+  double iex, iey, iez;  // 1 / e (1e300 on an axis-parallel component)
+};
+__device__ inline Ray3 ray_from_factors(const DevGeom3& g, const RayF3& f, int64_t r) {
   const int64_t per_view = int64_t(g.nr) * g.nc;
-  if (r >= per_view * g.nv) return;
   const int v = int(r / per_view);
   const int rem = int(r - int64_t(v) * per_view);
   const int row = rem / g.nc, col = rem - row * g.nc;
-  const double c = views[v].x, s = views[v].y;
+  const double2 cs = f.views[v];
+  const double2 cd = f.colt[int64_t(v) * g.nc + col];
+  const double idz = f.rowt[row];
+  const double nd = f.nrm[rem];
   const double u = (col - 0.5 * (g.nc - 1)) * g.cpitch, w = (row - 0.5 * (g.nr - 1)) * g.rpitch;
-  const double sx = g.sod * c, sy = g.sod * s, sz = 0.0;
-  const double dx = -(g.sdd - g.sod) * c - u * s - sx, dy = -(g.sdd - g.sod) * s + u * c - sy, dz = w - sz;
-  const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-  double ex = dx * inv, ey = dy * inv, ez = dz * inv;
-  // axis-parallel components (within 1e-12): the line moves to the centre of the voxel slab
-  // holding the source, the position the factorised gather (which measures from the
-  // source) sees, and keeps a 1e-12 tilt for the walks
-  const double hn = 0.5 * g.n, hz = 0.5 * g.nz;
-  const bool snx = fabs(ex) < 1e-12, sny = fabs(ey) < 1e-12, snz = fabs(ez) < 1e-12;
-  if (snx) ex = ex < 0 ? -1e-12 : 1e-12;
-  if (sny) ey = ey < 0 ? -1e-12 : 1e-12;
-  if (snz) ez = ez < 0 ? -1e-12 : 1e-12;
-  const double tc = -(sx * ex + sy * ey + sz * ez);
-  double ox = sx + tc * ex, oy = sy + tc * ey, oz = sz + tc * ez;
-  if (snx) ox = (floor(edge_snap3(sx / g.pixel + hn)) + 0.5 - hn) * g.pixel;
-  if (sny) oy = (floor(edge_snap3(sy / g.pixel + hn)) + 0.5 - hn) * g.pixel;
-  if (snz) oz = (floor(edge_snap3(sz / g.pixel + hz)) + 0.5 - hz) * g.pixel;
-  A[r] = make_double4(ox, oy, oz, 1.0 / ex);
-  B[r] = make_double4(1.0 / ey, 1.0 / ez, ex, ey);
-  C[r] = ez;
+  const double dx = -g.sdd * cs.x - u * cs.y, dy = -g.sdd * cs.y + u * cs.x;
+  const double ind = 1.0 / nd;
+  const bool snx = fabs(cd.x) >= 1e299, sny = fabs(cd.y) >= 1e299, snz = fabs(idz) >= 1e299;
+  const double ipix = 1.0 / g.pixel;
+  Ray3 q;
+  q.X = g.sod * cs.x * ipix + 0.5 * g.n;
+  q.Y = g.sod * cs.y * ipix + 0.5 * g.n;
+  q.Z = 0.5 * g.nz;
+  q.ex = snx ? 0.0 : dx * ind;
+  q.ey = sny ? 0.0 : dy * ind;
+  q.ez = snz ? 0.0 : w * ind;
+  q.iex = snx ? 1e300 : cd.x * nd;
+  q.iey = sny ? 1e300 : cd.y * nd;
+  q.iez = snz ? 1e300 : idz * nd;
+  if (snx) q.X = edge_snap3(q.X);
+  if (sny) q.Y = edge_snap3(q.Y);
+  if (snz) q.Z = edge_snap3(q.Z);
+  return q;
 }
 
 // ------------------------------------------------------------------ octree helpers
@@ -214,7 +219,7 @@ __global__ __launch_bounds__(kB) void k3_mu64(DevGeom3 g, const T* __restrict__ 
 }
 
 __global__ __launch_bounds__(kB) void k3_levmap(DevGeom3 g, const uint8_t* __restrict__ mask,
-                                                uint8_t* __restrict__ lev) {
+                                                uint8_t* __restrict__ lev, uint8_t* __restrict__ levC) {
   const int64_t p = int64_t(blockIdx.x) * kB + threadIdx.x;
   const int n = g.n;
   if (p >= int64_t(n) * n * g.nz) return;
@@ -222,6 +227,7 @@ __global__ __launch_bounds__(kB) void k3_levmap(DevGeom3 g, const uint8_t* __res
   int l = g.L;
   while (l >= 1 && split3(mask, n, l, s >> l, r >> l, c >> l)) --l;
   lev[p] = uint8_t(l);
+  if (levC) levC[(int64_t(s) * n + c) * n + r] = uint8_t(l);
 }
 
 // coef(z) = sum over the support of basis function z of its value times vol (Omega^T vol),
@@ -319,11 +325,11 @@ struct Walker3 {
   int ax, ay, az;
   int n, nz;
 
-  __device__ bool init(const DevGeom3& g, double ox, double oy, double oz, double iex, double iey, double iez,
-                       double ex, double ey, double ez) {
+  __device__ bool init(const DevGeom3& g, const Ray3& q) {
     n = g.n; nz = g.nz;
     const double ipix = 1.0 / g.pixel;
-    const double X = ox * ipix + 0.5 * n, Y = oy * ipix + 0.5 * n, Z = oz * ipix + 0.5 * nz;
+    const double X = q.X, Y = q.Y, Z = q.Z;
+    const double ex = q.ex, ey = q.ey, ez = q.ez, iex = q.iex, iey = q.iey, iez = q.iez;
     x0 = ex < 0.0 ? double(n) - X : X;
     y0 = ey < 0.0 ? double(n) - Y : Y;
     z0 = ez < 0.0 ? double(nz) - Z : Z;
@@ -373,8 +379,7 @@ struct Walker3 {
 // I-divergence term. x-major rays read the [z][x][y] records (neighbouring lanes,
 // neighbouring rays of a detector row, then touch neighbouring addresses).
 template <typename T>
-__global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, const double4* __restrict__ A,
-                                                 const double4* __restrict__ B, const double* __restrict__ C,
+__global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, RayF3 f,
                                                  const Rec3<T>* __restrict__ recR, const Rec3<T>* __restrict__ recC,
                                                  const T* __restrict__ d, const T* __restrict__ i0v,
                                                  const double* __restrict__ i0s, T* __restrict__ q,
@@ -385,13 +390,12 @@ __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, const double4* __re
   double term = 0.0;
   if (k < M) {
     const int64_t r = row_major_ray(g, k);
-    const double4 a = A[r], b = B[r];
-    const double ex = b.z, ey = b.w;
+    const Ray3 ray = ray_from_factors(g, f, r);
     Walker3 w;
     double acc = 0.0;
-    if (w.init(g, a.x, a.y, a.z, a.w, b.x, b.y, ex, ey, C[r])) {
+    if (w.init(g, ray)) {
       const int n = g.n;
-      const bool xmaj = fabs(ex) >= fabs(ey);
+      const bool xmaj = fabs(ray.ex) >= fabs(ray.ey);
       const Rec3<T>* __restrict__ base = xmaj ? recC : recR;
       // [z][x][y] or [z][y][x] address of the mirrored voxel (x, y, z), clamped into range
       auto addr = [&](int x, int y, int z) {
@@ -790,16 +794,16 @@ struct Z0Vis3 {
 };
 
 template <int LT>
-__global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, const double4* __restrict__ A, const double4* __restrict__ B,
-                                            const double* __restrict__ C, const uint8_t* __restrict__ lev,
-                                            double* __restrict__ part_max, double* __restrict__ part_cnt) {
+__global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, RayF3 f, const uint8_t* __restrict__ lev,
+                                            const uint8_t* __restrict__ levC, double* __restrict__ part_max,
+                                            double* __restrict__ part_cnt) {
   const int blk = blockIdx.x;
   const int64_t k = int64_t(blk) * kB + threadIdx.x;
   const int64_t M = int64_t(g.nv) * g.nr * g.nc;
   double sum = 0.0, cnt = 0.0;
   if (k < M) {
     const int64_t r = row_major_ray(g, k);
-    const double4 a = A[r], b = B[r];
+    const Ray3 ray = ray_from_factors(g, f, r);
     Z0Vis3<LT> z;
     const double tol = 1e-9 * g.pixel;
     z.sum = 0.0; z.cnt = 0; z.accLL = 0.0;
@@ -814,11 +818,15 @@ __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, const double4* __restric
       for (int d = 0; d < 7; ++d) z.acc[m][d] = 0.0;
     }
     Walker3 w;
-    if (w.init(g, a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, C[r])) {
+    if (w.init(g, ray)) {
       const int n = g.n;
+      // x-major rays read the [z][x][y] level map (neighbouring lanes, neighbouring addresses)
+      const bool xmaj = fabs(ray.ex) >= fabs(ray.ey);
+      const uint8_t* __restrict__ lv = xmaj ? levC : lev;
       for (int step = 0; step < 4 * (2 * n + g.nz) + 8; ++step) {
         const int ix = w.rx(), iy = w.ry(), iz = w.rz();
-        const int l = LT > 0 ? int(lev[__umul24(__umul24(unsigned(iz), unsigned(n)) + iy, unsigned(n)) + ix]) : 0;
+        const unsigned a0 = xmaj ? unsigned(ix) : unsigned(iy), a1 = xmaj ? unsigned(iy) : unsigned(ix);
+        const int l = LT > 0 ? int(lv[__umul24(__umul24(unsigned(iz), unsigned(n)) + a0, unsigned(n)) + a1]) : 0;
         double chord;
         const bool go = w.step(l, chord);
         z.visit(ix, iy, iz, l, chord);
@@ -898,17 +906,11 @@ __global__ __launch_bounds__(kB) void k3_expand(DevGeom3 g, const uint8_t* __res
 // ------------------------------------------------------------------ launchers
 
 template <typename T>
-void Geo3<T>::ray_table(const DevGeom3& g, const double2* views, void* A, void* B, double* C, hipStream_t s) {
-  const int64_t M = int64_t(g.nv) * g.nr * g.nc;
-  hipLaunchKernelGGL(k3_ray_table, dim3(blocks3(M)), dim3(kB), 0, s, g, views, (double4*)A, (double4*)B, C);
-}
-template <typename T>
-int Geo3<T>::forward(const DevGeom3& g, const void* A, const void* B, const double* C, const void* recR,
-                     const void* recC, const T* d, const T* i0v, const double* i0s, T* q, T* p, double* part,
-                     hipStream_t s) {
+int Geo3<T>::forward(const DevGeom3& g, const RayF3& f, const void* recR, const void* recC, const T* d,
+                     const T* i0v, const double* i0s, T* q, T* p, double* part, hipStream_t s) {
   const int nb = blocks3(int64_t(g.nv) * g.nr * g.nc);
-  hipLaunchKernelGGL(k3_forward<T>, dim3(nb), dim3(kB), 0, s, g, (const double4*)A, (const double4*)B, C,
-                     (const Rec3<T>*)recR, (const Rec3<T>*)recC, d, i0v, i0s, q, p, part);
+  hipLaunchKernelGGL(k3_forward<T>, dim3(nb), dim3(kB), 0, s, g, f, (const Rec3<T>*)recR, (const Rec3<T>*)recC, d,
+                     i0v, i0s, q, p, part);
   return nb;
 }
 template <typename T>
@@ -991,21 +993,19 @@ void Geo3<T>::grad_scores(const DevGeom3& g, const uint8_t* mask, const T* coef,
 template struct Geo3<float>;
 template struct Geo3<double>;
 
-int z0_partials3(const DevGeom3& g, const void* A, const void* B, const double* C, const uint8_t* lev,
-                 double* part_max, double* part_cnt, hipStream_t s) {
+int z0_partials3(const DevGeom3& g, const RayF3& f, const uint8_t* lev, const uint8_t* levC, double* part_max,
+                 double* part_cnt, hipStream_t s) {
   const int nb = blocks3(int64_t(g.nv) * g.nr * g.nc);
-  auto a = (const double4*)A;
-  auto b = (const double4*)B;
   switch (g.L) {
 #define Z3_CASE(K) \
-    case K: hipLaunchKernelGGL(k3_z0<K>, dim3(nb), dim3(kB), 0, s, g, a, b, C, lev, part_max, part_cnt); break;
+    case K: hipLaunchKernelGGL(k3_z0<K>, dim3(nb), dim3(kB), 0, s, g, f, lev, levC, part_max, part_cnt); break;
     Z3_CASE(0) Z3_CASE(1) Z3_CASE(2) Z3_CASE(3) Z3_CASE(4)
 #undef Z3_CASE
   }
   return nb;
 }
-void levmap3(const DevGeom3& g, const uint8_t* mask, uint8_t* lev, hipStream_t s) {
-  hipLaunchKernelGGL(k3_levmap, dim3(blocks3(int64_t(g.n) * g.n * g.nz)), dim3(kB), 0, s, g, mask, lev);
+void levmap3(const DevGeom3& g, const uint8_t* mask, uint8_t* lev, uint8_t* levC, hipStream_t s) {
+  hipLaunchKernelGGL(k3_levmap, dim3(blocks3(int64_t(g.n) * g.n * g.nz)), dim3(kB), 0, s, g, mask, lev, levC);
 }
 namespace {
 struct ListSpec3 {
