@@ -1046,6 +1046,7 @@ struct Z0Visitor {
   double accLL;
   double sum;
   int cnt;
+  int dirty;              // bit m: acc[m] holds chords of the current level-m node
   int px, py;             // pixel of the previous leaf (all bits set before the first)
   __device__ inline void flush_level(int m) {
 #pragma unroll
@@ -1066,8 +1067,13 @@ struct Z0Visitor {
     px = ix; py = iy;
 #pragma unroll
     for (int m = 1; m <= LT; ++m) {
-      if (dif >> m) flush_level(m);   // a new node at level m (empty sums before the first leaf)
+      // a new node at level m: its sums enter the total (untouched sums are zero: nothing to add)
+      if ((dif >> m) && (dirty >> m & 1)) {
+        flush_level(m);
+        dirty &= ~(1 << m);
+      }
       if (m > l) {
+        dirty |= 1 << m;
         const int right = (ix >> (m - 1)) & 1, bottom = (iy >> (m - 1)) & 1;
         const double cr = flip_sign(chord, right);
         acc[m][0] += cr;
@@ -1103,7 +1109,7 @@ __global__ __launch_bounds__(kBlock) void k_z0(DevGeom g, const double2* __restr
       z.tolm[m] = tol * double(1 << m);
       z.acc[m][0] = z.acc[m][1] = z.acc[m][2] = 0.0;
     }
-    z.accLL = 0.0; z.sum = 0.0; z.cnt = 0; z.px = z.py = -1;
+    z.accLL = 0.0; z.sum = 0.0; z.cnt = 0; z.dirty = 0; z.px = z.py = -1;
     walk<double, (LT > 0)>(g, ox, oy, ex, ey, 1.0 / ex, 1.0 / ey, lev, z);
 #pragma unroll
     for (int m = 1; m <= LT; ++m) z.flush_level(m);

@@ -755,6 +755,7 @@ struct Z0Vis3 {
   double accLL;
   double sum;
   int cnt;
+  int dirty;               // bit m: acc[m] holds chords of the current level-m node
   int px, py, pz;          // voxel of the previous leaf (all bits set before the first)
   __device__ void flush(int m) {
 #pragma unroll
@@ -775,8 +776,13 @@ struct Z0Vis3 {
     px = ix; py = iy; pz = iz;
 #pragma unroll
     for (int m = 1; m <= LT; ++m) {
-      if (dif >> m) flush(m);    // a new node at level m (empty sums before the first leaf)
+      // a new node at level m: its sums enter the total (untouched sums are zero: nothing to add)
+      if ((dif >> m) && (dirty >> m & 1)) {
+        flush(m);
+        dirty &= ~(1 << m);
+      }
       if (m > l) {
+        dirty |= 1 << m;
         const int bx = (ix >> (m - 1)) & 1, by = (iy >> (m - 1)) & 1, bz = (iz >> (m - 1)) & 1;
         const double cx = flip_sign(chord, bx), cy = flip_sign(chord, by), cxy = flip_sign(cx, by);
         acc[m][0] += cx;                    // types (tz, ty, tx) = 001 .. 111
@@ -806,7 +812,7 @@ __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, RayF3 f, const uint8_t* 
     const Ray3 ray = ray_from_factors(g, f, r);
     Z0Vis3<LT> z;
     const double tol = 1e-9 * g.pixel;
-    z.sum = 0.0; z.cnt = 0; z.accLL = 0.0;
+    z.sum = 0.0; z.cnt = 0; z.accLL = 0.0; z.dirty = 0;
     z.px = z.py = z.pz = -1;
     z.sc[0] = scale3(LT);
     z.tolm[0] = tol / z.sc[0];
