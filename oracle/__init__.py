@@ -23,6 +23,9 @@ Iterative Image Reconstruction for X-Ray Imaging for Security Applications"
                problem (eq. 1.3 with lambda = 0), wavelet AM combined with ordered
                subsets of views (Conclusion), and z-slices sharing one tree chosen on
                the slice-summed image (Results)
+  vol3d.py     cone-beam 3-D Siddon H, the 3-D Haar octree and its tree rule, and the
+               Results section's per-slice representation of a volume (2-D Haar of every
+               z-slice, one tree grown on the slice-summed image) on the same cone rays
 
 Parity status: every function is pinned by the `-m "not gpu"` tests in
 tests/test_oracle_*.py (closed forms, brute force, invariants, a hand-computed golden

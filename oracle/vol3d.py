@@ -28,7 +28,7 @@ when its seven details are active (tree masks use the same layout).
 import numpy as np
 import scipy.sparse as sp
 
-from . import wam
+from . import haar, wam
 from .geometry import axis_cos_sin, snap_axis_parallel
 
 DETAILS = [(tz, ty, tx) for tz in (0, 1) for ty in (0, 1) for tx in (0, 1) if (tz, ty, tx) != (0, 0, 0)]
@@ -441,3 +441,95 @@ def wam_solve3(H, n, nz, levels, d, i0, n_iters, pixel, schedule=(), frac=0.1, O
     trace.append(wam.idiv(d, wam.beer_mean(i0, H @ (Omega @ beta))))
     return dict(beta=beta.reshape(nz, n, n), mu=(Omega @ beta).reshape(nz, n, n), idiv=np.array(trace),
                 trees=trees, z0=z0s, held=held_total, mask=mask, b=b_all.reshape(nz, n, n))
+
+
+# ------------------------------------------------------------------ 2-D Haar per z-slice
+
+# The Results section represents its volumes slice by slice: "each z-slice" carries a
+# Level-3 2-D Haar transform, and one tree serves the whole volume, grown where the image
+# summed over the slices exceeds 0.1 of its maximum. Coefficients of slice s sit in the 2-D
+# Mallat layout of haar.py at [s][y][x]; node (l, s, i, j) covers the voxels [i 2^l,
+# (i+1) 2^l) x [j 2^l, (j+1) 2^l) of slice s (one voxel deep).
+
+def slice_synthesis_matrix3(n, nz, levels):
+    """Omega of the per-slice representation: block diagonal, the 2-D synthesis matrix of
+    haar.py once per slice (voxel (s, r, c) and coefficient (s, y, x) both at (s n + .) n + .)."""
+    return sp.kron(sp.identity(nz, format="csr"), haar.synthesis_matrix(n, levels), format="csr")
+
+
+def slice_mask3(mask2d, nz):
+    """The volume's mask: the one 2-D tree in every slice."""
+    return np.repeat(np.asarray(mask2d, np.uint8)[None], nz, axis=0)
+
+
+def expand_tree_slices3(beta, mask2d, levels, frac, Omega2d):
+    """Tree rule of the Results section for slices sharing one tree: the synthesized images of
+    the slices summed over z (= Omega2d applied to the summed coefficients), thr = frac x the
+    summed image's maximum, and every leaf of the shared tree with a pixel of the summed
+    image above thr (strict) splits once (nothing when the maximum is <= 0). beta: [nz, n, n].
+    Returns (new 2-D mask, nodes split)."""
+    summed = np.asarray(beta, np.float64).sum(axis=0)
+    return wam.expand_tree(summed, mask2d, levels, frac, Omega2d)
+
+
+def slice_wam_solve3(H, n, nz, levels, d, i0, n_iters, pixel, schedule=(), frac=0.1, beta0=None, mask0=None,
+                     masks=None):
+    """Algorithm 1 on a cone-beam volume whose slices carry 2-D Haar transforms sharing one
+    tree (same steps as wam_solve3: b for every coefficient (eq. 1.6), Z0 (eq. 1.61) per tree,
+    the sign split of eq. 1.10 and the zero of eq. 1.9 for every active coefficient; the tree
+    rule of expand_tree_slices3 before each scheduled update). masks: optional {j: 2-D mask}
+    giving the shared tree before update j (overrides the rule there). mask0 is a 2-D mask.
+    Returns beta [nz, n, n], mu, the I-divergence trace (n_iters + 1), the trees (j, 2-D mask),
+    Z0 and W = nnz(Phi) per tree, the held count and the final 2-D mask."""
+    O2 = haar.synthesis_matrix(n, levels)
+    Omega = slice_synthesis_matrix3(n, nz, levels)
+    d = np.asarray(d, np.float64)
+    N = n * n * nz
+    beta = np.zeros(N) if beta0 is None else np.array(beta0, np.float64).ravel()
+    mask2 = haar.approx_mask(n, levels) if mask0 is None else np.array(mask0, np.uint8)
+    masks = masks or {}
+    b_all = Omega.T @ (H.T @ d)
+    trace, trees, z0s, ws, held_total = [], [], [], [], 0
+    Phi = None
+    for j in range(n_iters):
+        changed = False
+        if j in masks:
+            mask2 = np.array(masks[j], np.uint8)
+            changed = True
+        elif j in schedule:
+            mask2, _ = expand_tree_slices3(beta.reshape(nz, n, n), mask2, levels, frac, O2)
+            changed = True
+        if Phi is None or changed:
+            Phi, act = wam.phi_matrix(H, Omega, slice_mask3(mask2, nz), pixel)
+            Php, Phm = wam.split_phi(Phi)
+            z0 = wam.z0_of(Phi)
+            trees.append((j, mask2.copy()))
+            z0s.append(z0)
+            ws.append(int(Phi.nnz))
+        q_hat = wam.beer_mean(i0, Phi @ beta[act])
+        trace.append(wam.idiv(d, q_hat))
+        delta, held = wam.closed_form_update(b_all[act], Php.T @ q_hat, Phm.T @ q_hat, z0)
+        held_total += int(held.sum())
+        beta[act] += delta
+    trace.append(wam.idiv(d, wam.beer_mean(i0, H @ (Omega @ beta))))
+    return dict(beta=beta.reshape(nz, n, n), mu=(Omega @ beta).reshape(nz, n, n), idiv=np.array(trace),
+                trees=trees, z0=z0s, w=ws, held=held_total, mask=mask2, b=b_all.reshape(nz, n, n))
+
+
+def slice_node_phi3(g, o, e, lev, s, i, j):
+    """Projections along the rays (o, e) of the three detail basis functions of the per-slice
+    node (lev, s, i, j), from box clipping of its four quadrants (one voxel deep in slice s):
+    [D1, D2, D3] with D1 = 2^-lev (TL - TR + BL - BR), D2 = 2^-lev (TL + TR - BL - BR),
+    D3 = 2^-lev (TL - TR - BL + BR) over the quadrant chords (T = smaller y index, L = smaller x)."""
+    exy, ez = edges3(g)
+    h = 1 << (lev - 1)
+    q = {}
+    for by in (0, 1):
+        for bx in (0, 1):
+            x0, y0 = (2 * j + bx) * h, (2 * i + by) * h
+            lo = np.array([exy[x0], exy[y0], ez[s]])
+            hi = np.array([exy[x0 + h], exy[y0 + h], ez[s + 1]])
+            q[(by, bx)] = box_chord3(o, e, lo, hi)
+    tl, tr, bl, br = q[(0, 0)], q[(0, 1)], q[(1, 0)], q[(1, 1)]
+    sc = 2.0 ** -lev
+    return [sc * (tl - tr + bl - br), sc * (tl + tr - bl - br), sc * (tl - tr - bl + br)]

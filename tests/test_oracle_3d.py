@@ -294,3 +294,103 @@ def test_cone_central_column_at_quarter_turns_takes_the_plus_side():
                                     else np.array([[-2.0, exy[2], ez[0]]]),
                                     np.array([[exy[3], 2.0, ez[-1]]]) if v % 2 else np.array([[2.0, exy[3], ez[-1]]]))
             np.testing.assert_allclose(h.sum(), want[0], atol=1e-12)
+
+
+# ------------------------------------------------------------------ 2-D Haar per z-slice
+
+def test_slice_haar_is_orthonormal_and_the_2d_cascade_per_slice():
+    """The per-slice synthesis applies the textbook 2-D cascade to every slice on its own."""
+    from oracle import haar
+    n, nz, L = 8, 3, 2
+    O = vol3d.slice_synthesis_matrix3(n, nz, L).toarray()
+    np.testing.assert_allclose(O.T @ O, np.eye(n * n * nz), atol=1e-13)
+    beta = np.random.default_rng(0).normal(size=(nz, n, n))
+    mu = (O @ beta.ravel()).reshape(nz, n, n)
+    for s in range(nz):
+        np.testing.assert_allclose(mu[s], haar.cascade_synthesis(beta[s], L), atol=1e-13)
+
+
+def _box_matrix(g, o, e, boxes_lo, boxes_hi):
+    return vol3d.box_chord3(o[:, None, :], e[:, None, :], boxes_lo[None], boxes_hi[None])
+
+
+def test_slice_node_phi_from_quadrant_clipping_equals_h_omega():
+    """phi(y|z) of a per-slice detail = 2^-l (signed sum of its quadrants' chords) along cone
+    rays, against the columns of H Omega; every level, nodes in several slices."""
+    g = tiny_geom(8, 5, 4, 6, 12)
+    L = 3
+    o, e = vol3d.rays3(g)
+    Phi = (vol3d.system_matrix3(g) @ vol3d.slice_synthesis_matrix3(g.n, g.nz, L)).toarray()
+    for lev in range(1, L + 1):
+        m = g.n >> lev
+        for s in (0, 2, 4):
+            for i, j in ((0, 0), (m - 1, 0), (m - 1, m - 1)):
+                phis = vol3d.slice_node_phi3(g, o, e, lev, s, i, j)
+                for (zr, zc), ph in zip(((i, m + j), (m + i, j), (m + i, m + j)), phis):
+                    col = (s * g.n + zr) * g.n + zc
+                    np.testing.assert_allclose(Phi[:, col], ph, atol=1e-12)
+
+
+def test_slice_z0_closed_form_and_coarse_box_reduction():
+    """Approximation-only per-slice tree: Z0 = 2^-L max chord through the volume, and the
+    whole solve equals voxel AM over the 2^L x 2^L x 1 root boxes (system matrix of the boxes
+    by direct box clipping), with mu constant on each box."""
+    g = tiny_geom(8, 4, 5, 6, 12)
+    L = 1
+    o, e = vol3d.rays3(g)
+    H = vol3d.system_matrix3(g)
+    shapes = synth.make_ellipsoids(np.random.default_rng(7), g.n, g.nz, g.pixel, 3, 0.06, 0)
+    d = np.random.default_rng(8).poisson(2e4 * np.exp(-synth.line_integrals3(shapes, o, e))).astype(float)
+    r = vol3d.slice_wam_solve3(H, g.n, g.nz, L, d, 2e4, 6, g.pixel)
+    lo = np.array([-g.n / 2, -g.n / 2, -g.nz / 2]) * g.pixel
+    assert abs(r["z0"][0] - 2.0 ** -L * vol3d.box_chord3(o, e, lo, -lo).max()) <= 1e-12 * r["z0"][0]
+    exy, ez = vol3d.edges3(g)
+    nb, s_ = g.n >> L, 1 << L
+    bs, bi, bj = np.meshgrid(np.arange(g.nz), np.arange(nb), np.arange(nb), indexing="ij")
+    blo = np.stack([exy[bj.ravel() * s_], exy[bi.ravel() * s_], ez[bs.ravel()]], axis=1)
+    bhi = np.stack([exy[(bj.ravel() + 1) * s_], exy[(bi.ravel() + 1) * s_], ez[bs.ravel() + 1]], axis=1)
+    import scipy.sparse as sp
+    Hc = sp.csr_matrix(_box_matrix(g, o, e, blo, bhi))
+    rc = vol3d.wam_solve3(Hc, nb, g.nz, 0, d, 2e4, 6, g.pixel)
+    np.testing.assert_allclose(r["mu"][:, ::s_, ::s_], rc["mu"], rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(r["idiv"], rc["idiv"], rtol=1e-11)
+    # and mu is constant on every root box
+    np.testing.assert_allclose(r["mu"], np.repeat(np.repeat(rc["mu"], s_, 1), s_, 2), rtol=1e-10, atol=1e-13)
+
+
+def test_slice_solve_is_monotone_across_expansions_and_noise_free_data_are_fixed():
+    g = tiny_geom(16, 6, 8, 8, 24)
+    L = 2
+    o, e = vol3d.rays3(g)
+    H = vol3d.system_matrix3(g)
+    shapes = synth.make_ellipsoids(np.random.default_rng(9), g.n, g.nz, g.pixel, 5, 0.06, 1)
+    d = np.random.default_rng(10).poisson(5e4 * np.exp(-synth.line_integrals3(shapes, o, e))).astype(float)
+    r = vol3d.slice_wam_solve3(H, g.n, g.nz, L, d, 5e4, 12, g.pixel, schedule=[3, 7])
+    tr = r["idiv"]
+    assert np.all(tr[1:] <= tr[:-1] * (1 + 1e-13))
+    assert len(r["trees"]) == 3 and r["trees"][2][1].sum() > r["trees"][0][1].sum()
+    # consistent data from a slice-leaf-constant volume on the final tree: a fixed point
+    from oracle import haar
+    O = vol3d.slice_synthesis_matrix3(g.n, g.nz, L)
+    beta = np.where(vol3d.slice_mask3(r["mask"], g.nz) > 0, r["beta"], 0.0)
+    q = 3e4 * np.exp(-(H @ (O @ beta.ravel())))
+    again = vol3d.slice_wam_solve3(H, g.n, g.nz, L, q, 3e4, 2, g.pixel, beta0=beta, mask0=r["mask"])
+    np.testing.assert_allclose(again["beta"], beta, atol=1e-12)
+    assert haar.valid_mask(r["mask"], L)
+
+
+def test_slice_rule_splits_where_the_summed_image_exceeds_the_threshold():
+    """Hand-made: two slices of 4x4 with 1-level nodes (2x2 blocks). Slice 0 holds 1.0 on the
+    top-left block, both slices hold 0.06 on the bottom-right block: each 0.06 is below 0.1 x
+    max, their sum 0.12 is above it, so the top-left and bottom-right roots split (shared by
+    both slices) and the other two do not."""
+    from oracle import haar
+    n, nz, L = 4, 2, 1
+    mu = np.zeros((nz, n, n))
+    mu[0, :2, :2] = 1.0
+    mu[:, 2:, 2:] = 0.06
+    mu[1, 2:, :2] = 0.05                          # 0.05 in one slice only: stays
+    beta = np.stack([haar.cascade_analysis(mu[s], L) for s in range(nz)])
+    new, cnt = vol3d.expand_tree_slices3(beta, haar.approx_mask(n, L), L, 0.1, haar.synthesis_matrix(n, L))
+    assert cnt == 2
+    np.testing.assert_array_equal(haar.split_flags(new, 1), [[True, False], [False, True]])
