@@ -38,6 +38,13 @@
  *            (m = n >> l, mz = nz >> l), basis 2^(-3l/2) times, per flagged axis, +1 on the
  *            lower and -1 on the upper half; the approximation of root (k, i, j) sits at
  *            [k][i][j], basis 2^(-3L/2). A node splits into its seven details together.
+ *   per-slice (WAMCT_CONE, wavelet_dims = 2) every z-slice s holds the 2-D Haar coefficients
+ *            of its n x n image in the 2-D Mallat layout above ([s][y][x]); node (l, s, i, j)
+ *            covers the voxels [i 2^l, (i+1) 2^l) x [j 2^l, ...) of slice s; the slices share
+ *            one tree (the mask holds the same n x n tree in every slice); the tree rule
+ *            synthesizes every slice, sums the images over the slices in FP64 and splits
+ *            every leaf with a pixel of the summed image above frac x its maximum (Results).
+ *            n must be divisible by 2^levels, nz need not.
  *   tree     the active set Z_s (footnote to eq. 1.61) is a uint8 n x n mask in Mallat
  *            layout: approximations always active; a node's three details are active
  *            together ("split"), and only if its parent is split or it is a root.
@@ -106,6 +113,11 @@ typedef struct {
                           chords exact to ~1e-13 mm; WAMCT_F32 chords carry an absolute error
                           of about 1e-7 times the image half-diagonal. */
   int32_t batch;       /* scans in the stack, 1 <= batch <= 65535 */
+  int32_t wavelet_dims;/* 0: the geometry's default (2-D Haar for parallel and fan beam, 3-D Haar
+                          octree for the cone beam). 2 with the cone beam: the 2-D Haar transform
+                          of every z-slice (Results: "each z-slice represented by a Level 3
+                          Haar" with one tree for the volume), see "per-slice" below. 3 is valid
+                          for the cone beam only. */
 } wamct_options;
 
 enum {                 /* kernel classes reported by wamct_get_timing */

@@ -59,6 +59,8 @@ std::string validate(const wamct_geometry* g, const wamct_options* o) {
   if (o->geometry != WAMCT_F32 && o->geometry != WAMCT_F64) return fmt("unknown geometry precision %d", o->geometry);
   if (o->geometry == WAMCT_F32 && o->dtype == WAMCT_F64) return "geometry precision must be at least dtype";
   if (o->batch < 1 || o->batch > 65535) return fmt("batch = %d outside [1, 65535]", o->batch);
+  if (o->wavelet_dims != 0 && o->wavelet_dims != 2)
+    return fmt("wavelet_dims = %d: 2-D scans take the 2-D Haar transform (0 or 2)", o->wavelet_dims);
   return "";
 }
 }  // namespace

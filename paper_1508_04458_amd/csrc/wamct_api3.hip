@@ -31,8 +31,13 @@ std::string validate3(const wamct_geometry* g, const wamct_options* o) {
   if (!(g->sod > rc)) return fmt("cone beam needs sod (%g) > the volume's circumradius in x-y (%g)", g->sod, rc);
   if (!(g->sdd > g->sod) || !std::isfinite(g->sdd)) return "cone beam needs finite sdd > sod";
   if (o->levels < 0 || o->levels > 4) return fmt("cone beam: levels = %d outside [0, 4]", o->levels);
-  if (g->n % (1 << o->levels) || g->nz % (1 << o->levels))
+  if (o->wavelet_dims != 0 && o->wavelet_dims != 2 && o->wavelet_dims != 3)
+    return fmt("cone beam: wavelet_dims = %d outside {0, 2, 3}", o->wavelet_dims);
+  if (o->wavelet_dims == 2) {
+    if (g->n % (1 << o->levels)) return fmt("n = %d must be divisible by 2^levels = %d", g->n, 1 << o->levels);
+  } else if (g->n % (1 << o->levels) || g->nz % (1 << o->levels)) {
     return fmt("n = %d and nz = %d must be divisible by 2^levels = %d", g->n, g->nz, 1 << o->levels);
+  }
   if (o->dtype != WAMCT_F32 && o->dtype != WAMCT_F64) return fmt("unknown dtype %d", o->dtype);
   if (o->geometry != WAMCT_F64) return "cone beam: ray geometry is FP64 only";
   if (o->batch != 1) return "cone beam: one scan per context (batch = 1)";
@@ -97,6 +102,13 @@ struct Ctx3 final : wamct_ctx {
   }
 
     RayF3 rayf() const { return RayF3{views, colt, rowt, nrm}; }
+  // one z-slice as a 2-D image (the 2-D tree helpers take the slices as a stack)
+  DevGeom slice_geom() const {
+    DevGeom g2{};
+    g2.kind = 1; g2.n = g.n; g2.L = g.L; g2.pixel = g.pixel;
+    g2.nv = 1; g2.nb = 1; g2.vs0 = 0; g2.vss = 1; g2.nvs = 1;
+    return g2;
+  }
 template <typename Q>
   wamct_status alloc(Q*& p, int64_t count) {
     void* v = nullptr;
@@ -203,6 +215,7 @@ template <typename Q>
   wamct_status init(const wamct_geometry& G, const wamct_options& O, hipStream_t s) override {
     st = s;
     g.n = G.n; g.nz = G.nz; g.nv = G.n_views; g.nr = G.n_rows; g.nc = G.n_bins; g.L = O.levels;
+    g.wd = O.wavelet_dims == 2 ? 2 : 3;
     g.pixel = G.pixel; g.cpitch = G.bin_pitch; g.rpitch = G.row_pitch; g.sod = G.sod; g.sdd = G.sdd;
     M = int64_t(g.nv) * g.nr * g.nc;
     N = int64_t(g.n) * g.n * g.nz;
@@ -406,7 +419,22 @@ template <typename Q>
       LAUNCHED();
       return enq_tree(s);
     }
-    if (g.L > 0) {
+    if (g.L > 0 && g.wd == 2) {
+      // Results: every slice synthesized (FP64), the images summed over the slices (in slice
+      // order), and the tree every slice shares grown on the summed image
+      {
+        Scope sc(this, WAMCT_K_TREE, s);
+        Geo3<T>::mu64(g, beta, mu64, partd, s);
+        const DevGeom g2 = slice_geom();
+        const int nbk = sum_slices(g2, mu64, partd, g.nz, s);
+        reduce_max(partd, nbk, scal + 2, s);
+        HIPCHK(hipMemcpyAsync(mask_old, mask, size_t(g.n) * g.n, hipMemcpyDeviceToDevice, s));
+        fill_i32(ints + 2, 1, 0, s);
+        expand(g2, mask_old, mask, mu64, scal + 2, frac, ints + 2, 1, s);
+        broadcast_slice3(g, mask, s);
+      }
+      LAUNCHED();
+    } else if (g.L > 0) {
       {
         Scope sc(this, WAMCT_K_TREE, s);
         const int nbk = Geo3<T>::mu64(g, beta, mu64, partd, s);
@@ -637,6 +665,8 @@ template <typename Q>
   int32_t tree_sharing() const override { return 0; }
   wamct_status set_tree_rule(int32_t r) override {
     if (r != WAMCT_RULE_VALUE && r != WAMCT_RULE_GRADIENT) return fail(WAMCT_E_INVALID, fmt("unknown tree rule %d", r));
+    if (r == WAMCT_RULE_GRADIENT && g.wd == 2)
+      return fail(WAMCT_E_UNSUPPORTED, "the residual-gradient rule is implemented for the octree (wavelet_dims 3)");
     HIPCHK(hipStreamSynchronize(st));
     if (r == WAMCT_RULE_GRADIENT && !coefg) CHECKED(alloc(coefg, N));   // gradient coefficients
     rule = r;

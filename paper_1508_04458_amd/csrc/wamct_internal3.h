@@ -13,8 +13,13 @@ struct DevGeom3 {
   int n, nz;        // volume n x n x nz, layout [z][y][x]
   int nv, nr, nc;   // views, detector rows, detector columns
   int L;            // Haar levels
+  int wd;           // wavelet dimensions: 3 = 3-D Haar octree, 2 = 2-D Haar per z-slice (one
+                    // tree for every slice; a node is one voxel deep, its z index the slice)
   double pixel, cpitch, rpitch, sod, sdd;
 };
+
+// z shift of a level-l node: octree nodes halve in z as well, per-slice nodes do not
+__host__ __device__ inline int node_zshift(int wd, int l) { return wd == 3 ? l : 0; }
 
 // Work item of the 3-D node-driven backprojection: one octree node or one box.
 //   bit 31     : 1 = node with octant chords (seven details, plus the approximation when the
@@ -72,6 +77,9 @@ struct Geo3 {
   // node's first detail position of score (other entries untouched)
   static void grad_scores(const DevGeom3& g, const uint8_t* mask, const T* coef, double* score, hipStream_t s);
 };
+
+// wd = 2: mask slices 1 .. nz-1 = slice 0 (the tree every slice shares)
+void broadcast_slice3(const DevGeom3& g, uint8_t* mask, hipStream_t s);
 
 // Z0 and W of the current octree (per ray FP64 walk); returns the number of blocks.
 // lev: per-voxel leaf level [z][y][x]; levC the same in [z][x][y] (read by x-major rays)

@@ -1,5 +1,7 @@
 // HIP kernels of wavelet-tree AM on a 3-D volume for gfx950: circular cone beam with a flat
-// detector and a 3-D Haar octree (seven details per node).
+// detector, and either a 3-D Haar octree (seven details per node) or the 2-D Haar transform
+// of every z-slice with one quadtree shared by the slices (three details per node, a node one
+// voxel deep; the Results section's representation of its volumes).
 //
 // Method: Degirmenci, O'Sullivan, Politte, arXiv 1508.04458, Introduction (eqs. 1.2-1.10,
 // Algorithm 1) and Results (tree rule), applied to voxels and octree nodes. As in 2-D the
@@ -147,22 +149,33 @@ __device__ inline int64_t detail_pos(int n, int nz, int l, int d, int k, int i, 
 
 __device__ inline double scale3(int l) { return exp2(-1.5 * double(l)); }
 
-// mu(voxel) = 2^(-3L/2) beta_LL(root) + sum over levels of 2^(-3l/2) sum_d sign_d beta_d
-template <typename T, typename R>
+// Per-slice 2-D Haar (wd = 2) uses the detail slots d = 0, 1, 2 (types t = 1, 2, 3: tz = 0, so
+// detail_pos gives [k][i][m + j], [k][m + i][j], [k][m + i][m + j] in slice k: the 2-D Mallat
+// positions of D1, D2, D3) and the basis 2^-l; the octree all seven and 2^(-3l/2).
+template <int WD> __device__ constexpr int n_details() { return WD == 3 ? 7 : 3; }
+template <int WD> __device__ inline double scale_w(int l) { return WD == 3 ? scale3(l) : exp2(-double(l)); }
+
+// mu(voxel) = scale(L) beta_LL(root) + sum over levels of scale(l) sum_d sign_d beta_d
+template <typename T, typename R, int WD>
 __device__ inline R synth_voxel(const T* __restrict__ beta, int n, int nz, int L, int s, int r, int c) {
-  R v = R(beta[(int64_t(s >> L) * n + (r >> L)) * n + (c >> L)]) * R(scale3(L));
+  R v = R(beta[(int64_t(s >> node_zshift(WD, L)) * n + (r >> L)) * n + (c >> L)]) * R(scale_w<WD>(L));
   for (int l = L; l >= 1; --l) {
-    const int k = s >> l, i = r >> l, j = c >> l;
-    const int oct = (((s >> (l - 1)) & 1) << 2) | (((r >> (l - 1)) & 1) << 1) | ((c >> (l - 1)) & 1);
+    const int k = s >> node_zshift(WD, l), i = r >> l, j = c >> l;
+    const int oct = (WD == 3 ? ((s >> (l - 1)) & 1) << 2 : 0) | (((r >> (l - 1)) & 1) << 1) | ((c >> (l - 1)) & 1);
     R acc = R(0);
 #pragma unroll
-    for (int d = 0; d < 7; ++d) {
+    for (int d = 0; d < n_details<WD>(); ++d) {
       const R b = R(beta[detail_pos(n, nz, l, d, k, i, j)]);
       acc += (__popc(uint32_t((d + 1) & oct)) & 1) ? -b : b;
     }
-    v += acc * R(scale3(l));
+    v += acc * R(scale_w<WD>(l));
   }
   return v;
+}
+template <typename T, typename R>
+__device__ inline R synth_voxel_g(const DevGeom3& g, const T* __restrict__ beta, int s, int r, int c) {
+  return g.wd == 2 ? synth_voxel<T, R, 2>(beta, g.n, g.nz, g.L, s, r, c)
+                   : synth_voxel<T, R, 3>(beta, g.n, g.nz, g.L, s, r, c);
 }
 
 // Leaf record: value rounded to 4 free low mantissa bits that hold the leaf level.
@@ -190,7 +203,7 @@ __global__ __launch_bounds__(kB) void k3_synth_records(DevGeom3 g, const T* __re
   const int n = g.n;
   if (p >= int64_t(n) * n * g.nz) return;
   const int s = int(p / (int64_t(n) * n)), r = int((p / n) % n), c = int(p % n);
-  const T v = lev ? synth_voxel<T, T>(beta, n, g.nz, g.L, s, r, c) : beta[p];
+  const T v = lev ? synth_voxel_g<T, T>(g, beta, s, r, c) : beta[p];
   const uint32_t l = lev ? lev[p] : 0u;
   recR[p] = Rec3<T>::make(v, l);
   recC[(int64_t(s) * n + c) * n + r] = Rec3<T>::make(v, l);
@@ -201,7 +214,7 @@ __global__ __launch_bounds__(kB) void k3_synth(DevGeom3 g, const T* __restrict__
   const int64_t p = int64_t(blockIdx.x) * kB + threadIdx.x;
   const int n = g.n;
   if (p >= int64_t(n) * n * g.nz) return;
-  mu[p] = synth_voxel<T, T>(beta, n, g.nz, g.L, int(p / (int64_t(n) * n)), int((p / n) % n), int(p % n));
+  mu[p] = synth_voxel_g<T, T>(g, beta, int(p / (int64_t(n) * n)), int((p / n) % n), int(p % n));
 }
 
 template <typename T>
@@ -211,7 +224,7 @@ __global__ __launch_bounds__(kB) void k3_mu64(DevGeom3 g, const T* __restrict__ 
   const int n = g.n;
   double v = -INFINITY;
   if (p < int64_t(n) * n * g.nz) {
-    v = synth_voxel<T, double>(beta, n, g.nz, g.L, int(p / (int64_t(n) * n)), int((p / n) % n), int(p % n));
+    v = synth_voxel_g<T, double>(g, beta, int(p / (int64_t(n) * n)), int((p / n) % n), int(p % n));
     mu64[p] = v;
   }
   v = breduce<true>(v);
@@ -225,7 +238,7 @@ __global__ __launch_bounds__(kB) void k3_levmap(DevGeom3 g, const uint8_t* __res
   if (p >= int64_t(n) * n * g.nz) return;
   const int s = int(p / (int64_t(n) * n)), r = int((p / n) % n), c = int(p % n);
   int l = g.L;
-  while (l >= 1 && split3(mask, n, l, s >> l, r >> l, c >> l)) --l;
+  while (l >= 1 && split3(mask, n, l, s >> node_zshift(g.wd, l), r >> l, c >> l)) --l;
   lev[p] = uint8_t(l);
   if (levC) levC[(int64_t(s) * n + c) * n + r] = uint8_t(l);
 }
@@ -238,32 +251,33 @@ __global__ __launch_bounds__(kB) void k3_analysis(DevGeom3 g, const T* __restric
   const int n = g.n, nz = g.nz, L = g.L;
   if (p >= int64_t(n) * n * nz) return;
   const int z = int(p / (int64_t(n) * n)), y = int((p / n) % n), x = int(p % n);
+  const bool oc = g.wd == 3;   // octree; else 2-D Haar of slice z
   int l = 0, t = 0;
   for (int lv = L; lv >= 1; --lv) {
-    const int m = n >> lv, mz = nz >> lv;
-    if (z < 2 * mz && y < 2 * m && x < 2 * m) {
-      t = (z >= mz ? 4 : 0) | (y >= m ? 2 : 0) | (x >= m ? 1 : 0);
+    const int m = n >> lv, mz = oc ? nz >> lv : nz;
+    if ((!oc || z < 2 * mz) && y < 2 * m && x < 2 * m) {
+      t = (oc && z >= mz ? 4 : 0) | (y >= m ? 2 : 0) | (x >= m ? 1 : 0);
       if (t != 0 || lv == L) { l = lv; break; }
     }
   }
   double acc = 0.0;
   if (t == 0) {  // approximation of root (z, y, x) (or a voxel when L = 0)
-    const int s = 1 << L;
-    for (int a = 0; a < s; ++a)
+    const int s = 1 << L, sz = oc ? s : 1;
+    for (int a = 0; a < sz; ++a)
       for (int b = 0; b < s; ++b)
-        for (int c = 0; c < s; ++c) acc += double(vol[(int64_t(z * s + a) * n + y * s + b) * n + x * s + c]);
-    acc *= scale3(L);
+        for (int c = 0; c < s; ++c) acc += double(vol[(int64_t(z * sz + a) * n + y * s + b) * n + x * s + c]);
+    acc *= oc ? scale3(L) : exp2(-double(L));
   } else {
-    const int m = n >> l, mz = nz >> l, s = 1 << l, h = s >> 1;
+    const int m = n >> l, mz = oc ? nz >> l : nz, s = 1 << l, h = s >> 1, sz = oc ? s : 1;
     const int k = z % mz, i = y % m, j = x % m;
-    for (int a = 0; a < s; ++a)
+    for (int a = 0; a < sz; ++a)
       for (int b = 0; b < s; ++b)
         for (int c = 0; c < s; ++c) {
-          const int oct = ((a >= h) << 2) | ((b >= h) << 1) | (c >= h);
-          const double v = double(vol[(int64_t(k * s + a) * n + i * s + b) * n + j * s + c]);
+          const int oct = (oc && a >= h ? 4 : 0) | ((b >= h) << 1) | (c >= h);
+          const double v = double(vol[(int64_t(k * sz + a) * n + i * s + b) * n + j * s + c]);
           acc += (__popc(uint32_t(t & oct)) & 1) ? -v : v;
         }
-    acc *= scale3(l);
+    acc *= oc ? scale3(l) : exp2(-double(l));
   }
   coef[p] = T(acc);
 }
@@ -282,20 +296,22 @@ __global__ __launch_bounds__(kB) void k3_check_mask(DevGeom3 g, const uint8_t* _
   const int n = g.n, nz = g.nz, L = g.L;
   if (p >= int64_t(n) * n * nz) return;
   const int z = int(p / (int64_t(n) * n)), y = int((p / n) % n), x = int(p % n);
-  if (z < (nz >> L) && y < (n >> L) && x < (n >> L)) {
+  const bool oc = g.wd == 3;   // octree; else one quadtree shared by the slices
+  if (!oc && mask[p] != mask[int64_t(y) * n + x]) { atomicAdd(bad, 1); return; }
+  if ((!oc || z < (nz >> L)) && y < (n >> L) && x < (n >> L)) {
     if (mask[p] != 1) atomicAdd(bad, 1);
     return;
   }
   if (mask[p] > 1) { atomicAdd(bad, 1); return; }
   int l = 0;
   for (int lv = L; lv >= 1; --lv)
-    if (z < 2 * (nz >> lv) && y < 2 * (n >> lv) && x < 2 * (n >> lv)) { l = lv; break; }
+    if ((!oc || z < 2 * (nz >> lv)) && y < 2 * (n >> lv) && x < 2 * (n >> lv)) { l = lv; break; }
   if (l == 0) { atomicAdd(bad, 1); return; }
-  const int m = n >> l, mz = nz >> l;
+  const int m = n >> l, mz = oc ? nz >> l : nz;
   const int k = z % mz, i = y % m, j = x % m;
   const bool f = split3(mask, n, l, k, i, j);
   if ((mask[p] != 0) != f) { atomicAdd(bad, 1); return; }
-  if (f && l < L && !split3(mask, n, l + 1, k >> 1, i >> 1, j >> 1)) atomicAdd(bad, 1);
+  if (f && l < L && !split3(mask, n, l + 1, oc ? k >> 1 : k, i >> 1, j >> 1)) atomicAdd(bad, 1);
 }
 
 __global__ void k3_approx_mask(DevGeom3 g, uint8_t* __restrict__ mask) {
@@ -303,7 +319,15 @@ __global__ void k3_approx_mask(DevGeom3 g, uint8_t* __restrict__ mask) {
   const int n = g.n;
   if (p >= int64_t(n) * n * g.nz) return;
   const int z = int(p / (int64_t(n) * n)), y = int((p / n) % n), x = int(p % n);
-  mask[p] = (z < (g.nz >> g.L) && y < (n >> g.L) && x < (n >> g.L)) ? 1 : 0;
+  mask[p] = (z < (g.nz >> node_zshift(g.wd, g.L)) && y < (n >> g.L) && x < (n >> g.L)) ? 1 : 0;
+}
+
+// slices 1 .. nz-1 of the mask take slice 0 (wd = 2: one tree shared by every slice)
+__global__ void k3_bcast_slice0(DevGeom3 g, uint8_t* __restrict__ mask) {
+  const int64_t nn = int64_t(g.n) * g.n;
+  const int64_t p = nn + int64_t(blockIdx.x) * kB + threadIdx.x;
+  if (p >= nn * g.nz) return;
+  mask[p] = mask[p % nn];
 }
 
 // ------------------------------------------------------------------ forward (leaf walk)
@@ -313,7 +337,9 @@ __global__ void k3_approx_mask(DevGeom3 g, uint8_t* __restrict__ mask) {
 // boundaries stay aligned since 2^l divides n and nz): a leaf is left through the nearest of
 // its three upper faces; the crossed axis steps to the neighbouring leaf, the two others take
 // the exit point's voxel, clamped into the old leaf's range and never moving backwards.
-// Voxel indices fit in 32 bits (n, nz <= 512).
+// Voxel indices fit in 32 bits (n, nz <= 512). WD = 2: leaves are 2^l x 2^l x 1 blocks of
+// one slice (their z face is the voxel's).
+template <int WD>
 struct Walker3 {
   double x0, y0, z0;   // mirrored voxel coordinates of the ray at t = 0
   double ux, uy, uz;   // voxels per unit t along each axis
@@ -357,8 +383,8 @@ struct Walker3 {
   // Leaves the current leaf (level l): chord = parameter length inside it; returns whether the
   // walk goes on (then x, y, z is a voxel of the next leaf; else possibly out of range).
   __device__ bool step(int l, double& chord) {
-    const int s = 1 << l;
-    const int ex_ = (x & -s) + s, ey_ = (y & -s) + s, ez_ = (z & -s) + s;
+    const int s = 1 << l, sz = WD == 3 ? s : 1;
+    const int ex_ = (x & -s) + s, ey_ = (y & -s) + s, ez_ = (z & -sz) + sz;
     const double tX = fma(double(ex_), kx, cx), tY = fma(double(ey_), ky, cy), tZ = fma(double(ez_), kz, cz);
     const bool ax0 = tX <= tY && tX <= tZ;
     const bool ax1 = !ax0 && tY <= tZ;
@@ -378,7 +404,7 @@ struct Walker3 {
 // Per ray: p = sum over the leaves crossed of chord * leaf value; then Beer's law and the FP64
 // I-divergence term. x-major rays read the [z][x][y] records (neighbouring lanes,
 // neighbouring rays of a detector row, then touch neighbouring addresses).
-template <typename T>
+template <typename T, int WD>
 __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, RayF3 f,
                                                  const Rec3<T>* __restrict__ recR, const Rec3<T>* __restrict__ recC,
                                                  const T* __restrict__ d, const T* __restrict__ i0v,
@@ -391,7 +417,7 @@ __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, RayF3 f,
   if (k < M) {
     const int64_t r = row_major_ray(g, k);
     const Ray3 ray = ray_from_factors(g, f, r);
-    Walker3 w;
+    Walker3<WD> w;
     double acc = 0.0;
     if (w.init(g, ray)) {
       const int n = g.n;
@@ -482,15 +508,17 @@ __global__ __launch_bounds__(kB) void k3_scale_rays(DevGeom3 g, const T* __restr
 // seven detail values from a 2x2x2 Haar butterfly of the octant chords. Per detail the signed
 // sum S and the sum of magnitudes A are kept: the positive part is (A + S) / 2 and the
 // negative part (S - A) / 2 (per (ray, coefficient) sign split, eq. 1.10).
-template <typename T, bool SPLIT>
+// WD = 2 (2-D Haar per slice): the node box is one voxel deep, split nodes take the chords of
+// their four quadrants (one z slab) and the three details of a 2x2 butterfly (scale 2^-l).
+template <typename T, bool SPLIT, int WD>
 __device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __restrict__ views,
                                            const double2* __restrict__ colt, const double* __restrict__ rowt,
                                            const T* __restrict__ y, int l, int k, int i, int j, int v0, int v1) {
-  const int n = g.n, nz = g.nz, s = 1 << l;
+  const int n = g.n, nz = g.nz, s = 1 << l, sz = WD == 3 ? s : 1;
   const double pix = g.pixel, hn = 0.5 * n, hz = 0.5 * nz;
   const double X0 = (double(j * s) - hn) * pix, X2 = (double((j + 1) * s) - hn) * pix;
   const double Y0 = (double(i * s) - hn) * pix, Y2 = (double((i + 1) * s) - hn) * pix;
-  const double Z0 = (double(k * s) - hz) * pix, Z2 = (double((k + 1) * s) - hz) * pix;
+  const double Z0 = (double(k * sz) - hz) * pix, Z2 = (double((k + 1) * sz) - hz) * pix;
   const double X1 = 0.5 * (X0 + X2), Y1 = 0.5 * (Y0 + Y2), Z1 = 0.5 * (Z0 + Z2);
   const float sod = float(g.sod), sdd = float(g.sdd);
   const float icp = float(1.0 / g.cpitch), irp = float(1.0 / g.rpitch);
@@ -498,7 +526,7 @@ __device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __r
   // |phi| <= 1e-12 pixel is rounding residue of chord differences, taken as 0 (phi is
   // 2^(-3l/2) times the butterfly outputs, in parameter units of the unnormalised ray
   // direction: chords there are mm / |D|, and |D| >= sdd)
-  const double tq = 1e-12 * g.pixel * exp2(1.5 * double(l)) / g.sdd;
+  const double tq = 1e-12 * g.pixel / scale_w<WD>(l) / g.sdd;
   Sums3<double> r;
 #pragma unroll
   for (int q = 0; q < kSlots3; ++q) r.v[q] = 0.0;
@@ -538,6 +566,33 @@ __device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __r
           const double hi = fmin(fmin(fmax(tx0, tx2), fmax(ty0, ty2)), zhi);
           const double chd = hi - lo;
           r.v[0] += chd > tq ? double(yr[col]) * chd : 0.0;
+        }
+        continue;
+      }
+      if (WD == 2) {
+        const double zlo = fmin(tz0, tz2), zhi = fmax(tz0, tz2);
+        for (int col = clo; col <= chi; ++col) {
+          const double2 cd = cv[col];
+          const double yv = double(yr[col]);
+          const double tx0 = ax0 * cd.x, tx1 = ax1 * cd.x, tx2 = ax2 * cd.x;
+          const double ty0 = ay0 * cd.y, ty1 = ay1 * cd.y, ty2 = ay2 * cd.y;
+          const double xl[2] = {fmin(tx0, tx1), fmin(tx1, tx2)}, xh[2] = {fmax(tx0, tx1), fmax(tx1, tx2)};
+          const double yl[2] = {fmin(ty0, ty1), fmin(ty1, ty2)}, yh[2] = {fmax(ty0, ty1), fmax(ty1, ty2)};
+          double ch[4];   // quadrant (by, bx) chords in the slice's z slab
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            ch[q] = fmax(fmin(fmin(xh[q & 1], yh[q >> 1]), zhi) - fmax(fmax(xl[q & 1], yl[q >> 1]), zlo), 0.0);
+          // types t = 1 (x), 2 (y), 3 (x and y): + on the lower half, - on the upper half
+          const double det[3] = {ch[0] - ch[1] + ch[2] - ch[3], ch[0] + ch[1] - ch[2] - ch[3],
+                                 ch[0] - ch[1] - ch[2] + ch[3]};
+          const double box = ch[0] + ch[1] + ch[2] + ch[3];
+          r.v[0] += box > tq ? yv * box : 0.0;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const double wv = fabs(det[d]) > tq ? yv * det[d] : 0.0;
+            r.v[1 + d] += wv;
+            r.v[8 + d] += fabs(wv);
+          }
         }
         continue;
       }
@@ -632,13 +687,13 @@ __device__ inline void seg_range3(const GArgs3<T>& a, int& start, int& count) {
   }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int WD>
 __device__ inline void item_finish3(const GArgs3<T>& a, uint32_t w, const Sums3<double>& r) {
   const int n = a.g.n, nz = a.g.nz;
   const bool split = (w >> 31) != 0;
   const int l = int((w >> 27) & 15u);
   const int k = int((w >> 18) & 0x1ffu), i = int((w >> 9) & 0x1ffu), j = int(w & 0x1ffu);
-  const double sc = scale3(l);
+  const double sc = scale_w<WD>(l);
   const int64_t root = (int64_t(k) * n + i) * n + j;
   if (MODE == kPlain) {
     a.out[root] = T(r.v[0] * sc);
@@ -648,7 +703,7 @@ __device__ inline void item_finish3(const GArgs3<T>& a, uint32_t w, const Sums3<
   if (MODE == kSplit) {
     if (is_root) { a.bp[root] = T(r.v[0] * sc); a.bm[root] = T(0); }
     if (split)
-      for (int d = 0; d < 7; ++d) {
+      for (int d = 0; d < n_details<WD>(); ++d) {
         const int64_t z = detail_pos(n, nz, l, d, k, i, j);
         a.bp[z] = T(0.5 * (r.v[8 + d] + r.v[1 + d]) * sc);
         a.bm[z] = T(0.5 * (r.v[1 + d] - r.v[8 + d]) * sc);
@@ -658,31 +713,31 @@ __device__ inline void item_finish3(const GArgs3<T>& a, uint32_t w, const Sums3<
   const double z0 = *a.z0;
   if (is_root) a.beta[root] = T(double(a.beta[root]) + am_delta3(double(a.b[root]), r.v[0] * sc, 0.0, z0, a.held));
   if (split)
-    for (int d = 0; d < 7; ++d) {
+    for (int d = 0; d < n_details<WD>(); ++d) {
       const int64_t z = detail_pos(n, nz, l, d, k, i, j);
       const double bp = 0.5 * (r.v[8 + d] + r.v[1 + d]) * sc, bm = 0.5 * (r.v[1 + d] - r.v[8 + d]) * sc;
       a.beta[z] = T(double(a.beta[z]) + am_delta3(double(a.b[z]), bp, bm, z0, a.held));
     }
 }
 
-template <typename T, int MODE, bool SPLIT>
+template <typename T, int MODE, bool SPLIT, int WD>
 __global__ __launch_bounds__(kB) void k3_gather(GArgs3<T> a) {
   int start, count;
   seg_range3(a, start, count);
   const int it = xcd_unit3(blockIdx.x, gridDim.x) * kB + threadIdx.x;
   if (it >= count) return;
   const uint32_t w = item3_word(a.items, start + it, a.g.n);
-  const Sums3<double> r = item_sums3<T, SPLIT>(a.g, a.views, a.colt, a.rowt, a.y, int((w >> 27) & 15u),
-                                               int((w >> 18) & 0x1ffu), int((w >> 9) & 0x1ffu), int(w & 0x1ffu), 0,
-                                               a.g.nv);
-  item_finish3<T, MODE>(a, w, r);
+  const Sums3<double> r = item_sums3<T, SPLIT, WD>(a.g, a.views, a.colt, a.rowt, a.y, int((w >> 27) & 15u),
+                                                   int((w >> 18) & 0x1ffu), int((w >> 9) & 0x1ffu), int(w & 0x1ffu),
+                                                   0, a.g.nv);
+  item_finish3<T, MODE, WD>(a, w, r);
 }
 
 // (item, view chunk) tasks: a block of 4 waves takes 64 items; wave w handles view chunk
 // 4 group + w; the four chunk sums are added in LDS in wave order and stored per group.
 // Capped at 128 VGPRs (4 waves per SIMD instead of 3; a few values spill): measured 3 %
 // faster on the 512x512x256 cone update.
-template <typename T, bool SPLIT>
+template <typename T, bool SPLIT, int WD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k3_gather_part(GArgs3<T> a) {
   __shared__ double sh[4][kSlots3][64];
   int start, count;
@@ -697,8 +752,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   if (idx < count && chunk < a.chunks) {
     const uint32_t w = item3_word(a.items, start + idx, a.g.n);
     const int v0 = chunk * a.vpc, v1 = min(a.g.nv, v0 + a.vpc);
-    r = item_sums3<T, SPLIT>(a.g, a.views, a.colt, a.rowt, a.y, int((w >> 27) & 15u), int((w >> 18) & 0x1ffu),
-                             int((w >> 9) & 0x1ffu), int(w & 0x1ffu), v0, v1);
+    r = item_sums3<T, SPLIT, WD>(a.g, a.views, a.colt, a.rowt, a.y, int((w >> 27) & 15u), int((w >> 18) & 0x1ffu),
+                                 int((w >> 9) & 0x1ffu), int(w & 0x1ffu), v0, v1);
   }
 #pragma unroll
   for (int q = 0; q < kSlots3; ++q) sh[wv][q][lane] = r.v[q];
@@ -713,7 +768,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 // adds the chunk groups of each item in group order, then the item's final step
-template <typename T, int MODE>
+template <typename T, int MODE, int WD>
 __global__ __launch_bounds__(1024) void k3_gather_finish(GArgs3<T> a) {
   __shared__ double sh[kSlots3][64];
   int start, count;
@@ -732,7 +787,7 @@ __global__ __launch_bounds__(1024) void k3_gather_finish(GArgs3<T> a) {
   Sums3<double> r;
 #pragma unroll
   for (int q = 0; q < kSlots3; ++q) r.v[q] = sh[q][lane];
-  item_finish3<T, MODE>(a, w, r);
+  item_finish3<T, MODE, WD>(a, w, r);
 }
 
 // ------------------------------------------------------------------ Z0 and W (eq. 1.61)
@@ -747,11 +802,14 @@ __device__ inline double flip_sign(double v, int neg) {
 // voxels of consecutive leaves), 2^(-3m/2) |sum| of its details enter the ray's total and
 // the non-zero ones are counted (threshold 1e-9 pixel on the scaled value). Z0 = max over
 // rays of the totals, W = total count.
-template <int LT>
+// WD = 2 (2-D Haar per slice): three details per node (the types with tz = 0), scale 2^-m,
+// and a node belongs to one slice: a change of slice starts new nodes at every level.
+template <int LT, int WD>
 struct Z0Vis3 {
+  static constexpr int ND = WD == 3 ? 7 : 3;
   double tolm[LT + 1];     // count threshold per level, unscaled (index 0: root approximations)
-  double sc[LT + 1];       // 2^(-3m/2) per level (index 0: 2^(-3 LT / 2), the roots)
-  double acc[LT + 1][7];
+  double sc[LT + 1];       // scale of the level-m basis (index 0: scale of level LT, the roots)
+  double acc[LT + 1][ND];
   double accLL;
   double sum;
   int cnt;
@@ -759,7 +817,7 @@ struct Z0Vis3 {
   int px, py, pz;          // voxel of the previous leaf (all bits set before the first)
   __device__ void flush(int m) {
 #pragma unroll
-    for (int d = 0; d < 7; ++d) {
+    for (int d = 0; d < ND; ++d) {
       const double a = fabs(acc[m][d]);
       sum = fma(a, sc[m], sum);
       cnt += a > tolm[m] ? 1 : 0;
@@ -772,7 +830,7 @@ struct Z0Vis3 {
     accLL = 0.0;
   }
   __device__ void visit(int ix, int iy, int iz, int l, double chord) {
-    const int dif = (ix ^ px) | (iy ^ py) | (iz ^ pz);
+    const int dif = WD == 3 ? (ix ^ px) | (iy ^ py) | (iz ^ pz) : ((ix ^ px) | (iy ^ py) | (iz != pz ? ~0 : 0));
     px = ix; py = iy; pz = iz;
 #pragma unroll
     for (int m = 1; m <= LT; ++m) {
@@ -783,15 +841,18 @@ struct Z0Vis3 {
       }
       if (m > l) {
         dirty |= 1 << m;
-        const int bx = (ix >> (m - 1)) & 1, by = (iy >> (m - 1)) & 1, bz = (iz >> (m - 1)) & 1;
+        const int bx = (ix >> (m - 1)) & 1, by = (iy >> (m - 1)) & 1;
         const double cx = flip_sign(chord, bx), cy = flip_sign(chord, by), cxy = flip_sign(cx, by);
         acc[m][0] += cx;                    // types (tz, ty, tx) = 001 .. 111
         acc[m][1] += cy;
         acc[m][2] += cxy;
-        acc[m][3] += flip_sign(chord, bz);
-        acc[m][4] += flip_sign(cx, bz);
-        acc[m][5] += flip_sign(cy, bz);
-        acc[m][6] += flip_sign(cxy, bz);
+        if (WD == 3) {
+          const int bz = (iz >> (m - 1)) & 1;
+          acc[m][3 % ND] += flip_sign(chord, bz);
+          acc[m][4 % ND] += flip_sign(cx, bz);
+          acc[m][5 % ND] += flip_sign(cy, bz);
+          acc[m][6 % ND] += flip_sign(cxy, bz);
+        }
       }
     }
     if (dif >> LT) flushLL();
@@ -799,7 +860,7 @@ struct Z0Vis3 {
   }
 };
 
-template <int LT>
+template <int LT, int WD>
 __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, RayF3 f, const uint8_t* __restrict__ lev,
                                             const uint8_t* __restrict__ levC, double* __restrict__ part_max,
                                             double* __restrict__ part_cnt) {
@@ -810,20 +871,20 @@ __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, RayF3 f, const uint8_t* 
   if (k < M) {
     const int64_t r = row_major_ray(g, k);
     const Ray3 ray = ray_from_factors(g, f, r);
-    Z0Vis3<LT> z;
+    Z0Vis3<LT, WD> z;
     const double tol = 1e-9 * g.pixel;
     z.sum = 0.0; z.cnt = 0; z.accLL = 0.0; z.dirty = 0;
     z.px = z.py = z.pz = -1;
-    z.sc[0] = scale3(LT);
+    z.sc[0] = scale_w<WD>(LT);
     z.tolm[0] = tol / z.sc[0];
 #pragma unroll
     for (int m = 1; m <= LT; ++m) {
-      z.sc[m] = scale3(m);
+      z.sc[m] = scale_w<WD>(m);
       z.tolm[m] = tol / z.sc[m];
 #pragma unroll
-      for (int d = 0; d < 7; ++d) z.acc[m][d] = 0.0;
+      for (int d = 0; d < Z0Vis3<LT, WD>::ND; ++d) z.acc[m][d] = 0.0;
     }
-    Walker3 w;
+    Walker3<WD> w;
     if (w.init(g, ray)) {
       const int n = g.n;
       // x-major rays read the [z][x][y] level map (neighbouring lanes, neighbouring addresses)
@@ -915,8 +976,12 @@ template <typename T>
 int Geo3<T>::forward(const DevGeom3& g, const RayF3& f, const void* recR, const void* recC, const T* d,
                      const T* i0v, const double* i0s, T* q, T* p, double* part, hipStream_t s) {
   const int nb = blocks3(int64_t(g.nv) * g.nr * g.nc);
-  hipLaunchKernelGGL(k3_forward<T>, dim3(nb), dim3(kB), 0, s, g, f, (const Rec3<T>*)recR, (const Rec3<T>*)recC, d,
-                     i0v, i0s, q, p, part);
+  if (g.wd == 2)
+    hipLaunchKernelGGL((k3_forward<T, 2>), dim3(nb), dim3(kB), 0, s, g, f, (const Rec3<T>*)recR, (const Rec3<T>*)recC,
+                       d, i0v, i0s, q, p, part);
+  else
+    hipLaunchKernelGGL((k3_forward<T, 3>), dim3(nb), dim3(kB), 0, s, g, f, (const Rec3<T>*)recR, (const Rec3<T>*)recC,
+                       d, i0v, i0s, q, p, part);
   return nb;
 }
 template <typename T>
@@ -929,20 +994,25 @@ template <typename T>
 void Geo3<T>::scale_rays(const DevGeom3& g, const T* y, const double* nrm, T* out, hipStream_t s) {
   hipLaunchKernelGGL(k3_scale_rays<T>, dim3(blocks3(int64_t(g.nv) * g.nr * g.nc)), dim3(kB), 0, s, g, y, nrm, out);
 }
-template <typename T, int MODE, bool SPLIT>
+template <typename T, int MODE, bool SPLIT, int WD>
 static void gather_seg3(const GArgs3<T>& a, const Segment& sg, hipStream_t s) {
   if (sg.chunks <= 1) {
-    hipLaunchKernelGGL((k3_gather<T, MODE, SPLIT>), dim3(xcd_pad3(blocks3(sg.count))), dim3(kB), 0, s, a);
+    hipLaunchKernelGGL((k3_gather<T, MODE, SPLIT, WD>), dim3(xcd_pad3(blocks3(sg.count))), dim3(kB), 0, s, a);
     return;
   }
   const int groups = (sg.chunks + 3) / 4;
-  hipLaunchKernelGGL((k3_gather_part<T, SPLIT>), dim3(((sg.count + 63) / 64) * groups), dim3(256), 0, s, a);
-  hipLaunchKernelGGL((k3_gather_finish<T, MODE>), dim3((sg.count + 63) / 64), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL((k3_gather_part<T, SPLIT, WD>), dim3(((sg.count + 63) / 64) * groups), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k3_gather_finish<T, MODE, WD>), dim3((sg.count + 63) / 64), dim3(1024), 0, s, a);
 }
 template <typename T, int MODE>
 static void gather_mode3(const GArgs3<T>& a, const Segment& sg, bool split, hipStream_t s) {
-  if (split) gather_seg3<T, MODE, true>(a, sg, s);
-  else gather_seg3<T, MODE, false>(a, sg, s);
+  if (a.g.wd == 2) {
+    if (split) gather_seg3<T, MODE, true, 2>(a, sg, s);
+    else gather_seg3<T, MODE, false, 2>(a, sg, s);
+  } else {
+    if (split) gather_seg3<T, MODE, true, 3>(a, sg, s);
+    else gather_seg3<T, MODE, false, 3>(a, sg, s);
+  }
 }
 template <typename T>
 void Geo3<T>::gather(const DevGeom3& g, int mode, const double2* views, const double2* colt, const double* rowt,
@@ -1003,8 +1073,13 @@ int z0_partials3(const DevGeom3& g, const RayF3& f, const uint8_t* lev, const ui
                  double* part_cnt, hipStream_t s) {
   const int nb = blocks3(int64_t(g.nv) * g.nr * g.nc);
   switch (g.L) {
-#define Z3_CASE(K) \
-    case K: hipLaunchKernelGGL(k3_z0<K>, dim3(nb), dim3(kB), 0, s, g, f, lev, levC, part_max, part_cnt); break;
+#define Z3_CASE(K)                                                                                        \
+    case K:                                                                                               \
+      if (g.wd == 2)                                                                                      \
+        hipLaunchKernelGGL((k3_z0<K, 2>), dim3(nb), dim3(kB), 0, s, g, f, lev, levC, part_max, part_cnt); \
+      else                                                                                                \
+        hipLaunchKernelGGL((k3_z0<K, 3>), dim3(nb), dim3(kB), 0, s, g, f, lev, levC, part_max, part_cnt); \
+      break;
     Z3_CASE(0) Z3_CASE(1) Z3_CASE(2) Z3_CASE(3) Z3_CASE(4)
 #undef Z3_CASE
   }
@@ -1016,12 +1091,12 @@ void levmap3(const DevGeom3& g, const uint8_t* mask, uint8_t* lev, uint8_t* levC
 namespace {
 struct ListSpec3 {
   const uint8_t* mask;
-  int n, nz;
+  int n, nz, wd;
   __device__ bool keep(int, int l, int filter, int64_t code, uint32_t& word) const {
     const int j = int(morton3_compact(uint32_t(code)));
     const int i = int(morton3_compact(uint32_t(code >> 1)));
     const int k = int(morton3_compact(uint32_t(code >> 2)));
-    const int m = n >> l, mz = nz >> l;
+    const int m = n >> l, mz = nz >> node_zshift(wd, l);
     if (i >= m || j >= m || k >= mz) return false;
     const bool sp = l > 0 && split3(mask, n, l, k, i, j);
     word = item3_pack(sp ? 1 : 0, l, k, i, j);
@@ -1037,7 +1112,7 @@ PassTable list_passes3(const DevGeom3& g) {
   const int n_seg = L >= 1 ? L + 1 : 2;
   for (int sgi = 0; sgi < n_seg; ++sgi) {
     const int l = sgi <= 1 ? L : L - (sgi - 1);
-    const int m = g.n >> l, mz = g.nz >> l;
+    const int m = g.n >> l, mz = g.nz >> node_zshift(g.wd, l);
     int pw = 1;
     while (pw < m || pw < mz) pw <<= 1;
     const int filter = sgi == 1 ? 1 : 0;
@@ -1058,7 +1133,7 @@ void build_items3(const DevGeom3& g, const uint8_t* mask, uint32_t* items, int* 
   const int nblk = pt.blk_start[pt.n_pass];
   int* bcount = scratch;
   int* boff = scratch + nblk;
-  const ListSpec3 sp{mask, g.n, g.nz};
+  const ListSpec3 sp{mask, g.n, g.nz, g.wd};
   hipLaunchKernelGGL(k_list_count<ListSpec3>, dim3(nblk, 1), dim3(kListThreads), 0, s, sp, pt, bcount);
   hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(kListThreads), 0, s, pt, bcount, boff, counts, kInts);
   hipLaunchKernelGGL(k_list_write<ListSpec3>, dim3(nblk, 1), dim3(kListThreads), 0, s, sp, pt, boff, items,
@@ -1074,6 +1149,10 @@ void expand3(const DevGeom3& g, const uint8_t* mask_old, uint8_t* mask, const do
 }
 void check_mask3(const DevGeom3& g, const uint8_t* mask, int* bad, hipStream_t s) {
   hipLaunchKernelGGL(k3_check_mask, dim3(blocks3(int64_t(g.n) * g.n * g.nz)), dim3(kB), 0, s, g, mask, bad);
+}
+void broadcast_slice3(const DevGeom3& g, uint8_t* mask, hipStream_t s) {
+  const int64_t rest = int64_t(g.n) * g.n * (g.nz - 1);
+  if (rest > 0) hipLaunchKernelGGL(k3_bcast_slice0, dim3(blocks3(rest)), dim3(kB), 0, s, g, mask);
 }
 void approx_mask3(const DevGeom3& g, uint8_t* mask, hipStream_t s) {
   hipLaunchKernelGGL(k3_approx_mask, dim3(blocks3(int64_t(g.n) * g.n * g.nz)), dim3(kB), 0, s, g, mask);
