@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--cone-full-iters", type=int, default=60,
                     help="cone: cap for the equal-I-div voxel-AM run")
     ap.add_argument("--no-fan512", action="store_true", help="cone512: skip the nested fan512 workload")
+    ap.add_argument("--no-slices", action="store_true",
+                    help="cone: skip the per-slice 2-D Haar representation (one shared tree)")
     ap.add_argument("--fan-steps", type=int, default=10, help="cone512: timed steps of the nested fan512 run")
     ap.add_argument("--fan-warmup", type=int, default=2, help="cone512: warm-up steps of the nested fan512 run")
     return ap.parse_args()
@@ -501,6 +503,31 @@ def bench_cone(args):
             "time_to_value_rule_final_idiv_ms": None if k_gr is None else round(k_gr * t_gr / J * 1e3, 1)}
         grc.close()
         log(f"gradient rule: {J / t_gr:.3f} it/s, final I-div {gtr[-1]:.4e} (value rule {tr[-1]:.4e})")
+    if not args.no_slices:
+        # the Results section's own representation of a volume: a 2-D Haar transform per
+        # z-slice, one tree grown on the slice-summed image (same schedule and fraction)
+        slc = api.Context(g, P.levels, "f32", device=dev, wavelet_dims=2)
+        slc.set_data(d, P.i0)
+        slc.reset()
+        s_tr = slc.solve(J, sched, 0.1).cpu().numpy()          # traced run (untimed)
+        s_st = slc.tree_stats()
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        slc.reset()
+        slc.solve(J, sched, 0.1, trace=False)
+        torch.cuda.synchronize()
+        t_sl = time.perf_counter() - t4
+        hit = np.nonzero(s_tr <= tr[-1])[0]
+        k_sl = int(hit[0]) if hit.size else None
+        out["slices"] = {
+            "representation": "2-D Haar per z-slice, one tree grown on the slice-summed image",
+            "iter_per_s": round(J / t_sl, 3), "ms_per_solve": round(t_sl * 1e3, 1),
+            "final_idiv": float(s_tr[-1]), "final_active": int(s_st["n_active"]), "final_w": int(s_st["w"]),
+            "idiv_decreasing": bool(np.all(np.diff(s_tr) <= 1e-6 * np.abs(s_tr[:-1]))),
+            "iters_to_octree_final_idiv": k_sl,
+            "time_to_octree_final_idiv_ms": None if k_sl is None else round(k_sl * t_sl / J * 1e3, 1)}
+        slc.close()
+        log(f"per-slice 2-D Haar: {J / t_sl:.3f} it/s, final I-div {s_tr[-1]:.4e} (octree {tr[-1]:.4e})")
     if not args.no_full_am:
         # voxel AM (levels = 0) from mu = 0 until it reaches the tree run's final I-divergence
         # (or the cap): the Results section compares the two at the same objective value
@@ -510,7 +537,8 @@ def bench_cone(args):
         torch.cuda.synchronize()
         target = float(tr[-1])
         # run until the lower of the value-rule and gradient-rule final I-divergences
-        stop_at = min(target, out.get("gradient_rule", {}).get("final_idiv", target))
+        stop_at = min(target, out.get("gradient_rule", {}).get("final_idiv", target),
+                      out.get("slices", {}).get("final_idiv", target))
         cap, chunk = args.cone_full_iters, 5
         buf = torch.empty(chunk, dtype=torch.float64, device=dev)
         trace, done, t_run = [], 0, 0.0
@@ -539,8 +567,10 @@ def bench_cone(args):
             eq.update(full_time_ms=round(t_eq * 1e3, 1), tree_time_ms=round(dt * 1e3 / args.steps, 1),
                       tree_speedup=round(t_eq / (dt / args.steps), 3))
         out["equal_idiv"] = eq
-        if "gradient_rule" in out:
-            gr = out["gradient_rule"]
+        for key in ("gradient_rule", "slices"):
+            if key not in out:
+                continue
+            gr = out[key]
             hit = [k for k, v in enumerate(trace) if v <= gr["final_idiv"]]
             k_f = hit[0] if hit else None
             gr.update(full_am_iters_to_its_final_idiv=k_f,

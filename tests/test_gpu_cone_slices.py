@@ -158,3 +158,71 @@ def test_slice_errors():
     assert api.validate(g2, 2, "f64", wavelet_dims=2) is None
     assert api.validate(g2, 2, "f64") is not None
     assert api.validate(g2, 2, "f64", wavelet_dims=5) is not None
+
+
+# ------------------------------------------------------------------ benchmark size
+
+def _cone512():
+    return synth.CONE_CONFIGS["cone512"]["geom"]()
+
+
+def test_cone512_slices_forward_sampled_rays():
+    """The cone512 geometry (188.7 M rays, 512 x 512 x 256, 3 levels per slice), FP32, on 400
+    sampled rays through Omega beta of a random shared tree (oracle: every slice synthesized by
+    the textbook 2-D cascade, 3-D Siddon of the sampled rays)."""
+    from test_gpu_cone512 import I0, at, sample_rays
+    g, L = _cone512(), 3
+    mask2 = synth.random_tree_mask(g.n, L, 61, p_split=0.55)
+    rng = np.random.default_rng(61)
+    beta = rng.standard_normal((g.nz, g.n, g.n), dtype=np.float32) * np.float32(0.002) * mask2[None]
+    r = g.n >> L
+    beta[:, :r, :r] = (0.02 * (1 << L) + rng.uniform(0, 0.01, (g.nz, r, r))).astype(np.float32)
+    c = make_ctx(g, L, "f32")
+    c.set_data(torch.full((g.n_rays,), 0.5 * I0, dtype=torch.float32, device="cuda"), I0)
+    c.set_state(torch.from_numpy(beta.ravel()).cuda(), torch.from_numpy(vol3d.slice_mask3(mask2, g.nz).ravel()).cuda())
+    q, _ = c.forward()
+    ids = sample_rays(g, 400, 62)
+    print(f"[cone512 slices] oracle: {ids.size} sampled rays", flush=True)
+    vol = np.stack([haar.cascade_synthesis(beta[s].astype(np.float64), L) for s in range(g.nz)])
+    p_ref = vol3d.project_rays3(g, vol, ids)
+    q_ref = I0 * np.exp(-p_ref)
+    got = at(q, ids)
+    tol = q_ref * (1e-5 * np.maximum(np.abs(p_ref), 1e-3 * p_ref.max()) + 2e-7)
+    assert np.all(np.abs(got - q_ref) <= tol), np.max(np.abs(got - q_ref) / q_ref)
+
+
+def test_cone512_slices_split_backprojection_sampled_nodes():
+    """Sign-split backprojection at sampled per-slice nodes of every level (each node's phi
+    over every ray of its detector shadow, by quadrant clipping), 1e-5 of the larger sum."""
+    g, L = _cone512(), 3
+    n, nz = g.n, g.nz
+    mask2 = synth.random_tree_mask(n, L, 63, p_split=0.6)
+    c = make_ctx(g, L, "f32")
+    c.set_state(torch.zeros(g.n_voxels, dtype=torch.float32, device="cuda"),
+                torch.from_numpy(vol3d.slice_mask3(mask2, nz).ravel()).cuda())
+    y = np.random.default_rng(63).random(g.n_rays, dtype=np.float32)
+    bp, bm = (host(t).reshape(nz, n, n) for t in c.backproject_split(torch.from_numpy(y).cuda()))
+    exy, ez = vol3d.edges3(g)
+    rng = np.random.default_rng(64)
+    checked = 0
+    for lev in range(L, 0, -1):
+        m, s_ = n >> lev, 1 << lev
+        split = haar.split_flags(mask2, lev)
+        cand = np.argwhere(split)
+        for i, j in cand[rng.choice(len(cand), min(3, len(cand)), replace=False)]:
+            s = int(rng.integers(0, nz))
+            lo = np.array([exy[j * s_], exy[i * s_], ez[s]])
+            hi = np.array([exy[(j + 1) * s_], exy[(i + 1) * s_], ez[s + 1]])
+            ids = vol3d.box_shadow3(g, lo, hi)
+            o, e = vol3d.rays3(g, ids=ids)
+            phis = vol3d.slice_node_phi3(g, o, e, lev, s, i, j)
+            print(f"[cone512 slices] node ({lev}, {s}, {i}, {j}): {ids.size} rays", flush=True)
+            yy = y[ids].astype(np.float64)
+            for (zr, zc), ph in zip(((i, m + j), (m + i, j), (m + i, m + j)), phis):
+                ph = np.where(np.abs(ph) <= 1e-12 * g.pixel, 0.0, ph)
+                rp, rm = float(yy @ np.maximum(ph, 0.0)), float(yy @ np.minimum(ph, 0.0))
+                scale = max(abs(rp), abs(rm), 1e-30)
+                assert abs(bp[s, zr, zc] - rp) <= 1e-5 * scale, (lev, s, i, j, bp[s, zr, zc], rp)
+                assert abs(bm[s, zr, zc] - rm) <= 1e-5 * scale, (lev, s, i, j, bm[s, zr, zc], rm)
+                checked += 1
+    assert checked >= 27
