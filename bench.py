@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--cone-full-iters", type=int, default=60,
                     help="cone: cap for the equal-I-div voxel-AM run")
     ap.add_argument("--no-fan512", action="store_true", help="cone512: skip the nested fan512 workload")
+    ap.add_argument("--no-uneven", action="store_true", help="cone512: skip the nested uneven batch")
+    ap.add_argument("--uneven-steps", type=int, default=2, help="cone512: timed steps of the nested uneven batch")
     ap.add_argument("--no-slices", action="store_true",
                     help="cone: skip the per-slice 2-D Haar representation (one shared tree)")
     ap.add_argument("--fan-steps", type=int, default=10, help="cone512: timed steps of the nested fan512 run")
@@ -177,7 +179,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def bench_uneven(args):
+def bench_uneven(args, steps=None, warmup=None, autotune=None):
     """Uneven batch: `problems` independent fan-beam scans (image side from {128, 256, 384,
     512}, views from {360, 540, 720}, 2n bins, I0 in [1e4, 1e5]), each solved with the
     3-level tree-adaptive AM (100 iterations, expansions 21/43/85). Scans of one geometry
@@ -187,6 +189,9 @@ def bench_uneven(args):
     import torch
     from paper_1508_04458_amd import api, synth
 
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    autotune = args.autotune if autotune is None else autotune
     workers = max(1, min(16, os.cpu_count() or 1))
     specs = synth.uneven_specs(args.problems)
     log(f"drawing {len(specs)} problems with {workers} processes")
@@ -236,22 +241,38 @@ def bench_uneven(args):
         batch.reset()
         return batch.solve(J, sched, 0.1)
 
-    chosen = None
-    for _ in range(args.warmup):
+    tune = None
+    for _ in range(warmup):
         step()
-    if args.autotune:
+    if autotune:
+        # one step with the default shapes, then the measured choice of tiling and leaf-walk
+        # lanes per context (each candidate timed on the context's current, last tree)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        t_default = time.perf_counter() - t0
+        defaults = [(c.tiling(), c.walk_lanes()) for c in ctxs]
         chosen = batch.autotune(1)
-        log(f"tiling chosen: {chosen}")
+        lanes = [c.walk_lanes() for c in ctxs]
+        log(f"autotune: tiling {chosen}, walk lanes {lanes}")
         step()
+        tune = {"ms_per_step_default_shapes": round(t_default * 1e3, 3),
+                "default_tiling_lanes": defaults,
+                "chosen_tiling": chosen, "chosen_walk_lanes": lanes,
+                "classes": [[c.n, c.geom.n_views, c.S] for c in ctxs]}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         tr = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms_step = dt * 1e3 / args.steps
+    ms_step = dt * 1e3 / steps
     n_prob = sum(c.S for c in ctxs)
-    it_s = n_prob * J * args.steps / dt
+    it_s = n_prob * J * steps / dt
+    if tune is not None:
+        tune["ms_per_step_tuned"] = round(ms_step, 3)
+        tune["speedup"] = round(tune["ms_per_step_default_shapes"] / ms_step, 3)
     final = [float(t.reshape(-1, J + 1)[:, -1].sum().item()) for t in tr]
     stats = batch.stats()
     log(f"batch: {ms_step:.1f} ms per step")
@@ -281,7 +302,7 @@ def bench_uneven(args):
             "frac": round(alg / per_step_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": "whole batch iteration (graph replay)", "alg_bytes_per_step": int(alg)}
     out = {"metric": METRIC, "value": round(it_s, 2), "unit": "AM iter/s (problem-iterations)", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "steps": steps, "warmup": warmup, "ms_per_step": round(ms_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32" if args.geometry == "f32" else "f32 data, f64 ray geometry", "data": "synthetic",
            "config": {"workload": f"uneven batch: {n_prob} fan-beam problems (n in {{128,256,384,512}}, views in "
@@ -289,10 +310,13 @@ def bench_uneven(args):
                                   f"3-level tree AM, {J} iterations, expansions at {sched}",
                       "problems": n_prob, "classes": len(ctxs), "rays": M, "pixels": NN,
                       "streams": args.streams, "graph": not args.no_graph},
-           "gray_voxel_per_s": round(2 * w_it * args.steps / dt / 1e9, 3),
-           "final_idiv_sum": sum(final), "batch_stats": stats, "tiling": chosen, "sequential": seq,
+           "gray_voxel_per_s": round(2 * w_it * steps / dt / 1e9, 3),
+           "final_idiv_sum": sum(final), "batch_stats": stats, "autotune": tune, "sequential": seq,
            "roofline": roof}
-    print(json.dumps(out), flush=True)
+    for c in ctxs:
+        c.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_loss(args):
@@ -806,7 +830,7 @@ def main():
               "multi-GPU design is not built.", file=sys.stderr)
         sys.exit(2)
     if args.config == "uneven":
-        bench_uneven(args)
+        print(json.dumps(bench_uneven(args)), flush=True)
         return
     if args.config == "loss16":
         bench_loss(args)
@@ -825,6 +849,12 @@ def main():
             for k in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
                 fan.pop(k, None)
             out["fan512"] = fan
+        if args.config == "cone512" and not args.no_uneven:
+            log("uneven batch (nested)")
+            un = bench_uneven(args, steps=args.uneven_steps, warmup=1, autotune=True)
+            for k in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
+                un.pop(k, None)
+            out["uneven"] = un
     else:
         out = bench_fan(args, args.config, args.steps, args.warmup)
     copy_calibration(args, dev, out)

@@ -247,6 +247,14 @@ wamct_status wamct_get_timing(wamct_ctx* ctx, double* ms, int64_t* launches);
  * reallocate the context's partial-sum buffer (synchronizes). Results do not depend on the
  * tiling beyond floating-point summation order. */
 wamct_status wamct_set_tiling(wamct_ctx* ctx, int32_t lanes);
+/* Lanes per ray of the tree's leaf walk (the forward pass over the leaves, Algorithm 1's
+ * first step): each ray's path through the image is cut into `lanes` equal pieces walked by
+ * neighbouring lanes and added (1, 2 or 4; 0 = chosen by the ray count of the launch: 4 below
+ * 2^17 rays, 2 below 2^21, else 1). Results do not depend on it beyond floating-point
+ * summation order. E_INVALID for other values; E_UNSUPPORTED for levels = 0 (one lane per ray
+ * of the pixel walk) and the cone beam. wamct_get_walk_lanes gives the lanes in use. */
+wamct_status wamct_set_walk_lanes(wamct_ctx* ctx, int32_t lanes);
+wamct_status wamct_get_walk_lanes(wamct_ctx* ctx, int32_t* lanes);
 wamct_status wamct_get_tiling(wamct_ctx* ctx, int32_t* lanes);
 
 /* Ordered subsets of views (the combination with ordered subsets that the Conclusion names;
@@ -370,11 +378,14 @@ wamct_status wamct_batch_reset(wamct_batch* batch);
  * of wamct_solve on each context alone. Synchronizes once per tree change. */
 wamct_status wamct_batch_solve(wamct_batch* batch, int32_t n_iters, const int32_t* expand_at, int32_t n_expand,
                                double frac, double* const* idiv);
-/* Autotuner of the backprojection tiling: for every context, n_trial iterations (after
- * one untimed) are timed with HIP events at each candidate (HOST int32[n_candidates];
- * NULL = 2^18 .. 2^22) on the context's own stream, its state restored after every trial,
- * and the fastest is kept (wamct_set_tiling). chosen: HOST int32[n_ctx] (nullable). Tunes
- * on each context's current tree. Synchronizes; may allocate. */
+/* Autotuner of the launch shapes: for every context, n_trial iterations (after one untimed)
+ * are timed with HIP events on the context's own stream, its state restored after every
+ * trial: first at each candidate backprojection tiling (HOST int32[n_candidates]; NULL =
+ * 2^18 .. 2^22), the fastest kept (wamct_set_tiling), then, for contexts with a leaf walk
+ * (2-D, levels >= 1), at 1, 2 and 4 lanes per ray with that tiling, the fastest kept
+ * (wamct_set_walk_lanes). chosen: HOST int32[n_ctx] (nullable) receives the tilings (the
+ * lanes: wamct_get_walk_lanes). Tunes on each context's current tree. Synchronizes; may
+ * allocate. */
 wamct_status wamct_batch_autotune(wamct_batch* batch, int32_t n_trial, const int32_t* candidates,
                                   int32_t n_candidates, int32_t* chosen);
 /* Stream index of each context (HOST int32[n_ctx]), graph launches so far, nodes of the

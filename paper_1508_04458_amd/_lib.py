@@ -30,6 +30,7 @@ SYMBOLS = (
     "wamct_batch_stats", "wamct_set_subsets", "wamct_get_subsets", "wamct_set_tree_sharing",
     "wamct_get_tree_sharing", "wamct_set_tree_rule", "wamct_get_tree_rule", "wamct_set_penalty",
     "wamct_get_penalty", "wamct_set_tree_schedule", "wamct_get_tree_schedule", "wamct_idiv_noalloc",
+    "wamct_set_walk_lanes", "wamct_get_walk_lanes",
 )
 
 
@@ -98,6 +99,8 @@ def _load():
         "wamct_set_tree_schedule": (vp, i32, P(i32), vp),
         "wamct_get_tree_schedule": (vp, P(i32), P(i32), i32),
         "wamct_idiv_noalloc": (i32, i64, i32, vp, vp, vp, vp),
+        "wamct_set_walk_lanes": (vp, i32),
+        "wamct_get_walk_lanes": (vp, P(i32)),
         "wamct_batch_create": (i32, P(vp), i32, i32, vp, P(vp)),
         "wamct_batch_destroy": (vp,),
         "wamct_batch_reset": (vp,),

@@ -183,6 +183,15 @@ class Context:
         self._call(lib.wamct_get_tree_schedule, ctypes.byref(n), arr, n.value)
         return [int(arr[k]) for k in range(n.value)]
 
+    def set_walk_lanes(self, lanes: int) -> None:
+        """Lanes per ray of the leaf walk: 1, 2 or 4 (0: by the launch's ray count)."""
+        self._call(lib.wamct_set_walk_lanes, int(lanes))
+
+    def walk_lanes(self) -> int:
+        v = ctypes.c_int32()
+        self._call(lib.wamct_get_walk_lanes, ctypes.byref(v))
+        return v.value
+
     def set_tree_sharing(self, shared: bool) -> None:
         """Scans as z-slices of one volume sharing one tree grown on the slice-summed image."""
         self._call(lib.wamct_set_tree_sharing, 1 if shared else 0)

@@ -114,6 +114,7 @@ struct Ctx final : wamct_ctx {
   bool has_data = false, tree_dirty = true, i0v_used = false;
   int32_t iters = 0;
   int target_lanes = kTargetLanes;
+  int walk_k = 0;             // lanes per ray of the leaf walk (0: by launch size)
   // timing
   uint32_t timing_mask = 0;   // bit k: record kernel class k
   struct Rec { int kind; hipEvent_t a, b; };
@@ -141,6 +142,13 @@ struct Ctx final : wamct_ctx {
   bool has_data_() const override { return has_data; }
   bool tree_dirty_() const override { return tree_dirty; }
   int32_t tiling() const override { return target_lanes; }
+  wamct_status set_walk_lanes(int32_t k) override {
+    if (k != 0 && k != 1 && k != 2 && k != 4) return fail(WAMCT_E_INVALID, fmt("walk lanes %d not in {0, 1, 2, 4}", k));
+    if (g.L == 0) return fail(WAMCT_E_UNSUPPORTED, "levels = 0 walks pixels, one lane per ray");
+    walk_k = k;
+    return WAMCT_OK;
+  }
+  int32_t walk_lanes() const override { return g.L == 0 ? 0 : walk_k > 0 ? walk_k : leaf_pieces(M * P); }
   void count_iters(int k) override { iters += k; }
 
   template <typename Q>
@@ -640,7 +648,7 @@ struct Ctx final : wamct_ctx {
         Launch<T>::synth_records(g, beta, lev, leafR, leafC, P, s);
       }
       Scope sc(this, WAMCT_K_FORWARD, s);
-      return Geo<T, R>::forward_records(gg, A, B, leafR, leafC, d, iv, scal + 4, q, nullptr, pd, P, s);
+      return Geo<T, R>::forward_records(gg, A, B, leafR, leafC, d, iv, scal + 4, q, nullptr, pd, P, s, walk_k);
     }
     {
       Scope sc(this, WAMCT_K_SYNTH, s);
@@ -1214,8 +1222,29 @@ struct wamct_batch {
     return leave();
   }
 
-  // Per context: time n_trial iterations (after one untimed) at each candidate tiling on
-  // the context's own stream, restoring its state after every trial; keep the fastest.
+  // n_trial iterations of context c (after one untimed) timed with HIP events on its own
+  // stream, its state restored afterwards: *ms
+  wamct_status trial(wamct_ctx* c, int n_trial, hipEvent_t e0, hipEvent_t e1, float* ms) {
+    const hipStream_t s = c->stream();
+    wamct_status r = WAMCT_OK;
+    if (c->tree_dirty_()) {
+      r = c->enq_tree(s);
+      if (!r && hipStreamSynchronize(s) != hipSuccess) r = fail(WAMCT_E_HIP, "synchronize");
+      if (!r) r = c->finish_tree(nullptr);
+    }
+    if (!r) r = c->save_state(s);
+    if (!r) r = c->enq_iteration(s, nullptr, 0, false);
+    if (!r && hipEventRecord(e0, s) != hipSuccess) r = fail(WAMCT_E_HIP, "hipEventRecord");
+    for (int t = 0; t < n_trial && !r; ++t) r = c->enq_iteration(s, nullptr, 0, false);
+    if (!r && hipEventRecord(e1, s) != hipSuccess) r = fail(WAMCT_E_HIP, "hipEventRecord");
+    if (!r) r = c->restore_state(s);
+    if (!r && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+      r = fail(WAMCT_E_HIP, "trial timing failed");
+    if (r && err.empty()) err = c->err;
+    return r;
+  }
+  // Per context: the fastest backprojection tiling among the candidates, then (trees of
+  // 2-D contexts) the fastest lanes per ray of the leaf walk among 1, 2 and 4 at that tiling.
   wamct_status autotune(int n_trial, const int32_t* cand, int n_cand, int32_t* chosen) {
     err.clear();
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1224,37 +1253,35 @@ struct wamct_batch {
     wamct_status res = WAMCT_OK;
     for (size_t i = 0; i < ctx.size() && res == WAMCT_OK; ++i) {
       wamct_ctx* c = ctx[i];
-      const hipStream_t s = c->stream();
       int32_t best = c->tiling();
       float best_ms = -1.f;
       for (int k = 0; k < n_cand && res == WAMCT_OK; ++k) {
-        wamct_status r = c->set_tiling(cand[k]);
-        if (!r && c->tree_dirty_()) {
-          r = c->enq_tree(s);
-          if (!r && hipStreamSynchronize(s) != hipSuccess) r = fail(WAMCT_E_HIP, "synchronize");
-          if (!r) r = c->finish_tree(nullptr);
-        }
-        if (!r) r = c->save_state(s);
-        if (!r) r = c->enq_iteration(s, nullptr, 0, false);
-        if (!r && hipEventRecord(e0, s) != hipSuccess) r = fail(WAMCT_E_HIP, "hipEventRecord");
-        for (int t = 0; t < n_trial && !r; ++t) r = c->enq_iteration(s, nullptr, 0, false);
-        if (!r && hipEventRecord(e1, s) != hipSuccess) r = fail(WAMCT_E_HIP, "hipEventRecord");
-        if (!r) r = c->restore_state(s);
         float ms = 0.f;
-        if (!r && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-          r = fail(WAMCT_E_HIP, "trial timing failed");
-        if (r) {
-          if (err.empty()) err = c->err;
-          res = r;
-          break;
-        }
-        if (best_ms < 0 || ms < best_ms) { best_ms = ms; best = cand[k]; }
+        wamct_status r = c->set_tiling(cand[k]);
+        if (r) { err = c->err; res = r; break; }
+        res = trial(c, n_trial, e0, e1, &ms);
+        if (!res && (best_ms < 0 || ms < best_ms)) { best_ms = ms; best = cand[k]; }
       }
       if (res == WAMCT_OK) {
         wamct_status r = c->set_tiling(best);
         if (r) res = from(c, r);
       }
       if (chosen) chosen[i] = best;
+      // lanes per ray of the leaf walk (contexts that have one)
+      const int32_t auto_k = c->walk_lanes();
+      if (res == WAMCT_OK && auto_k > 0 && c->set_walk_lanes(auto_k) == WAMCT_OK) {
+        int32_t best_k = auto_k;
+        float best_kms = -1.f;
+        static const int32_t kLanes[] = {1, 2, 4};
+        for (int32_t kk : kLanes) {
+          float ms = 0.f;
+          if (c->set_walk_lanes(kk)) break;
+          res = trial(c, n_trial, e0, e1, &ms);
+          if (res) break;
+          if (best_kms < 0 || ms < best_kms) { best_kms = ms; best_k = kk; }
+        }
+        if (res == WAMCT_OK) c->set_walk_lanes(best_k);
+      }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -1373,6 +1400,13 @@ wamct_status wamct_set_subsets(wamct_ctx* ctx, int32_t n_subsets) { CTX_CALL(set
 wamct_status wamct_set_tree_sharing(wamct_ctx* ctx, int32_t shared) { CTX_CALL(set_tree_sharing(shared)); }
 wamct_status wamct_set_tree_rule(wamct_ctx* ctx, int32_t rule) { CTX_CALL(set_tree_rule(rule)); }
 wamct_status wamct_set_penalty(wamct_ctx* ctx, double lambda) { CTX_CALL(set_penalty(lambda)); }
+wamct_status wamct_set_walk_lanes(wamct_ctx* ctx, int32_t lanes) { CTX_CALL(set_walk_lanes(lanes)); }
+wamct_status wamct_get_walk_lanes(wamct_ctx* ctx, int32_t* lanes) {
+  if (!ctx) { g_last_error = "ctx is NULL"; return WAMCT_E_INVALID; }
+  if (!lanes) return ctx->fail(WAMCT_E_INVALID, "lanes must not be NULL");
+  *lanes = ctx->walk_lanes();
+  return WAMCT_OK;
+}
 wamct_status wamct_set_tree_schedule(wamct_ctx* ctx, int32_t n_trees, const int32_t* at, const uint8_t* masks) {
   CTX_CALL(set_tree_schedule(n_trees, at, masks));
 }

@@ -72,6 +72,9 @@ struct wamct_ctx {
   virtual wamct_status get_timing(double*, int64_t*) = 0;
   virtual wamct_status set_tiling(int32_t) = 0;
   virtual int32_t tiling() const = 0;
+  // lanes per ray of the leaf walk (0 = chosen by the launch size); 2-D trees only
+  virtual wamct_status set_walk_lanes(int32_t) { return fail(WAMCT_E_UNSUPPORTED, "no leaf-walk lanes to set"); }
+  virtual int32_t walk_lanes() const { return 0; }
   virtual wamct_status set_subsets(int32_t) = 0;
   virtual int32_t subsets() const = 0;
   virtual wamct_status set_tree_sharing(int32_t) = 0;

@@ -115,6 +115,9 @@ struct Launch {
   static void residual(const T* d, const T* q, const double* gscale, T* r, int64_t len, hipStream_t s);
 };
 
+// lanes per ray of the leaf walk chosen for a launch over `rays` rays (all scans)
+int leaf_pieces(int64_t rays);
+
 // Kernels whose ray arithmetic runs in R (float or double, R at least as wide as T).
 template <typename T, typename R>
 struct Geo {
@@ -130,9 +133,10 @@ struct Geo {
   static int forward(const DevGeom& g, const void* A, const void* B, const T* muR, const T* muC, const T* d,
                      const T* i0v, const double* i0s, T* q, T* p, double* part, int S, hipStream_t s);
   // leaf walk over (value, level) records read from global memory
+  // lanes: lanes per ray (1, 2 or 4; 0 = leaf_pieces of the launch's ray count)
   static int forward_records(const DevGeom& g, const void* A, const void* B, const void* leafR, const void* leafC,
                              const T* d, const T* i0v, const double* i0s, T* q, T* p, double* part, int S,
-                             hipStream_t s);
+                             hipStream_t s, int lanes = 0);
   // node-driven backprojection of y over the segments of `items` (items null: every pixel
   // as a level-0 box), over the views of g's subset. counts: per-scan level counts (stride
   // kInts; null for fixed ranges); z0 per scan at stride z0stride, held at stride kInts;

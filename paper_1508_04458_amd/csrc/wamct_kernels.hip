@@ -1376,16 +1376,18 @@ int Geo<T, R>::forward(const DevGeom& g, const void* A, const void* B, const T* 
                      (const typename V4<R>::t*)B, muR, muC, d, i0v, i0s, q, p, part);
   return nb;
 }
+// rays per lane group: a launch with fewer than 2^21 rays splits each ray over 2 lanes, one
+// with fewer than 2^17 over 4 (the GPU holds 2^19 lanes at 8 waves per SIMD; two half-length
+// walks per ray also hide more of the record-load latency, measured faster for the 737K rays
+// of a 720 x 1024 scan)
+int leaf_pieces(int64_t rays) { return rays >= (int64_t(1) << 21) ? 1 : (rays >= (int64_t(1) << 17) ? 2 : 4); }
+
 template <typename T, typename R>
 int Geo<T, R>::forward_records(const DevGeom& g, const void* A, const void* B, const void* leafR, const void* leafC,
                                const T* d, const T* i0v, const double* i0s, T* q, T* p, double* part, int S,
-                               hipStream_t s) {
-  // rays per lane group: a launch with fewer than 2^21 rays splits each ray over 2 lanes,
-  // one with fewer than 2^17 over 4 (the GPU holds 2^19 lanes at 8 waves per SIMD; two
-  // half-length walks per ray also hide more of the record-load latency, measured faster
-  // for the 737K rays of a 720 x 1024 scan)
+                               hipStream_t s, int lanes) {
   const int64_t rays = int64_t(g.nvs) * g.nb * S;
-  const int k = rays >= (int64_t(1) << 21) ? 1 : (rays >= (int64_t(1) << 17) ? 2 : 4);
+  const int k = lanes > 0 ? lanes : leaf_pieces(rays);
   const int nb = blocks_for(int64_t(g.nvs) * g.nb * k);
   auto a = (const typename V4<R>::t*)A;
   auto b = (const typename V4<R>::t*)B;

@@ -124,13 +124,15 @@ def test_batch_equals_each_context_alone(graph):
 
 
 def test_batch_matches_oracle_and_autotune_keeps_results_fp64():
-    """FP64 uneven batch after tiling autotuning: every scan matches the oracle's solve."""
+    """FP64 uneven batch after autotuning (tiling and leaf-walk lanes per ray): every scan
+    matches the oracle's solve."""
     ctxs = _uneven_contexts(5, 4, "f64")
     batch = _api().Batch([c for c, _ in ctxs], n_streams=2, graph=True)
     cand = [1 << 12, 1 << 16, 1 << 20]
     chosen = batch.autotune(1, cand)
     assert len(chosen) == len(ctxs) and all(v in cand for v in chosen)
     assert [c.tiling() for c, _ in ctxs] == chosen
+    assert all(c.walk_lanes() in (1, 2, 4) for c, _ in ctxs)     # the second, measured knob
     P0 = ctxs[0][1][0]
     out = batch.solve(N_IT, P0.schedule, 0.1)
     for (c, probs), idv in zip(ctxs, out):

@@ -436,3 +436,33 @@ def test_scan_that_misses_the_image_is_rejected():
         with pytest.raises(_lib.WamctError) as e:
             make_ctx(g, levels, "f64")
         assert e.value.status == _lib.E_INVALID and "Z0 = 0" in str(e.value)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_walk_lanes_all_match_oracle(dtype):
+    """The leaf walk cut into 1, 2 or 4 pieces per ray (the autotuner's second knob) gives
+    the oracle's projections each time; invalid lane counts are rejected."""
+    from paper_1508_04458_amd import _lib
+    P, H = problem("fan128")
+    g = P.geom
+    L = P.levels
+    beta, mask = _random_state(g, L, 21)
+    O = haar.synthesis_matrix(g.n, L)
+    p_ref = H @ (O @ beta.ravel())
+    q_ref = wam.beer_mean(P.i0, p_ref)
+    c = make_ctx(g, L, dtype, P.d, P.i0)
+    c.set_state(dev(beta.ravel(), dtype), dev(mask.ravel(), torch.uint8))
+    assert c.walk_lanes() == 4          # 46,080 rays (< 2^17): four lanes per ray by default
+    for k in (1, 2, 4):
+        c.set_walk_lanes(k)
+        assert c.walk_lanes() == k
+        q = host(c.forward()[0])
+        assert np.all(np.abs(q - q_ref) <= q_ref * proj_tol(p_ref, dtype) * 1.01 +
+                      (1e-7 if dtype == "f32" else 1e-13) * q_ref), k
+    for bad in (3, 8, -1):
+        with pytest.raises(_lib.WamctError):
+            c.set_walk_lanes(bad)
+    full = make_ctx(g, 0, dtype)
+    with pytest.raises(_lib.WamctError) as e:
+        full.set_walk_lanes(2)
+    assert e.value.status == _lib.E_UNSUPPORTED
