@@ -23,6 +23,9 @@ Iterative Image Reconstruction for X-Ray Imaging for Security Applications"
                problem (eq. 1.3 with lambda = 0), wavelet AM combined with ordered
                subsets of views (Conclusion), and z-slices sharing one tree chosen on
                the slice-summed image (Results)
+  daub.py      orthonormal Daubechies-4 wavelets with periodic boundary in the same Mallat
+               layout and tree structure (a "different wavelet type", Conclusion): Omega,
+               the 1-D basis, and an independent textbook filter bank
   vol3d.py     cone-beam 3-D Siddon H, the 3-D Haar octree and its tree rule, and the
                Results section's per-slice representation of a volume (2-D Haar of every
                z-slice, one tree grown on the slice-summed image) on the same cone rays
@@ -34,4 +37,4 @@ with; it is pinned by those invariants (monotone I-divergence, the exact reducti
 approximation-only tree to pixel AM on the coarse grid, fixed points), not by numbers
 from the paper.
 """
-from . import geometry, siddon, haar, wam  # noqa: F401
+from . import geometry, siddon, haar, wam, daub  # noqa: F401
