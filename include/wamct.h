@@ -45,6 +45,17 @@
  *            synthesizes every slice, sums the images over the slices in FP64 and splits
  *            every leaf with a pixel of the summed image above frac x its maximum (Results).
  *            n must be divisible by 2^levels, nz need not.
+ *   Daubechies-4 (wavelet = WAMCT_D4) the same Mallat layout and tree, with the orthonormal
+ *            four-tap Daubechies basis, periodic in x and y: h = (1 + r, 3 + r, 3 - r, 1 - r) /
+ *            (4 sqrt 2), r = sqrt 3, g[t] = (-1)^t h[3 - t]; level-0 scaling functions are the
+ *            pixels, phi_l,j = sum_t h[t] phi_l-1,(2j+t) mod (n >> (l-1)) and psi_l,j likewise
+ *            with g, supported on the 3 x 2^l - 2 pixels from 2^l j (mod n). Root (i, j): phi_L,i
+ *            (y) phi_L,j (x) at [i][j]; node (l, i, j): D1 = phi_l,i(y) psi_l,j(x) at [i][m+j], D2 =
+ *            psi_l,i(y) phi_l,j(x) at [m+i][j], D3 = psi_l,i(y) psi_l,j(x) at [m+i][m+j]. The tree
+ *            rule splits a leaf when the largest pixel of its block (rows [i 2^l, (i+1) 2^l),
+ *            columns likewise) exceeds frac x the image maximum. The mu of the forward pass and
+ *            of the rule is synthesized per pixel; b-hat+/- and Z0 take each ray's chords through
+ *            the basis function's support weighted by its value in each pixel.
  *   tree     the active set Z_s (footnote to eq. 1.61) is a uint8 n x n mask in Mallat
  *            layout: approximations always active; a node's three details are active
  *            together ("split"), and only if its parent is split or it is a root.
@@ -118,7 +129,13 @@ typedef struct {
                           of every z-slice (Results: "each z-slice represented by a Level 3
                           Haar" with one tree for the volume), see "per-slice" below. 3 is valid
                           for the cone beam only. */
+  int32_t wavelet;     /* WAMCT_HAAR (0) or WAMCT_D4 (1): the wavelet family of Omega. WAMCT_D4 is
+                          the orthonormal Daubechies-4 basis with periodic boundary (Conclusion:
+                          other wavelet types), see "Daubechies-4" below; it needs a parallel or
+                          fan beam, batch = 1, levels >= 1 and n >> levels >= 4. */
 } wamct_options;
+
+enum { WAMCT_HAAR = 0, WAMCT_D4 = 1 };
 
 enum {                 /* kernel classes reported by wamct_get_timing */
   WAMCT_K_SYNTH = 0,   /* mu = Omega beta over the active tree                      */

@@ -44,7 +44,8 @@ class Geometry(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("dtype", ctypes.c_int32), ("geometry", ctypes.c_int32),
-                ("batch", ctypes.c_int32), ("wavelet_dims", ctypes.c_int32)]
+                ("batch", ctypes.c_int32), ("wavelet_dims", ctypes.c_int32),
+                ("wavelet", ctypes.c_int32)]
 
 
 class WamctError(RuntimeError):

@@ -25,16 +25,20 @@ def _geometry(g) -> _lib.Geometry:
                          1, 1, 0.0)
 
 
-def _options(levels, dtype, geometry, batch=1, wavelet_dims=0):
+_WAVELETS = {"haar": 0, "d4": 1}
+
+
+def _options(levels, dtype, geometry, batch=1, wavelet_dims=0, wavelet="haar"):
     return _lib.Options(int(levels), _DT[dtype][0] if dtype in _DT else 99,
-                        _DT[geometry][0] if geometry in _DT else 99, int(batch), int(wavelet_dims))
+                        _DT[geometry][0] if geometry in _DT else 99, int(batch), int(wavelet_dims),
+                        _WAVELETS.get(wavelet, 99))
 
 
 def validate(g, levels: int, dtype: str = "f32", geometry: str = "f64", batch: int = 1,
-             wavelet_dims: int = 0) -> Optional[str]:
+             wavelet_dims: int = 0, wavelet: str = "haar") -> Optional[str]:
     """Host-only check of geometry and options; returns None when valid, else the message."""
     buf = ctypes.create_string_buffer(512)
-    opt = _options(levels, dtype, geometry, batch, wavelet_dims)
+    opt = _options(levels, dtype, geometry, batch, wavelet_dims, wavelet)
     st = lib.wamct_validate(ctypes.byref(_geometry(g)), ctypes.byref(opt), buf, 512)
     return None if st == _lib.OK else buf.value.decode()
 
@@ -49,7 +53,7 @@ class Context:
     per-scan leading dimension is left out of every returned tensor."""
 
     def __init__(self, geom, levels: int, dtype: str = "f32", device="cuda", geometry: str = "f64",
-                 batch: int = 1, wavelet_dims: int = 0):
+                 batch: int = 1, wavelet_dims: int = 0, wavelet: str = "haar"):
         if dtype not in _DT:
             raise ValueError("dtype must be 'f32' or 'f64'")
         self.geom = geom
@@ -71,10 +75,11 @@ class Context:
         self.npix = int(np.prod(self.img_shape))
         self.S = int(batch)
         self.wavelet_dims = int(wavelet_dims)
+        self.wavelet = wavelet
         self._h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream
-            opt = _options(self.levels, dtype, geometry, self.S, wavelet_dims)
+            opt = _options(self.levels, dtype, geometry, self.S, wavelet_dims, wavelet)
             check(lib.wamct_create(ctypes.byref(_geometry(geom)), ctypes.byref(opt),
                                    ctypes.c_void_p(stream), ctypes.byref(self._h)))
 

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("wamct_kernels.hip", "wamct_api.hip", "wamct_kernels3.hip",
-                                                   "wamct_api3.hip")]
+                                                   "wamct_api3.hip", "wamct_d4.hip")]
 OUT = os.path.join(HERE, "libwamct.so")
 
 FLAGS = [

@@ -61,6 +61,14 @@ std::string validate(const wamct_geometry* g, const wamct_options* o) {
   if (o->batch < 1 || o->batch > 65535) return fmt("batch = %d outside [1, 65535]", o->batch);
   if (o->wavelet_dims != 0 && o->wavelet_dims != 2)
     return fmt("wavelet_dims = %d: 2-D scans take the 2-D Haar transform (0 or 2)", o->wavelet_dims);
+  if (o->wavelet != WAMCT_HAAR && o->wavelet != WAMCT_D4) return fmt("unknown wavelet %d", o->wavelet);
+  if (o->wavelet == WAMCT_D4) {
+    if (o->levels < 1) return "Daubechies-4 needs levels >= 1";
+    if ((g->n >> o->levels) < 4)
+      return fmt("Daubechies-4 needs n >> levels >= 4 (n = %d, levels = %d): a support must not wrap onto itself",
+                 g->n, o->levels);
+    if (o->batch != 1) return fmt("Daubechies-4 is implemented for one scan per context (batch = %d)", o->batch);
+  }
   return "";
 }
 }  // namespace
@@ -115,6 +123,10 @@ struct Ctx final : wamct_ctx {
   int32_t iters = 0;
   int target_lanes = kTargetLanes;
   int walk_k = 0;             // lanes per ray of the leaf walk (0: by launch size)
+  // Daubechies-4 basis (wavelet = WAMCT_D4): basis tables and the per-ray Z0 sums
+  bool d4 = false;
+  D4Dev tb{};
+  double* zsum = nullptr;
   // timing
   uint32_t timing_mask = 0;   // bit k: record kernel class k
   struct Rec { int kind; hipEvent_t a, b; };
@@ -145,10 +157,13 @@ struct Ctx final : wamct_ctx {
   wamct_status set_walk_lanes(int32_t k) override {
     if (k != 0 && k != 1 && k != 2 && k != 4) return fail(WAMCT_E_INVALID, fmt("walk lanes %d not in {0, 1, 2, 4}", k));
     if (g.L == 0) return fail(WAMCT_E_UNSUPPORTED, "levels = 0 walks pixels, one lane per ray");
+    if (d4) return fail(WAMCT_E_UNSUPPORTED, "the Daubechies-4 forward pass walks pixels, one lane per ray");
     walk_k = k;
     return WAMCT_OK;
   }
-  int32_t walk_lanes() const override { return g.L == 0 ? 0 : walk_k > 0 ? walk_k : leaf_pieces(M * P); }
+  int32_t walk_lanes() const override {
+    return g.L == 0 || d4 ? 0 : walk_k > 0 ? walk_k : leaf_pieces(M * P);
+  }
   void count_iters(int k) override { iters += k; }
 
   template <typename Q>
@@ -306,6 +321,7 @@ struct Ctx final : wamct_ctx {
     return WAMCT_OK;
   }
   wamct_status set_subsets(int32_t ns) override {
+    if (ns > 1 && d4) return fail(WAMCT_E_UNSUPPORTED, "ordered subsets are not implemented for Daubechies-4");
     if (ns > 1 && lam > 0.0)
       return fail(WAMCT_E_UNSUPPORTED, "ordered subsets are not implemented with the roughness penalty");
     if (ns < 1 || ns > g.nv) return fail(WAMCT_E_INVALID, fmt("n_subsets = %d outside [1, n_views = %d]", ns, g.nv));
@@ -341,6 +357,8 @@ struct Ctx final : wamct_ctx {
     if (r != WAMCT_RULE_VALUE && r != WAMCT_RULE_GRADIENT) return fail(WAMCT_E_INVALID, fmt("unknown tree rule %d", r));
     if (r == WAMCT_RULE_GRADIENT && shared_tree)
       return fail(WAMCT_E_UNSUPPORTED, "the residual-gradient rule is not implemented for slices sharing one tree");
+    if (r == WAMCT_RULE_GRADIENT && d4)
+      return fail(WAMCT_E_UNSUPPORTED, "the residual-gradient rule is not implemented for Daubechies-4");
     HIPCHK(hipStreamSynchronize(st));
     rule = r;
     return WAMCT_OK;
@@ -350,6 +368,7 @@ struct Ctx final : wamct_ctx {
     if (!(l >= 0.0) || !std::isfinite(l)) return fail(WAMCT_E_INVALID, "the penalty weight must be finite and >= 0");
     if (l > 0.0 && n_sub > 1)
       return fail(WAMCT_E_UNSUPPORTED, "the roughness penalty is not implemented with ordered subsets");
+    if (l > 0.0 && d4) return fail(WAMCT_E_UNSUPPORTED, "the roughness penalty is not implemented for Daubechies-4");
     HIPCHK(hipStreamSynchronize(st));
     if (l > 0.0 && !gpen) CHECKED(alloc(gpen, NN * P));
     lam = l;
@@ -358,6 +377,7 @@ struct Ctx final : wamct_ctx {
   double penalty() const override { return lam; }
   wamct_status set_tree_sharing(int32_t on) override {
     if (on != 0 && on != 1) return fail(WAMCT_E_INVALID, "shared must be 0 or 1");
+    if (on == 1 && d4) return fail(WAMCT_E_UNSUPPORTED, "tree sharing is not implemented for Daubechies-4");
     if (on == 1 && rule == WAMCT_RULE_GRADIENT)
       return fail(WAMCT_E_UNSUPPORTED, "the residual-gradient rule is not implemented for slices sharing one tree");
     shared_tree = on == 1;
@@ -452,6 +472,7 @@ struct Ctx final : wamct_ctx {
     nb_rays = int((M + 255) / 256);
     nb_pix = int((NN + 255) / 256);
     np = std::max(4 * nb_rays, nb_pix) + 1;   // the tree walk may use 4 lanes per ray
+    d4 = O.wavelet == WAMCT_D4;
     if (hipHostMalloc((void**)&h_ints, sizeof(int) * kInts * P, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&h_scal, sizeof(double) * kScal * P, hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
@@ -466,9 +487,22 @@ struct Ctx final : wamct_ctx {
     CHECKED(alloc(d, M * P)); CHECKED(alloc(i0v, M * P)); CHECKED(alloc(q, M * P));
     CHECKED(alloc(beta, NN * P)); CHECKED(alloc(b, NN * P));
     CHECKED(alloc(mu, NN * P)); CHECKED(alloc(muT, NN * P)); CHECKED(alloc(img, NN));
-    if (g.L > 0) {
+    if (g.L > 0 && !d4) {
       CHECKED(alloc_bytes(leafR, sizeof(T) * size_t(NN * P)));
       CHECKED(alloc_bytes(leafC, sizeof(T) * size_t(NN * P)));
+    }
+    if (d4) {
+      std::vector<double> hf, hg;
+      d4_tables(g.L, hf, hg, tb);
+      double *df = nullptr, *dg = nullptr;
+      CHECKED(alloc(df, int64_t(hf.size())));
+      CHECKED(alloc(dg, int64_t(hg.size())));
+      HIPCHK(hipMemcpyAsync(df, hf.data(), sizeof(double) * hf.size(), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(dg, hg.data(), sizeof(double) * hg.size(), hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+      tb.f = df;
+      tb.g = dg;
+      CHECKED(alloc(zsum, M));
     }
     CHECKED(alloc(mask, NN * P)); CHECKED(alloc(mask_old, NN * P)); CHECKED(alloc(lev, NN * P));
     CHECKED(alloc(items, NN * P)); CHECKED(alloc(mu64, NN * P));
@@ -539,7 +573,8 @@ struct Ctx final : wamct_ctx {
       Scope sc(this, WAMCT_K_OTHER, st);
       for (int p = 0; p < P; ++p) {
         CHECKED(gather(kPlain, d + p * M, pix_segs, 1, nullptr, nullptr, nullptr, nullptr, img, st));
-        Launch<T>::analysis(g, img, b + p * NN, st);
+        if (d4) D4<T, R>::analysis(g, tb, img, b + p * NN, st);
+        else Launch<T>::analysis(g, img, b + p * NN, st);
       }
       if (n_sub > 1) CHECKED(precompute_bsub(st));
     }
@@ -552,7 +587,18 @@ struct Ctx final : wamct_ctx {
   // Work list, leaf levels, Z0 and W of every scan's tree, then a copy of the per-scan
   // counters and scalars to pinned host memory (read by finish_tree once s has finished).
   wamct_status enq_tree(hipStream_t s) override {
-    {
+    if (d4) {
+      // Z0 (eq. 1.61): per-ray sums of |phi| over the work list's coefficients, then the
+      // largest; W: the non-zero (ray, coefficient) pairs per item, summed (mu64 holds them)
+      Scope sc(this, WAMCT_K_TREE, s);
+      build_items(g, mask, items, ints + 8, P, list_tmp, s);
+      Launch<double>::fill(zsum, M, 0.0, s);
+      Launch<double>::fill(mu64, NN, 0.0, s);
+      D4<T, R>::gather(g, kD4Z0, tb, views, A, B, nullptr, items, ints + 8, int(NN), nullptr, nullptr, nullptr,
+                       nullptr, nullptr, nullptr, zsum, mu64, s);
+      reduce_stack(true, zsum, int(M), M, scal + 0, kScal, nullptr, 1, s);
+      reduce_stack(false, mu64, int(NN), NN, scal + 1, kScal, nullptr, 1, s);
+    } else {
       Scope sc(this, WAMCT_K_TREE, s);
       build_items(g, mask, items, ints + 8, P, list_tmp, s);
       Launch<T>::levmap(g, mask, lev, P, s);
@@ -642,6 +688,16 @@ struct Ctx final : wamct_ctx {
   // (over the views of gg; partials of the I-divergence only when `pd` is not null)
   int forward_pass(hipStream_t s, const DevGeom& gg, double* pd) {
     const T* iv = i0v_used ? i0v : nullptr;
+    if (d4) {
+      // Daubechies-4: mu is not constant on the leaves; synthesize it per pixel (both
+      // layouts) and project with the pixel walk
+      {
+        Scope sc(this, WAMCT_K_SYNTH, s);
+        D4<T, R>::synth(g, tb, beta, mu, muT, s);
+      }
+      Scope sc(this, WAMCT_K_FORWARD, s);
+      return Geo<T, R>::forward(gg, A, B, mu, muT, d, iv, scal + 4, q, nullptr, pd, P, s);
+    }
     if (g.L > 0) {
       {
         Scope sc(this, WAMCT_K_SYNTH, s);
@@ -684,6 +740,16 @@ struct Ctx final : wamct_ctx {
     }
     const int nbk = forward_pass(s);
     store_idiv(nbk, out, ostride, counted, s);
+    if (d4) {
+      {
+        Scope sc(this, WAMCT_K_UPDATE, s);
+        D4<T, R>::gather(g, kD4Update, tb, views, A, B, q, items, ints + 8, int(NN), beta, b, scal + 0, ints + 0,
+                         nullptr, nullptr, nullptr, nullptr, s);
+      }
+      ++iters;
+      LAUNCHED();
+      return WAMCT_OK;
+    }
     if (lam > 0.0) {
       // gradient of the roughness penalty at beta-hat for every coefficient:
       // Omega^T grad R(Omega beta-hat) (mu and part2 are free at this point of an iteration)
@@ -724,6 +790,20 @@ struct Ctx final : wamct_ctx {
   // a shared tree the rule runs once, on the image summed over the stack's slices, and the
   // resulting tree is copied to every slice.
   wamct_status enq_expand(hipStream_t s, double frac) override {
+    if (d4) {
+      // the Results rule on the per-pixel FP64 image: a leaf splits when the largest pixel
+      // of its block exceeds frac x the maximum
+      {
+        Scope sc(this, WAMCT_K_TREE, s);
+        const int nbk = D4<T, R>::mu64(g, tb, beta, mu64, partd, s);
+        reduce_stack(true, partd, nbk, nbk, scal + 2, kScal, nullptr, 1, s);
+        HIPCHK(hipMemcpyAsync(mask_old, mask, NN, hipMemcpyDeviceToDevice, s));
+        fill_i32_strided(ints + 2, 1, kInts, 0, s);
+        expand(g, mask_old, mask, mu64, scal + 2, frac, ints + 2, 1, s, 2);
+      }
+      LAUNCHED();
+      return enq_tree(s);
+    }
     if (g.L > 0 && shared_tree && P > 1) {
       {
         Scope sc(this, WAMCT_K_TREE, s);
@@ -832,7 +912,8 @@ struct Ctx final : wamct_ctx {
   wamct_status synthesize(void* out) override {
     if (!out) return fail(WAMCT_E_INVALID, "mu must not be NULL");
     Scope sc(this, WAMCT_K_SYNTH, st);
-    Launch<T>::synth(g, beta, (T*)out, P, st);
+    if (d4) D4<T, R>::synth(g, tb, beta, (T*)out, nullptr, st);
+    else Launch<T>::synth(g, beta, (T*)out, P, st);
     LAUNCHED();
     return WAMCT_OK;
   }
@@ -860,7 +941,11 @@ struct Ctx final : wamct_ctx {
     Scope sc(this, WAMCT_K_OTHER, st);
     Launch<T>::fill((T*)bp, NN * P, T(0), st);
     Launch<T>::fill((T*)bm, NN * P, T(0), st);
-    CHECKED(gather(kSplit, (const T*)y, segs, P, nullptr, nullptr, (T*)bp, (T*)bm, nullptr, st));
+    if (d4)
+      D4<T, R>::gather(g, kD4Split, tb, views, A, B, (const T*)y, items, ints + 8, int(NN), nullptr, nullptr,
+                       nullptr, nullptr, (T*)bp, (T*)bm, nullptr, nullptr, st);
+    else
+      CHECKED(gather(kSplit, (const T*)y, segs, P, nullptr, nullptr, (T*)bp, (T*)bm, nullptr, st));
     LAUNCHED();
     return WAMCT_OK;
   }
@@ -933,7 +1018,8 @@ struct Ctx final : wamct_ctx {
       T* qk = (T*)qout + size_t(k) * M;
       {
         Scope sc(this, WAMCT_K_SYNTH, st);
-        Launch<T>::synth_layouts(g, ck, mu, muT, 1, st);
+        if (d4) D4<T, R>::synth(g, tb, ck, mu, muT, st);
+        else Launch<T>::synth_layouts(g, ck, mu, muT, 1, st);
       }
       int nbk;
       {
@@ -959,7 +1045,8 @@ struct Ctx final : wamct_ctx {
       Launch<T>::residual((const T*)dd + size_t(k) * M, (const T*)qq + size_t(k) * M, gscale ? gscale + k : nullptr,
                           q, M, st);
       CHECKED(gather(kPlain, q, pix_segs, 1, nullptr, nullptr, nullptr, nullptr, img, st));
-      Launch<T>::analysis(g, img, (T*)grad + size_t(k) * NN, st);
+      if (d4) D4<T, R>::analysis(g, tb, img, (T*)grad + size_t(k) * NN, st);
+      else Launch<T>::analysis(g, img, (T*)grad + size_t(k) * NN, st);
     }
     LAUNCHED();
     return WAMCT_OK;

@@ -33,6 +33,8 @@ std::string validate3(const wamct_geometry* g, const wamct_options* o) {
   if (o->levels < 0 || o->levels > 4) return fmt("cone beam: levels = %d outside [0, 4]", o->levels);
   if (o->wavelet_dims != 0 && o->wavelet_dims != 2 && o->wavelet_dims != 3)
     return fmt("cone beam: wavelet_dims = %d outside {0, 2, 3}", o->wavelet_dims);
+  if (o->wavelet != WAMCT_HAAR)
+    return fmt("cone beam: wavelet = %d, only the Haar basis (0) is implemented for the cone beam", o->wavelet);
   if (o->wavelet_dims == 2) {
     if (g->n % (1 << o->levels)) return fmt("n = %d must be divisible by 2^levels = %d", g->n, 1 << o->levels);
   } else if (g->n % (1 << o->levels) || g->nz % (1 << o->levels)) {

@@ -1,7 +1,10 @@
 // Internal interface between the C ABI (wamct_api.hip) and the kernels (wamct_kernels.hip).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
+
+#include <vector>
 
 namespace wamct {
 
@@ -51,6 +54,26 @@ __device__ inline R ordered_sum(const R* __restrict__ x, int n, size_t stride) {
   }
   for (; c < n; ++c) s += x[size_t(c) * stride];
   return s;
+}
+
+// Positive root t of bp t^2 - b t + bm = 0 (eq. 1.9 with t = exp(-Z0 (beta - beta_hat)))
+// -> delta = -ln(t) / Z0. Cases (bp >= 0 >= bm): bp > 0 uses the cancellation-free form
+// of the quadratic root; bp = 0 > bm is linear (t = bm / b); bp = bm = 0 means no ray sees
+// the coefficient (delta = 0). No finite minimizer (t <= 0): hold and count.
+template <typename R>
+__device__ inline R am_delta(R b, R bp, R bm, R z0, int* held) {
+  R t;
+  if (bp > R(0)) {
+    const R s = sqrt(fmax(b * b - R(4) * bp * bm, R(0)));
+    t = b >= R(0) ? (b + s) / (R(2) * bp) : (R(2) * bm) / (b - s);
+  } else if (bm < R(0)) {
+    t = bm / b;
+  } else {
+    return R(0);
+  }
+  if (t > R(0) && isfinite(t)) return -log(t) / z0;
+  atomicAdd(held, 1);
+  return R(0);
 }
 
 // A run of work items of one level, processed with its views split into `chunks` ranges
@@ -147,6 +170,38 @@ struct Geo {
                      int S, hipStream_t s, const T* gpen = nullptr, double lam = 0.0);
 };
 
+// Daubechies-4 (periodic) basis tables on the device: per level l (1..L) the samples of the
+// scaling function (f) and of the wavelet (g) at position 0, offsets 0 .. len[l] - 1 from the
+// function's first pixel (len = 3 x 2^l - 2), starting at f + off[l] and g + off[l]. The
+// function at position j is the same samples shifted by 2^l j (mod n).
+struct D4Dev {
+  const double* f;
+  const double* g;
+  int off[kMaxLevels + 1];
+  int len[kMaxLevels + 1];
+};
+// Host samples of the tables (f, g concatenated over l = 1..L) and their offsets and lengths.
+void d4_tables(int L, std::vector<double>& f, std::vector<double>& g, D4Dev& tb);
+// Modes of the Daubechies-4 gather.
+enum D4Mode { kD4Split = 0, kD4Update = 1, kD4Z0 = 2 };
+template <typename T, typename R>
+struct D4 {
+  // mu = Omega beta in row-major muR and, when muC is not null, column-major muC (one scan)
+  static void synth(const DevGeom& g, const D4Dev& tb, const T* beta, T* muR, T* muC, hipStream_t s);
+  // FP64 mu = Omega beta and per-block maxima. Returns the number of blocks.
+  static int mu64(const DevGeom& g, const D4Dev& tb, const T* beta, double* mu64, double* part, hipStream_t s);
+  // coef = Omega^T img (FP64 accumulation)
+  static void analysis(const DevGeom& g, const D4Dev& tb, const T* img, T* coef, hipStream_t s);
+  // Node-driven backprojection of y over the work list (n_items read on the device, at most
+  // max_items): kD4Split -> bp, bm; kD4Update -> beta += the eq. 1.9 zero (b, z0, held);
+  // kD4Z0 -> zsum[ray] += sum |phi| over the list's coefficients (zsum zeroed by the caller)
+  // and cnt[item] = number of non-zero phi of the item. A, B: the ray table of Geo.
+  static void gather(const DevGeom& g, int mode, const D4Dev& tb, const double2* views, const void* A,
+                     const void* B, const T* y, const uint32_t* items, const int* n_items, int max_items, T* beta,
+                     const T* b, const double* z0, int* held, T* bp, T* bm, double* zsum, double* cnt,
+                     hipStream_t s);
+};
+
 // Z0 and W of the current tree: per-ray FP64 sums of |phi| over active coefficients and
 // counts of phi != 0; per-block partial max / sum. Returns the blocks per scan.
 int z0_partials(const DevGeom& g, const double2* views, const uint8_t* lev, double* part_max,
@@ -172,7 +227,8 @@ void build_items(const DevGeom& g, const uint8_t* mask, uint32_t* items, int* co
                  hipStream_t s);
 // Tree rule: split every leaf of mask_old whose value exceeds frac * max (maxv at stride
 // kScal, n_split at stride kInts). rule 0: the FP64 image mu64 (leaf-constant); rule 1: the
-// leaf scores of grad_scores held in mu64 at each node's first detail position.
+// leaf scores of grad_scores held in mu64 at each node's first detail position; rule 2: the
+// largest pixel of mu64 over the leaf's block (images not constant on the leaves).
 void expand(const DevGeom& g, const uint8_t* mask_old, uint8_t* mask, const double* mu64,
             const double* maxv, double frac, int* n_split, int S, hipStream_t s, int rule = 0);
 // Sum of the FP64 images of S slices into slice 0 (slice order) and per-block maxima of the

@@ -538,26 +538,6 @@ __global__ __launch_bounds__(kBlock) void k_idiv_terms(int M, const T* __restric
 
 // ------------------------------------------------------------------ node-driven gather
 
-// Positive root t of bp t^2 - b t + bm = 0 (eq. 1.9 with t = exp(-Z0 (beta - beta_hat)))
-// -> delta = -ln(t) / Z0. Cases (bp >= 0 >= bm): bp > 0 uses the cancellation-free form
-// of the quadratic root; bp = 0 > bm is linear (t = bm / b); bp = bm = 0 means no ray sees
-// the coefficient (delta = 0). No finite minimizer (t <= 0): hold and count.
-template <typename R>
-__device__ inline R am_delta(R b, R bp, R bm, R z0, int* held) {
-  R t;
-  if (bp > R(0)) {
-    const R s = sqrt(fmax(b * b - R(4) * bp * bm, R(0)));
-    t = b >= R(0) ? (b + s) / (R(2) * bp) : (R(2) * bm) / (b - s);
-  } else if (bm < R(0)) {
-    t = bm / b;
-  } else {
-    return R(0);
-  }
-  if (t > R(0) && isfinite(t)) return -log(t) / z0;
-  atomicAdd(held, 1);
-  return R(0);
-}
-
 // Sums of one work item over a range of views. For every view the item's box is projected
 // onto the detector (its four corners bound the bins whose rays can hit it; FP32 suffices
 // for this bound, which is widened by 1e-3 bin), and for each such ray the chord through
@@ -1186,7 +1166,8 @@ __global__ __launch_bounds__(kBlock) void k_residual_inplace(int64_t len, const 
 
 // Tree rule: rule 0 (Results) splits leaves whose leaf-constant value mu64 exceeds frac x max;
 // rule 1 (residual gradient) splits leaves whose score (k_grad_scores, in `val`) exceeds
-// frac x max score.
+// frac x max score; rule 2 (the Results rule for bases that are not constant on the leaves)
+// splits leaves with any pixel of mu64 above frac x max.
 __global__ __launch_bounds__(kBlock) void k_expand(DevGeom g, const uint8_t* __restrict__ old,
                                                    uint8_t* __restrict__ mask, const double* __restrict__ mu64,
                                                    const double* __restrict__ maxv, double frac,
@@ -1214,8 +1195,18 @@ __global__ __launch_bounds__(kBlock) void k_expand(DevGeom g, const uint8_t* __r
   if (is_split(old, n, l, i, j)) return;
   if (l < g.L && !is_split(old, n, l + 1, i >> 1, j >> 1)) return;
   const int s = 1 << l;
-  // rule 0: leaf-constant value (any pixel of the block); rule 1: the node's score
-  const double val = rule == 0 ? mu64[(i * s) * n + j * s] : mu64[i * n + m + j];
+  // rule 0: leaf-constant value (any pixel of the block); rule 1: the node's score; rule 2:
+  // the block's largest pixel
+  double val;
+  if (rule == 1) {
+    val = mu64[i * n + m + j];
+  } else if (rule == 2) {
+    val = -INFINITY;
+    for (int r = i * s; r < (i + 1) * s; ++r)
+      for (int c = j * s; c < (j + 1) * s; ++c) val = fmax(val, mu64[int64_t(r) * n + c]);
+  } else {
+    val = mu64[(i * s) * n + j * s];
+  }
   if (val > frac * top) {
     mask[i * n + m + j] = 1;
     mask[(m + i) * n + j] = 1;

@@ -122,3 +122,19 @@ def test_idiv_noalloc_rejects_bad_sizes_on_the_host(lib):
                  (lib.F32, 256 * 4096, 257, x, x, x)):
         assert L.wamct_idiv_noalloc(*args, None) == lib.E_INVALID, args
     assert b"static buffer" in L.wamct_last_error(None)
+
+
+def test_d4_validation_on_the_host(lib):
+    """Daubechies-4 options: accepted for 2-D scans with n >> levels >= 4; rejected (with the
+    reason) for levels 0, wrapping supports, stacks, the cone beam and unknown families."""
+    from paper_1508_04458_amd import api
+    fan = synth.fan_geometry(96, 75, 131)
+    assert api.validate(fan, 3, "f32", wavelet="d4") is None
+    assert api.validate(synth.parallel_geometry(64, 90, 96, 1.0), 4, "f64", wavelet="d4") is None
+    for args, kw, needle in (((fan, 0, "f32"), {}, "levels >= 1"),
+                             ((synth.parallel_geometry(64, 90, 96, 1.0), 5, "f32"), {}, "n >> levels >= 4"),
+                             ((fan, 2, "f32", "f64", 2), {}, "one scan per context"),
+                             ((synth.CONE_CONFIGS["cone32"]["geom"](), 1, "f32"), {}, "only the Haar basis")):
+        msg = api.validate(*args, wavelet="d4", **kw)
+        assert msg is not None and needle in msg, msg
+    assert "unknown wavelet" in api.validate(fan, 2, "f32", wavelet="coiflet")
