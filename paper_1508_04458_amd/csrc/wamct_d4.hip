@@ -144,68 +144,64 @@ __global__ __launch_bounds__(kD4Block) void k_d4_analysis(int n, int L, D4Dev tb
   coef[p] = T(acc);
 }
 
-// The sums of one ray through one node's support: vals[0..3] = the projections of phi phi
-// (approximation), phi_y psi_x (D1), psi_y phi_x (D2), psi_y psi_x (D3) along the ray: the ray
-// is clipped to the support (up to four boxes where the support wraps at the border) and
-// walked pixel by pixel (plane crossings in parameter order), each chord weighted by the basis
-// values at the pixel holding the chord's midpoint.
-template <typename R>
-__device__ inline void d4_ray(const DevGeom& g, const D4Dev& tb, int l, int x0, int y0, double ox, double oy,
-                              double ex, double ey, double iex, double iey, double vals[4]) {
-  const int n = g.n, len = tb.len[l];
-  const double pix = g.pixel, hn = 0.5 * n;
-  const double* F = tb.f + tb.off[l];
-  const double* G = tb.g + tb.off[l];
-  vals[0] = vals[1] = vals[2] = vals[3] = 0.0;
-  for (int pyk = 0; pyk < 2; ++pyk) {
-    // y piece: pixel rows [ya, yb) of the image, support offsets from oyoff
-    const int ys = y0, ye = y0 + len;
-    int ya, yb, oyoff;
-    if (pyk == 0) { ya = ys; yb = ye < n ? ye : n; oyoff = 0; }
-    else { if (ye <= n) break; ya = 0; yb = ye - n; oyoff = n - ys; }
-    for (int pxk = 0; pxk < 2; ++pxk) {
-      const int xs = x0, xe = x0 + len;
-      int xa, xb, oxoff;
-      if (pxk == 0) { xa = xs; xb = xe < n ? xe : n; oxoff = 0; }
-      else { if (xe <= n) break; xa = 0; xb = xe - n; oxoff = n - xs; }
-      const double X0 = (xa - hn) * pix, X1 = (xb - hn) * pix, Y0 = (ya - hn) * pix, Y1 = (yb - hn) * pix;
-      const double tx0 = (X0 - ox) * iex, tx1 = (X1 - ox) * iex, ty0 = (Y0 - oy) * iey, ty1 = (Y1 - oy) * iey;
-      const double t_in = fmax(fmin(tx0, tx1), fmin(ty0, ty1));
-      const double t_out = fmin(fmax(tx0, tx1), fmax(ty0, ty1));
-      if (!(t_out > t_in)) continue;
-      // interior planes in parameter order: x planes xa+1 .. xb-1, y planes ya+1 .. yb-1
-      const bool xpos = iex > 0.0, ypos = iey > 0.0;
-      int kx = xpos ? xa + 1 : xb - 1, ky = ypos ? ya + 1 : yb - 1;
-      const int kx_end = xpos ? xb : xa, ky_end = ypos ? yb : ya;
-      double t = t_in;
-      for (int step = 0; step < 2 * len + 4; ++step) {
-        const double tx = kx != kx_end ? ((kx - hn) * pix - ox) * iex : INFINITY;
-        const double ty = ky != ky_end ? ((ky - hn) * pix - oy) * iey : INFINITY;
-        const double te = fmax(fmin(fmin(tx, ty), t_out), t);
-        const double c = te - t;
-        if (c > 0.0) {
-          const double tm = t + 0.5 * c;
-          int px = int(floor((ox + tm * ex) / pix + hn)), py = int(floor((oy + tm * ey) / pix + hn));
-          px = px < xa ? xa : (px > xb - 1 ? xb - 1 : px);
-          py = py < ya ? ya : (py > yb - 1 ? yb - 1 : py);
-          const int offx = px - xa + oxoff, offy = py - ya + oyoff;
-          const double fx = F[offx], gx = G[offx], fy = F[offy], gy = G[offy];
-          vals[0] += c * fy * fx;
-          vals[1] += c * fy * gx;
-          vals[2] += c * gy * fx;
-          vals[3] += c * gy * gx;
-        }
-        if (te >= t_out) break;
-        if (tx <= ty) kx += xpos ? 1 : -1;
-        else ky += ypos ? 1 : -1;
-        t = te;
-      }
+// One ray through one rectangle of pixels [xa, xb) x [ya, yb) of a basis function's support
+// (table offsets of pixel (px, py): px - xa + oxoff, py - ya + oyoff): v[0..3] += the chord in
+// every pixel times phi(y) phi(x), phi(y) psi(x), psi(y) phi(x), psi(y) psi(x). The ray is
+// clipped to the rectangle (slab test), the entry pixel taken on the side the ray moves into,
+// and the walk steps to the nearer of the next x and y planes, each plane parameter computed
+// directly from its index (no accumulated error); a segment whose end lies before its start
+// (an entry pixel one off at a corner) adds nothing and moves on. Basis values change only
+// when the walk crosses a plane of their axis.
+__device__ inline void d4_piece(double ox, double oy, double ex, double ey, double iex, double iey, int xa,
+                                int xb, int ya, int yb, int oxoff, int oyoff, const double* __restrict__ F,
+                                const double* __restrict__ G, double pix, double ipix, double hn, double v[4]) {
+  const double tx0 = ((xa - hn) * pix - ox) * iex, tx1 = ((xb - hn) * pix - ox) * iex;
+  const double ty0 = ((ya - hn) * pix - oy) * iey, ty1 = ((yb - hn) * pix - oy) * iey;
+  const double t_in = fmax(fmin(tx0, tx1), fmin(ty0, ty1));
+  const double t_out = fmin(fmax(tx0, tx1), fmax(ty0, ty1));
+  if (!(t_out > t_in)) return;
+  const bool xp = iex > 0.0, yp = iey > 0.0;
+  const double fx = (ox + t_in * ex) * ipix + hn, fy = (oy + t_in * ey) * ipix + hn;
+  int px = xp ? int(floor(fx)) : int(ceil(fx)) - 1;
+  int py = yp ? int(floor(fy)) : int(ceil(fy)) - 1;
+  px = px < xa ? xa : (px > xb - 1 ? xb - 1 : px);
+  py = py < ya ? ya : (py > yb - 1 ? yb - 1 : py);
+  const int dx = xp ? 1 : -1, dy = yp ? 1 : -1, nx = xp ? 1 : 0, ny = yp ? 1 : 0;
+  double txn = ((px + nx - hn) * pix - ox) * iex, tyn = ((py + ny - hn) * pix - oy) * iey;
+  double fxv = F[px - xa + oxoff], gxv = G[px - xa + oxoff];
+  double fyv = F[py - ya + oyoff], gyv = G[py - ya + oyoff];
+  double t = t_in;
+  const int steps = (xb - xa) + (yb - ya);
+  for (int k = 0; k < steps; ++k) {
+    const double te = fmin(fmin(txn, tyn), t_out);
+    const double c = te - t;
+    if (c > 0.0) {
+      const double cy = c * fyv, cg = c * gyv;
+      v[0] += cy * fxv;
+      v[1] += cy * gxv;
+      v[2] += cg * fxv;
+      v[3] += cg * gxv;
+      t = te;
+    }
+    if (te >= t_out) break;
+    if (txn <= tyn) {
+      px += dx;
+      if (px < xa || px >= xb) break;
+      txn = ((px + nx - hn) * pix - ox) * iex;
+      fxv = F[px - xa + oxoff];
+      gxv = G[px - xa + oxoff];
+    } else {
+      py += dy;
+      if (py < ya || py >= yb) break;
+      tyn = ((py + ny - hn) * pix - oy) * iey;
+      fyv = F[py - ya + oyoff];
+      gyv = G[py - ya + oyoff];
     }
   }
 }
 
 // Bin range of view v whose rays can meet the box [X0, X1) x [Y0, Y1) (mm): projections of the
-// four corners on the detector, widened by 1e-3 bin.
+// four corners on the detector, widened by 1e-3 bin; empty when lo > hi.
 __device__ inline void d4_bins(const DevGeom& g, double2 cs, double X0, double X1, double Y0, double Y1, int& lo,
                                int& hi) {
   double umin = 1e300, umax = -1e300;
@@ -222,108 +218,162 @@ __device__ inline void d4_bins(const DevGeom& g, double2 cs, double X0, double X
     umax = fmax(umax, u);
   }
   const double c0 = 0.5 * (g.nb - 1);
-  lo = int(ceil(umin / g.pitch + c0 - 1e-3));
-  hi = int(floor(umax / g.pitch + c0 + 1e-3));
-  lo = lo < 0 ? 0 : lo;
-  hi = hi > g.nb - 1 ? g.nb - 1 : hi;
+  const double flo = fmin(fmax(umin / g.pitch + c0 - 1e-3, -1.0), double(g.nb));
+  const double fhi = fmin(fmax(umax / g.pitch + c0 + 1e-3, -1.0), double(g.nb));
+  lo = max(int(ceil(flo)), 0);
+  hi = min(int(floor(fhi)), g.nb - 1);
 }
 
-// One lane per work item (a root: its approximation, and its three details when split; a
-// split node: its three details), over every view. kD4Split: b-hat+ and b-hat- of the item's
-// coefficients (eq. 1.10; the sign split per (ray, coefficient), |phi| <= 1e-12 pixel counted
-// as 0) into bp and bm; kD4Update: the same sums, then the zero of eq. 1.9 (beta += delta);
-// kD4Z0: per ray, sum |phi| over the item's coefficients added to zsum[ray] (atomics: eq.
-// 1.61 needs each ray's total over all items) and the item's number of non-zero (ray,
-// coefficient) pairs into cnt[item].
+constexpr int kD4Waves = kD4Block / 64;
+
+// Rectangle q (0 .. count - 1) of a support of len x len pixels from (x0, y0), wrapped at the
+// border n: q enumerates (upper or wrapped part in y) x (left or wrapped part in x), the
+// wrapped parts present only when the support passes the border (wx, wy).
+struct D4Rect {
+  int xa, xb, ya, yb, ox, oy;
+};
+__device__ inline D4Rect d4_rect(int q, int x0, int y0, int len, int n, bool wx) {
+  const int qx = wx ? (q & 1) : 0, qy = wx ? (q >> 1) : q;
+  D4Rect r;
+  r.ya = qy == 0 ? y0 : 0;
+  r.yb = qy == 0 ? min(y0 + len, n) : y0 + len - n;
+  r.oy = qy == 0 ? 0 : n - y0;
+  r.xa = qx == 0 ? x0 : 0;
+  r.xb = qx == 0 ? min(x0 + len, n) : x0 + len - n;
+  r.ox = qx == 0 ? 0 : n - x0;
+  return r;
+}
+// Whether the line (origin o, inverse direction ie) crosses the rectangle (mm bounds).
+__device__ inline bool d4_hits(const D4Rect& r, double ox, double oy, double iex, double iey, double pix,
+                               double hn) {
+  const double tx0 = ((r.xa - hn) * pix - ox) * iex, tx1 = ((r.xb - hn) * pix - ox) * iex;
+  const double ty0 = ((r.ya - hn) * pix - oy) * iey, ty1 = ((r.yb - hn) * pix - oy) * iey;
+  return fmin(fmax(tx0, tx1), fmax(ty0, ty1)) > fmax(fmin(tx0, tx1), fmin(ty0, ty1));
+}
+
+// One wave per work item (a root: its approximation, and its three details when split; a split
+// node: its three details); lane k takes the views k, k + 64, ... and the wave's sums are
+// combined by a fixed butterfly (deterministic). The support of the item's functions (len x
+// len pixels from (2^l i, 2^l j), wrapped at the border into up to four rectangles) is
+// projected per view to a bin range per rectangle; a ray is taken in the loop of the first
+// rectangle it crosses (exact slab test) and walked through that rectangle and the later ones.
+// kD4Split: b-hat+ and b-hat- of the item's coefficients (eq. 1.10; sign split per (ray,
+// coefficient); |phi| <= 1e-12 pixel counted as 0) into bp and bm; kD4Update: the same sums,
+// then the zero of eq. 1.9 (beta += delta); kD4Z0: per ray, sum |phi| over the item's
+// coefficients added to zsum[ray] (atomics: eq. 1.61 needs each ray's total over all items)
+// and the item's number of non-zero (ray, coefficient) pairs into cnt[item]. The basis tables
+// are staged in LDS (dynamic, 2 x total table length doubles).
 template <typename T, typename R, int MODE>
-__global__ __launch_bounds__(kD4Block) void k_d4_gather(DevGeom g, D4Dev tb, const double2* __restrict__ views,
+__global__ __launch_bounds__(kD4Block) void k_d4_gather(DevGeom g, D4Dev tb, int tab_len,
+                                                        const double2* __restrict__ views,
                                                         const typename V4R<R>::t* __restrict__ A,
                                                         const typename V4R<R>::t* __restrict__ B,
                                                         const T* __restrict__ y, const uint32_t* __restrict__ items,
                                                         const int* __restrict__ n_items, T* __restrict__ beta,
-                                                        const T* __restrict__ b,
-                                                        const double* __restrict__ z0, int* __restrict__ held,
-                                                        T* __restrict__ bp, T* __restrict__ bm,
-                                                        double* __restrict__ zsum, double* __restrict__ cnt) {
-  const int it = blockIdx.x * kD4Block + threadIdx.x;
-  if (it >= *n_items) return;
+                                                        const T* __restrict__ b, const double* __restrict__ z0,
+                                                        int* __restrict__ held, T* __restrict__ bp,
+                                                        T* __restrict__ bm, double* __restrict__ zsum,
+                                                        double* __restrict__ cnt) {
+  extern __shared__ double lds[];
+  for (int k = threadIdx.x; k < tab_len; k += kD4Block) {
+    lds[k] = tb.f[k];
+    lds[tab_len + k] = tb.g[k];
+  }
+  __syncthreads();
+  const int it = blockIdx.x * kD4Waves + int(threadIdx.x >> 6);
+  const int lane = int(threadIdx.x & 63);
+  if (it >= *n_items) return;   // uniform over the wave
   const uint32_t w = items[it];
   const bool quad = (w >> 31) != 0;
   const int l = int((w >> 27) & 15u), i = int((w >> 13) & 0x1fffu), j = int(w & 0x1fffu);
   const int n = g.n, m = n >> l, s = 1 << l;
   const bool root = l == g.L;
   const double tq = 1e-12 * g.pixel;
+  const double pix = g.pixel, ipix = 1.0 / g.pixel, hn = 0.5 * n;
+  const int len = tb.len[l];
+  const double* F = lds + tb.off[l];
+  const double* G = lds + tab_len + tb.off[l];
+  const int y0 = s * i, x0 = s * j;
+  const bool wx = x0 + len > n, wy = y0 + len > n;
+  const int nr = (wx ? 2 : 1) * (wy ? 2 : 1);
   double S[4] = {0, 0, 0, 0}, Aab[4] = {0, 0, 0, 0};
   double nz = 0.0;
-  const double hn = 0.5 * n, pix = g.pixel;
-  const int len = tb.len[l];
-  for (int v = 0; v < g.nv; ++v) {
+  for (int v = lane; v < g.nv; v += 64) {
     const double2 cs = views[v];
-    for (int pyk = 0; pyk < 2; ++pyk) {
-      const int ye = s * i + len;
-      if (pyk == 1 && ye <= n) break;
-      const int ya = pyk == 0 ? s * i : 0, yb = pyk == 0 ? (ye < n ? ye : n) : ye - n;
-      for (int pxk = 0; pxk < 2; ++pxk) {
-        const int xe = s * j + len;
-        if (pxk == 1 && xe <= n) break;
-        const int xa = pxk == 0 ? s * j : 0, xb = pxk == 0 ? (xe < n ? xe : n) : xe - n;
-        int lo, hi;
-        d4_bins(g, cs, (xa - hn) * pix, (xb - hn) * pix, (ya - hn) * pix, (yb - hn) * pix, lo, hi);
-        for (int bin = lo; bin <= hi; ++bin) {
-          // rays meeting several pieces of the support are summed once per ray below: take
-          // the ray only from the first piece its bin range reaches
-          bool seen = false;
-          for (int qy = 0; qy <= pyk && !seen; ++qy)
-            for (int qx = 0; qx < 2 && !seen; ++qx) {
-              if (qy == pyk && qx >= pxk) break;
-              if (qx == 1 && xe <= n) break;
-              if (qy == 1 && ye <= n) break;
-              const int ya2 = qy == 0 ? s * i : 0, yb2 = qy == 0 ? (ye < n ? ye : n) : ye - n;
-              const int xa2 = qx == 0 ? s * j : 0, xb2 = qx == 0 ? (xe < n ? xe : n) : xe - n;
-              int lo2, hi2;
-              d4_bins(g, cs, (xa2 - hn) * pix, (xb2 - hn) * pix, (ya2 - hn) * pix, (yb2 - hn) * pix, lo2, hi2);
-              seen = bin >= lo2 && bin <= hi2;
-            }
-          if (seen) continue;
-          const int r = v * g.nb + bin;
-          const auto a = A[r];
-          const auto bb = B[r];
-          double vals[4];
-          d4_ray<R>(g, tb, l, s * j, s * i, double(a.x), double(a.y), double(bb.x), double(bb.y), double(a.z),
-                    double(a.w), vals);
-          const bool use[4] = {root, quad, quad, quad};
-          if (MODE == kD4Z0) {
-            double zs = 0.0;
-            for (int k = 0; k < 4; ++k)
-              if (use[k] && fabs(vals[k]) > tq) { zs += fabs(vals[k]); nz += 1.0; }
-            if (zs > 0.0) atomicAdd(zsum + r, zs);
-          } else {
-            const double yv = double(y[r]);
-            for (int k = 0; k < 4; ++k) {
-              const double wv = use[k] && fabs(vals[k]) > tq ? yv * vals[k] : 0.0;
-              S[k] += wv;
-              Aab[k] += fabs(wv);
-            }
+    for (int q = 0; q < nr; ++q) {
+      const D4Rect rq = d4_rect(q, x0, y0, len, n, wx);
+      int lo, hi;
+      d4_bins(g, cs, (rq.xa - hn) * pix, (rq.xb - hn) * pix, (rq.ya - hn) * pix, (rq.yb - hn) * pix, lo, hi);
+      for (int bin = lo; bin <= hi; ++bin) {
+        const int r = v * g.nb + bin;
+        const auto a = A[r];
+        const double ox = double(a.x), oy = double(a.y), iex = double(a.z), iey = double(a.w);
+        if (nr > 1) {
+          bool mine = d4_hits(rq, ox, oy, iex, iey, pix, hn);
+          for (int q2 = 0; q2 < q && mine; ++q2)
+            mine = !d4_hits(d4_rect(q2, x0, y0, len, n, wx), ox, oy, iex, iey, pix, hn);
+          if (!mine) continue;
+        }
+        const auto bb = B[r];
+        const double ex = double(bb.x), ey = double(bb.y);
+        double vals[4] = {0, 0, 0, 0};
+#pragma unroll 1
+        for (int q2 = q; q2 < nr; ++q2) {
+          const D4Rect r2 = d4_rect(q2, x0, y0, len, n, wx);
+          d4_piece(ox, oy, ex, ey, iex, iey, r2.xa, r2.xb, r2.ya, r2.yb, r2.ox, r2.oy, F, G, pix, ipix, hn, vals);
+        }
+        if (MODE == kD4Z0) {
+          double zs = 0.0;
+          if (root && fabs(vals[0]) > tq) { zs += fabs(vals[0]); nz += 1.0; }
+          if (quad) {
+#pragma unroll
+            for (int k = 1; k < 4; ++k)
+              if (fabs(vals[k]) > tq) { zs += fabs(vals[k]); nz += 1.0; }
+          }
+          if (zs > 0.0) atomicAdd(zsum + r, zs);
+        } else {
+          const double yv = double(y[r]);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const double wv = fabs(vals[k]) > tq ? yv * vals[k] : 0.0;
+            S[k] += wv;
+            Aab[k] += fabs(wv);
           }
         }
       }
     }
   }
+  // butterfly over the wave: every lane ends with the same totals, added in the same order
   if (MODE == kD4Z0) {
-    cnt[it] = nz;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nz += __shfl_xor(nz, o, 64);
+    if (lane == 0) cnt[it] = nz;
     return;
   }
-  const int64_t pos[4] = {int64_t(i) * n + j, int64_t(i) * n + m + j, int64_t(m + i) * n + j,
-                          int64_t(m + i) * n + m + j};
-  for (int k = 0; k < 4; ++k) {
-    if (!(k == 0 ? root : quad)) continue;
-    const double p = 0.5 * (Aab[k] + S[k]), q = 0.5 * (S[k] - Aab[k]);
-    if (MODE == kD4Split) {
-      bp[pos[k]] = T(p);
-      bm[pos[k]] = T(q);
-    } else {
-      beta[pos[k]] = T(double(beta[pos[k]]) + am_delta<double>(double(b[pos[k]]), p, q, *z0, held));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      S[k] += __shfl_xor(S[k], o, 64);
+      Aab[k] += __shfl_xor(Aab[k], o, 64);
     }
+  }
+  // lane k writes coefficient k (the approximation only for a root, the details only when split)
+  if (lane >= 4 || (lane == 0 ? !root : !quad)) return;
+  const int64_t pos = lane == 0 ? int64_t(i) * n + j
+                    : lane == 1 ? int64_t(i) * n + m + j
+                    : lane == 2 ? int64_t(m + i) * n + j
+                                : int64_t(m + i) * n + m + j;
+  double Sk = S[0], Ak = Aab[0];
+#pragma unroll
+  for (int k = 1; k < 4; ++k)
+    if (lane == k) { Sk = S[k]; Ak = Aab[k]; }
+  const double p = 0.5 * (Ak + Sk), qn = 0.5 * (Sk - Ak);
+  if (MODE == kD4Split) {
+    bp[pos] = T(p);
+    bm[pos] = T(qn);
+  } else {
+    beta[pos] = T(double(beta[pos]) + am_delta<double>(double(b[pos]), p, qn, *z0, held));
   }
 }
 
@@ -356,16 +406,18 @@ void D4<T, R>::gather(const DevGeom& g, int mode, const D4Dev& tb, const double2
   if (max_items <= 0) return;
   auto a = (const typename V4R<R>::t*)A;
   auto bb = (const typename V4R<R>::t*)B;
-  const dim3 grid(d4_blocks(max_items));
+  const int tab_len = tb.off[g.L] + tb.len[g.L];
+  const size_t lds = sizeof(double) * 2 * size_t(tab_len);
+  const dim3 grid((max_items + kD4Waves - 1) / kD4Waves);
   if (mode == kD4Split)
-    hipLaunchKernelGGL((k_d4_gather<T, R, kD4Split>), grid, dim3(kD4Block), 0, s, g, tb, views, a, bb, y, items,
-                       n_items, beta, b, z0, held, bp, bm, zsum, cnt);
+    hipLaunchKernelGGL((k_d4_gather<T, R, kD4Split>), grid, dim3(kD4Block), lds, s, g, tb, tab_len, views, a, bb, y,
+                       items, n_items, beta, b, z0, held, bp, bm, zsum, cnt);
   else if (mode == kD4Update)
-    hipLaunchKernelGGL((k_d4_gather<T, R, kD4Update>), grid, dim3(kD4Block), 0, s, g, tb, views, a, bb, y, items,
-                       n_items, beta, b, z0, held, bp, bm, zsum, cnt);
+    hipLaunchKernelGGL((k_d4_gather<T, R, kD4Update>), grid, dim3(kD4Block), lds, s, g, tb, tab_len, views, a, bb,
+                       y, items, n_items, beta, b, z0, held, bp, bm, zsum, cnt);
   else
-    hipLaunchKernelGGL((k_d4_gather<T, R, kD4Z0>), grid, dim3(kD4Block), 0, s, g, tb, views, a, bb, y, items,
-                       n_items, beta, b, z0, held, bp, bm, zsum, cnt);
+    hipLaunchKernelGGL((k_d4_gather<T, R, kD4Z0>), grid, dim3(kD4Block), lds, s, g, tb, tab_len, views, a, bb, y,
+                       items, n_items, beta, b, z0, held, bp, bm, zsum, cnt);
 }
 template struct D4<float, float>;
 template struct D4<float, double>;
