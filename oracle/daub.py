@@ -48,12 +48,17 @@ def basis_1d(n, levels):
 
 
 def synthesis_matrix(n, levels):
-    """Omega (n*n x n*n, CSR): column z = the basis image of Mallat coefficient z."""
+    """Omega (n*n x n*n, CSR): column z = the basis image of Mallat coefficient z, the outer
+    product of its 1-D functions (row function along y, column function along x), assembled
+    from their non-zero samples (entries below 1e-15 in magnitude dropped)."""
     phi, psi = basis_1d(n, levels)
-    cols = np.zeros((n * n, n * n))
+    rows, cols, vals = [], [], []
 
     def put(r, c, fy, fx):
-        cols[:, r * n + c] = np.outer(fy, fx).ravel()
+        iy, ix = np.flatnonzero(fy), np.flatnonzero(fx)
+        rows.append((iy[:, None] * n + ix[None, :]).ravel())
+        cols.append(np.full(iy.size * ix.size, r * n + c, np.int64))
+        vals.append(np.outer(fy[iy], fx[ix]).ravel())
 
     m = n >> levels
     for i in range(m):
@@ -66,8 +71,9 @@ def synthesis_matrix(n, levels):
                 put(i, m + j, phi[l][i], psi[l][j])
                 put(m + i, j, psi[l][i], phi[l][j])
                 put(m + i, m + j, psi[l][i], psi[l][j])
-    cols[np.abs(cols) < 1e-15] = 0.0
-    return sp.csr_matrix(cols)
+    v = np.concatenate(vals)
+    keep = np.abs(v) >= 1e-15
+    return sp.csr_matrix((v[keep], (np.concatenate(rows)[keep], np.concatenate(cols)[keep])), shape=(n * n, n * n))
 
 
 def cascade_analysis(img, levels):
