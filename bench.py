@@ -56,6 +56,8 @@ def parse():
                     help="after the run, copy a MIB-sized buffer 3 times (reference kernel for PMC byte counters)")
     ap.add_argument("--os-subsets", type=int, default=8, help="fan512: ordered-subsets comparison (0 = skip)")
     ap.add_argument("--no-gradient-rule", action="store_true", help="fan512: skip the residual-gradient rule leg")
+    ap.add_argument("--no-d4", action="store_true", help="fan512: skip the Daubechies-4 leg")
+    ap.add_argument("--d4-steps", type=int, default=3, help="fan512: timed solves of the Daubechies-4 leg")
     ap.add_argument("--problems", type=int, default=256, help="uneven: number of problems")
     ap.add_argument("--streams", type=int, default=4, help="uneven: streams of the batch")
     ap.add_argument("--no-graph", action="store_true", help="uneven: launch directly instead of graph replay")
@@ -812,6 +814,54 @@ def bench_fan(args, config, steps, warmup):
             "time_to_tree_final_idiv_ms": None if k_os is None else round(k_os * t_os / J * 1e3, 3),
             "idiv_at_pass": {str(k): float(otr[k]) for k in (1, 2, 5, 10, 21, 43, 85) if k <= J}}
         osc.close()
+
+    # ---- the same solve with the Daubechies-4 basis (same tree rule, schedule and fraction):
+    # per-pixel synthesis, pixel-walk forward, support-walking sign-split gather
+    if not args.no_d4:
+        dc = api.Context(g, P.levels, "f32", device=dev, geometry=args.geometry, wavelet="d4")
+        dc.set_data(d, P.i0)
+        dc.reset()
+        dseg = []
+        for k, (a, b) in enumerate(zip(marks[:-1], marks[1:])):     # traced run (untimed)
+            if k > 0:
+                dc.expand(0.1)
+            st = dc.tree_stats()
+            dseg.append(dict(start=a, iters=b - a, w=st["w"], n_active=st["n_active"], z0=st["z0"]))
+            dc.iterate(b - a)
+        dc.reset()
+        didiv = torch.empty(J + 1, dtype=torch.float64, device=dev)
+        dc.solve(J, sched, 0.1, didiv)
+        dtr = didiv.cpu().numpy()
+        n_d4 = max(1, args.d4_steps)
+        torch.cuda.synchronize()
+        dc.timing(True, ("update",))
+        t4 = time.perf_counter()
+        for _ in range(n_d4):
+            dc.reset()
+            dc.solve(J, sched, 0.1, didiv)
+        torch.cuda.synchronize()
+        t_d4 = (time.perf_counter() - t4) / n_d4
+        dtim = dc.get_timing()["update"]
+        dc.timing(False)
+        d_upd_ms = dtim["ms"] / max(1, dtim["launches"])
+        d_w = sum(x["w"] * x["iters"] for x in dseg) / J
+        d_act = sum(x["n_active"] * x["iters"] for x in dseg) / J
+        d_alg = 8.0 * d_w + 4.0 * M + 12.0 * d_act
+        hit = np.nonzero(tr <= dtr[-1])[0]
+        k_h = int(hit[0]) if hit.size else None
+        out["wavelet_d4"] = {
+            "iter_per_s": round(J / t_d4, 2), "ms_per_solve": round(t_d4 * 1e3, 3), "steps": n_d4,
+            "final_idiv": float(dtr[-1]), "trees": dseg,
+            "haar_iters_to_d4_final_idiv": k_h,
+            "haar_time_to_d4_final_idiv_ms": None if k_h is None else round(k_h * ms_step / J, 3),
+            "roofline_update": roofline(d_alg, d_upd_ms, None,
+                                        kernels="k_d4_gather (one wave per work item, support walk)",
+                                        avg_pass_ms=round(d_upd_ms, 5), passes=dtim["launches"],
+                                        alg_bytes_per_pass=int(d_alg),
+                                        note="phi recomputed by walking every ray through each active "
+                                             "support; bound by VALU issue, not by memory")}
+        dc.close()
+        log(f"{config}: Daubechies-4 {J / t_d4:.1f} it/s, final I-div {dtr[-1]:.4e}")
 
     if not args.no_cpu_baseline:
         log(f"{config}: CPU oracle on {args.cpu_views} views")

@@ -1,7 +1,7 @@
 """Orthonormal Daubechies-4 wavelets on an n x n image with periodic boundary, FP64 (test
 infrastructure; see oracle/__init__.py).
 
-The Conclusion names "different wavelet types" as future work; this is one: the compactly
+The Conclusion lists other wavelet families as future work; this is one: the compactly
 supported orthonormal wavelet with two vanishing moments (four filter taps), in the same
 2-D Mallat layout and tree structure as haar.py, so Algorithm 1 and the tree rule of the
 Results section apply unchanged with this Omega (wam.wam_solve(..., Omega=synthesis_matrix)).

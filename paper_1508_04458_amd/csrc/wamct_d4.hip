@@ -1,5 +1,5 @@
-// Orthonormal Daubechies-4 wavelets (periodic boundary) for the 2-D scans: a "different
-// wavelet type" in the sense of the Conclusion, in the same Mallat layout and tree structure
+// Orthonormal Daubechies-4 wavelets (periodic boundary) for the 2-D scans: another wavelet
+// family in the sense of the Conclusion, in the same Mallat layout and tree structure
 // as the Haar basis, so Algorithm 1 (eqs. 1.6, 1.9, 1.10, 1.61) and the tree rule of the
 // Results section run unchanged. The D4 basis functions are not constant on the tree's
 // blocks, so there is no leaf walk: the forward pass synthesizes mu = Omega beta pixel by
