@@ -471,7 +471,8 @@ struct Ctx final : wamct_ctx {
     NN = int64_t(g.n) * g.n;
     nb_rays = int((M + 255) / 256);
     nb_pix = int((NN + 255) / 256);
-    np = std::max(4 * nb_rays, nb_pix) + 1;   // the tree walk may use 4 lanes per ray
+    // the tree walk may use 4 lanes per ray; walk grids are padded to a multiple of 8 blocks
+    np = std::max(4 * nb_rays, nb_pix) + 8;
     d4 = O.wavelet == WAMCT_D4;
     if (hipHostMalloc((void**)&h_ints, sizeof(int) * kInts * P, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&h_scal, sizeof(double) * kScal * P, hipHostMallocDefault) != hipSuccess) {

@@ -221,7 +221,7 @@ template <typename Q>
     g.pixel = G.pixel; g.cpitch = G.bin_pitch; g.rpitch = G.row_pitch; g.sod = G.sod; g.sdd = G.sdd;
     M = int64_t(g.nv) * g.nr * g.nc;
     N = int64_t(g.n) * g.n * g.nz;
-    np = int(std::max((M + 255) / 256, (N + 255) / 256)) + 1;
+    np = int(std::max((M + 255) / 256, (N + 255) / 256)) + 8;   // walk grids: multiples of 8 blocks
     if (hipHostMalloc((void**)&h_ints, sizeof(int) * kInts, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&h_scal, sizeof(double) * kScal, hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();

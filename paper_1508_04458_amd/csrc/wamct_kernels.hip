@@ -338,7 +338,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4
     muR += oi; muC += oi;
     d = at(d, orr); i0v = at(i0v, orr); q = at(q, orr); pout = at(pout, orr);
   }
-  const int k = blockIdx.x * kBlock + threadIdx.x;
+  const int rb = xcd_rotate(blockIdx.x);
+  const int k = rb * kBlock + threadIdx.x;
   const int r = subset_ray(g, k);
   double term = 0.0;
   if (k < g.nvs * g.nb) {
@@ -405,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4
   }
   if (part) {
     term = block_reduce<false>(term);
-    if (threadIdx.x == 0) part[sc * gridDim.x + blockIdx.x] = term;
+    if (threadIdx.x == 0) part[sc * gridDim.x + rb] = term;
   }
 }
 
@@ -437,7 +438,8 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
     leafR += oi; leafC += oi;
     d = at(d, orr); i0v = at(i0v, orr); q = at(q, orr); pout = at(pout, orr);
   }
-  const int lane_id = blockIdx.x * kBlock + threadIdx.x;
+  const int rb = xcd_rotate(blockIdx.x);
+  const int lane_id = rb * kBlock + threadIdx.x;
   const int k = lane_id / K, piece = lane_id % K;
   const int r = subset_ray(g, k);
   double term = 0.0;
@@ -516,7 +518,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
   }
   if (part) {
     term = block_reduce<false>(term);
-    if (threadIdx.x == 0) part[sc * gridDim.x + blockIdx.x] = term;
+    if (threadIdx.x == 0) part[sc * gridDim.x + rb] = term;
   }
 }
 
@@ -1072,7 +1074,8 @@ __global__ __launch_bounds__(kBlock) void k_z0(DevGeom g, const double2* __restr
                                                const uint8_t* __restrict__ lev, double* __restrict__ part_max,
                                                double* __restrict__ part_cnt) {
   lev += int64_t(blockIdx.y) * g.n * g.n;
-  const int k = blockIdx.x * kBlock + threadIdx.x;
+  const int rb = xcd_rotate(blockIdx.x);
+  const int k = rb * kBlock + threadIdx.x;
   double sum = 0.0, cnt = 0.0;
   if (k < g.nvs * g.nb) {
     const int r = subset_ray(g, k);
@@ -1101,7 +1104,7 @@ __global__ __launch_bounds__(kBlock) void k_z0(DevGeom g, const double2* __restr
   __syncthreads();
   const double ct = block_reduce<false>(cnt);
   if (threadIdx.x == 0) {
-    const int o = blockIdx.y * gridDim.x + blockIdx.x;
+    const int o = blockIdx.y * gridDim.x + rb;
     part_max[o] = mx;
     part_cnt[o] = ct;
   }
@@ -1362,7 +1365,7 @@ void Geo<T, R>::view_table(const DevGeom& g, const double2* views, void* vF, hip
 template <typename T, typename R>
 int Geo<T, R>::forward(const DevGeom& g, const void* A, const void* B, const T* muR, const T* muC, const T* d,
                        const T* i0v, const double* i0s, T* q, T* p, double* part, int S, hipStream_t s) {
-  const int nb = blocks_for(int64_t(g.nvs) * g.nb);
+  const int nb = xcd_blocks(blocks_for(int64_t(g.nvs) * g.nb));
   hipLaunchKernelGGL((k_forward<T, R, 8>), dim3(nb, S), dim3(kBlock), 0, s, g, (const typename V4<R>::t*)A,
                      (const typename V4<R>::t*)B, muR, muC, d, i0v, i0s, q, p, part);
   return nb;
@@ -1379,7 +1382,7 @@ int Geo<T, R>::forward_records(const DevGeom& g, const void* A, const void* B, c
                                hipStream_t s, int lanes) {
   const int64_t rays = int64_t(g.nvs) * g.nb * S;
   const int k = lanes > 0 ? lanes : leaf_pieces(rays);
-  const int nb = blocks_for(int64_t(g.nvs) * g.nb * k);
+  const int nb = xcd_blocks(blocks_for(int64_t(g.nvs) * g.nb * k));
   auto a = (const typename V4<R>::t*)A;
   auto b = (const typename V4<R>::t*)B;
   auto lr = (const Leaf<T>*)leafR;
@@ -1467,7 +1470,7 @@ template struct Geo<double, double>;
 
 int z0_partials(const DevGeom& g, const double2* views, const uint8_t* lev, double* part_max,
                 double* part_cnt, int S, hipStream_t s) {
-  const int nb = blocks_for(int64_t(g.nvs) * g.nb);
+  const int nb = xcd_blocks(blocks_for(int64_t(g.nvs) * g.nb));
   switch (g.L) {
 #define Z0_CASE(K) \
     case K: hipLaunchKernelGGL(k_z0<K>, dim3(nb, S), dim3(kBlock), 0, s, g, views, lev, part_max, part_cnt); break;

@@ -410,7 +410,7 @@ __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, RayF3 f,
                                                  const T* __restrict__ d, const T* __restrict__ i0v,
                                                  const double* __restrict__ i0s, T* __restrict__ q,
                                                  T* __restrict__ pout, double* __restrict__ part) {
-  const int blk = blockIdx.x;
+  const int blk = xcd_rotate(blockIdx.x);
   const int64_t k = int64_t(blk) * kB + threadIdx.x;
   const int64_t M = int64_t(g.nv) * g.nr * g.nc;
   double term = 0.0;
@@ -864,7 +864,7 @@ template <int LT, int WD>
 __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, RayF3 f, const uint8_t* __restrict__ lev,
                                             const uint8_t* __restrict__ levC, double* __restrict__ part_max,
                                             double* __restrict__ part_cnt) {
-  const int blk = blockIdx.x;
+  const int blk = xcd_rotate(blockIdx.x);
   const int64_t k = int64_t(blk) * kB + threadIdx.x;
   const int64_t M = int64_t(g.nv) * g.nr * g.nc;
   double sum = 0.0, cnt = 0.0;
@@ -975,7 +975,7 @@ __global__ __launch_bounds__(kB) void k3_expand(DevGeom3 g, const uint8_t* __res
 template <typename T>
 int Geo3<T>::forward(const DevGeom3& g, const RayF3& f, const void* recR, const void* recC, const T* d,
                      const T* i0v, const double* i0s, T* q, T* p, double* part, hipStream_t s) {
-  const int nb = blocks3(int64_t(g.nv) * g.nr * g.nc);
+  const int nb = xcd_blocks(blocks3(int64_t(g.nv) * g.nr * g.nc));
   if (g.wd == 2)
     hipLaunchKernelGGL((k3_forward<T, 2>), dim3(nb), dim3(kB), 0, s, g, f, (const Rec3<T>*)recR, (const Rec3<T>*)recC,
                        d, i0v, i0s, q, p, part);
@@ -1071,7 +1071,7 @@ template struct Geo3<double>;
 
 int z0_partials3(const DevGeom3& g, const RayF3& f, const uint8_t* lev, const uint8_t* levC, double* part_max,
                  double* part_cnt, hipStream_t s) {
-  const int nb = blocks3(int64_t(g.nv) * g.nr * g.nc);
+  const int nb = xcd_blocks(blocks3(int64_t(g.nv) * g.nr * g.nc));
   switch (g.L) {
 #define Z3_CASE(K)                                                                                        \
     case K:                                                                                               \
