@@ -80,22 +80,28 @@ __host__ __device__ inline void walk(const DevGeom& g, R ox, R oy, R ex, R ey, R
   int x = imin(imax(int(fma(t_in, ux, x0)), 0), n - 1);
   int y = imin(imax(int(fma(t_in, uy, y0)), 0), n - 1);
   R t = t_in;
+  // leaf level of the mirrored pixel (x, y), clamped into range
+  auto level = [&](int xm, int ym) {
+    return TREE ? int(lev[((imin(ym, n - 1) ^ my) + ay) * n + ((imin(xm, n - 1) ^ mx) + ax)]) : 0;
+  };
+  int l = level(x, y);
   for (int step = 0; step < 4 * n + 8; ++step) {
     const int rx = (x ^ mx) + ax, ry = (y ^ my) + ay;
-    const int l = TREE ? int(lev[ry * n + rx]) : 0;
     const int s = 1 << l;
     const int ex_ = (x & -s) + s, ey_ = (y & -s) + s;
     const R tX = fma(R(ex_), kx, cx), tY = fma(R(ey_), ky, cy);
     const bool cross_x = tX <= tY;
     const R te = fmax(fmin(fmin(tX, tY), t_out), t);
-    f(rx, ry, l, te - t);
-    if (te >= t_out) break;
     const int xo = imin(imax(int(fma(te, ux, x0)), x), ex_ - 1);
     const int yo = imin(imax(int(fma(te, uy, y0)), y), ey_ - 1);
-    x = cross_x ? ex_ : xo;
-    y = cross_x ? yo : ey_;
-    if (x >= n || y >= n) break;
+    const int xn = cross_x ? ex_ : xo, yn = cross_x ? yo : ey_;
+    const int ln = level(xn, yn);   // the next leaf's level, in flight while f runs
+    f(rx, ry, l, te - t);
+    if (te >= t_out || xn >= n || yn >= n) break;
+    x = xn;
+    y = yn;
     t = te;
+    l = ln;
   }
 }
 

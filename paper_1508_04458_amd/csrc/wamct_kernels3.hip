@@ -890,14 +890,23 @@ __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, RayF3 f, const uint8_t* 
       // x-major rays read the [z][x][y] level map (neighbouring lanes, neighbouring addresses)
       const bool xmaj = fabs(ray.ex) >= fabs(ray.ey);
       const uint8_t* __restrict__ lv = xmaj ? levC : lev;
+      // leaf level at mirrored voxel (x, y, z), clamped into range (past the last leaf the
+      // value is loaded and not used)
+      auto level = [&](int x, int y, int zz) {
+        if (LT == 0) return 0;
+        const unsigned rx = w.real_x(min(x, n - 1)), ry = w.real_y(min(y, n - 1)), rz = w.real_z(min(zz, g.nz - 1));
+        const unsigned a0 = xmaj ? rx : ry, a1 = xmaj ? ry : rx;
+        return int(lv[__umul24(__umul24(rz, unsigned(n)) + a0, unsigned(n)) + a1]);
+      };
+      int l = level(w.x, w.y, w.z);
       for (int step = 0; step < 4 * (2 * n + g.nz) + 8; ++step) {
         const int ix = w.rx(), iy = w.ry(), iz = w.rz();
-        const unsigned a0 = xmaj ? unsigned(ix) : unsigned(iy), a1 = xmaj ? unsigned(iy) : unsigned(ix);
-        const int l = LT > 0 ? int(lv[__umul24(__umul24(unsigned(iz), unsigned(n)) + a0, unsigned(n)) + a1]) : 0;
         double chord;
         const bool go = w.step(l, chord);
+        const int ln = level(w.x, w.y, w.z);   // the next leaf's level, in flight during the visit
         z.visit(ix, iy, iz, l, chord);
         if (!go) break;
+        l = ln;
       }
 #pragma unroll
       for (int m = 1; m <= LT; ++m) z.flush(m);
