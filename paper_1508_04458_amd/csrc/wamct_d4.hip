@@ -237,7 +237,10 @@ __device__ inline void d4_bins(const DevGeom& g, double2 cs, double X0, double X
   hi = min(int(floor(fhi)), g.nb - 1);
 }
 
-constexpr int kD4Waves = kD4Block / 64;
+// The gather runs one work item per 64-lane block: items differ widely in cost (a split root
+// has four coefficients, a level-1 node three over a support a quarter as wide), and a block of
+// several items would hold its wave slots until its slowest item ends.
+constexpr int kD4GatherBlock = 64;
 
 // Rectangle q (0 .. count - 1) of a support of len x len pixels from (x0, y0), wrapped at the
 // border n: q enumerates (upper or wrapped part in y) x (left or wrapped part in x), the
@@ -263,8 +266,8 @@ __device__ inline bool d4_hits(const D4Rect& r, double sx, double cx, double sy,
   return fmin(fmax(tx0, tx1), fmax(ty0, ty1)) > fmax(fmin(tx0, tx1), fmin(ty0, ty1));
 }
 
-// One wave per work item (a root: its approximation, and its three details when split; a split
-// node: its three details); lane k takes the views k, k + 64, ... and the wave's sums are
+// One wave (one block) per work item (a root: its approximation, and its three details when
+// split; a split node: its three details); lane k takes the views k, k + 64, ... and the wave's sums are
 // combined by a fixed butterfly (deterministic). The support of the item's functions (len x
 // len pixels from (2^l i, 2^l j), wrapped at the border into up to four rectangles) is
 // projected per view to a bin range per rectangle; a ray is taken in the loop of the first
@@ -278,7 +281,7 @@ __device__ inline bool d4_hits(const D4Rect& r, double sx, double cx, double sy,
 // from the ray table's (origin, inverse direction). Registers are capped for four waves per
 // SIMD (128 VGPRs, no spills; measured 1.2x faster than three waves at 146).
 template <typename T, typename R, int MODE>
-__global__ __launch_bounds__(kD4Block) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_d4_gather(
+__global__ __launch_bounds__(kD4GatherBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_d4_gather(
     DevGeom g, D4Dev tb, int tab_len, const double2* __restrict__ views, const typename V4R<R>::t* __restrict__ A,
                                                         const T* __restrict__ y, const uint32_t* __restrict__ items,
                                                         const int* __restrict__ n_items, T* __restrict__ beta,
@@ -286,12 +289,12 @@ __global__ __launch_bounds__(kD4Block) __attribute__((amdgpu_waves_per_eu(4, 8))
                                                         int* __restrict__ held, T* __restrict__ bp,
                                                         T* __restrict__ bm, double* __restrict__ zsum,
                                                         double* __restrict__ cnt) {
+  const int it = blockIdx.x;
+  const int lane = int(threadIdx.x);
+  if (it >= *n_items) return;   // uniform over the block
   extern __shared__ double2 lds2[];
-  for (int k = threadIdx.x; k < tab_len; k += kD4Block) lds2[k] = make_double2(tb.f[k], tb.g[k]);
+  for (int k = lane; k < tab_len; k += kD4GatherBlock) lds2[k] = make_double2(tb.f[k], tb.g[k]);
   __syncthreads();
-  const int it = blockIdx.x * kD4Waves + int(threadIdx.x >> 6);
-  const int lane = int(threadIdx.x & 63);
-  if (it >= *n_items) return;   // uniform over the wave
   const uint32_t w = items[it];
   const bool quad = (w >> 31) != 0;
   const int l = int((w >> 27) & 15u), i = int((w >> 13) & 0x1fffu), j = int(w & 0x1fffu);
@@ -414,15 +417,15 @@ void D4<T, R>::gather(const DevGeom& g, int mode, const D4Dev& tb, const double2
   (void)B;   // the walk needs the origin and inverse direction only
   const int tab_len = tb.off[g.L] + tb.len[g.L];
   const size_t lds = sizeof(double2) * size_t(tab_len);
-  const dim3 grid((max_items + kD4Waves - 1) / kD4Waves);
+  const dim3 grid(max_items);
   if (mode == kD4Split)
-    hipLaunchKernelGGL((k_d4_gather<T, R, kD4Split>), grid, dim3(kD4Block), lds, s, g, tb, tab_len, views, a, y,
+    hipLaunchKernelGGL((k_d4_gather<T, R, kD4Split>), grid, dim3(kD4GatherBlock), lds, s, g, tb, tab_len, views, a, y,
                        items, n_items, beta, b, z0, held, bp, bm, zsum, cnt);
   else if (mode == kD4Update)
-    hipLaunchKernelGGL((k_d4_gather<T, R, kD4Update>), grid, dim3(kD4Block), lds, s, g, tb, tab_len, views, a,
+    hipLaunchKernelGGL((k_d4_gather<T, R, kD4Update>), grid, dim3(kD4GatherBlock), lds, s, g, tb, tab_len, views, a,
                        y, items, n_items, beta, b, z0, held, bp, bm, zsum, cnt);
   else
-    hipLaunchKernelGGL((k_d4_gather<T, R, kD4Z0>), grid, dim3(kD4Block), lds, s, g, tb, tab_len, views, a, y,
+    hipLaunchKernelGGL((k_d4_gather<T, R, kD4Z0>), grid, dim3(kD4GatherBlock), lds, s, g, tb, tab_len, views, a, y,
                        items, n_items, beta, b, z0, held, bp, bm, zsum, cnt);
 }
 template struct D4<float, float>;
