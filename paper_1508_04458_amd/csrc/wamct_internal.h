@@ -40,11 +40,14 @@ enum GatherMode { kPlain = 0, kSplit = 1, kUpdate = 2 };
 
 // Workgroups reach the 8 XCDs round-robin in launch order. The ray walks take their ray block
 // through a rotation within each aligned group of 8 blocks: the j-th block an XCD receives is
-// ray block 8 j + (xcd + j) mod 8, so every XCD cycles through all parts of a view (without it,
-// a view of 4 or 8 blocks sends its central, longest rays always to the same XCDs and the
-// others idle) while the XCDs still work on neighbouring rays at any time. Walk grids are
-// padded to a multiple of 8 (xcd_blocks); blocks past the rays write zero partial sums.
-__host__ __device__ inline int xcd_rotate(int b) { return (b & ~7) | ((b + (b >> 3)) & 7); }
+// ray block 8 j + (xcd + (j >> p)) mod 8, so every XCD cycles through all parts of a view
+// (without it, a view of 4 or 8 blocks sends its central, longest rays always to the same XCDs
+// and the others idle) while the XCDs still work on neighbouring rays at any time. p = 0
+// rotates at every group; a larger p keeps an XCD on the same part of consecutive views for
+// 2^p groups (their rays reuse the records in that XCD's L2) and still balances a launch of
+// many times 2^p groups. Walk grids are padded to a multiple of 8 (xcd_blocks); blocks past the
+// rays write zero partial sums.
+__host__ __device__ inline int xcd_rotate(int b, int p = 0) { return (b & ~7) | ((b + (b >> (3 + p))) & 7); }
 inline int xcd_blocks(int64_t blocks) { return int((blocks + 7) / 8 * 8); }
 
 // x[0] + x[stride] + ... + x[(n - 1) stride], added strictly in index order (the same

@@ -19,6 +19,9 @@ namespace wamct {
 namespace {
 
 constexpr int kB = 256;
+// Groups of 8 walk blocks an XCD keeps the same part of the detector rows (2^6 groups: 128
+// consecutive views of a row; the records they cross stay in its L2).
+constexpr int kRotate3 = 6;
 inline int blocks3(int64_t n, int b = kB) { return int((n + b - 1) / b); }
 
 // Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b mod 8), each XCD with
@@ -410,7 +413,7 @@ __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, RayF3 f,
                                                  const T* __restrict__ d, const T* __restrict__ i0v,
                                                  const double* __restrict__ i0s, T* __restrict__ q,
                                                  T* __restrict__ pout, double* __restrict__ part) {
-  const int blk = xcd_rotate(blockIdx.x);
+  const int blk = xcd_rotate(blockIdx.x, kRotate3);
   const int64_t k = int64_t(blk) * kB + threadIdx.x;
   const int64_t M = int64_t(g.nv) * g.nr * g.nc;
   double term = 0.0;
@@ -864,7 +867,7 @@ template <int LT, int WD>
 __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, RayF3 f, const uint8_t* __restrict__ lev,
                                             const uint8_t* __restrict__ levC, double* __restrict__ part_max,
                                             double* __restrict__ part_cnt) {
-  const int blk = xcd_rotate(blockIdx.x);
+  const int blk = xcd_rotate(blockIdx.x, kRotate3);
   const int64_t k = int64_t(blk) * kB + threadIdx.x;
   const int64_t M = int64_t(g.nv) * g.nr * g.nc;
   double sum = 0.0, cnt = 0.0;
