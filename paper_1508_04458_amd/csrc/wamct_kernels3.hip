@@ -19,9 +19,9 @@ namespace wamct {
 namespace {
 
 constexpr int kB = 256;
-// Groups of 8 walk blocks an XCD keeps the same part of the detector rows (2^6 groups: 128
+// Groups of 8 walk blocks an XCD keeps the same part of the detector rows (2^8 groups: 512
 // consecutive views of a row; the records they cross stay in its L2).
-constexpr int kRotate3 = 6;
+constexpr int kRotate3 = 8;
 inline int blocks3(int64_t n, int b = kB) { return int((n + b - 1) / b); }
 
 // Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b mod 8), each XCD with
@@ -745,8 +745,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   __shared__ double sh[4][kSlots3][64];
   int start, count;
   seg_range3(a, start, count);
-  const int n_ig = (a.count + 63) / 64;
-  const int ig = blockIdx.x % n_ig, group = blockIdx.x / n_ig;
+  // Block 8 j + x runs on XCD x (round-robin dispatch): it takes view-chunk group j / per and
+  // item group x per + j mod per (item groups padded to 8 per, the padding without items), so
+  // at any time an XCD works on one compact region of the volume, whose rays overlap in its L2
+  const int n_ig = (a.count + 63) / 64, per = (n_ig + 7) >> 3;
+  const int jj = int(blockIdx.x >> 3);
+  const int group = jj / per, ig = int(blockIdx.x & 7) * per + jj % per;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int idx = ig * 64 + lane, chunk = group * 4 + wv;
   Sums3<double> r;
@@ -1013,7 +1017,8 @@ static void gather_seg3(const GArgs3<T>& a, const Segment& sg, hipStream_t s) {
     return;
   }
   const int groups = (sg.chunks + 3) / 4;
-  hipLaunchKernelGGL((k3_gather_part<T, SPLIT, WD>), dim3(((sg.count + 63) / 64) * groups), dim3(256), 0, s, a);
+  const int per = ((sg.count + 63) / 64 + 7) >> 3;   // item groups per XCD (k3_gather_part)
+  hipLaunchKernelGGL((k3_gather_part<T, SPLIT, WD>), dim3(8 * per * groups), dim3(256), 0, s, a);
   hipLaunchKernelGGL((k3_gather_finish<T, MODE, WD>), dim3((sg.count + 63) / 64), dim3(1024), 0, s, a);
 }
 template <typename T, int MODE>
