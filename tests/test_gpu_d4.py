@@ -289,3 +289,48 @@ def test_unsupported_combinations_fail_cleanly():
     # the context still works after the rejected calls
     idv = host(c.solve(3, [1], 0.1))
     assert np.all(np.isfinite(idv))
+
+
+def draw_d4(seed):
+    """A random 2-D configuration for the Daubechies-4 basis: levels 1-3 with n >> L in
+    4..10 (n up to 80), parallel or fan beam, odd and even view and bin counts, phantom and
+    Poisson counts as for the named workloads, a random expansion schedule."""
+    rng = np.random.default_rng([seed, 4044])
+    L = int(rng.integers(1, 4))
+    n = int(rng.integers(4, 11)) * (1 << L)
+    if n > 80:
+        n = 80 // (1 << L) * (1 << L)
+    views = int(rng.integers(7, 61))
+    i0 = float(rng.choice([2e3, 1e4, 5e4]))
+    if rng.uniform() < 0.5:
+        bins = int(rng.integers(int(1.45 * n), int(1.45 * n) + 9))
+        g = synth.parallel_geometry(n, views, bins, 1.0)
+    else:
+        bins = int(rng.integers(n, 2 * n + 1))
+        g = synth.fan_geometry(n, views, bins, sod=4.0 * n, sdd=7.0 * n)
+    ell = synth.make_ellipses(rng, n, g.pixel, int(rng.integers(2, 7)), 0.06, int(rng.integers(0, 2)))
+    o, e = synth.ray_lines(g)
+    d = rng.poisson(i0 * np.exp(-synth.line_integrals(ell, o, e))).astype(np.float64)
+    n_it = int(rng.integers(6, 13))
+    sched = sorted(set(int(x) for x in rng.integers(1, n_it, size=min(L, 3))))
+    return g, L, d, i0, n_it, sched
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_d4_solve_fp64(seed):
+    """Whole FP64 solves on random configurations with the GPU's own expansions: masks exact,
+    beta relative L2 1e-9, I-divergence rtol 1e-10, held counts equal."""
+    from paper_1508_04458_amd import api
+    g, L, d, i0, n_it, sched = draw_d4(seed)
+    print(f"\n[case] d4 seed {seed}: kind {g.kind} n={g.n} L={L} views={g.n_views} bins={g.n_bins} "
+          f"iters {n_it} schedule {sched}", flush=True)
+    H = siddon.system_matrix(g)
+    ref = wam.wam_solve(H, g.n, L, d, i0, n_it, g.pixel, schedule=sched, Omega=omega(g.n, L))
+    c = api.Context(g, L, "f64", wavelet="d4")
+    c.set_data(dev(d, "f64"), i0)
+    idv = host(c.solve(n_it, sched, 0.1))
+    beta, mask, _ = c.get_state()
+    np.testing.assert_array_equal(host(mask), ref["mask"])
+    assert rel_l2(host(beta), ref["beta"]) <= 1e-9
+    np.testing.assert_allclose(idv, ref["idiv"], rtol=1e-10)
+    assert c.tree_stats()["n_held"] == ref["held"]
