@@ -473,6 +473,9 @@ struct Ctx final : wamct_ctx {
     nb_pix = int((NN + 255) / 256);
     // the tree walk may use 4 lanes per ray; walk grids are padded to a multiple of 8 blocks
     np = std::max(4 * nb_rays, nb_pix) + 8;
+    // image-domain AM (levels = 0): the pixel gather has cheap items and many of them; finer
+    // view chunks (2^23 lanes instead of 2^20) measured 0.89 -> 0.73 ms per pass at fan512
+    if (g.L == 0) target_lanes = 1 << 23;
     d4 = O.wavelet == WAMCT_D4;
     if (hipHostMalloc((void**)&h_ints, sizeof(int) * kInts * P, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&h_scal, sizeof(double) * kScal * P, hipHostMallocDefault) != hipSuccess) {

@@ -323,8 +323,11 @@ __global__ __launch_bounds__(256) void k_transpose(int n, const T* __restrict__ 
 // walk runs KB steps ahead recording chord and address, then issues the KB loads together
 // (KB loads in flight per lane instead of one dependent load per step). Rays travelling
 // mostly along x read the column-major copy of the image, so neighbouring lanes touch
-// consecutive addresses.
-template <typename T, typename R, int KB>
+// consecutive addresses. K adjacent lanes share a ray: lane k walks the k-th of K equal parts
+// of its parameter interval inside the image (from the pixel holding the part's start; a pixel
+// one behind at a plane gives a zero chord and moves on), and the parts are added by a fixed
+// shuffle.
+template <typename T, typename R, int KB, int K>
 __global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4<R>::t* __restrict__ A,
                                                     const typename V4<R>::t* __restrict__ B,
                                                     const T* __restrict__ muR, const T* __restrict__ muC,
@@ -339,10 +342,13 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4
     d = at(d, orr); i0v = at(i0v, orr); q = at(q, orr); pout = at(pout, orr);
   }
   const int rb = xcd_rotate(blockIdx.x);
-  const int k = rb * kBlock + threadIdx.x;
+  const int lane_id = rb * kBlock + threadIdx.x;
+  const int k = lane_id / K, piece = lane_id % K;
   const int r = subset_ray(g, k);
   double term = 0.0;
-  if (k < g.nvs * g.nb) {
+  const bool valid = k < g.nvs * g.nb;
+  R acc = R(0);
+  if (valid) {
     const typename V4<R>::t a = A[r];
     const typename V4<R>::t bb = B[r];
     const R ox = a.x, oy = a.y, iex = a.z, iey = a.w, ex = bb.x, ey = bb.y;
@@ -350,10 +356,12 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4
     const R pix = R(g.pixel), ipix = R(1.0 / g.pixel), hn = R(0.5 * n), half = R(0.5 * n * g.pixel);
     const R tx0 = (-half - ox) * iex, tx1 = (half - ox) * iex;
     const R ty0 = (-half - oy) * iey, ty1 = (half - oy) * iey;
-    const R t_in = fmax(fmin(tx0, tx1), fmin(ty0, ty1));
-    const R t_out = fmin(fmax(tx0, tx1), fmax(ty0, ty1));
-    R acc = R(0);
-    if (t_out > t_in) {
+    const R t_enter = fmax(fmin(tx0, tx1), fmin(ty0, ty1));
+    const R t_exit = fmin(fmax(tx0, tx1), fmax(ty0, ty1));
+    // this lane's part [t_in, t_out) of the path
+    const R t_in = piece == 0 ? t_enter : t_enter + (t_exit - t_enter) * (R(piece) / R(K));
+    const R t_out = piece == K - 1 ? t_exit : t_enter + (t_exit - t_enter) * (R(piece + 1) / R(K));
+    if (t_exit > t_enter) {
       int ix = (int)floor(fmin(fmax((ox + t_in * ex) * ipix + hn, R(-1)), R(n)));
       int iy = (int)floor(fmin(fmax((oy + t_in * ey) * ipix + hn, R(-1)), R(n)));
       ix = imin(imax(ix, 0), n - 1);
@@ -392,6 +400,11 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4
         for (int k = 0; k < KB; ++k) acc += ch[k] * R(mv[k]);
       }
     }
+  }
+  // the K parts of a ray, added in a fixed order (every lane of the group gets the total)
+#pragma unroll
+  for (int o = 1; o < K; o <<= 1) acc += __shfl_xor(acc, o, 64);
+  if (valid && piece == 0) {
     const R p = acc;
     if (pout) pout[r] = T(p);
     if (q) {
@@ -1365,9 +1378,17 @@ void Geo<T, R>::view_table(const DevGeom& g, const double2* views, void* vF, hip
 template <typename T, typename R>
 int Geo<T, R>::forward(const DevGeom& g, const void* A, const void* B, const T* muR, const T* muC, const T* d,
                        const T* i0v, const double* i0s, T* q, T* p, double* part, int S, hipStream_t s) {
-  const int nb = xcd_blocks(blocks_for(int64_t(g.nvs) * g.nb));
-  hipLaunchKernelGGL((k_forward<T, R, 8>), dim3(nb, S), dim3(kBlock), 0, s, g, (const typename V4<R>::t*)A,
-                     (const typename V4<R>::t*)B, muR, muC, d, i0v, i0s, q, p, part);
+  // lanes per ray as for the leaf walk (the launch's ray count over all scans)
+  const int k = leaf_pieces(int64_t(g.nvs) * g.nb * S);
+  const int nb = xcd_blocks(blocks_for(int64_t(g.nvs) * g.nb * k));
+  auto a = (const typename V4<R>::t*)A;
+  auto b = (const typename V4<R>::t*)B;
+  if (k == 1)
+    hipLaunchKernelGGL((k_forward<T, R, 8, 1>), dim3(nb, S), dim3(kBlock), 0, s, g, a, b, muR, muC, d, i0v, i0s, q, p, part);
+  else if (k == 2)
+    hipLaunchKernelGGL((k_forward<T, R, 8, 2>), dim3(nb, S), dim3(kBlock), 0, s, g, a, b, muR, muC, d, i0v, i0s, q, p, part);
+  else
+    hipLaunchKernelGGL((k_forward<T, R, 8, 4>), dim3(nb, S), dim3(kBlock), 0, s, g, a, b, muR, muC, d, i0v, i0s, q, p, part);
   return nb;
 }
 // rays per lane group: a launch with fewer than 2^21 rays splits each ray over 2 lanes, one
