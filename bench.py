@@ -82,6 +82,7 @@ KERNEL_SOURCES_2D = ("wamct_kernels.hip", "wamct_geom.h", "wamct_internal.h", "w
                      "wamct_api.hip", "wamct_ctx.h")
 KERNEL_SOURCES_3D = ("wamct_kernels3.hip", "wamct_internal3.h", "wamct_internal.h", "wamct_worklist.h",
                      "wamct_api3.hip", "wamct_ctx.h")
+KERNEL_SOURCES_D4 = ("wamct_d4.hip", "wamct_internal.h", "wamct_api.hip")
 
 
 def kernel_source_hash(files=KERNEL_SOURCES_2D, tiling=None):
@@ -108,7 +109,7 @@ def host_info():
     return {"cpu_model": model, "nproc": os.cpu_count()}
 
 
-def roofline(alg_bytes, ms, traffic, **kw):
+def roofline(alg_bytes, ms, traffic, valu_issue=None, **kw):
     """Roofline object of one launch (or pass) of `ms` milliseconds: `achieved`/`frac` are the
     stored-Phi-equivalent (algorithmic) bytes over the time against the 8 TB/s HBM peak;
     `measured_gbs`/`measured_frac` are the measured memory-side bytes (`traffic`, from the
@@ -121,13 +122,18 @@ def roofline(alg_bytes, ms, traffic, **kw):
         r.update(measured_gbs=round(m, 1), measured_frac=round(m / HBM_PEAK_GBS, 4))
     else:
         r.update(measured_gbs=None, measured_frac=None)
+    # measured VALU issue (wave64 VALU instructions per CU-cycle; a CU issues at most one):
+    # the fraction of the VALU roof the same kernels reach, from the committed counters
+    r["valu_issue_frac"] = valu_issue
     r.update(kw)
     return r
 
 
-def measured_traffic(kernel_hash, config, phase):
-    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) of a phase's kernels
-    from the committed rocprofv3 PMC summary, only if taken on the current kernel source."""
+def measured_traffic(kernel_hash, config, phase, key="bytes_per_launch"):
+    """A phase's measured figure from the committed rocprofv3 summary, only if taken on the
+    current kernel source: HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated;
+    key "bytes_per_launch") or the VALU issue rate (wave64 VALU instructions per CU-cycle,
+    SQ_INSTS_VALU over 256 CUs x the active cycles; key "valu_issue")."""
     path = os.path.join(ROOT, "profiles", f"traffic_{config}.json")
     if not os.path.exists(path):
         return None
@@ -135,7 +141,28 @@ def measured_traffic(kernel_hash, config, phase):
         rec = json.load(f)
     if rec.get("kernel_hash") != kernel_hash:
         return None
-    return rec.get("bytes_per_launch", {}).get(phase)
+    return rec.get(key, {}).get(phase)
+
+
+def measure_copy_peak(dev):
+    """HBM bandwidth of a plain device copy on this GPU (1 GiB, read + write bytes over the
+    HIP-event time of 10 copies after 2 warm-up copies), GB/s: the measured roof beside the
+    8 TB/s published peak."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 10 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
 
 
 GOLD_FAN512 = os.path.join(ROOT, "tests", "golden", "fan512_solve.npz")
@@ -150,7 +177,6 @@ def cpu_baseline(P, n_views_sample):
     the work per iteration is that of the whole scan's, in proportion; otherwise the tree rule
     runs on the subset."""
     import numpy as np
-    from oracle import siddon, wam
     g = P.geom
     step = max(1, g.n_views // n_views_sample)
     views = np.arange(0, g.n_views, step)[:n_views_sample]
@@ -161,20 +187,52 @@ def cpu_baseline(P, n_views_sample):
         nn = g.n * g.n
         mk = np.unpackbits(z["masks"], axis=1)[:, :nn].reshape(-1, g.n, g.n)
         masks = {int(a): mk[k] for k, a in enumerate(z["tree_at"]) if k > 0}
-    H = siddon.system_matrix(g, views=views)
-    t0 = time.perf_counter()
-    r = wam.wam_solve(H, g.n, P.levels, P.d[rows], P.i0, P.n_iters, g.pixel,
-                      schedule=() if masks else P.schedule, masks=masks)
-    dt = time.perf_counter() - t0
+    job = ("fan", g, views, P.levels, P.d[rows], P.i0, P.n_iters, () if masks else tuple(P.schedule), masks)
+    dt, final = _oracle_sample_job(job)
     scale = g.n_views / len(views)
     per_iter = dt * scale / P.n_iters
     trees = ("the whole scan's tree sequence of the oracle (trees at "
              f"{sorted(masks)})" if masks else f"its own tree rule (expansions {P.schedule})")
-    return {"value": 1.0 / per_iter, "unit": "AM iter/s", "cores": 1, "kind": "oracle",
-            "sample": (f"FP64 NumPy/SciPy oracle, Algorithm 1, {P.n_iters} iterations on the rays of "
-                       f"{len(views)} of {g.n_views} views following {trees}; solve time {dt:.1f} s "
-                       f"scaled by {scale:.0f}; setup (H, b) excluded; single thread"),
-            "host": host_info(), "final_idiv_sample": float(r["idiv"][-1])}
+    out = {"value": 1.0 / per_iter, "unit": "AM iter/s", "cores": 1, "kind": "oracle",
+           "sample": (f"FP64 NumPy/SciPy oracle, Algorithm 1, {P.n_iters} iterations on the rays of "
+                      f"{len(views)} of {g.n_views} views following {trees}; solve time {dt:.1f} s "
+                      f"scaled by {scale:.0f}; setup (H, b) excluded; single thread"),
+           "host": host_info(), "final_idiv_sample": final}
+    out["all_cores"] = _oracle_all_cores(job, scale, P.n_iters)
+    return out
+
+
+def _oracle_sample_job(job):
+    """One oracle solve of a CPU-baseline sample (runs in the bench process or in a forked
+    worker; NumPy/SciPy only): builds H (untimed), times Algorithm 1. -> (seconds, final I-div)."""
+    if job[0] == "fan":
+        _, g, views, levels, d, i0, n_iters, schedule, masks = job
+        from oracle import siddon, wam
+        H = siddon.system_matrix(g, views=views)
+        t0 = time.perf_counter()
+        r = wam.wam_solve(H, g.n, levels, d, i0, n_iters, g.pixel, schedule=schedule, masks=masks)
+        return time.perf_counter() - t0, float(r["idiv"][-1])
+    _, g, levels, d, i0, n_iters, schedule = job
+    from oracle import vol3d
+    H = vol3d.system_matrix3(g)
+    t0 = time.perf_counter()
+    r = vol3d.wam_solve3(H, g.n, g.nz, levels, d, i0, n_iters, g.pixel, schedule=schedule)
+    return time.perf_counter() - t0, float(r["idiv"][-1])
+
+
+def _oracle_all_cores(job, scale, n_iters):
+    """The secondary CPU baseline: the same sample solved by W single-threaded worker processes
+    at once (W = the host's logical CPUs, at most 16), each an independent problem; throughput =
+    W samples per the slowest worker's solve time, scaled as the single-thread figure."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    w = max(1, min(16, os.cpu_count() or 1))
+    with cf.ProcessPoolExecutor(w, mp_context=mp.get_context("fork")) as ex:
+        res = list(ex.map(_oracle_sample_job, [job] * w))
+    slowest = max(dt for dt, _ in res)
+    return {"value": w / (slowest * scale / n_iters), "unit": "AM iter/s", "cores": w,
+            "sample": f"{w} concurrent single-threaded solves of the same sample (one per process; slowest "
+                      f"{slowest:.1f} s, fastest {min(dt for dt, _ in res):.1f} s), scaled as the single-thread figure"}
 
 
 def log(msg):
@@ -394,14 +452,11 @@ def cone_cpu_baseline(name, n_full_rays, n_full_side):
     synthesis matrix at full size would not fit a CPU run): Algorithm 1 with the octree rule
     and its schedule; solve time (trees, Phi builds, iterations; not H or b) scaled to the
     full workload by the ratio of rays x volume side (the number of ray-voxel crossings)."""
-    from oracle import vol3d
     from paper_1508_04458_amd import synth
     P = synth.make_cone_problem(name)
     g = P.geom
-    H = vol3d.system_matrix3(g)
-    t0 = time.perf_counter()
-    vol3d.wam_solve3(H, g.n, g.nz, P.levels, P.d, P.i0, P.n_iters, g.pixel, schedule=P.schedule)
-    dt = time.perf_counter() - t0
+    job = ("cone", g, P.levels, P.d, P.i0, P.n_iters, tuple(P.schedule))
+    dt, _ = _oracle_sample_job(job)
     scale = (n_full_rays * n_full_side) / (g.n_rays * g.n)
     per_iter = dt * scale / P.n_iters
     return {"value": 1.0 / per_iter, "unit": "AM iter/s", "cores": 1, "kind": "oracle",
@@ -409,7 +464,7 @@ def cone_cpu_baseline(name, n_full_rays, n_full_side):
                        f"{P.schedule}) on the downscaled case {name} ({g.n}^2 x {g.nz}, {g.n_views} views of "
                        f"{g.n_rows} x {g.n_cols}); solve time {dt:.1f} s scaled by rays x side = {scale:.0f}; "
                        f"setup (H, b) excluded; single thread"),
-            "host": host_info()}
+            "host": host_info(), "all_cores": _oracle_all_cores(job, scale, P.n_iters)}
 
 
 def bench_cone(args):
@@ -488,10 +543,12 @@ def bench_cone(args):
     up_ms = up["ms"] / max(1, J * args.steps)
     alg_fw = 8.0 * w_avg + 4.0 * active_avg + 8.0 * M
     alg_up = 8.0 * w_avg + 4.0 * M + 12.0 * active_avg
-    r_fw = roofline(alg_fw, fw_ms, measured_traffic(khash, args.config, "forward"), kernel="k3_forward<float>",
+    r_fw = roofline(alg_fw, fw_ms, measured_traffic(khash, args.config, "forward"),
+                    measured_traffic(khash, args.config, "forward", "valu_issue"), kernel="k3_forward<float>",
                     avg_launch_ms=round(fw_ms, 4), launches=fw["launches"], alg_bytes_per_launch=int(alg_fw),
                     kernel_hash=khash)
     r_up = roofline(alg_up, up_ms, measured_traffic(khash, args.config, "update"),
+                    measured_traffic(khash, args.config, "update", "valu_issue"),
                     kernels="k3_gather_part + k3_gather_finish per octree level", avg_pass_ms=round(up_ms, 4),
                     passes=J * args.steps, alg_bytes_per_pass=int(alg_up), kernel_hash=khash)
     dominant = "update" if up["ms"] >= fw["ms"] else "forward"
@@ -695,7 +752,8 @@ def bench_fan(args, config, steps, warmup):
     fw_ms = fw["ms"] / max(1, fw["launches"])
     alg_fw = 8.0 * w_update_avg + 4.0 * active_avg + 8.0 * M
     khash = kernel_source_hash(KERNEL_SOURCES_2D, ctx.tiling())
-    roof = roofline(alg_fw, fw_ms, measured_traffic(khash, config, "forward"), kernel="k_forward_rec<float,double>",
+    roof = roofline(alg_fw, fw_ms, measured_traffic(khash, config, "forward"),
+                    measured_traffic(khash, config, "forward", "valu_issue"), kernel="k_forward_rec<float,double>",
                     avg_launch_ms=round(fw_ms, 5), launches=fw["launches"], alg_bytes_per_launch=int(alg_fw),
                     kernel_hash=khash)
     # the update pass (sign-split backprojection + eq. 1.9 zero; one or two kernels per level)
@@ -703,6 +761,7 @@ def bench_fan(args, config, steps, warmup):
     upd_ms = up["ms"] / max(1, up["launches"])
     alg_up = 8.0 * w_update_avg + 4.0 * M + 12.0 * active_avg
     roof_up = roofline(alg_up, upd_ms, measured_traffic(khash, config, "update"),
+                       measured_traffic(khash, config, "update", "valu_issue"),
                        kernels="k_gather_part + k_gather_finish over the chunked tree levels (+ k_gather per "
                                "level that fills the GPU alone)",
                        avg_pass_ms=round(upd_ms, 5), passes=up["launches"], alg_bytes_per_pass=int(alg_up))
@@ -847,6 +906,7 @@ def bench_fan(args, config, steps, warmup):
         d_w = sum(x["w"] * x["iters"] for x in dseg) / J
         d_act = sum(x["n_active"] * x["iters"] for x in dseg) / J
         d_alg = 8.0 * d_w + 4.0 * M + 12.0 * d_act
+        d4hash = kernel_source_hash(KERNEL_SOURCES_D4, None)
         hit = np.nonzero(tr <= dtr[-1])[0]
         k_h = int(hit[0]) if hit.size else None
         out["wavelet_d4"] = {
@@ -854,7 +914,8 @@ def bench_fan(args, config, steps, warmup):
             "final_idiv": float(dtr[-1]), "trees": dseg,
             "haar_iters_to_d4_final_idiv": k_h,
             "haar_time_to_d4_final_idiv_ms": None if k_h is None else round(k_h * ms_step / J, 3),
-            "roofline_update": roofline(d_alg, d_upd_ms, None,
+            "roofline_update": roofline(d_alg, d_upd_ms, measured_traffic(d4hash, "d4_fan512", "update"),
+                                        measured_traffic(d4hash, "d4_fan512", "update", "valu_issue"),
                                         kernels="k_d4_gather (one wave per work item, support walk)",
                                         avg_pass_ms=round(d_upd_ms, 5), passes=dtim["launches"],
                                         alg_bytes_per_pass=int(d_alg),
@@ -891,6 +952,7 @@ def main():
             os.environ[k] = "1"
     import torch
     dev = torch.device("cuda", 0)
+    copy_gbs = measure_copy_peak(dev)
     if args.config.startswith("cone"):
         out = bench_cone(args)
         if args.config == "cone512" and not args.no_fan512:
@@ -907,6 +969,7 @@ def main():
             out["uneven"] = un
     else:
         out = bench_fan(args, args.config, args.steps, args.warmup)
+    out["hbm_copy_peak_gbs"] = copy_gbs
     copy_calibration(args, dev, out)
     print(json.dumps(out), flush=True)
 
