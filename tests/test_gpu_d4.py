@@ -334,3 +334,46 @@ def test_random_d4_solve_fp64(seed):
     assert rel_l2(host(beta), ref["beta"]) <= 1e-9
     np.testing.assert_allclose(idv, ref["idiv"], rtol=1e-10)
     assert c.tree_stats()["n_held"] == ref["held"]
+
+
+def test_tree_schedule_fp64_matches_oracle():
+    """The oracle's tree sequence Z_s^(j) given as Algorithm 1's input through the device-side
+    schedule (no host round trip of the state): beta 1e-9, I-divergence rtol 1e-10."""
+    P, H = problem("fan96")
+    g = P.geom
+    L = 3
+    O = omega(g.n, L)
+    ref = wam.wam_solve(H, g.n, L, P.d, P.i0, P.n_iters, g.pixel, schedule=P.schedule, Omega=O)
+    trees = ref["trees"][1:]
+    c = make_ctx(g, L, "f64", P.d, P.i0)
+    masks = torch.stack([dev(m.ravel(), torch.uint8) for _, m in trees])
+    c.set_tree_schedule([j for j, _ in trees], masks)
+    idv = host(c.solve(P.n_iters, [], 0.1))
+    beta, mask, _ = c.get_state()
+    np.testing.assert_array_equal(host(mask), ref["mask"])
+    assert rel_l2(host(beta), ref["beta"]) <= 1e-9
+    np.testing.assert_allclose(idv, ref["idiv"], rtol=1e-10)
+
+
+def test_batch_with_haar_and_d4_contexts_equals_each_alone():
+    """A Daubechies-4 context and a Haar context in one batch (graph replay on two streams):
+    each reproduces its own solve bit for bit (FP32)."""
+    from paper_1508_04458_amd import api
+    P, _ = problem("fan96")
+    g = P.geom
+    ctxs = [api.Context(g, 3, "f32", wavelet="d4"), api.Context(g, 3, "f32")]
+    alone = []
+    for c in ctxs:
+        c.set_data(dev(P.d, "f32"), P.i0)
+        idv = host(c.solve(P.n_iters, P.schedule, 0.1))
+        alone.append((idv, host(c.get_state()[0]), host(c.get_state()[1])))
+        c.reset()
+    batch = api.Batch(ctxs, n_streams=2, graph=True)
+    out = batch.solve(P.n_iters, P.schedule, 0.1)
+    for c, (idv, beta, mask), got in zip(ctxs, alone, out):
+        b2, m2, it = c.get_state()
+        assert it == P.n_iters
+        np.testing.assert_array_equal(host(got), idv)
+        np.testing.assert_array_equal(host(b2), beta)
+        np.testing.assert_array_equal(host(m2), mask)
+    assert batch.stats()["graph_launches"] == P.n_iters
