@@ -595,11 +595,14 @@ def bench_cone(args):
         s_tr = slc.solve(J, sched, 0.1).cpu().numpy()          # traced run (untimed)
         s_st = slc.tree_stats()
         torch.cuda.synchronize()
+        slc.timing(True)
         t4 = time.perf_counter()
         slc.reset()
         slc.solve(J, sched, 0.1, trace=False)
         torch.cuda.synchronize()
         t_sl = time.perf_counter() - t4
+        s_tim = slc.get_timing()
+        slc.timing(False)
         hit = np.nonzero(s_tr <= tr[-1])[0]
         k_sl = int(hit[0]) if hit.size else None
         out["slices"] = {
@@ -608,7 +611,8 @@ def bench_cone(args):
             "final_idiv": float(s_tr[-1]), "final_active": int(s_st["n_active"]), "final_w": int(s_st["w"]),
             "idiv_decreasing": bool(np.all(np.diff(s_tr) <= 1e-6 * np.abs(s_tr[:-1]))),
             "iters_to_octree_final_idiv": k_sl,
-            "time_to_octree_final_idiv_ms": None if k_sl is None else round(k_sl * t_sl / J * 1e3, 1)}
+            "time_to_octree_final_idiv_ms": None if k_sl is None else round(k_sl * t_sl / J * 1e3, 1),
+            "time_ms_per_solve_by_kernel": {k: round(v["ms"], 2) for k, v in s_tim.items()}}
         slc.close()
         log(f"per-slice 2-D Haar: {J / t_sl:.3f} it/s, final I-div {s_tr[-1]:.4e} (octree {tr[-1]:.4e})")
     if not args.no_full_am:
