@@ -68,6 +68,15 @@ __device__ inline R ordered_sum(const R* __restrict__ x, int n, size_t stride) {
   return s;
 }
 
+// v with its sign flipped where s is negative (s = -0.0 counts as negative): one integer op
+// on the sign bit, for the direction-dependent signs of the Haar detail integrals.
+__device__ inline double xsign(double v, double s) {
+  return __longlong_as_double(__double_as_longlong(v) ^ (__double_as_longlong(s) & (1ll << 63)));
+}
+__device__ inline float xsign(float v, float s) {
+  return __int_as_float(__float_as_int(v) ^ (__float_as_int(s) & int(0x80000000u)));
+}
+
 // Positive root t of bp t^2 - b t + bm = 0 (eq. 1.9 with t = exp(-Z0 (beta - beta_hat)))
 // -> delta = -ln(t) / Z0. Cases (bp >= 0 >= bm): bp > 0 uses the cancellation-free form
 // of the quadratic root; bp = 0 > bm is linear (t = bm / b); bp = bm = 0 means no ray sees

@@ -556,9 +556,10 @@ __global__ __launch_bounds__(kBlock) void k_idiv_terms(int M, const T* __restric
 // Sums of one work item over a range of views. For every view the item's box is projected
 // onto the detector (its four corners bound the bins whose rays can hit it; FP32 suffices
 // for this bound, which is widened by 1e-3 bin), and for each such ray the chord through
-// the box, or through its four quadrants, is computed in R by slab clipping with the same
-// ray table as the forward pass. Details of node (l, i, j) have phi = 2^-l sum_q s_k(q)
-// chord(q); an approximation has 2^-L chord(box). The sign split of eq. 1.10 is taken per
+// the box is computed in R by slab clipping with the same ray table as the forward pass, and
+// for a split node the quadrant combinations from the box interval and the ray's crossings of
+// the box's mid-lines. Details of node (l, i, j) have phi = 2^-l sum_q s_k(q) chord(q); an
+// approximation has 2^-L chord(box). The sign split of eq. 1.10 is taken per
 // (ray, coefficient), so b-hat+ and b-hat- need no atomics.
 template <typename R>
 struct ItemSums {
@@ -630,18 +631,24 @@ __device__ inline ItemSums<R> item_sums_k(const DevGeom& g, const float2* __rest
         const R ch = hi - lo;
         r.acc += ch > tq ? yv * ch : R(0);
       } else {
+        // Box interval [lo, hi] and the mid-line crossings clamped into it: along x the ray is
+        // in the left half on one side of cx (before cx when it moves towards +x), so the
+        // quadrant combinations (+ on the lower half) are lengths between the crossings:
+        // x: s_x (2 cx - lo - hi), y: s_y (2 cy - lo - hi), xy: s_x s_y (hi - lo - 2 |cx - cy|),
+        // with s the sign of the ray's direction along the axis.
         const R tx1 = (dx1 - ox) * a.z, ty1 = (dy1 - oy) * a.w;
-        const R xl0 = fmin(tx0, tx1), xh0 = fmax(tx0, tx1), xl1 = fmin(tx1, tx2), xh1 = fmax(tx1, tx2);
-        const R yl0 = fmin(ty0, ty1), yh0 = fmax(ty0, ty1), yl1 = fmin(ty1, ty2), yh1 = fmax(ty1, ty2);
-        const R cTL = fmax(fmin(xh0, yh0) - fmax(xl0, yl0), R(0));
-        const R cTR = fmax(fmin(xh1, yh0) - fmax(xl1, yl0), R(0));
-        const R cBL = fmax(fmin(xh0, yh1) - fmax(xl0, yl1), R(0));
-        const R cBR = fmax(fmin(xh1, yh1) - fmax(xl1, yl1), R(0));
-        const R u1 = cTL - cTR, u2 = cBL - cBR, w1v = cTL + cTR, w2v = cBL + cBR;
-        const R p1 = u1 + u2, p2 = w1v - w2v, p3 = u1 - u2, pb = w1v + w2v;
-        const R w1 = fabs(p1) > tq ? yv * p1 : R(0), w2 = fabs(p2) > tq ? yv * p2 : R(0);
-        const R w3 = fabs(p3) > tq ? yv * p3 : R(0);
-        r.acc += pb > tq ? yv * pb : R(0);
+        const R lo = fmax(fmin(tx0, tx2), fmin(ty0, ty2));
+        const R hi = fmin(fmax(tx0, tx2), fmax(ty0, ty2));
+        const R pb = hi - lo;
+        // a ray that misses the box adds nothing (its values below stay finite, times 0)
+        const R yq = pb > tq ? yv : R(0);
+        const R cx = fmin(fmax(tx1, lo), hi), cy = fmin(fmax(ty1, lo), hi);
+        const R lh = lo + hi;
+        const R p1 = xsign(R(2) * cx - lh, a.z), p2 = xsign(R(2) * cy - lh, a.w);
+        const R p3 = xsign(pb - R(2) * fabs(cx - cy), xsign(a.z, a.w));
+        const R w1 = fabs(p1) > tq ? yq * p1 : R(0), w2 = fabs(p2) > tq ? yq * p2 : R(0);
+        const R w3 = fabs(p3) > tq ? yq * p3 : R(0);
+        r.acc += yq * pb;
         r.s0 += w1; r.a0 += fabs(w1);
         r.s1 += w2; r.a1 += fabs(w2);
         r.s2 += w3; r.a2 += fabs(w3);

@@ -506,13 +506,14 @@ __global__ __launch_bounds__(kB) void k3_scale_rays(DevGeom3 g, const T* __restr
 
 // Sums of one item over views [v0, v1). Per view the item box's eight corners are projected
 // onto the detector (FP32 with the hardware reciprocal, widened by 1e-3 element) to bound the
-// rows and columns whose rays can cross it; per such ray the parameter intervals of the box,
-// or of its eight octants, come from slab clipping in FP64 (z slabs once per row), and the
-// seven detail values from a 2x2x2 Haar butterfly of the octant chords. Per detail the signed
-// sum S and the sum of magnitudes A are kept: the positive part is (A + S) / 2 and the
-// negative part (S - A) / 2 (per (ray, coefficient) sign split, eq. 1.10).
-// WD = 2 (2-D Haar per slice): the node box is one voxel deep, split nodes take the chords of
-// their four quadrants (one z slab) and the three details of a 2x2 butterfly (scale 2^-l).
+// rows and columns whose rays can cross it; per such ray the parameter interval of the box
+// comes from slab clipping in FP64 (z slabs once per row), and the seven detail values (the
+// 2x2x2 Haar combinations of the octant chords) from the box interval and the ray's three
+// mid-plane crossings. Per detail the signed sum S and the sum of magnitudes A are kept: the
+// positive part is (A + S) / 2 and the negative part (S - A) / 2 (per (ray, coefficient) sign
+// split, eq. 1.10).
+// WD = 2 (2-D Haar per slice): the node box is one voxel deep, split nodes take the three
+// details of its four quadrants (one z slab, the x and y crossings; scale 2^-l).
 template <typename T, bool SPLIT, int WD>
 __device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __restrict__ views,
                                            const double2* __restrict__ colt, const double* __restrict__ rowt,
@@ -572,62 +573,45 @@ __device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __r
         }
         continue;
       }
-      if (WD == 2) {
-        const double zlo = fmin(tz0, tz2), zhi = fmax(tz0, tz2);
-        for (int col = clo; col <= chi; ++col) {
-          const double2 cd = cv[col];
-          const double yv = double(yr[col]);
-          const double tx0 = ax0 * cd.x, tx1 = ax1 * cd.x, tx2 = ax2 * cd.x;
-          const double ty0 = ay0 * cd.y, ty1 = ay1 * cd.y, ty2 = ay2 * cd.y;
-          const double xl[2] = {fmin(tx0, tx1), fmin(tx1, tx2)}, xh[2] = {fmax(tx0, tx1), fmax(tx1, tx2)};
-          const double yl[2] = {fmin(ty0, ty1), fmin(ty1, ty2)}, yh[2] = {fmax(ty0, ty1), fmax(ty1, ty2)};
-          double ch[4];   // quadrant (by, bx) chords in the slice's z slab
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            ch[q] = fmax(fmin(fmin(xh[q & 1], yh[q >> 1]), zhi) - fmax(fmax(xl[q & 1], yl[q >> 1]), zlo), 0.0);
-          // types t = 1 (x), 2 (y), 3 (x and y): + on the lower half, - on the upper half
-          const double det[3] = {ch[0] - ch[1] + ch[2] - ch[3], ch[0] + ch[1] - ch[2] - ch[3],
-                                 ch[0] - ch[1] - ch[2] + ch[3]};
-          const double box = ch[0] + ch[1] + ch[2] + ch[3];
-          r.v[0] += box > tq ? yv * box : 0.0;
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            const double wv = fabs(det[d]) > tq ? yv * det[d] : 0.0;
-            r.v[1 + d] += wv;
-            r.v[8 + d] += fabs(wv);
-          }
-        }
-        continue;
-      }
-      const double tz1 = Z1 * iz;
-      const double zl[2] = {fmin(tz0, tz1), fmin(tz1, tz2)}, zh[2] = {fmax(tz0, tz1), fmax(tz1, tz2)};
+      // Per ray: the box's parameter interval [lo, hi] and the mid-plane crossings clamped
+      // into it. Along an axis the ray is in the lower half on one side of its crossing c
+      // (before c when it moves up that axis, after c otherwise), so the signed length of a
+      // product of half indicators (+ lower, - upper) is a sum of lengths between the sorted
+      // crossings: one axis s (2 c - lo - hi), two axes s s' (hi - lo - 2 |c - c'|), three
+      // axes s s' s'' (2 (c1 - c2 + c3) - lo - hi) with c1 <= c2 <= c3 and s the sign of the
+      // ray's direction along the axis. These are the butterfly outputs of the octant chords
+      // without forming the chords.
+      const double zlo = fmin(tz0, tz2), zhi = fmax(tz0, tz2);
+      const double tz1 = WD == 3 ? Z1 * iz : 0.0;
       for (int col = clo; col <= chi; ++col) {
         const double2 cd = cv[col];
-        const double yv = double(yr[col]);
         const double tx0 = ax0 * cd.x, tx1 = ax1 * cd.x, tx2 = ax2 * cd.x;
         const double ty0 = ay0 * cd.y, ty1 = ay1 * cd.y, ty2 = ay2 * cd.y;
-        const double xl[2] = {fmin(tx0, tx1), fmin(tx1, tx2)}, xh[2] = {fmax(tx0, tx1), fmax(tx1, tx2)};
-        const double yl[2] = {fmin(ty0, ty1), fmin(ty1, ty2)}, yh[2] = {fmax(ty0, ty1), fmax(ty1, ty2)};
-        double lq[4], hq[4];   // xy quarter (by, bx) intervals
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          lq[q] = fmax(xl[q & 1], yl[q >> 1]);
-          hq[q] = fmin(xh[q & 1], yh[q >> 1]);
+        const double lo = fmax(fmax(fmin(tx0, tx2), fmin(ty0, ty2)), zlo);
+        const double hi = fmin(fmin(fmax(tx0, tx2), fmax(ty0, ty2)), zhi);
+        const double box = hi - lo;
+        // a ray that misses the box (or grazes it within the residue) adds nothing; the values
+        // below stay finite for it and are multiplied by 0
+        const double yl = double(yr[col]);
+        const double yv = box > tq ? yl : 0.0;
+        const double cx = fmin(fmax(tx1, lo), hi), cy = fmin(fmax(ty1, lo), hi);
+        const double lh = lo + hi;
+        const double sxy = xsign(cd.x, cd.y);   // sign of the product of the x and y directions
+        double det[7];
+        det[0] = xsign(2.0 * cx - lh, cd.x);
+        det[1] = xsign(2.0 * cy - lh, cd.y);
+        det[2] = xsign(box - 2.0 * fabs(cx - cy), sxy);
+        if (WD == 3) {
+          const double cz = fmin(fmax(tz1, lo), hi);
+          const double med = fmax(fmin(cx, cy), fmin(fmax(cx, cy), cz));
+          det[3] = xsign(2.0 * cz - lh, iz);
+          det[4] = xsign(xsign(box - 2.0 * fabs(cx - cz), cd.x), iz);
+          det[5] = xsign(xsign(box - 2.0 * fabs(cy - cz), cd.y), iz);
+          det[6] = xsign(xsign(2.0 * (cx + cy + cz - 2.0 * med) - lh, sxy), iz);
         }
-        double ch[8];
+        r.v[0] += yv * box;
 #pragma unroll
-        for (int o = 0; o < 8; ++o) ch[o] = fmax(fmin(hq[o & 3], zh[o >> 2]) - fmax(lq[o & 3], zl[o >> 2]), 0.0);
-        // 2x2x2 butterfly: x, then y, then z (lower half +, upper half -)
-        double s1[4], d1[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) { s1[q] = ch[2 * q] + ch[2 * q + 1]; d1[q] = ch[2 * q] - ch[2 * q + 1]; }
-        const double ss0 = s1[0] + s1[1], sd0 = s1[0] - s1[1], ds0 = d1[0] + d1[1], dd0 = d1[0] - d1[1];
-        const double ss1 = s1[2] + s1[3], sd1 = s1[2] - s1[3], ds1 = d1[2] + d1[3], dd1 = d1[2] - d1[3];
-        const double det[7] = {ds0 + ds1, sd0 + sd1, dd0 + dd1, ss0 - ss1, ds0 - ds1, sd0 - sd1, dd0 - dd1};
-        const double box = ss0 + ss1;
-        r.v[0] += box > tq ? yv * box : 0.0;
-#pragma unroll
-        for (int d = 0; d < 7; ++d) {
+        for (int d = 0; d < n_details<WD>(); ++d) {
           const double wv = fabs(det[d]) > tq ? yv * det[d] : 0.0;
           r.v[1 + d] += wv;
           r.v[8 + d] += fabs(wv);
