@@ -563,12 +563,28 @@ __device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __r
       const T* __restrict__ yr = y + (int64_t(v) * g.nr + row) * g.nc;
       if (!SPLIT) {
         const double zlo = fmin(tz0, tz2), zhi = fmax(tz0, tz2);
-        for (int col = clo; col <= chi; ++col) {
-          const double2 cd = cv[col];
+        const auto chord = [&](double2 cd) {
           const double tx0 = ax0 * cd.x, tx2 = ax2 * cd.x, ty0 = ay0 * cd.y, ty2 = ay2 * cd.y;
           const double lo = fmax(fmax(fmin(tx0, tx2), fmin(ty0, ty2)), zlo);
           const double hi = fmin(fmin(fmax(tx0, tx2), fmax(ty0, ty2)), zhi);
-          const double chd = hi - lo;
+          return hi - lo;
+        };
+        // columns four at a time with all eight loads issued before the first use (one
+        // memory wait per four rays instead of two per ray); sums in column order
+        int col = clo;
+        for (; col + 3 <= chi; col += 4) {
+          double2 cd[4];
+          T yy[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) { cd[u] = cv[col + u]; yy[u] = yr[col + u]; }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double chd = chord(cd[u]);
+            r.v[0] += chd > tq ? double(yy[u]) * chd : 0.0;
+          }
+        }
+        for (; col <= chi; ++col) {
+          const double chd = chord(cv[col]);
           r.v[0] += chd > tq ? double(yr[col]) * chd : 0.0;
         }
         continue;
