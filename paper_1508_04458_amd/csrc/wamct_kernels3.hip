@@ -377,28 +377,47 @@ struct Walker3 {
     z = min(max(int(fma(t_in, uz, z0)), 0), nz - 1);
     return true;
   }
+  int i0, dx, dy, dz;  // record index = i0 + dx x + dy y + dz z (mirrored voxel), see layout
   __device__ int real_x(int m) const { return (m ^ xx) + ax; }
   __device__ int real_y(int m) const { return (m ^ xy) + ay; }
   __device__ int real_z(int m) const { return (m ^ xz) + az; }
   __device__ int rx() const { return real_x(x); }
   __device__ int ry() const { return real_y(y); }
   __device__ int rz() const { return real_z(z); }
+  // Per-voxel arrays in [z][x][y] (x-major) or [z][y][x] order: along each axis the real index
+  // is c + s m of the mirrored one (c = 0, s = 1, or c = size - 1, s = -1), so the flat index
+  // is linear in the mirrored coordinates with signed per-ray strides.
+  __device__ void layout(bool xmaj) {
+    const int cxr = ax + xx, cyr = ay + xy, czr = az + xz;
+    const int sx = 2 * xx + 1, sy = 2 * xy + 1, sz = 2 * xz + 1;
+    i0 = xmaj ? (czr * n + cxr) * n + cyr : (czr * n + cyr) * n + cxr;
+    dx = xmaj ? sx * n : sx;
+    dy = xmaj ? sy : sy * n;
+    dz = sz * n * n;
+  }
+  // flat index of mirrored voxel (x, y, z), clamped into the volume (a walk's last step may
+  // leave it)
+  __device__ unsigned index(int x_, int y_, int z_) const {
+    return unsigned(i0 + __mul24(dx, min(x_, n - 1)) + __mul24(dy, min(y_, n - 1)) + __mul24(dz, min(z_, nz - 1)));
+  }
   // Leaves the current leaf (level l): chord = parameter length inside it; returns whether the
   // walk goes on (then x, y, z is a voxel of the next leaf; else possibly out of range).
   __device__ bool step(int l, double& chord) {
-    const int s = 1 << l, sz = WD == 3 ? s : 1;
-    const int ex_ = (x & -s) + s, ey_ = (y & -s) + s, ez_ = (z & -sz) + sz;
-    const double tX = fma(double(ex_), kx, cx), tY = fma(double(ey_), ky, cy), tZ = fma(double(ez_), kz, cz);
+    const int m = (1 << l) - 1;
+    // last voxel of the leaf along each axis (leaf boundaries are multiples of 2^l)
+    const int hx = x | m, hy = y | m, hz = WD == 3 ? (z | m) : z;
+    const double tX = fma(double(hx + 1), kx, cx), tY = fma(double(hy + 1), ky, cy);
+    const double tZ = fma(double(hz + 1), kz, cz);
     const bool ax0 = tX <= tY && tX <= tZ;
     const bool ax1 = !ax0 && tY <= tZ;
     const double te = fmax(fmin(fmin(tX, fmin(tY, tZ)), t_out), t);
     chord = te - t;
-    int nx = min(max(int(fma(te, ux, x0)), x), ex_ - 1);
-    int ny = min(max(int(fma(te, uy, y0)), y), ey_ - 1);
-    int nzv = min(max(int(fma(te, uz, z0)), z), ez_ - 1);
-    nx = ax0 ? ex_ : nx;
-    ny = ax1 ? ey_ : ny;
-    nzv = (!ax0 && !ax1) ? ez_ : nzv;
+    int nx = min(max(int(fma(te, ux, x0)), x), hx);
+    int ny = min(max(int(fma(te, uy, y0)), y), hy);
+    int nzv = min(max(int(fma(te, uz, z0)), z), hz);
+    nx = ax0 ? hx + 1 : nx;
+    ny = ax1 ? hy + 1 : ny;
+    nzv = (!ax0 && !ax1) ? hz + 1 : nzv;
     t = te; x = nx; y = ny; z = nzv;
     return te < t_out && nx < n && ny < n && nzv < nz;
   }
@@ -426,17 +445,12 @@ __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, RayF3 f,
       const int n = g.n;
       const bool xmaj = fabs(ray.ex) >= fabs(ray.ey);
       const Rec3<T>* __restrict__ base = xmaj ? recC : recR;
-      // [z][x][y] or [z][y][x] address of the mirrored voxel (x, y, z), clamped into range
-      auto addr = [&](int x, int y, int z) {
-        const unsigned rx = w.real_x(min(x, n - 1)), ry = w.real_y(min(y, n - 1)), rz = w.real_z(min(z, g.nz - 1));
-        const unsigned nn = unsigned(n);
-        return xmaj ? __umul24(__umul24(rz, nn) + rx, nn) + ry : __umul24(__umul24(rz, nn) + ry, nn) + rx;
-      };
-      Rec3<T> rec = base[addr(w.x, w.y, w.z)];
+      w.layout(xmaj);
+      Rec3<T> rec = base[w.index(w.x, w.y, w.z)];
       for (int step = 0; step < 4 * (2 * n + g.nz) + 8; ++step) {
         double chord;
         const bool go = w.step(int(rec.lev()), chord);
-        const Rec3<T> nrec = base[addr(w.x, w.y, w.z)];
+        const Rec3<T> nrec = base[w.index(w.x, w.y, w.z)];
         acc += chord * double(rec.mu());
         if (!go) break;
         rec = nrec;
@@ -899,11 +913,10 @@ __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, RayF3 f, const uint8_t* 
       const uint8_t* __restrict__ lv = xmaj ? levC : lev;
       // leaf level at mirrored voxel (x, y, z), clamped into range (past the last leaf the
       // value is loaded and not used)
+      w.layout(xmaj);
       auto level = [&](int x, int y, int zz) {
         if (LT == 0) return 0;
-        const unsigned rx = w.real_x(min(x, n - 1)), ry = w.real_y(min(y, n - 1)), rz = w.real_z(min(zz, g.nz - 1));
-        const unsigned a0 = xmaj ? rx : ry, a1 = xmaj ? ry : rx;
-        return int(lv[__umul24(__umul24(rz, unsigned(n)) + a0, unsigned(n)) + a1]);
+        return int(lv[w.index(x, y, zz)]);
       };
       int l = level(w.x, w.y, w.z);
       for (int step = 0; step < 4 * (2 * n + g.nz) + 8; ++step) {
