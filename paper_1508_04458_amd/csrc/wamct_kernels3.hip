@@ -348,6 +348,7 @@ struct Walker3 {
   double ux, uy, uz;   // voxels per unit t along each axis
   double kx, ky, kz;   // t per voxel along each axis
   double cx, cy, cz;   // t at mirrored coordinate 0
+  double cx1, cy1, cz1;  // t at mirrored coordinate 1
   double t, t_out;
   int x, y, z;         // current voxel, mirrored frame
   int xx, xy, xz;      // real index = (mirrored ^ x) + a: (0, 0), or (-1, size) for size - 1 - mirrored
@@ -368,6 +369,7 @@ struct Walker3 {
     xy = ey < 0.0 ? -1 : 0; ay = ey < 0.0 ? n : 0;
     xz = ez < 0.0 ? -1 : 0; az = ez < 0.0 ? nz : 0;
     cx = -x0 * kx; cy = -y0 * ky; cz = -z0 * kz;
+    cx1 = cx + kx; cy1 = cy + ky; cz1 = cz + kz;
     const double t_in = fmax(fmax(cx, cy), cz);
     t_out = fmin(fmin((double(n) - x0) * kx, (double(n) - y0) * ky), (double(nz) - z0) * kz);
     if (!(t_out > t_in)) return false;
@@ -406,18 +408,22 @@ struct Walker3 {
     const int m = (1 << l) - 1;
     // last voxel of the leaf along each axis (leaf boundaries are multiples of 2^l)
     const int hx = x | m, hy = y | m, hz = WD == 3 ? (z | m) : z;
-    const double tX = fma(double(hx + 1), kx, cx), tY = fma(double(hy + 1), ky, cy);
-    const double tZ = fma(double(hz + 1), kz, cz);
+    const double tX = fma(double(hx), kx, cx1), tY = fma(double(hy), ky, cy1);
+    const double tZ = fma(double(hz), kz, cz1);
     const bool ax0 = tX <= tY && tX <= tZ;
     const bool ax1 = !ax0 && tY <= tZ;
-    const double te = fmax(fmin(fmin(tX, fmin(tY, tZ)), t_out), t);
+    // the leaf's faces lie inside the volume, so te <= t_out and te >= t up to rounding (a
+    // chord of an ulp below 0 where the ray passes an edge; the voxel indices never move
+    // backwards and the index test below ends the walk at the volume's faces)
+    const double te = fmin(tX, fmin(tY, tZ));
     chord = te - t;
     int nx = min(max(int(fma(te, ux, x0)), x), hx);
     int ny = min(max(int(fma(te, uy, y0)), y), hy);
     int nzv = min(max(int(fma(te, uz, z0)), z), hz);
-    nx = ax0 ? hx + 1 : nx;
-    ny = ax1 ? hy + 1 : ny;
-    nzv = (!ax0 && !ax1) ? hz + 1 : nzv;
+    // the crossed axis moves to the next leaf (the clamped exit voxel there is hx, hy or hz)
+    nx += int(ax0);
+    ny += int(ax1);
+    nzv += int(!ax0 && !ax1);
     t = te; x = nx; y = ny; z = nzv;
     return te < t_out && nx < n && ny < n && nzv < nz;
   }
