@@ -484,28 +484,29 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
       const R cu0 = eu < R(0) ? R(n) - Ou : Ou, cw0 = ew < R(0) ? R(n) - Ow : Ow;
       const R cue = fabs(eu) * ipix, cwe = fabs(ew) * ipix;
       const R dtu = fabs(ieu) * pix, dtw = fabs(iew) * pix;
-      const R tu0 = -cu0 * dtu, tw0 = -cw0 * dtw;
-      // real index = (mirrored ^ x) + a: (x, a) = (0, 0), or (-1, n) for n - 1 - mirrored
-      const int xu = eu < R(0) ? -1 : 0, au = eu < R(0) ? n : 0;
-      const int xw = ew < R(0) ? -1 : 0, aw = ew < R(0) ? n : 0;
-      auto idx = [&](int u, int w) {
-        return __umul24(unsigned((imin(u, n - 1) ^ xu) + au), unsigned(n)) + unsigned((imin(w, n - 1) ^ xw) + aw);
-      };
+      const R tu1 = (R(1) - cu0) * dtu, tw1 = (R(1) - cw0) * dtw;   // planes u = 1, w = 1
+      // real index = c + s m of the mirrored one (c = 0, s = 1, or c = n - 1, s = -1), so the
+      // record index (real u) n + (real w) is linear in the mirrored pixel
+      const int su = eu < R(0) ? -1 : 1, sw = ew < R(0) ? -1 : 1;
+      const int i0 = (eu < R(0) ? n - 1 : 0) * n + (ew < R(0) ? n - 1 : 0), du = su * n;
+      auto idx = [&](int u, int w) { return unsigned(i0 + __mul24(du, imin(u, n - 1)) + __mul24(sw, imin(w, n - 1))); };
       int iu = imin(imax(int(fma(t_s, cue, cu0)), 0), n - 1);
       int iw = imin(imax(int(fma(t_s, cwe, cw0)), 0), n - 1);
       Leaf<T> rec = base[idx(iu, iw)];
       R t = t_s;
       for (int step = 0; step < 4 * n + 8; ++step) {
-        const int s = 1 << int(rec.lev());
-        const int eu_ = (iu & -s) + s, ew_ = (iw & -s) + s;   // upper planes of the leaf
-        const R tU = fma(R(eu_), dtu, tu0), tW = fma(R(ew_), dtw, tw0);
+        const int m = (1 << int(rec.lev())) - 1;
+        const int hu = iu | m, hw = iw | m;   // last pixel of the leaf along u and w
+        const R tU = fma(R(hu), dtu, tu1), tW = fma(R(hw), dtw, tw1);   // its upper planes
         const bool cu = tU <= tW;   // the leaf is left through a u plane
-        const R te = fmax(fmin(fmin(tU, tW), t_out), t);
+        // the planes lie ahead of t up to rounding (a chord an ulp below 0 where the ray
+        // passes a corner; the pixel indices never move backwards)
+        const R te = fmin(fmin(tU, tW), t_out);
         // the axis not crossed takes the exit point's pixel, clamped into the old leaf's
-        // range and never moving backwards; the crossed axis steps to the neighbour leaf
-        const int ou = imin(imax(int(fma(te, cue, cu0)), iu), eu_ - 1);
-        const int ow = imin(imax(int(fma(te, cwe, cw0)), iw), ew_ - 1);
-        const int niu = cu ? eu_ : ou, niw = cu ? ow : ew_;
+        // range and never moving backwards; the crossed axis steps to the neighbour leaf (its
+        // exit point's pixel clamps to the leaf's last one)
+        const int niu = imin(imax(int(fma(te, cue, cu0)), iu), hu) + int(cu);
+        const int niw = imin(imax(int(fma(te, cwe, cw0)), iw), hw) + int(!cu);
         const bool go = te < t_out && niu < n && niw < n;
         const Leaf<T> nrec = base[idx(niu, niw)];
         acc += (te - t) * R(rec.mu());
