@@ -71,30 +71,32 @@ __host__ __device__ inline void walk(const DevGeom& g, R ox, R oy, R ex, R ey, R
   const R ux = fabs(ex) * ipix, uy = fabs(ey) * ipix;             // pixels per unit t
   const R kx = fabs(iex) * R(g.pixel), ky = fabs(iey) * R(g.pixel);   // t per pixel
   const R cx = -x0 * kx, cy = -y0 * ky;                           // t at mirrored coordinate 0
-  // real index = (mirrored ^ m) + a: (m, a) = (0, 0), or (-1, n) for n - 1 - mirrored
-  const int mx = ex < R(0) ? -1 : 0, ax = ex < R(0) ? n : 0;
-  const int my = ey < R(0) ? -1 : 0, ay = ey < R(0) ? n : 0;
+  const R cx1 = (R(1) - x0) * kx, cy1 = (R(1) - y0) * ky;         // t at mirrored coordinate 1
+  // real index = c + s m of the mirrored one (c = 0, s = 1, or c = n - 1, s = -1)
+  const int sx = ex < R(0) ? -1 : 1, cxr = ex < R(0) ? n - 1 : 0;
+  const int sy = ey < R(0) ? -1 : 1, cyr = ey < R(0) ? n - 1 : 0;
   const R t_in = fmax(cx, cy);
   const R t_out = fmin(fma(R(n), kx, cx), fma(R(n), ky, cy));
   if (!(t_out > t_in)) return;
   int x = imin(imax(int(fma(t_in, ux, x0)), 0), n - 1);
   int y = imin(imax(int(fma(t_in, uy, y0)), 0), n - 1);
   R t = t_in;
-  // leaf level of the mirrored pixel (x, y), clamped into range
-  auto level = [&](int xm, int ym) {
-    return TREE ? int(lev[((imin(ym, n - 1) ^ my) + ay) * n + ((imin(xm, n - 1) ^ mx) + ax)]) : 0;
-  };
+  // leaf level of the mirrored pixel (x, y), clamped into range: row-major index linear in
+  // the mirrored coordinates
+  const int i0 = cyr * n + cxr, dy = sy * n;
+  auto level = [&](int xm, int ym) { return TREE ? int(lev[i0 + dy * imin(ym, n - 1) + sx * imin(xm, n - 1)]) : 0; };
   int l = level(x, y);
   for (int step = 0; step < 4 * n + 8; ++step) {
-    const int rx = (x ^ mx) + ax, ry = (y ^ my) + ay;
-    const int s = 1 << l;
-    const int ex_ = (x & -s) + s, ey_ = (y & -s) + s;
-    const R tX = fma(R(ex_), kx, cx), tY = fma(R(ey_), ky, cy);
+    const int rx = cxr + sx * x, ry = cyr + sy * y;
+    const int m = (1 << l) - 1;
+    const int hx = x | m, hy = y | m;   // last pixel of the leaf along x and y
+    const R tX = fma(R(hx), kx, cx1), tY = fma(R(hy), ky, cy1);   // its upper planes
     const bool cross_x = tX <= tY;
-    const R te = fmax(fmin(fmin(tX, tY), t_out), t);
-    const int xo = imin(imax(int(fma(te, ux, x0)), x), ex_ - 1);
-    const int yo = imin(imax(int(fma(te, uy, y0)), y), ey_ - 1);
-    const int xn = cross_x ? ex_ : xo, yn = cross_x ? yo : ey_;
+    // the planes lie inside the image and ahead of t, up to rounding (a chord an ulp below 0
+    // where the ray passes a corner; the pixel indices never move backwards)
+    const R te = fmin(tX, tY);
+    const int xn = imin(imax(int(fma(te, ux, x0)), x), hx) + int(cross_x);
+    const int yn = imin(imax(int(fma(te, uy, y0)), y), hy) + int(!cross_x);
     const int ln = level(xn, yn);   // the next leaf's level, in flight while f runs
     f(rx, ry, l, te - t);
     if (te >= t_out || xn >= n || yn >= n) break;
