@@ -619,7 +619,9 @@ __device__ inline ItemSums<R> item_sums_k(const DevGeom& g, const float2* __rest
       sy = R(g.sod * cv.y);
     }
     const R dx0 = X0 - sx, dx1 = X1 - sx, dx2 = X2 - sx, dy0 = Y0 - sy, dy1 = Y1 - sy, dy2 = Y2 - sy;
-    const auto ray = [&](const typename V4<R>::t& a, const R yv) {
+    for (int bb = blo; bb <= bhi; ++bb) {
+      const typename V4<R>::t a = A[base + bb];
+      const R yv = R(y[base + bb]);
       // origin offset: 0 for the fan beam (parameters from S), the ray's origin otherwise
       const R ox = FAN ? R(0) : a.x, oy = FAN ? R(0) : a.y;
       const R tx0 = (dx0 - ox) * a.z, tx2 = (dx2 - ox) * a.z;
@@ -652,19 +654,7 @@ __device__ inline ItemSums<R> item_sums_k(const DevGeom& g, const float2* __rest
         r.s1 += w2; r.a1 += fabs(w2);
         r.s2 += w3; r.a2 += fabs(w3);
       }
-    };
-    // bins four at a time with all their loads issued before the first use (one memory wait
-    // per four rays); sums in bin order
-    int bb = blo;
-    for (; bb + 3 <= bhi; bb += 4) {
-      typename V4<R>::t a4[4];
-      T y4[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) { a4[u] = A[base + bb + u]; y4[u] = y[base + bb + u]; }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) ray(a4[u], R(y4[u]));
     }
-    for (; bb <= bhi; ++bb) ray(A[base + bb], R(y[base + bb]));
   }
   return r;
 }
