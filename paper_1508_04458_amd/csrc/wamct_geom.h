@@ -59,8 +59,8 @@ __host__ __device__ inline void ray_of(const DevGeom& g, double2 cs, int b, doub
 // parameter of the leaf is the nearer of its two upper planes, and the next pixel is the
 // neighbour across that plane, its other coordinate taken at the exit point and clamped into
 // the leaf's range (monotone even when rounding puts the exit point on a corner). Every step
-// moves to a new leaf, so at most 2n steps occur; the loop bound 4n + 8 only guards against
-// malformed input.
+// adds at least one to the crossed axis' index and lowers neither, and the walk stops once an
+// index reaches n, so it ends after at most 2n steps for any levels below 32 in the map.
 template <typename R, bool TREE, typename F>
 __host__ __device__ inline void walk(const DevGeom& g, R ox, R oy, R ex, R ey, R iex, R iey,
                             const uint8_t* lev, F& f) {
@@ -86,7 +86,7 @@ __host__ __device__ inline void walk(const DevGeom& g, R ox, R oy, R ex, R ey, R
   const int i0 = cyr * n + cxr, dy = sy * n;
   auto level = [&](int xm, int ym) { return TREE ? int(lev[i0 + dy * imin(ym, n - 1) + sx * imin(xm, n - 1)]) : 0; };
   int l = level(x, y);
-  for (int step = 0; step < 4 * n + 8; ++step) {
+  for (;;) {
     const int rx = cxr + sx * x, ry = cyr + sy * y;
     const int m = (1 << l) - 1;
     const int hx = x | m, hy = y | m;   // last pixel of the leaf along x and y

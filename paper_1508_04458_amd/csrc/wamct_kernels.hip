@@ -430,8 +430,10 @@ __global__ __launch_bounds__(kBlock) void k_forward(DevGeom g, const typename V4
 // nearer of the leaf's two exit planes; the next pixel is the neighbour across that plane,
 // its other coordinate taken from the exit point (FP32 suffices: it is clamped into the old
 // leaf's range and never moves backwards, so rounding at a corner only moves a vanishing
-// chord between neighbours and cannot reverse the walk). Every step enters a new leaf, so
-// at most 2n steps occur (loop bound 4n + 8). x-major rays read the column-major records.
+// chord between neighbours and cannot reverse the walk). Every step adds at least one to the
+// crossed axis' pixel index and never lowers the other, and the walk stops once an index
+// reaches n, so it ends after at most 2n steps for any levels in the records (no step
+// counter). x-major rays read the column-major records.
 // With K > 1, K adjacent lanes share a ray (for launches with too few rays to fill the
 // GPU): lane k walks the k-th of K equal parameter pieces of the ray's path through the
 // image from the pixel holding the piece's first point, and the K sums are added across
@@ -494,7 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_rec(DevGeom g, const typenam
       int iw = imin(imax(int(fma(t_s, cwe, cw0)), 0), n - 1);
       Leaf<T> rec = base[idx(iu, iw)];
       R t = t_s;
-      for (int step = 0; step < 4 * n + 8; ++step) {
+      for (;;) {   // ends: see the kernel's comment
         const int m = (1 << int(rec.lev())) - 1;
         const int hu = iu | m, hw = iw | m;   // last pixel of the leaf along u and w
         const R tU = fma(R(hu), dtu, tu1), tW = fma(R(hw), dtw, tw1);   // its upper planes

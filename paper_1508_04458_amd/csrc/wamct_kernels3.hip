@@ -420,7 +420,9 @@ struct Walker3 {
     int nx = min(max(int(fma(te, ux, x0)), x), hx);
     int ny = min(max(int(fma(te, uy, y0)), y), hy);
     int nzv = min(max(int(fma(te, uz, z0)), z), hz);
-    // the crossed axis moves to the next leaf (the clamped exit voxel there is hx, hy or hz)
+    // the crossed axis moves to the next leaf (the clamped exit voxel there is hx, hy or hz):
+    // every step adds one to one index and lowers none, so a walk that stops once an index
+    // leaves the volume ends after at most 2 n + nz steps, for any leaf levels below 32
     nx += int(ax0);
     ny += int(ax1);
     nzv += int(!ax0 && !ax1);
@@ -453,7 +455,7 @@ __global__ __launch_bounds__(kB) void k3_forward(DevGeom3 g, RayF3 f,
       const Rec3<T>* __restrict__ base = xmaj ? recC : recR;
       w.layout(xmaj);
       Rec3<T> rec = base[w.index(w.x, w.y, w.z)];
-      for (int step = 0; step < 4 * (2 * n + g.nz) + 8; ++step) {
+      for (;;) {   // ends within 2 n + nz steps (Walker3::step)
         double chord;
         const bool go = w.step(int(rec.lev()), chord);
         const Rec3<T> nrec = base[w.index(w.x, w.y, w.z)];
@@ -925,7 +927,7 @@ __global__ __launch_bounds__(kB) void k3_z0(DevGeom3 g, RayF3 f, const uint8_t* 
         return int(lv[w.index(x, y, zz)]);
       };
       int l = level(w.x, w.y, w.z);
-      for (int step = 0; step < 4 * (2 * n + g.nz) + 8; ++step) {
+      for (;;) {   // ends within 2 n + nz steps (Walker3::step)
         const int ix = w.rx(), iy = w.ry(), iz = w.rz();
         double chord;
         const bool go = w.step(l, chord);
