@@ -579,45 +579,38 @@ __device__ inline Sums3<double> item_sums3(const DevGeom3& g, const double2* __r
     const double ax0 = X0 - Sx, ax1 = X1 - Sx, ax2 = X2 - Sx;
     const double ay0 = Y0 - Sy, ay1 = Y1 - Sy, ay2 = Y2 - Sy;
     const double2* __restrict__ cv = colt + int64_t(v) * g.nc;
-    if (!SPLIT) {
-      // Rows in blocks of four: every column's factors are loaded once per block and its x
-      // and y slab interval is shared by the four rays of the column, each of which only
-      // applies the z slab of its row (rows past the last repeat it and add nothing); sums in
-      // (block, column, row) order
-      for (int r0 = rlo; r0 <= rhi; r0 += 4) {
-        double zl[4], zh[4];
-        const T* __restrict__ yq[4];
-        bool live[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int row = min(r0 + u, rhi);
-          live[u] = r0 + u <= rhi;
-          const double iz = rowt[row];
-          zl[u] = fmin(Z0 * iz, Z2 * iz);
-          zh[u] = fmax(Z0 * iz, Z2 * iz);
-          yq[u] = y + (int64_t(v) * g.nr + row) * g.nc;
-        }
-        for (int col = clo; col <= chi; ++col) {
-          const double2 cd = cv[col];
-          T yy[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) yy[u] = yq[u][col];
-          const double tx0 = ax0 * cd.x, tx2 = ax2 * cd.x, ty0 = ay0 * cd.y, ty2 = ay2 * cd.y;
-          const double lxy = fmax(fmin(tx0, tx2), fmin(ty0, ty2));
-          const double hxy = fmin(fmax(tx0, tx2), fmax(ty0, ty2));
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const double chd = fmin(hxy, zh[u]) - fmax(lxy, zl[u]);
-            r.v[0] += live[u] && chd > tq ? double(yy[u]) * chd : 0.0;
-          }
-        }
-      }
-      continue;
-    }
     for (int row = rlo; row <= rhi; ++row) {
       const double iz = rowt[row];
       const double tz0 = Z0 * iz, tz2 = Z2 * iz;
       const T* __restrict__ yr = y + (int64_t(v) * g.nr + row) * g.nc;
+      if (!SPLIT) {
+        const double zlo = fmin(tz0, tz2), zhi = fmax(tz0, tz2);
+        const auto chord = [&](double2 cd) {
+          const double tx0 = ax0 * cd.x, tx2 = ax2 * cd.x, ty0 = ay0 * cd.y, ty2 = ay2 * cd.y;
+          const double lo = fmax(fmax(fmin(tx0, tx2), fmin(ty0, ty2)), zlo);
+          const double hi = fmin(fmin(fmax(tx0, tx2), fmax(ty0, ty2)), zhi);
+          return hi - lo;
+        };
+        // columns four at a time with all eight loads issued before the first use (one
+        // memory wait per four rays instead of two per ray); sums in column order
+        int col = clo;
+        for (; col + 3 <= chi; col += 4) {
+          double2 cd[4];
+          T yy[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) { cd[u] = cv[col + u]; yy[u] = yr[col + u]; }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double chd = chord(cd[u]);
+            r.v[0] += chd > tq ? double(yy[u]) * chd : 0.0;
+          }
+        }
+        for (; col <= chi; ++col) {
+          const double chd = chord(cv[col]);
+          r.v[0] += chd > tq ? double(yr[col]) * chd : 0.0;
+        }
+        continue;
+      }
       // Per ray: the box's parameter interval [lo, hi] and the mid-plane crossings clamped
       // into it. Along an axis the ray is in the lower half on one side of its crossing c
       // (before c when it moves up that axis, after c otherwise), so the signed length of a
